@@ -1,0 +1,124 @@
+/*
+ * sosfilt.h -- C ABI of the MI355X (gfx950) cascaded-biquad filter library.
+ *
+ * The library filters FP32 signals through a cascade of K second-order
+ * sections (biquads) with the multi-block method of Zhai & Paris, "Parallel
+ * Cascaded Recursive Filtering on Multi-Core CPUs and GPUs" (Part II):
+ *   - each group of C = N*L samples is viewed in the stride-N permuted
+ *     (multi-block) form of Sec. II-B, Eqs. (2)-(5): lane l of a group holds
+ *     the N consecutive samples [l*N, l*N + N);
+ *   - every lane is solved at zero incoming state by one divide-and-conquer
+ *     level followed by one-sided cyclic reduction per parity (Sec. II-D/E,
+ *     Eqs. (14)-(23)), which exposes both terminal samples of the lane before
+ *     any back substitution;
+ *   - the lanes' zero-state terminal states are combined by a cross-lane scan
+ *     (the role of Eq. (13)), the group's incoming state arrives over a
+ *     decoupled lookback between groups (Sec. IV-B, Eq. (25)), and the
+ *     homogeneous correction is folded into the back substitution
+ *     (Sec. II-F, Eq. (24)); all K sections run in registers inside one kernel
+ *     launch per call (Sec. IV-A).
+ *
+ * Conventions shared by every entry point
+ *   sections : K x 6 FP32 rows [b0 b1 b2 a0 a1 a2] (scipy "sos" layout),
+ *              row-major, DEVICE memory. Each row is divided by its a0 in FP64
+ *              on the device before use. b0 is kept in the feed-forward part,
+ *              so b0 == 0 is allowed. Eq. (1) of the paper is the b0 = 1 case.
+ *   zi, zf   : K x 2 FP32 transposed-direct-form-II states (z1, z2) per
+ *              section, DEVICE memory: the scipy sosfilt convention. zi == NULL
+ *              means zero initial state; zf == NULL means "do not write".
+ *              zf is the state after the last real sample n-1.
+ *   x, y     : n FP32 samples, DEVICE memory. y may equal x (in place);
+ *              partial overlap is not allowed.
+ *   stream   : the HIP stream all work is enqueued on; every call returns
+ *              as soon as the work is enqueued. Buffers must stay valid until
+ *              the stream has executed the work.
+ *
+ * Ownership: the caller owns every data buffer. The handle owns its workspace
+ * (coefficient tables, lookback descriptors, ticket/epoch words); it grows on
+ * the first call of a larger shape and is reused afterwards. Calls that share
+ * one handle must be ordered (same stream, or synchronised): the workspace is
+ * not shared safely between concurrently running calls. Use one handle per
+ * concurrently used stream.
+ *
+ * Errors: every function returns an int status and never aborts across the
+ * ABI. Argument errors are detected synchronously. Problems found on the
+ * device (a0 == 0, a section outside the stability triangle, a lookback that
+ * did not resolve in time) make the affected outputs NaN and are reported by
+ * sos_last_error().
+ */
+#ifndef SOSFILT_H
+#define SOSFILT_H
+
+#include <stdint.h>
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SOS_OK = 0,
+    SOS_EINVAL = -1,      /* bad argument (null pointer, negative size, K out of range ...) */
+    SOS_EA0 = -2,         /* a section has a0 == 0                                          */
+    SOS_EUNSTABLE = -3,   /* |a2| > 1 or |a1| > 1 + a2 after normalisation                   */
+    SOS_ENOMEM = -4,      /* device allocation failed                                        */
+    SOS_EHIP = -5,        /* a HIP runtime call failed                                       */
+    SOS_ETIMEOUT = -6,    /* a lookback wait exceeded its bound (outputs poisoned with NaN)  */
+    SOS_ECLOSED = -7,     /* object already destroyed / stream closed                        */
+    SOS_EBUSY = -8        /* resource temporarily exhausted                                  */
+};
+
+#define SOS_MAX_SECTIONS 64
+
+typedef struct sos_ctx *sos_handle_t;
+
+/* Create a handle bound to HIP device `hip_device` (the device must be the
+ * current device whenever the handle is used). Returns SOS_OK or an error. */
+int sos_create(sos_handle_t *h, int hip_device);
+
+/* Free the handle and its workspace. Synchronises the device first. */
+int sos_destroy(sos_handle_t h);
+
+/* Static text for a status code. */
+const char *sos_strerror(int code);
+
+/* Synchronises the handle's device, returns the first device-side error
+ * (SOS_EA0, SOS_EUNSTABLE, SOS_ETIMEOUT) raised since the previous call of
+ * sos_last_error on this handle, or SOS_OK, and clears it. */
+int sos_last_error(sos_handle_t h);
+
+/* Samples per lane N of the group tile (the group holds C = 64*N samples):
+ * one of 16, 32, 64. 0 restores the default. Applies to later calls. */
+int sos_set_tile(sos_handle_t h, int samples_per_lane);
+int sos_get_tile(sos_handle_t h);
+
+/*
+ * Plain filter, one signal (Sec. IV-A/B; Eqs. (1)-(25)).
+ *   y[0..n) = cascade(sections[0..K))(x[0..n)) starting from zi; zf receives
+ *   the final states. 0 <= K <= SOS_MAX_SECTIONS, n >= 0.
+ *   n == 0: y is not touched and zf := zi (zeros if zi == NULL).
+ *   K == 0: y := x.
+ * Enqueues: one coefficient-preparation kernel (FP64 tables) and one filter
+ * kernel (ticketed groups, register-resident cascade, decoupled lookback).
+ */
+int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y,
+               int64_t n, const float *zi, float *zf, hipStream_t stream);
+
+/* Debug/inspection: after a completed sos_filter call on this handle, copy the
+ * resolved state at the end of every (group, section) -- the "global carry" of
+ * Sec. II-F that the decoupled lookback publishes, as a TDF-II pair -- to host
+ * memory `out` (groups x K x 2 floats, group-major) and return the number of
+ * groups and sections through *groups and *K. For a full group g this is the
+ * state after sample (g+1)*C - 1; for a zero-padded last group it is the state
+ * after the padding. out may be NULL to query the sizes; capacity_floats is
+ * the size of out. Synchronises the device. Returns SOS_EINVAL if out is too
+ * small or no call was made. */
+int sos_debug_carries(sos_handle_t h, float *out, int64_t capacity_floats, int64_t *groups,
+                      int *K);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOSFILT_H */

@@ -1,0 +1,192 @@
+"""MI355X (gfx950) cascaded-biquad filtering: Python binding of libsosfilt.
+
+Thin ctypes layer over the C ABI in include/sosfilt.h. It only marshals
+arguments (device pointers of torch tensors, the current HIP stream); every
+step of the filter runs in the HIP kernels of libsosfilt.so. There is no CPU
+fallback: if the library is missing, importing the binding's functions fails.
+
+    from paper_2607_23763_amd import sosfilt
+    y, zf = sosfilt(x, sos, zi)        # x: (n,) float32 on the GPU, sos: (K, 6)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsosfilt.so")
+
+SOS_OK = 0
+SOS_EINVAL = -1
+SOS_EA0 = -2
+SOS_EUNSTABLE = -3
+SOS_ENOMEM = -4
+SOS_EHIP = -5
+SOS_ETIMEOUT = -6
+SOS_ECLOSED = -7
+SOS_EBUSY = -8
+SOS_MAX_SECTIONS = 64
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+class SosError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what or "sosfilt", strerror(code), code))
+
+
+def lib():
+    """Load libsosfilt.so (built by __graft_entry__.build()); raises if missing."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("libsosfilt.so is not built (%s); run __graft_entry__.build()"
+                                  % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+            L.sos_create.argtypes = [ctypes.POINTER(vp), i32]
+            L.sos_destroy.argtypes = [vp]
+            L.sos_strerror.argtypes = [i32]
+            L.sos_strerror.restype = ctypes.c_char_p
+            L.sos_last_error.argtypes = [vp]
+            L.sos_set_tile.argtypes = [vp, i32]
+            L.sos_get_tile.argtypes = [vp]
+            L.sos_filter.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp]
+            L.sos_debug_carries.argtypes = [vp, vp, i64, ctypes.POINTER(i64),
+                                            ctypes.POINTER(i32)]
+            for name in ("sos_create", "sos_destroy", "sos_last_error", "sos_set_tile",
+                         "sos_get_tile", "sos_filter", "sos_debug_carries"):
+                getattr(L, name).restype = i32
+            _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().sos_strerror(int(code)).decode()
+    except ImportError:
+        return "status %d" % code
+
+
+def _check(rc: int, what: str):
+    if rc != SOS_OK:
+        raise SosError(rc, what)
+
+
+def _stream_ptr(device=None):
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Handle:
+    """Owns a libsosfilt handle (workspace: tables, lookback descriptors)."""
+
+    def __init__(self, device: int = 0, tile: int = 0):
+        self._h = ctypes.c_void_p()
+        self.device = int(device)
+        _check(lib().sos_create(ctypes.byref(self._h), self.device), "sos_create")
+        if tile:
+            self.set_tile(tile)
+
+    def close(self):
+        if self._h:
+            lib().sos_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def set_tile(self, n: int):
+        _check(lib().sos_set_tile(self._h, int(n)), "sos_set_tile")
+
+    def tile(self) -> int:
+        return int(lib().sos_get_tile(self._h))
+
+    def last_error(self) -> int:
+        return int(lib().sos_last_error(self._h))
+
+    def carries(self):
+        """Resolved per-(group, section) end states of the last call, (groups, K, 2)."""
+        import numpy as np
+
+        g = ctypes.c_int64()
+        k = ctypes.c_int32()
+        _check(lib().sos_debug_carries(self._h, None, 0, ctypes.byref(g), ctypes.byref(k)),
+               "sos_debug_carries")
+        out = np.empty((g.value, k.value, 2), dtype=np.float32)
+        _check(lib().sos_debug_carries(self._h, out.ctypes.data_as(ctypes.c_void_p), out.size,
+                                       ctypes.byref(g), ctypes.byref(k)), "sos_debug_carries")
+        return out
+
+
+_handles = {}
+_handles_lock = threading.Lock()
+
+
+def default_handle(device: int = 0) -> Handle:
+    with _handles_lock:
+        h = _handles.get(device)
+        if h is None:
+            h = Handle(device)
+            _handles[device] = h
+        return h
+
+
+def _as_dev_f32(t, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU torch tensor" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    return t.contiguous()
+
+
+def sosfilt_(x, sos, y=None, zi=None, zf=None, handle: Handle | None = None):
+    """Low-level call: filter device tensor x into y (may be x) with the K x 6
+    device tensor sos; optional zi (K, 2) and zf (K, 2) outputs. Enqueued on
+    the current stream."""
+    import torch
+
+    x = _as_dev_f32(x, "x")
+    sos = _as_dev_f32(sos, "sos").reshape(-1, 6)
+    K = sos.shape[0]
+    if y is None:
+        y = torch.empty_like(x)
+    h = handle or default_handle(x.device.index or 0)
+    rc = lib().sos_filter(
+        h.ptr, ctypes.c_void_p(sos.data_ptr()), K, ctypes.c_void_p(x.data_ptr()),
+        ctypes.c_void_p(y.data_ptr()), x.numel(),
+        ctypes.c_void_p(zi.data_ptr()) if zi is not None else None,
+        ctypes.c_void_p(zf.data_ptr()) if zf is not None else None,
+        _stream_ptr(x.device))
+    _check(rc, "sos_filter")
+    return y
+
+
+def sosfilt(x, sos, zi=None, handle: Handle | None = None):
+    """y, zf = sosfilt(x, sos, zi): cascade of K biquads over a 1-D float32
+    GPU tensor; sos is (K, 6) [b0 b1 b2 a0 a1 a2]; zi/zf are (K, 2) TDF-II states."""
+    import torch
+
+    x = _as_dev_f32(x, "x").reshape(-1)
+    sos = _as_dev_f32(sos, "sos").reshape(-1, 6)
+    K = sos.shape[0]
+    if zi is not None:
+        zi = _as_dev_f32(zi, "zi").reshape(K, 2)
+    zf = torch.empty((K, 2), dtype=torch.float32, device=x.device)
+    y = torch.empty_like(x)
+    sosfilt_(x, sos, y=y, zi=zi, zf=zf, handle=handle)
+    return y, zf

@@ -1,0 +1,269 @@
+// Host side of the C ABI declared in include/sosfilt.h: handle, workspace,
+// argument checks and kernel launches. No exception or abort crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "sosfilt.h"
+#include "sos_device.h"
+
+extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, float *tabs,
+                                      unsigned *ctrl, hipStream_t stream);
+extern "C" hipError_t sos_launch_fwd(int N, const float *x, float *y, int64_t n, int64_t groups,
+                                     const float *tabs, int K, const float *zi, float *zf,
+                                     unsigned long long *desc, unsigned *ctrl,
+                                     unsigned long long timeout_ticks, hipStream_t stream);
+extern "C" hipError_t sos_launch_fill(float *dst, const float *src, int64_t count,
+                                      hipStream_t stream);
+
+using namespace sosdev;
+
+struct sos_ctx {
+    int device = 0;
+    int tile = 0;                         // samples per lane N; 0 = default
+    unsigned *ctrl = nullptr;             // CTRL_WORDS
+    float *tabs = nullptr;
+    int tabs_cap = 0;                     // sections
+    unsigned long long *desc = nullptr;
+    size_t desc_cap = 0;                  // 64-bit words
+    unsigned long long timeout_ticks = 0;
+    int64_t last_groups = 0;
+    int last_K = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+constexpr int kDefaultTile = 32;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int ensure_tabs(sos_ctx *h, int K, hipStream_t stream)
+{
+    if (K <= h->tabs_cap) return SOS_OK;
+    if (h->tabs) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return SOS_EHIP;
+        (void)hipFree(h->tabs);
+        h->tabs = nullptr;
+        h->tabs_cap = 0;
+    }
+    const int cap = K < 8 ? 8 : K;
+    if (hipMalloc(&h->tabs, sizeof(float) * (size_t)TAB_FLOATS * cap) != hipSuccess)
+        return SOS_ENOMEM;
+    h->tabs_cap = cap;
+    return SOS_OK;
+}
+
+int ensure_desc(sos_ctx *h, size_t words, hipStream_t stream)
+{
+    if (words <= h->desc_cap) return SOS_OK;
+    if (h->desc) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return SOS_EHIP;
+        (void)hipFree(h->desc);
+        h->desc = nullptr;
+        h->desc_cap = 0;
+    }
+    size_t cap = words + words / 4 + 1024;
+    if (hipMalloc(&h->desc, cap * sizeof(unsigned long long)) != hipSuccess) return SOS_ENOMEM;
+    // Tag 0 never matches a launch epoch, so zeroed words read as "not published".
+    if (hipMemset(h->desc, 0, cap * sizeof(unsigned long long)) != hipSuccess) return SOS_EHIP;
+    h->desc_cap = cap;
+    return SOS_OK;
+}
+
+int tile_of(const sos_ctx *h)
+{
+    if (h->tile) return h->tile;
+    const char *e = std::getenv("SOS_TILE_N");
+    if (e) {
+        const int v = std::atoi(e);
+        if (v == 16 || v == 32 || v == 64) return v;
+    }
+    return kDefaultTile;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sos_strerror(int code)
+{
+    switch (code) {
+    case SOS_OK: return "ok";
+    case SOS_EINVAL: return "invalid argument";
+    case SOS_EA0: return "a section has a0 == 0";
+    case SOS_EUNSTABLE: return "a section is outside the stability triangle";
+    case SOS_ENOMEM: return "device allocation failed";
+    case SOS_EHIP: return "HIP runtime error";
+    case SOS_ETIMEOUT: return "lookback wait timed out";
+    case SOS_ECLOSED: return "closed";
+    case SOS_EBUSY: return "busy";
+    default: return "unknown status";
+    }
+}
+
+int sos_create(sos_handle_t *out, int hip_device)
+{
+    if (!out) return SOS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+        return SOS_EINVAL;
+    DeviceGuard g(hip_device);
+    if (!g.ok) return SOS_EHIP;
+    sos_ctx *h = new (std::nothrow) sos_ctx();
+    if (!h) return SOS_ENOMEM;
+    h->device = hip_device;
+    if (hipMalloc(&h->ctrl, sizeof(unsigned) * CTRL_WORDS) != hipSuccess) {
+        delete h;
+        return SOS_ENOMEM;
+    }
+    if (hipMemset(h->ctrl, 0, sizeof(unsigned) * CTRL_WORDS) != hipSuccess) {
+        (void)hipFree(h->ctrl);
+        delete h;
+        return SOS_EHIP;
+    }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;
+    double ms = 2000.0;
+    if (const char *e = std::getenv("SOS_TIMEOUT_MS")) ms = std::atof(e);
+    if (ms < 1.0) ms = 1.0;
+    h->timeout_ticks = (unsigned long long)(ms * (double)khz);
+    *out = h;
+    return SOS_OK;
+}
+
+int sos_destroy(sos_handle_t h)
+{
+    if (!h) return SOS_EINVAL;
+    {
+        DeviceGuard g(h->device);
+        (void)hipDeviceSynchronize();
+        if (h->desc) (void)hipFree(h->desc);
+        if (h->tabs) (void)hipFree(h->tabs);
+        if (h->ctrl) (void)hipFree(h->ctrl);
+    }
+    delete h;
+    return SOS_OK;
+}
+
+int sos_last_error(sos_handle_t h)
+{
+    if (!h) return SOS_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    if (hipDeviceSynchronize() != hipSuccess) return SOS_EHIP;
+    unsigned bits = 0;
+    if (hipMemcpy(&bits, h->ctrl + CTRL_ERR, sizeof(unsigned), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return SOS_EHIP;
+    if (bits && hipMemset(h->ctrl + CTRL_ERR, 0, sizeof(unsigned)) != hipSuccess) return SOS_EHIP;
+    if (bits & ERRBIT_A0) return SOS_EA0;
+    if (bits & ERRBIT_UNSTABLE) return SOS_EUNSTABLE;
+    if (bits & ERRBIT_TIMEOUT) return SOS_ETIMEOUT;
+    return SOS_OK;
+}
+
+int sos_set_tile(sos_handle_t h, int n)
+{
+    if (!h) return SOS_EINVAL;
+    if (n != 0 && n != 16 && n != 32 && n != 64) return SOS_EINVAL;
+    h->tile = n;
+    return SOS_OK;
+}
+
+int sos_get_tile(sos_handle_t h)
+{
+    if (!h) return SOS_EINVAL;
+    return tile_of(h);
+}
+
+int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y, int64_t n,
+               const float *zi, float *zf, hipStream_t stream)
+{
+    if (!h || K < 0 || K > SOS_MAX_SECTIONS || n < 0) return SOS_EINVAL;
+    if (K > 0 && !sections) return SOS_EINVAL;
+    if (n > 0 && (!x || !y)) return SOS_EINVAL;
+    if (n > 0 && x != y) {
+        // in place or disjoint only
+        const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, bytes = (uintptr_t)n * 4u;
+        if (xa < ya + bytes && ya < xa + bytes) return SOS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+
+    if (n == 0) {
+        if (zf && K > 0 && sos_launch_fill(zf, zi, 2 * (int64_t)K, stream) != hipSuccess)
+            return SOS_EHIP;
+        return SOS_OK;
+    }
+    if (K == 0) {
+        if (x != y && sos_launch_fill(y, x, n, stream) != hipSuccess) return SOS_EHIP;
+        return SOS_OK;
+    }
+    const int N = tile_of(h);
+    const int log2n = __builtin_ctz((unsigned)N);
+    const int64_t C = (int64_t)kLanes * N;
+    const int64_t groups = (n + C - 1) / C;
+    if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
+    int rc = ensure_tabs(h, K, stream);
+    if (rc) return rc;
+    rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
+    if (rc) return rc;
+    if (sos_launch_prep(sections, K, log2n, h->tabs, h->ctrl, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_fwd(N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
+                       h->timeout_ticks, stream) != hipSuccess)
+        return SOS_EHIP;
+    h->last_groups = groups;
+    h->last_K = K;
+    return SOS_OK;
+}
+
+int sos_debug_carries(sos_handle_t h, float *out, int64_t capacity_floats, int64_t *groups,
+                      int *K)
+{
+    if (!h) return SOS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (groups) *groups = h->last_groups;
+    if (K) *K = h->last_K;
+    if (!out) return SOS_OK;
+    const int64_t need = h->last_groups * h->last_K * 2;
+    if (need == 0 || capacity_floats < need) return SOS_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    if (hipDeviceSynchronize() != hipSuccess) return SOS_EHIP;
+    std::vector<unsigned long long> w((size_t)need * 2);
+    if (hipMemcpy(w.data(), h->desc, w.size() * sizeof(unsigned long long),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return SOS_EHIP;
+    for (int64_t i = 0; i < need / 2; ++i) {
+        const uint32_t v1 = (uint32_t)(w[4 * i + 2] & 0xffffffffu);
+        const uint32_t v2 = (uint32_t)(w[4 * i + 3] & 0xffffffffu);
+        std::memcpy(out + 2 * i, &v1, 4);
+        std::memcpy(out + 2 * i + 1, &v2, 4);
+    }
+    return SOS_OK;
+}
+
+}  // extern "C"

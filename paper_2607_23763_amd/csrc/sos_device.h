@@ -1,0 +1,58 @@
+// Device-side definitions shared by the HIP kernels of libsosfilt:
+// the per-section coefficient table layout, control words and small helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sosdev {
+
+// Native 128-bit vector (usable with the nontemporal builtins).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One wave (64 lanes) holds one group; lane l owns samples [l*N, l*N + N).
+constexpr int kLanes = 64;
+
+// Control words in device memory (one block per workspace).
+enum : int {
+    CTRL_TICKET = 0,   // next group ticket of the running launch
+    CTRL_EPOCH = 1,    // launch counter: tag of valid lookback descriptors
+    CTRL_ERR = 2,      // sticky device-side error bits (ERRBIT_*)
+    CTRL_WORDS = 16
+};
+enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u };
+
+// Per-section coefficient table (FP32 values computed in FP64 on the device).
+// Uniform entries are read with scalar loads; the two per-lane arrays with one
+// 128-bit load per lane.
+enum : int {
+    OFF_STATUS = 0,         // 0 = usable, else ERRBIT_* (stored as int bits)
+    OFF_TAPS = 4,           // [5] taps of B(z) A(-z): the level-1 right-hand side
+    OFF_B1 = 9, OFF_B2 = 10, OFF_A1 = 11, OFF_A2 = 12,
+    OFF_E = 16,             // [8] e_i, level-i coefficient of w^1 (e_0 = a1)
+    OFF_F = 24,             // [8] f_i, level-i coefficient of w^2 (f_0 = a2)
+    OFF_KS = 32,            // [6][4] T^(N*2^k), k = 0..5 (cross-lane scan steps)
+    OFF_TC = 56,            // [4] T^C: state map across a whole group
+    OFF_TW = 60,            // [4] T^(64*C): across one lookback window
+    OFF_G = 64,             // [kMaxN + 1] g[-1..kMaxN-1], impulse response of 1/A
+    OFF_LANEPOW = 208,      // [64][4] T^(N*l): group state -> incoming state of lane l
+    OFF_GRPPOW = 464,       // [64][4] T^(C*j): state j groups back -> this group
+    TAB_FLOATS = 720
+};
+constexpr int kMaxN = 128;
+static_assert(OFF_G + kMaxN + 1 <= OFF_LANEPOW, "table overlap");
+static_assert((OFF_LANEPOW % 4) == 0 && (OFF_GRPPOW % 4) == 0 && (TAB_FLOATS % 16) == 0,
+              "per-lane tables must be 16-byte aligned");
+
+// 2x2 row-major matrices (T acts on TDF-II states (z1, z2)).
+struct m2 {
+    double a, b, c, d;
+};
+__device__ inline m2 mmul(const m2 &x, const m2 &y)
+{
+    return {x.a * y.a + x.b * y.c, x.a * y.b + x.b * y.d,
+            x.c * y.a + x.d * y.c, x.c * y.b + x.d * y.d};
+}
+__device__ inline m2 mident() { return {1.0, 0.0, 0.0, 1.0}; }
+
+}  // namespace sosdev

@@ -1,0 +1,125 @@
+// Coefficient preparation on the device (FP64 arithmetic, FP32 tables).
+//
+// The paper notes that every coefficient of the reduction, the terminal scan
+// and the state correction depends only on the filter and is precomputed
+// (Sec. II-D, after Eq. (17)). This kernel does that for one launch: block s
+// normalises section s by a0, checks it, and writes its table (layout in
+// sos_device.h). Block 0 also resets the ticket counter and advances the
+// epoch that tags this launch's lookback descriptors, so that a launch (or a
+// graph replay) needs no memset.
+#include "sos_device.h"
+
+using namespace sosdev;
+
+namespace {
+
+__device__ inline m2 mpow_pow2(m2 m, int log2e)
+{
+    for (int i = 0; i < log2e; ++i) m = mmul(m, m);
+    return m;
+}
+
+__device__ inline void put(float *t, int off, const m2 &m)
+{
+    t[off + 0] = (float)m.a;
+    t[off + 1] = (float)m.b;
+    t[off + 2] = (float)m.c;
+    t[off + 3] = (float)m.d;
+}
+
+}  // namespace
+
+// sections: K x 6 rows; tabs: K x TAB_FLOATS; log2n = log2(N) of the group
+// tile (lane length N, group C = 64 N). Grid = (K), block = 64.
+extern "C" __global__ void __launch_bounds__(64)
+sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, float *__restrict__ tabs,
+                unsigned *__restrict__ ctrl)
+{
+    const int s = blockIdx.x;
+    const int l = threadIdx.x;
+    if (s == 0 && l == 0) {
+        ctrl[CTRL_TICKET] = 0u;
+        unsigned e = ctrl[CTRL_EPOCH] + 1u;
+        ctrl[CTRL_EPOCH] = (e == 0u) ? 1u : e;
+    }
+    if (s >= K) return;
+    const int N = 1 << log2n;
+    const float *row = sections + 6 * s;
+    const double a0 = (double)row[3];
+    unsigned status = 0u;
+    if (a0 == 0.0) status |= ERRBIT_A0;
+    const double inv = (a0 == 0.0) ? 0.0 : 1.0 / a0;
+    const double b0 = row[0] * inv, b1 = row[1] * inv, b2 = row[2] * inv;
+    const double a1 = row[4] * inv, a2 = row[5] * inv;
+    // closed stability triangle of z^2 + a1 z + a2 (NaN fails the test)
+    if (!(fabs(a2) <= 1.0 && fabs(a1) <= 1.0 + a2)) status |= ERRBIT_UNSTABLE;
+
+    float *t = tabs + (size_t)s * TAB_FLOATS;
+
+    // T maps the TDF-II state before a sample to the state after it at zero input.
+    const m2 T1 = {-a1, 1.0, -a2, 0.0};
+    const m2 TN = mpow_pow2(T1, log2n);     // across one lane (N samples)
+    m2 ks[6];
+    ks[0] = TN;
+    for (int k = 1; k < 6; ++k) ks[k] = mmul(ks[k - 1], ks[k - 1]);
+    const m2 TC = mmul(ks[5], ks[5]);        // TN^64: across one group
+    m2 tcp[6];
+    tcp[0] = TC;
+    for (int k = 1; k < 6; ++k) tcp[k] = mmul(tcp[k - 1], tcp[k - 1]);
+    const m2 TW = mmul(tcp[5], tcp[5]);      // TC^64: across one lookback window
+
+    // per-lane powers by binary expansion of the lane index
+    m2 lp = mident(), gp = mident();
+    for (int k = 0; k < 6; ++k)
+        if ((l >> k) & 1) {
+            lp = mmul(lp, ks[k]);
+            gp = mmul(gp, tcp[k]);
+        }
+    put(t, OFF_LANEPOW + 4 * l, lp);
+    put(t, OFF_GRPPOW + 4 * l, gp);
+
+    if (l == 0) {
+        t[OFF_STATUS] = __uint_as_float(status);
+        // level-1 right-hand side taps: B(z) A(-z) (Eq. (23) with a general b0)
+        t[OFF_TAPS + 0] = (float)b0;
+        t[OFF_TAPS + 1] = (float)(b1 - a1 * b0);
+        t[OFF_TAPS + 2] = (float)(b2 - a1 * b1 + a2 * b0);
+        t[OFF_TAPS + 3] = (float)(a2 * b1 - a1 * b2);
+        t[OFF_TAPS + 4] = (float)(a2 * b2);
+        t[OFF_B1] = (float)b1;
+        t[OFF_B2] = (float)b2;
+        t[OFF_A1] = (float)a1;
+        t[OFF_A2] = (float)a2;
+        // reduction levels: A_{i+1}(w^2) = A_i(w) A_i(-w)
+        double e = a1, f = a2;
+        for (int i = 0; i < 8; ++i) {
+            t[OFF_E + i] = (float)e;
+            t[OFF_F + i] = (float)f;
+            const double en = 2.0 * f - e * e;
+            f = f * f;
+            e = en;
+        }
+        // impulse response of 1/A(z), stored with g[-1] = 0 first
+        t[OFF_G] = 0.0f;
+        double gm2 = 0.0, gm1 = 0.0;
+        for (int m = 0; m < kMaxN; ++m) {
+            const double g = (m == 0) ? 1.0 : (-a1 * gm1 - a2 * gm2);
+            t[OFF_G + 1 + m] = (m < N) ? (float)g : 0.0f;
+            gm2 = gm1;
+            gm1 = g;
+        }
+        for (int k = 0; k < 6; ++k) put(t, OFF_KS + 4 * k, ks[k]);
+        put(t, OFF_TC, TC);
+        put(t, OFF_TW, TW);
+        if (status) atomicOr(&ctrl[CTRL_ERR], status);
+    }
+}
+
+extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, float *tabs,
+                                      unsigned *ctrl, hipStream_t stream)
+{
+    const int blocks = K > 0 ? K : 1;   // block 0 also resets the ticket and advances the epoch
+    hipLaunchKernelGGL(sos_prep_kernel, dim3(blocks), dim3(64), 0, stream, sections, K, log2n,
+                       tabs, ctrl);
+    return hipGetLastError();
+}

@@ -1,0 +1,48 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/*.h, and rejects bad arguments synchronously (no GPU
+work is started by these calls)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*\**\s*\**\s*(sos_[a-z0-9_]+)\s*\(",
+                            text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("sos_create", "sos_destroy", "sos_filter", "sos_strerror", "sos_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2607_23763_amd as P
+
+    lib = P.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_null_handle_rejections():
+    import paper_2607_23763_amd as P
+
+    lib = P.lib()
+    assert lib.sos_strerror(0) == b"ok"
+    assert lib.sos_strerror(-1) == b"invalid argument"
+    # every entry point rejects a NULL handle before touching the device
+    assert lib.sos_filter(None, None, 1, None, None, 10, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_set_tile(None, 32) == P.SOS_EINVAL
+    assert lib.sos_destroy(None) == P.SOS_EINVAL
+    assert lib.sos_create(None, 0) == P.SOS_EINVAL

@@ -1,0 +1,189 @@
+"""GPU parity of the plain filter (sos_filter) against the FP64 oracle.
+
+Every case draws seeded inputs from workloads.py, runs the HIP path through
+the C ABI, and compares element by element with oracle.sosfilt on the same
+float32 values promoted to float64. Bounds: relative L2 error <= 1e-5 for
+orders <= 8 (K <= 4) and <= 1e-4 at order 16 (K = 8); zf to the same bounds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import max_over_peak, rel_l2, tol_for
+
+pytestmark = pytest.mark.gpu
+
+TILES = (16, 32, 64)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2607_23763_amd as P
+
+    P.lib()
+    return P
+
+
+def run(torch, P, sos, x, zi=None, tile=0, handle=None):
+    h = handle or P.Handle(0, tile=tile)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(sos, dtype=np.float32)).cuda()
+    zd = None if zi is None else torch.from_numpy(np.ascontiguousarray(zi, np.float32)).cuda()
+    y, zf = P.sosfilt(xd, sd, zd, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    return y.cpu().numpy(), zf.cpu().numpy(), h
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_single_biquad_2p20(torch_cuda, P, tile):
+    """2nd-order Butterworth at 0.2*Nyquist, 2^20 N(0,1) samples, zi = 0."""
+    sos, x = workloads.single_biquad(1 << 20, seed=1)
+    y, zf, _ = run(torch_cuda, P, sos, x, tile=tile)
+    yr, zfr = oracle.sosfilt(sos, x)
+    print("tile", tile, "rel_l2", rel_l2(y, yr), "max/peak", max_over_peak(y, yr))
+    assert rel_l2(y, yr) <= 1e-5
+    assert max_over_peak(y, yr) < 1e-4
+    assert rel_l2(zf, zfr) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["butter", "random"])
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_sweep_sections(torch_cuda, P, K, kind):
+    sos = workloads.sweep_sections(K, kind)
+    n = (1 << 18) + 12345
+    x = workloads.signal(n, seed=2)
+    zi = workloads.initial_state(K, workloads.rng(40 + K))
+    for tile in TILES:
+        y, zf, _ = run(torch_cuda, P, sos, x, zi, tile=tile)
+        yr, zfr = oracle.sosfilt(sos, x, zi)
+        e = rel_l2(y, yr)
+        print(kind, "K", K, "tile", tile, "rel_l2", e, "zf", rel_l2(zf, zfr))
+        assert e <= tol_for(K), (kind, K, tile, e)
+        assert rel_l2(zf, zfr) <= tol_for(K), (kind, K, tile)
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_edge_lengths(torch_cuda, P, tile):
+    C = 64 * tile
+    g = workloads.rng(77)
+    for K in (1, 3):
+        sos = workloads.random_stable_sos(K, g)
+        zi = workloads.initial_state(K, g)
+        for n in (1, 2, 3, 5, tile - 1, tile, tile + 1, C - 1, C, C + 1, 2 * C, 3 * C + 17):
+            x = workloads.signal(n, seed=n)
+            y, zf, _ = run(torch_cuda, P, sos, x, zi, tile=tile)
+            yr, zfr = oracle.sosfilt(sos, x, zi)
+            assert rel_l2(y, yr) <= 1e-5, (K, n, tile)
+            assert rel_l2(zf, zfr) <= 1e-5, (K, n, tile, zf, zfr)
+
+
+def test_in_place_and_misaligned(torch_cuda, P):
+    torch = torch_cuda
+    K = 4
+    sos = workloads.sweep_sections(K, "random")
+    n = 200003
+    x = workloads.signal(n, seed=9)
+    yr, zfr = oracle.sosfilt(sos, x)
+    sd = torch.from_numpy(sos).cuda()
+    # in place
+    xd = torch.from_numpy(x).cuda()
+    zf = torch.empty((K, 2), device="cuda")
+    P.sosfilt_(xd, sd, y=xd, zf=zf)
+    torch.cuda.synchronize()
+    assert rel_l2(xd.cpu().numpy(), yr) <= 1e-5
+    # 4-byte-misaligned input and output (scalar load/store path)
+    buf = torch.zeros(n + 2, device="cuda")
+    buf[1:n + 1] = torch.from_numpy(x).cuda()
+    out = torch.zeros(n + 2, device="cuda")
+    P.sosfilt_(buf[1:n + 1], sd, y=out[1:n + 1], zf=zf)
+    torch.cuda.synchronize()
+    assert rel_l2(out[1:n + 1].cpu().numpy(), yr) <= 1e-5
+    assert out[0].item() == 0.0 and out[n + 1].item() == 0.0
+    assert rel_l2(zf.cpu().numpy(), zfr) <= 1e-5
+
+
+def test_degenerate_k0_n0(torch_cuda, P):
+    torch = torch_cuda
+    x = torch.from_numpy(workloads.signal(1000, 3)).cuda()
+    y, zf = P.sosfilt(x, torch.zeros((0, 6), device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.equal(y, x) and zf.numel() == 0
+    sos = torch.from_numpy(workloads.butterworth_sos(2)).cuda()
+    zi = torch.from_numpy(workloads.initial_state(2, workloads.rng(1))).cuda()
+    y, zf = P.sosfilt(torch.zeros(0, device="cuda"), sos, zi)
+    torch.cuda.synchronize()
+    assert y.numel() == 0 and torch.equal(zf, zi)
+    y, zf = P.sosfilt(torch.zeros(0, device="cuda"), sos, None)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(zf).item() == 0
+
+
+def test_lookback_carries_are_oracle_states(torch_cuda, P):
+    """The resolved carry each group publishes equals the oracle's state after
+    the group's last sample."""
+    K = 3
+    sos = workloads.sweep_sections(K, "random")
+    zi = workloads.initial_state(K, workloads.rng(5))
+    tile = 16
+    C = 64 * tile
+    G = 37
+    x = workloads.signal(G * C, seed=4)
+    _, _, h = run(torch_cuda, P, sos, x, zi, tile=tile)
+    car = h.carries()
+    assert car.shape == (G, K, 2)
+    for g in range(G):
+        _, st = oracle.sosfilt(sos, x[:(g + 1) * C], zi)
+        scale = max(1.0, np.max(np.abs(st)))
+        assert np.max(np.abs(car[g] - st)) <= 2e-5 * scale, (g, car[g], st)
+
+
+def test_bad_sections_report_and_poison(torch_cuda, P):
+    torch = torch_cuda
+    h = P.Handle(0)
+    x = torch.from_numpy(workloads.signal(5000, 2)).cuda()
+    sos = workloads.butterworth_sos(2).copy()
+    sos[1, 3] = 0.0                                   # a0 == 0
+    y, zf = P.sosfilt(x, torch.from_numpy(sos).cuda(), handle=h)
+    assert h.last_error() == P.SOS_EA0
+    assert torch.isnan(y).all().item() and torch.isnan(zf).all().item()
+    sos = workloads.butterworth_sos(1).copy()
+    sos[0, 5] = 1.5                                   # |a2| > 1
+    y, zf = P.sosfilt(x, torch.from_numpy(sos).cuda(), handle=h)
+    assert h.last_error() == P.SOS_EUNSTABLE
+    assert torch.isnan(y).all().item()
+    # the handle keeps working afterwards
+    sos = workloads.butterworth_sos(1)
+    y, zf = P.sosfilt(x, torch.from_numpy(sos).cuda(), handle=h)
+    assert h.last_error() == P.SOS_OK
+    yr, _ = oracle.sosfilt(sos, x.cpu().numpy())
+    assert rel_l2(y.cpu().numpy(), yr) <= 1e-5
+
+
+@pytest.mark.parametrize("K", [1, 8])
+def test_full_size_2p28(torch_cuda, P, K):
+    """2^28 samples in the launch configuration the benchmark times."""
+    torch = torch_cuda
+    sos = workloads.sweep_sections(K, "butter")
+    n = 1 << 28
+    x = workloads.signal(n, seed=2)
+    xd = torch.from_numpy(x).cuda()
+    y, zf = P.sosfilt(xd, torch.from_numpy(sos).cuda())
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    del y, xd
+    yr, zfr = oracle.sosfilt(sos, x)
+    e = rel_l2(yh, yr)
+    print("2^28 K", K, "rel_l2", e, "max/peak", max_over_peak(yh, yr))
+    assert e <= tol_for(K)
+    assert rel_l2(zf.cpu().numpy(), zfr) <= tol_for(K)
