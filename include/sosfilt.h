@@ -88,10 +88,14 @@ const char *sos_strerror(int code);
  * sos_last_error on this handle, or SOS_OK, and clears it. */
 int sos_last_error(sos_handle_t h);
 
-/* Samples per lane N of the group tile (the group holds C = 64*N samples):
- * one of 16, 32, 64. 0 restores the default. Applies to later calls. */
-int sos_set_tile(sos_handle_t h, int samples_per_lane);
-int sos_get_tile(sos_handle_t h);
+/* The paper's two tuning parameters (Sec. IV-D): L lanes (threads) per group
+ * and N samples per lane; a group holds C = L*N samples and one workgroup of
+ * L/64 wavefronts processes it. Compiled shapes: L in {64, 256, 512} with
+ * N in {16, 32, 64}, and L = 1024 with N in {16, 32}. sos_set_tile(h, 0, 0)
+ * restores the default. Applies to later calls (tables prepared for another
+ * shape must be prepared again). Unsupported shapes return SOS_EINVAL. */
+int sos_set_tile(sos_handle_t h, int L, int N);
+int sos_get_tile(sos_handle_t h, int *L, int *N);
 
 /*
  * Plain filter, one signal (Sec. IV-A/B; Eqs. (1)-(25)).
@@ -99,11 +103,31 @@ int sos_get_tile(sos_handle_t h);
  *   the final states. 0 <= K <= SOS_MAX_SECTIONS, n >= 0.
  *   n == 0: y is not touched and zf := zi (zeros if zi == NULL).
  *   K == 0: y := x.
- * Enqueues: one coefficient-preparation kernel (FP64 tables) and one filter
- * kernel (ticketed groups, register-resident cascade, decoupled lookback).
+ * Enqueues: the coefficient-preparation kernel (FP64 tables), a one-thread
+ * kernel that re-arms the ticket counter and the descriptor epoch, and the
+ * filter kernel (ticketed groups, register-resident cascade, decoupled
+ * lookback).
  */
 int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y,
                int64_t n, const float *zi, float *zf, hipStream_t stream);
+
+/* Two-step form of sos_filter for repeated calls with the same coefficients
+ * (Sec. II-D: every table depends only on the filter and is precomputed).
+ * sos_prepare enqueues the coefficient-preparation kernel for `sections`
+ * (K x 6, device) at the handle's current tile; sos_filter_prepared then
+ * enqueues only the filter kernel, with the same conventions as sos_filter.
+ * sos_filter_prepared returns SOS_EINVAL if nothing was prepared or the tile
+ * changed since. The sections buffer is read by the preparation kernel only. */
+int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream);
+int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, const float *zi,
+                        float *zf, hipStream_t stream);
+
+/* Memory-floor reference (the t_mem = b_s / BW term of the cost model,
+ * Eq. (28), with b_s = 8 bytes per sample): a plain streaming copy y = x of n
+ * FP32 samples with the same 128-bit nontemporal accesses as the filter.
+ * Device pointers; x and y must not overlap. Used to measure the achievable
+ * copy bandwidth and to calibrate hardware byte counters. */
+int sos_bench_copy(const float *x, float *y, int64_t n, hipStream_t stream);
 
 /* Debug/inspection: after a completed sos_filter call on this handle, copy the
  * resolved state at the end of every (group, section) -- the "global carry" of

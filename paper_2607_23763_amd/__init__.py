@@ -53,13 +53,17 @@ def lib():
             L.sos_strerror.argtypes = [i32]
             L.sos_strerror.restype = ctypes.c_char_p
             L.sos_last_error.argtypes = [vp]
-            L.sos_set_tile.argtypes = [vp, i32]
-            L.sos_get_tile.argtypes = [vp]
+            L.sos_set_tile.argtypes = [vp, i32, i32]
+            L.sos_get_tile.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
             L.sos_filter.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp]
             L.sos_debug_carries.argtypes = [vp, vp, i64, ctypes.POINTER(i64),
                                             ctypes.POINTER(i32)]
+            L.sos_prepare.argtypes = [vp, vp, i32, vp]
+            L.sos_filter_prepared.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+            L.sos_bench_copy.argtypes = [vp, vp, i64, vp]
             for name in ("sos_create", "sos_destroy", "sos_last_error", "sos_set_tile",
-                         "sos_get_tile", "sos_filter", "sos_debug_carries"):
+                         "sos_get_tile", "sos_filter", "sos_debug_carries", "sos_prepare",
+                         "sos_filter_prepared", "sos_bench_copy"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -86,12 +90,12 @@ def _stream_ptr(device=None):
 class Handle:
     """Owns a libsosfilt handle (workspace: tables, lookback descriptors)."""
 
-    def __init__(self, device: int = 0, tile: int = 0):
+    def __init__(self, device: int = 0, tile=None):
         self._h = ctypes.c_void_p()
         self.device = int(device)
         _check(lib().sos_create(ctypes.byref(self._h), self.device), "sos_create")
         if tile:
-            self.set_tile(tile)
+            self.set_tile(*tile)
 
     def close(self):
         if self._h:
@@ -108,11 +112,15 @@ class Handle:
     def ptr(self):
         return self._h
 
-    def set_tile(self, n: int):
-        _check(lib().sos_set_tile(self._h, int(n)), "sos_set_tile")
+    def set_tile(self, L: int, N: int):
+        """Group shape: L lanes (64 per wavefront) x N samples per lane."""
+        _check(lib().sos_set_tile(self._h, int(L), int(N)), "sos_set_tile")
 
-    def tile(self) -> int:
-        return int(lib().sos_get_tile(self._h))
+    def tile(self):
+        L = ctypes.c_int32()
+        N = ctypes.c_int32()
+        _check(lib().sos_get_tile(self._h, ctypes.byref(L), ctypes.byref(N)), "sos_get_tile")
+        return L.value, N.value
 
     def last_error(self) -> int:
         return int(lib().sos_last_error(self._h))
@@ -173,6 +181,33 @@ def sosfilt_(x, sos, y=None, zi=None, zf=None, handle: Handle | None = None):
         ctypes.c_void_p(zf.data_ptr()) if zf is not None else None,
         _stream_ptr(x.device))
     _check(rc, "sos_filter")
+    return y
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def prepare(sos, handle: Handle | None = None):
+    """Enqueue the coefficient tables for sos (K x 6 device tensor) on the
+    handle; later filter_prepared() calls reuse them."""
+    sos = _as_dev_f32(sos, "sos").reshape(-1, 6)
+    h = handle or default_handle(sos.device.index or 0)
+    _check(lib().sos_prepare(h.ptr, _p(sos), sos.shape[0], _stream_ptr(sos.device)), "sos_prepare")
+    return h
+
+
+def filter_prepared(x, y, zi=None, zf=None, handle: Handle | None = None):
+    """Filter device tensor x into y (may be x) with the prepared tables."""
+    h = handle or default_handle(x.device.index or 0)
+    _check(lib().sos_filter_prepared(h.ptr, _p(x), _p(y), x.numel(), _p(zi), _p(zf),
+                                     _stream_ptr(x.device)), "sos_filter_prepared")
+    return y
+
+
+def bench_copy(x, y):
+    """Plain streaming copy y = x (memory-floor reference kernel)."""
+    _check(lib().sos_bench_copy(_p(x), _p(y), x.numel(), _stream_ptr(x.device)), "sos_bench_copy")
     return y
 
 

@@ -12,20 +12,24 @@
 #include "sosfilt.h"
 #include "sos_device.h"
 
-extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, float *tabs,
-                                      unsigned *ctrl, hipStream_t stream);
-extern "C" hipError_t sos_launch_fwd(int N, const float *x, float *y, int64_t n, int64_t groups,
-                                     const float *tabs, int K, const float *zi, float *zf,
-                                     unsigned long long *desc, unsigned *ctrl,
+extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, int log2w,
+                                      float *tabs, unsigned *ctrl, hipStream_t stream);
+extern "C" hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
+extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int64_t n,
+                                     int64_t groups, const float *tabs, int K, const float *zi,
+                                     float *zf, unsigned long long *desc, unsigned *ctrl,
                                      unsigned long long timeout_ticks, hipStream_t stream);
+extern "C" int sos_fwd_shape_supported(int L, int N);
 extern "C" hipError_t sos_launch_fill(float *dst, const float *src, int64_t count,
                                       hipStream_t stream);
+extern "C" hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
 
 using namespace sosdev;
 
 struct sos_ctx {
     int device = 0;
-    int tile = 0;                         // samples per lane N; 0 = default
+    int tile_L = 0;                       // lanes per group L = 64 W; 0 = default
+    int tile_N = 0;                       // samples per lane N; 0 = default
     unsigned *ctrl = nullptr;             // CTRL_WORDS
     float *tabs = nullptr;
     int tabs_cap = 0;                     // sections
@@ -34,12 +38,16 @@ struct sos_ctx {
     unsigned long long timeout_ticks = 0;
     int64_t last_groups = 0;
     int last_K = 0;
+    int prep_K = -1;                      // tables currently prepared (K, tile L x N)
+    int prep_L = 0;
+    int prep_N = 0;
     std::mutex mu;
 };
 
 namespace {
 
-constexpr int kDefaultTile = 32;
+constexpr int kDefaultL = 512;
+constexpr int kDefaultN = 32;
 
 struct DeviceGuard {
     int prev = -1;
@@ -88,15 +96,23 @@ int ensure_desc(sos_ctx *h, size_t words, hipStream_t stream)
     return SOS_OK;
 }
 
-int tile_of(const sos_ctx *h)
+struct Tile {
+    int L, N;
+};
+
+Tile tile_of(const sos_ctx *h)
 {
-    if (h->tile) return h->tile;
-    const char *e = std::getenv("SOS_TILE_N");
-    if (e) {
+    Tile t{kDefaultL, kDefaultN};
+    if (const char *e = std::getenv("SOS_TILE_L")) {
         const int v = std::atoi(e);
-        if (v == 16 || v == 32 || v == 64) return v;
+        if (sos_fwd_shape_supported(v, t.N)) t.L = v;
     }
-    return kDefaultTile;
+    if (const char *e = std::getenv("SOS_TILE_N")) {
+        const int v = std::atoi(e);
+        if (sos_fwd_shape_supported(t.L, v)) t.N = v;
+    }
+    if (h->tile_L) t = Tile{h->tile_L, h->tile_N};
+    return t;
 }
 
 }  // namespace
@@ -135,7 +151,9 @@ int sos_create(sos_handle_t *out, int hip_device)
         delete h;
         return SOS_ENOMEM;
     }
-    if (hipMemset(h->ctrl, 0, sizeof(unsigned) * CTRL_WORDS) != hipSuccess) {
+    unsigned init[CTRL_WORDS] = {};
+    init[CTRL_EPOCH] = 1u;   // descriptor tag 0 is reserved for "never written"
+    if (hipMemcpy(h->ctrl, init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(h->ctrl);
         delete h;
         return SOS_EHIP;
@@ -183,35 +201,61 @@ int sos_last_error(sos_handle_t h)
     return SOS_OK;
 }
 
-int sos_set_tile(sos_handle_t h, int n)
+int sos_set_tile(sos_handle_t h, int L, int N)
 {
     if (!h) return SOS_EINVAL;
-    if (n != 0 && n != 16 && n != 32 && n != 64) return SOS_EINVAL;
-    h->tile = n;
+    if (L == 0 && N == 0) {
+        h->tile_L = h->tile_N = 0;
+        return SOS_OK;
+    }
+    if (!sos_fwd_shape_supported(L, N)) return SOS_EINVAL;
+    h->tile_L = L;
+    h->tile_N = N;
     return SOS_OK;
 }
 
-int sos_get_tile(sos_handle_t h)
+int sos_get_tile(sos_handle_t h, int *L, int *N)
 {
     if (!h) return SOS_EINVAL;
-    return tile_of(h);
+    const Tile t = tile_of(h);
+    if (L) *L = t.L;
+    if (N) *N = t.N;
+    return SOS_OK;
 }
 
-int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y, int64_t n,
-               const float *zi, float *zf, hipStream_t stream)
+static int check_signal(const float *x, float *y, int64_t n)
 {
-    if (!h || K < 0 || K > SOS_MAX_SECTIONS || n < 0) return SOS_EINVAL;
-    if (K > 0 && !sections) return SOS_EINVAL;
+    if (n < 0) return SOS_EINVAL;
     if (n > 0 && (!x || !y)) return SOS_EINVAL;
     if (n > 0 && x != y) {
         // in place or disjoint only
         const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, bytes = (uintptr_t)n * 4u;
         if (xa < ya + bytes && ya < xa + bytes) return SOS_EINVAL;
     }
-    std::lock_guard<std::mutex> lk(h->mu);
-    DeviceGuard g(h->device);
-    if (!g.ok) return SOS_EHIP;
+    return SOS_OK;
+}
 
+// Tables for `sections` at the handle's current tile (caller holds the lock).
+static int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream)
+{
+    const Tile t = tile_of(h);
+    int rc = ensure_tabs(h, K, stream);
+    if (rc) return rc;
+    if (sos_launch_prep(sections, K, __builtin_ctz((unsigned)t.N),
+                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl,
+                        stream) != hipSuccess)
+        return SOS_EHIP;
+    h->prep_K = K;
+    h->prep_L = t.L;
+    h->prep_N = t.N;
+    return SOS_OK;
+}
+
+// Filter with the prepared tables (caller holds the lock).
+static int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *zi,
+                         float *zf, hipStream_t stream)
+{
+    const int K = h->prep_K;
     if (n == 0) {
         if (zf && K > 0 && sos_launch_fill(zf, zi, 2 * (int64_t)K, stream) != hipSuccess)
             return SOS_EHIP;
@@ -221,23 +265,71 @@ int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, flo
         if (x != y && sos_launch_fill(y, x, n, stream) != hipSuccess) return SOS_EHIP;
         return SOS_OK;
     }
-    const int N = tile_of(h);
-    const int log2n = __builtin_ctz((unsigned)N);
-    const int64_t C = (int64_t)kLanes * N;
+    const int L = h->prep_L, N = h->prep_N;
+    const int64_t C = (int64_t)L * N;
     const int64_t groups = (n + C - 1) / C;
     if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
-    int rc = ensure_tabs(h, K, stream);
+    const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
     if (rc) return rc;
-    rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
-    if (rc) return rc;
-    if (sos_launch_prep(sections, K, log2n, h->tabs, h->ctrl, stream) != hipSuccess)
-        return SOS_EHIP;
-    if (sos_launch_fwd(N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
+    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    if (sos_launch_fwd(L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
                        h->timeout_ticks, stream) != hipSuccess)
         return SOS_EHIP;
     h->last_groups = groups;
     h->last_K = K;
     return SOS_OK;
+}
+
+int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream)
+{
+    if (!h || K < 0 || K > SOS_MAX_SECTIONS) return SOS_EINVAL;
+    if (K > 0 && !sections) return SOS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    return prepare_locked(h, sections, K, stream);
+}
+
+int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, const float *zi,
+                        float *zf, hipStream_t stream)
+{
+    if (!h) return SOS_EINVAL;
+    int rc = check_signal(x, y, n);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(h->mu);
+    const Tile t = tile_of(h);
+    if (h->prep_K < 0 || h->prep_N != t.N || h->prep_L != t.L) return SOS_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    return filter_locked(h, x, y, n, zi, zf, stream);
+}
+
+int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y, int64_t n,
+               const float *zi, float *zf, hipStream_t stream)
+{
+    if (!h || K < 0 || K > SOS_MAX_SECTIONS) return SOS_EINVAL;
+    if (K > 0 && !sections) return SOS_EINVAL;
+    int rc = check_signal(x, y, n);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    if (n > 0 && K > 0) {
+        rc = prepare_locked(h, sections, K, stream);
+        if (rc) return rc;
+    } else {
+        const Tile t = tile_of(h);   // degenerate calls need no tables
+        h->prep_K = K;
+        h->prep_L = t.L;
+        h->prep_N = t.N;
+    }
+    return filter_locked(h, x, y, n, zi, zf, stream);
+}
+
+int sos_bench_copy(const float *x, float *y, int64_t n, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return SOS_EINVAL;
+    return sos_launch_copy(x, y, n, stream) == hipSuccess ? SOS_OK : SOS_EHIP;
 }
 
 int sos_debug_carries(sos_handle_t h, float *out, int64_t capacity_floats, int64_t *groups,

@@ -10,7 +10,13 @@ namespace sosdev {
 // Native 128-bit vector (usable with the nontemporal builtins).
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// One wave (64 lanes) holds one group; lane l owns samples [l*N, l*N + N).
+// Read-only view of a table in the constant address space: wave-uniform
+// indexes compile to scalar (SMEM) loads into SGPRs instead of vector loads.
+typedef const __attribute__((address_space(4))) float ctab_t;
+__device__ __forceinline__ ctab_t *ctab(const float *p) { return (ctab_t *)p; }
+
+// A group is L = 64*W lanes held by W wavefronts of one workgroup; lane l of
+// the group owns samples [l*N, l*N + N).
 constexpr int kLanes = 64;
 
 // Control words in device memory (one block per workspace).
@@ -22,9 +28,10 @@ enum : int {
 };
 enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u };
 
-// Per-section coefficient table (FP32 values computed in FP64 on the device).
-// Uniform entries are read with scalar loads; the two per-lane arrays with one
-// 128-bit load per lane.
+// Per-section coefficient table (FP32 values computed in FP64 on the device)
+// for one group shape: L = 64*W lanes in W waves, N samples per lane,
+// C = L*N samples per group. Uniform entries are read with scalar loads; the
+// two per-lane arrays with one 128-bit load per lane.
 enum : int {
     OFF_STATUS = 0,         // 0 = usable, else ERRBIT_* (stored as int bits)
     OFF_TAPS = 4,           // [5] taps of B(z) A(-z): the level-1 right-hand side
@@ -34,13 +41,17 @@ enum : int {
     OFF_KS = 32,            // [6][4] T^(N*2^k), k = 0..5 (cross-lane scan steps)
     OFF_TC = 56,            // [4] T^C: state map across a whole group
     OFF_TW = 60,            // [4] T^(64*C): across one lookback window
-    OFF_G = 64,             // [kMaxN + 1] g[-1..kMaxN-1], impulse response of 1/A
-    OFF_LANEPOW = 208,      // [64][4] T^(N*l): group state -> incoming state of lane l
-    OFF_GRPPOW = 464,       // [64][4] T^(C*j): state j groups back -> this group
-    TAB_FLOATS = 720
+    OFF_TWAVE = 64,         // [4] T^(64*N): across one wave's 64 lanes
+    OFF_WPOW = 68,          // [16][4] T^(64*N*w): group state -> incoming state of wave w
+    OFF_G = 132,            // [kMaxN + 1] g[-1..kMaxN-1], impulse response of 1/A
+    OFF_LANEPOW = 264,      // [64][4] T^(N*l): wave state -> incoming state of lane l
+    OFF_GRPPOW = 520,       // [64][4] T^(C*j): state j groups back -> this group
+    TAB_FLOATS = 784
 };
 constexpr int kMaxN = 128;
+constexpr int kMaxWaves = 16;
 static_assert(OFF_G + kMaxN + 1 <= OFF_LANEPOW, "table overlap");
+static_assert(OFF_GRPPOW + 256 <= TAB_FLOATS, "table overlap");
 static_assert((OFF_LANEPOW % 4) == 0 && (OFF_GRPPOW % 4) == 0 && (TAB_FLOATS % 16) == 0,
               "per-lane tables must be 16-byte aligned");
 

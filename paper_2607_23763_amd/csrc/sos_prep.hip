@@ -2,11 +2,9 @@
 //
 // The paper notes that every coefficient of the reduction, the terminal scan
 // and the state correction depends only on the filter and is precomputed
-// (Sec. II-D, after Eq. (17)). This kernel does that for one launch: block s
-// normalises section s by a0, checks it, and writes its table (layout in
-// sos_device.h). Block 0 also resets the ticket counter and advances the
-// epoch that tags this launch's lookback descriptors, so that a launch (or a
-// graph replay) needs no memset.
+// (Sec. II-D, after Eq. (17)). This kernel does that once per coefficient set:
+// block s normalises section s by a0, checks it, and writes its table (layout
+// in sos_device.h).
 #include "sos_device.h"
 
 using namespace sosdev;
@@ -29,19 +27,15 @@ __device__ inline void put(float *t, int off, const m2 &m)
 
 }  // namespace
 
-// sections: K x 6 rows; tabs: K x TAB_FLOATS; log2n = log2(N) of the group
-// tile (lane length N, group C = 64 N). Grid = (K), block = 64.
+// sections: K x 6 rows; tabs: K x TAB_FLOATS; log2n = log2(N) samples per
+// lane, log2w = log2(W) waves per group (group C = 64 W N samples).
+// Grid = (K), block = 64.
 extern "C" __global__ void __launch_bounds__(64)
-sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, float *__restrict__ tabs,
-                unsigned *__restrict__ ctrl)
+sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
+                float *__restrict__ tabs, unsigned *__restrict__ ctrl)
 {
     const int s = blockIdx.x;
     const int l = threadIdx.x;
-    if (s == 0 && l == 0) {
-        ctrl[CTRL_TICKET] = 0u;
-        unsigned e = ctrl[CTRL_EPOCH] + 1u;
-        ctrl[CTRL_EPOCH] = (e == 0u) ? 1u : e;
-    }
     if (s >= K) return;
     const int N = 1 << log2n;
     const float *row = sections + 6 * s;
@@ -62,21 +56,26 @@ sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, float *__r
     m2 ks[6];
     ks[0] = TN;
     for (int k = 1; k < 6; ++k) ks[k] = mmul(ks[k - 1], ks[k - 1]);
-    const m2 TC = mmul(ks[5], ks[5]);        // TN^64: across one group
+    const m2 TWV = mmul(ks[5], ks[5]);       // TN^64: across one wave
+    const m2 TC = mpow_pow2(TWV, log2w);     // across one group of W waves
     m2 tcp[6];
     tcp[0] = TC;
     for (int k = 1; k < 6; ++k) tcp[k] = mmul(tcp[k - 1], tcp[k - 1]);
     const m2 TW = mmul(tcp[5], tcp[5]);      // TC^64: across one lookback window
 
     // per-lane powers by binary expansion of the lane index
-    m2 lp = mident(), gp = mident();
-    for (int k = 0; k < 6; ++k)
+    m2 lp = mident(), gp = mident(), wp = mident(), wk = TWV;
+    for (int k = 0; k < 6; ++k) {
         if ((l >> k) & 1) {
             lp = mmul(lp, ks[k]);
             gp = mmul(gp, tcp[k]);
+            wp = mmul(wp, wk);
         }
+        wk = mmul(wk, wk);
+    }
     put(t, OFF_LANEPOW + 4 * l, lp);
     put(t, OFF_GRPPOW + 4 * l, gp);
+    if (l < kMaxWaves) put(t, OFF_WPOW + 4 * l, wp);
 
     if (l == 0) {
         t[OFF_STATUS] = __uint_as_float(status);
@@ -111,15 +110,31 @@ sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, float *__r
         for (int k = 0; k < 6; ++k) put(t, OFF_KS + 4 * k, ks[k]);
         put(t, OFF_TC, TC);
         put(t, OFF_TW, TW);
+        put(t, OFF_TWAVE, TWV);
         if (status) atomicOr(&ctrl[CTRL_ERR], status);
     }
 }
 
-extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, float *tabs,
-                                      unsigned *ctrl, hipStream_t stream)
+extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, int log2w,
+                                      float *tabs, unsigned *ctrl, hipStream_t stream)
 {
-    const int blocks = K > 0 ? K : 1;   // block 0 also resets the ticket and advances the epoch
-    hipLaunchKernelGGL(sos_prep_kernel, dim3(blocks), dim3(64), 0, stream, sections, K, log2n,
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sos_prep_kernel, dim3(K), dim3(64), 0, stream, sections, K, log2n, log2w,
                        tabs, ctrl);
+    return hipGetLastError();
+}
+
+// Start of a filter launch: ticket counter to 0 and a fresh epoch tag for the
+// launch's lookback descriptors (tag 0 is never used). One thread.
+extern "C" __global__ void sos_arm_kernel(unsigned *ctrl)
+{
+    ctrl[CTRL_TICKET] = 0u;
+    const unsigned e = ctrl[CTRL_EPOCH] + 1u;
+    ctrl[CTRL_EPOCH] = (e == 0u) ? 1u : e;
+}
+
+extern "C" hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream)
+{
+    hipLaunchKernelGGL(sos_arm_kernel, dim3(1), dim3(1), 0, stream, ctrl);
     return hipGetLastError();
 }

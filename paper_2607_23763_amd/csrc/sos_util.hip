@@ -4,12 +4,25 @@
 
 namespace {
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
 // dst[i] = src ? src[i] : 0 for i < count
 __global__ void __launch_bounds__(256) fill_kernel(float *dst, const float *src, int64_t count)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
         dst[i] = src ? src[i] : 0.0f;
+}
+
+// Plain streaming copy y = x with the same 128-bit nontemporal accesses the
+// filter uses: 8 bytes of HBM traffic per sample and no arithmetic. It is the
+// achievable memory floor t_mem = b_s / BW of the cost model (Eq. (28)) and
+// the reference for scaling the HBM byte counters.
+__global__ void __launch_bounds__(256) copy_kernel(const f4 *x, f4 *y, int64_t n4)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
 }
 
 }  // namespace
@@ -22,4 +35,21 @@ extern "C" hipError_t sos_launch_fill(float *dst, const float *src, int64_t coun
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, dst, src, count);
     return hipGetLastError();
+}
+
+extern "C" hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) == 0;
+    const int64_t n4 = vec ? n / 4 : 0;
+    if (n4 > 0) {
+        int64_t blocks = (n4 + 255) / 256;
+        if (blocks > 256 * 64) blocks = 256 * 64;
+        hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(y), n4);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n4 * 4 < n) return sos_launch_fill(y + n4 * 4, x + n4 * 4, n - n4 * 4, stream);
+    return hipSuccess;
 }

@@ -14,7 +14,8 @@ from tests.gpu_util import max_over_peak, rel_l2, tol_for
 
 pytestmark = pytest.mark.gpu
 
-TILES = (16, 32, 64)
+# (L lanes per group, N samples per lane): one-wave groups and 4/8/16-wave groups
+TILES = ((64, 16), (64, 64), (256, 32), (512, 16), (512, 32), (512, 64), (1024, 16), (1024, 32))
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +35,7 @@ def P():
     return P
 
 
-def run(torch, P, sos, x, zi=None, tile=0, handle=None):
+def run(torch, P, sos, x, zi=None, tile=None, handle=None):
     h = handle or P.Handle(0, tile=tile)
     xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     sd = torch.from_numpy(np.ascontiguousarray(sos, dtype=np.float32)).cuda()
@@ -75,12 +76,15 @@ def test_sweep_sections(torch_cuda, P, K, kind):
 
 @pytest.mark.parametrize("tile", TILES)
 def test_edge_lengths(torch_cuda, P, tile):
-    C = 64 * tile
+    L, N = tile
+    C = L * N
+    CW = 64 * N
     g = workloads.rng(77)
     for K in (1, 3):
         sos = workloads.random_stable_sos(K, g)
         zi = workloads.initial_state(K, g)
-        for n in (1, 2, 3, 5, tile - 1, tile, tile + 1, C - 1, C, C + 1, 2 * C, 3 * C + 17):
+        for n in (1, 2, 3, 5, N - 1, N, N + 1, CW - 1, CW + 1, C - 1, C, C + 1, 2 * C,
+                  3 * C + 17):
             x = workloads.signal(n, seed=n)
             y, zf, _ = run(torch_cuda, P, sos, x, zi, tile=tile)
             yr, zfr = oracle.sosfilt(sos, x, zi)
@@ -135,8 +139,8 @@ def test_lookback_carries_are_oracle_states(torch_cuda, P):
     K = 3
     sos = workloads.sweep_sections(K, "random")
     zi = workloads.initial_state(K, workloads.rng(5))
-    tile = 16
-    C = 64 * tile
+    tile = (256, 16)
+    C = tile[0] * tile[1]
     G = 37
     x = workloads.signal(G * C, seed=4)
     _, _, h = run(torch_cuda, P, sos, x, zi, tile=tile)
