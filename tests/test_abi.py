@@ -43,6 +43,10 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_strerror(-1) == b"invalid argument"
     # every entry point rejects a NULL handle before touching the device
     assert lib.sos_filter(None, None, 1, None, None, 10, None, None, None) == P.SOS_EINVAL
-    assert lib.sos_set_tile(None, 32) == P.SOS_EINVAL
+    assert lib.sos_set_tile(None, 64, 32) == P.SOS_EINVAL
+    assert lib.sos_get_tile(None, None, None) == P.SOS_EINVAL
+    assert lib.sos_prepare(None, None, 1, None) == P.SOS_EINVAL
+    assert lib.sos_filter_prepared(None, None, None, 10, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_bench_copy(None, None, 10, None) == P.SOS_EINVAL
     assert lib.sos_destroy(None) == P.SOS_EINVAL
     assert lib.sos_create(None, 0) == P.SOS_EINVAL
