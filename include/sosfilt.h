@@ -111,6 +111,29 @@ int sos_get_tile(sos_handle_t h, int *L, int *N);
 int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y,
                int64_t n, const float *zi, float *zf, hipStream_t stream);
 
+/*
+ * Uneven batch in one persistent launch (Sec. IV-A/B applied per signal).
+ * B independent signals; signal i is x[sig_off[i] .. sig_off[i+1]) -> y at the
+ * same offsets, filtered by K[i] sections whose rows start at row sec_off[i]
+ * of `sections` (so rows sec_off[i] .. sec_off[i]+K[i]-1), with TDF-II states
+ * zi/zf at 2*sec_off[i] .. 2*(sec_off[i]+K[i]) - 1.
+ *   K, sec_off (B+1 entries used: B), sig_off (B+1) are DEVICE int arrays;
+ *   sections, x, y, zi, zf are DEVICE float arrays (zi/zf nullable).
+ *   kmax (host) bounds every K[i] (0 <= kmax <= SOS_MAX_SECTIONS);
+ *   total_samples (host) = sig_off[B], the size of x and y.
+ * The work table (groups per signal, ticket -> signal) is built on the device,
+ * so a sequence of calls with changing device-side contents can be captured
+ * in a HIP graph. Groups of all signals are drawn as tickets by a grid sized
+ * to the device's resident capacity. A signal whose entries are inconsistent
+ * (K[i] outside [0, kmax], offsets out of range or decreasing) is skipped and
+ * reported by sos_last_error() as SOS_EINVAL; sections that are invalid
+ * (a0 == 0, unstable) poison only their own signal. Signals with no samples
+ * get zf = zi. Calls on one handle must be ordered, as for sos_filter.
+ */
+int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_samples, const int32_t *K,
+                       const int32_t *sec_off, const float *sections, const int64_t *sig_off,
+                       const float *x, float *y, const float *zi, float *zf, hipStream_t stream);
+
 /* Two-step form of sos_filter for repeated calls with the same coefficients
  * (Sec. II-D: every table depends only on the filter and is precomputed).
  * sos_prepare enqueues the coefficient-preparation kernel for `sections`

@@ -61,9 +61,11 @@ def lib():
             L.sos_prepare.argtypes = [vp, vp, i32, vp]
             L.sos_filter_prepared.argtypes = [vp, vp, vp, i64, vp, vp, vp]
             L.sos_bench_copy.argtypes = [vp, vp, i64, vp]
+            L.sos_filter_batched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                             vp]
             for name in ("sos_create", "sos_destroy", "sos_last_error", "sos_set_tile",
                          "sos_get_tile", "sos_filter", "sos_debug_carries", "sos_prepare",
-                         "sos_filter_prepared", "sos_bench_copy"):
+                         "sos_filter_prepared", "sos_bench_copy", "sos_filter_batched"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -224,4 +226,40 @@ def sosfilt(x, sos, zi=None, handle: Handle | None = None):
     zf = torch.empty((K, 2), dtype=torch.float32, device=x.device)
     y = torch.empty_like(x)
     sosfilt_(x, sos, y=y, zi=zi, zf=zf, handle=handle)
+    return y, zf
+
+
+def sosfilt_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None, kmax=None,
+                    handle: Handle | None = None):
+    """Uneven batch: signal i is x[sig_off[i]:sig_off[i+1]] filtered by the K[i]
+    rows of `sections` starting at row sec_off[i] (default: prefix of K).
+    x, sections, zi: float32 GPU tensors; K (int32), sig_off (int64, B+1),
+    sec_off (int32, B+1): GPU tensors. Returns (y, zf) with zf shaped like zi
+    (sec_off[B] x 2). One persistent launch on the current stream."""
+    import torch
+
+    x = _as_dev_f32(x, "x").reshape(-1)
+    sections = _as_dev_f32(sections, "sections").reshape(-1, 6)
+    if K.dtype != torch.int32 or not K.is_cuda:
+        raise TypeError("K must be an int32 GPU tensor")
+    if sig_off.dtype != torch.int64 or not sig_off.is_cuda:
+        raise TypeError("sig_off must be an int64 GPU tensor")
+    B = K.numel()
+    if sec_off is None:
+        sec_off = torch.zeros(B + 1, dtype=torch.int32, device=x.device)
+        sec_off[1:] = torch.cumsum(K, 0, dtype=torch.int32)
+    if kmax is None:
+        kmax = int(K.max().item()) if B else 0
+    nsec = sections.shape[0]
+    if zi is not None:
+        zi = _as_dev_f32(zi, "zi").reshape(-1, 2)
+    if y is None:
+        y = torch.empty_like(x)
+    if zf is None:
+        zf = torch.empty((nsec, 2), dtype=torch.float32, device=x.device)
+    h = handle or default_handle(x.device.index or 0)
+    _check(lib().sos_filter_batched(h.ptr, B, int(kmax), x.numel(), _p(K.contiguous()),
+                                    _p(sec_off.contiguous()), _p(sections), _p(sig_off.contiguous()),
+                                    _p(x), _p(y), _p(zi), _p(zf), _stream_ptr(x.device)),
+           "sos_filter_batched")
     return y, zf

@@ -18,8 +18,28 @@ extern "C" hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
 extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int64_t n,
                                      int64_t groups, const float *tabs, int K, const float *zi,
                                      float *zf, unsigned long long *desc, unsigned *ctrl,
-                                     unsigned long long timeout_ticks, hipStream_t stream);
+                                     unsigned long long timeout_ticks, int64_t grid,
+                                     hipStream_t stream);
+extern "C" hipError_t sos_launch_fwd_batched(int L, int N, int B, int kmax, const int32_t *Ks,
+                                             const int32_t *sec_off, const int64_t *sig_off,
+                                             const int64_t *gpre, const int32_t *sigmap,
+                                             const int64_t *total_dev, const float *x, float *y,
+                                             const float *tabs, const float *zi, float *zf,
+                                             unsigned long long *desc, unsigned *ctrl,
+                                             unsigned long long timeout_ticks, int64_t grid,
+                                             hipStream_t stream);
+extern "C" hipError_t sos_launch_prep_batched(const float *sections, int B, int kmax,
+                                              const int32_t *Ks, const int32_t *sec_off,
+                                              int log2n, int log2w, float *tabs, unsigned *ctrl,
+                                              hipStream_t stream);
+extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t C, int64_t total_samples,
+                                           int64_t max_groups, const int32_t *Ks,
+                                           const int32_t *sec_off, const int64_t *sig_off,
+                                           int64_t *gpre, int32_t *sigmap, int64_t *total_dev,
+                                           const float *zi, float *zf, unsigned *ctrl,
+                                           hipStream_t stream);
 extern "C" int sos_fwd_shape_supported(int L, int N);
+extern "C" int sos_fwd_capacity(int L, int N);
 extern "C" hipError_t sos_launch_fill(float *dst, const float *src, int64_t count,
                                       hipStream_t stream);
 extern "C" hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
@@ -41,6 +61,12 @@ struct sos_ctx {
     int prep_K = -1;                      // tables currently prepared (K, tile L x N)
     int prep_L = 0;
     int prep_N = 0;
+    // uneven-batch work table
+    int64_t *gpre = nullptr;
+    size_t gpre_cap = 0;                  // entries
+    int32_t *sigmap = nullptr;
+    size_t sigmap_cap = 0;
+    int64_t *total_dev = nullptr;
     std::mutex mu;
 };
 
@@ -93,6 +119,22 @@ int ensure_desc(sos_ctx *h, size_t words, hipStream_t stream)
     // Tag 0 never matches a launch epoch, so zeroed words read as "not published".
     if (hipMemset(h->desc, 0, cap * sizeof(unsigned long long)) != hipSuccess) return SOS_EHIP;
     h->desc_cap = cap;
+    return SOS_OK;
+}
+
+template <typename T>
+int ensure_buf(T *&p, size_t &cap, size_t need, hipStream_t stream)
+{
+    if (need <= cap) return SOS_OK;
+    if (p) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return SOS_EHIP;
+        (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    const size_t c = need + need / 4 + 64;
+    if (hipMalloc(&p, c * sizeof(T)) != hipSuccess) return SOS_ENOMEM;
+    cap = c;
     return SOS_OK;
 }
 
@@ -179,6 +221,9 @@ int sos_destroy(sos_handle_t h)
         if (h->desc) (void)hipFree(h->desc);
         if (h->tabs) (void)hipFree(h->tabs);
         if (h->ctrl) (void)hipFree(h->ctrl);
+        if (h->gpre) (void)hipFree(h->gpre);
+        if (h->sigmap) (void)hipFree(h->sigmap);
+        if (h->total_dev) (void)hipFree(h->total_dev);
     }
     delete h;
     return SOS_OK;
@@ -198,6 +243,7 @@ int sos_last_error(sos_handle_t h)
     if (bits & ERRBIT_A0) return SOS_EA0;
     if (bits & ERRBIT_UNSTABLE) return SOS_EUNSTABLE;
     if (bits & ERRBIT_TIMEOUT) return SOS_ETIMEOUT;
+    if (bits & ERRBIT_BADARG) return SOS_EINVAL;
     return SOS_OK;
 }
 
@@ -272,8 +318,11 @@ static int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const 
     const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
     if (rc) return rc;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    int64_t grid = 0;   // one workgroup per group unless a persistent grid is asked for
+    if (const char *e = std::getenv("SOS_PERSISTENT"))
+        if (std::atoi(e) > 0) grid = (int64_t)std::atoi(e) * sos_fwd_capacity(L, N);
     if (sos_launch_fwd(L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
-                       h->timeout_ticks, stream) != hipSuccess)
+                       h->timeout_ticks, grid, stream) != hipSuccess)
         return SOS_EHIP;
     h->last_groups = groups;
     h->last_K = K;
@@ -324,6 +373,59 @@ int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, flo
         h->prep_N = t.N;
     }
     return filter_locked(h, x, y, n, zi, zf, stream);
+}
+
+int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_samples, const int32_t *K,
+                       const int32_t *sec_off, const float *sections, const int64_t *sig_off,
+                       const float *x, float *y, const float *zi, float *zf, hipStream_t stream)
+{
+    if (!h || B < 0 || kmax < 0 || kmax > SOS_MAX_SECTIONS || total_samples < 0)
+        return SOS_EINVAL;
+    if (B == 0) return SOS_OK;
+    if (!K || !sec_off || !sig_off) return SOS_EINVAL;
+    if (kmax > 0 && !sections) return SOS_EINVAL;
+    if (total_samples > 0 && (!x || !y)) return SOS_EINVAL;
+    if (total_samples > 0 && x != y) {
+        const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, bytes = (uintptr_t)total_samples * 4u;
+        if (xa < ya + bytes && ya < xa + bytes) return SOS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    const Tile t = tile_of(h);
+    const int64_t C = (int64_t)t.L * t.N;
+    const int64_t max_groups = total_samples / C + B;
+    if (max_groups >= (int64_t)1 << 31) return SOS_EINVAL;
+    const int kd = kmax > 0 ? kmax : 1;   // descriptor stride
+    int rc = ensure_tabs(h, B * kd, stream);
+    if (rc) return rc;
+    rc = ensure_desc(h, (size_t)max_groups * (size_t)kd * 4u, stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->gpre, h->gpre_cap, (size_t)B + 1, stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->sigmap, h->sigmap_cap, (size_t)max_groups, stream);
+    if (rc) return rc;
+    if (!h->total_dev && hipMalloc(&h->total_dev, sizeof(int64_t)) != hipSuccess)
+        return SOS_ENOMEM;
+    const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
+    if (kmax > 0 && sos_launch_prep_batched(sections, B, kmax, K, sec_off, log2n, log2w, h->tabs,
+                                            h->ctrl, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_worktable(B, kmax, C, total_samples, max_groups, K, sec_off, sig_off, h->gpre,
+                             h->sigmap, h->total_dev, zi, zf, h->ctrl, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    int64_t grid = sos_fwd_capacity(t.L, t.N);
+    if (grid > max_groups) grid = max_groups;
+    if (grid < 1) grid = 1;
+    if (sos_launch_fwd_batched(t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre, h->sigmap,
+                               h->total_dev, x, y, h->tabs, zi, zf, h->desc, h->ctrl,
+                               h->timeout_ticks, grid, stream) != hipSuccess)
+        return SOS_EHIP;
+    h->prep_K = -1;        // the batch overwrote the plain tables
+    h->last_groups = 0;
+    h->last_K = 0;
+    return SOS_OK;
 }
 
 int sos_bench_copy(const float *x, float *y, int64_t n, hipStream_t stream)

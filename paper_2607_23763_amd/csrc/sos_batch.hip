@@ -1,0 +1,111 @@
+// Work table of an uneven batch, built on the device so that a batched launch
+// can be captured in a HIP graph and replayed with new per-signal data.
+//
+// Signal i (samples [sig_off[i], sig_off[i+1]), K[i] sections at sec_off[i])
+// is cut into G_i = ceil(n_i / C) groups of C samples. gpre is the exclusive
+// prefix of the G_i, so tickets gpre[i] .. gpre[i+1]-1 are the groups of
+// signal i in order, and sigmap[t] names the signal of ticket t. A signal
+// whose arguments are inconsistent is given no groups and reported through the
+// handle's error bits; a signal with no samples gets zf = zi here.
+#include "sos_device.h"
+
+using namespace sosdev;
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+
+__device__ inline bool signal_ok(int i, int B, int kmax, int64_t total_samples,
+                                 const int32_t *Ks, const int32_t *sec_off,
+                                 const int64_t *sig_off)
+{
+    const int K = Ks[i];
+    const int64_t so = sec_off[i], a = sig_off[i], b = sig_off[i + 1];
+    return K >= 0 && K <= kmax && so >= 0 && so + K <= (int64_t)B * kmax && a >= 0 && b >= a &&
+           b <= total_samples;
+}
+
+// One block of kScanThreads threads: group counts and their exclusive prefix.
+__global__ void __launch_bounds__(kScanThreads)
+worktable_scan_kernel(int B, int kmax, int64_t C, int64_t total_samples, int64_t max_groups,
+                      const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
+                      int64_t *gpre, int64_t *total_dev, unsigned *ctrl)
+{
+    __shared__ int64_t part[kScanThreads];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < B; base += kScanThreads) {
+        const int i = base + tid;
+        int64_t gi = 0;
+        if (i < B) {
+            if (signal_ok(i, B, kmax, total_samples, Ks, sec_off, sig_off)) {
+                const int64_t n = sig_off[i + 1] - sig_off[i];
+                gi = (n + C - 1) / C;
+            } else {
+                atomicOr(&ctrl[CTRL_ERR], ERRBIT_BADARG);
+            }
+        }
+        part[tid] = gi;
+        __syncthreads();
+        // Hillis-Steele inclusive scan over the block
+        for (int d = 1; d < kScanThreads; d <<= 1) {
+            const int64_t v = tid >= d ? part[tid - d] : 0;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        if (i < B) gpre[i] = carry + part[tid] - gi;
+        __syncthreads();
+        if (tid == kScanThreads - 1) carry += part[tid];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int64_t tot = carry;
+        if (tot > max_groups) {          // cannot happen when total_samples is honest
+            atomicOr(&ctrl[CTRL_ERR], ERRBIT_BADARG);
+            tot = 0;
+        }
+        gpre[B] = tot;
+        *total_dev = tot;
+    }
+}
+
+// Block i: sigmap for the tickets of signal i; zf := zi for empty signals.
+__global__ void __launch_bounds__(256)
+worktable_fill_kernel(int B, const int64_t *gpre, const int64_t *total_dev, int32_t *sigmap,
+                      const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
+                      const float *zi, float *zf)
+{
+    const int i = blockIdx.x;
+    if (i >= B) return;
+    const int64_t a = gpre[i], b = gpre[i + 1];
+    if (*total_dev == 0 && b > a) return;   // the table was rejected as a whole
+    for (int64_t t = a + threadIdx.x; t < b; t += blockDim.x) sigmap[t] = i;
+    if (zf && a == b && sig_off[i + 1] == sig_off[i] && Ks[i] >= 0) {
+        // no samples: the final state is the initial state (zeros without zi)
+        const int64_t so = sec_off[i];
+        for (int k = threadIdx.x; k < 2 * Ks[i]; k += blockDim.x)
+            zf[2 * so + k] = zi ? zi[2 * so + k] : 0.0f;
+    }
+}
+
+}  // namespace
+
+extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t C, int64_t total_samples,
+                                           int64_t max_groups, const int32_t *Ks,
+                                           const int32_t *sec_off, const int64_t *sig_off,
+                                           int64_t *gpre, int32_t *sigmap, int64_t *total_dev,
+                                           const float *zi, float *zf, unsigned *ctrl,
+                                           hipStream_t stream)
+{
+    hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax, C,
+                       total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (B > 0)
+        hipLaunchKernelGGL(worktable_fill_kernel, dim3(B), dim3(256), 0, stream, B, gpre,
+                           total_dev, sigmap, Ks, sec_off, sig_off, zi, zf);
+    return hipGetLastError();
+}

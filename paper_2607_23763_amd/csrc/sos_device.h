@@ -26,7 +26,7 @@ enum : int {
     CTRL_ERR = 2,      // sticky device-side error bits (ERRBIT_*)
     CTRL_WORDS = 16
 };
-enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u };
+enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u, ERRBIT_BADARG = 8u };
 
 // Per-section coefficient table (FP32 values computed in FP64 on the device)
 // for one group shape: L = 64*W lanes in W waves, N samples per lane,
@@ -38,7 +38,7 @@ enum : int {
     OFF_B1 = 9, OFF_B2 = 10, OFF_A1 = 11, OFF_A2 = 12,
     OFF_E = 16,             // [8] e_i, level-i coefficient of w^1 (e_0 = a1)
     OFF_F = 24,             // [8] f_i, level-i coefficient of w^2 (f_0 = a2)
-    OFF_KS = 32,            // [6][4] T^(N*2^k), k = 0..5 (cross-lane scan steps)
+    OFF_KS = 32,            // [6][4] T^(N*2^k), k = 0..5 (in-row scan steps use k < 4)
     OFF_TC = 56,            // [4] T^C: state map across a whole group
     OFF_TW = 60,            // [4] T^(64*C): across one lookback window
     OFF_TWAVE = 64,         // [4] T^(64*N): across one wave's 64 lanes
@@ -46,13 +46,16 @@ enum : int {
     OFF_G = 132,            // [kMaxN + 1] g[-1..kMaxN-1], impulse response of 1/A
     OFF_LANEPOW = 264,      // [64][4] T^(N*l): wave state -> incoming state of lane l
     OFF_GRPPOW = 520,       // [64][4] T^(C*j): state j groups back -> this group
-    TAB_FLOATS = 784
+    OFF_SCANPOW = 776,      // [64][8] T^(N*((l%16)+1)), T^(N*(l-31)): cross-row scan steps
+    TAB_FLOATS = 1296
 };
 constexpr int kMaxN = 128;
 constexpr int kMaxWaves = 16;
 static_assert(OFF_G + kMaxN + 1 <= OFF_LANEPOW, "table overlap");
-static_assert(OFF_GRPPOW + 256 <= TAB_FLOATS, "table overlap");
-static_assert((OFF_LANEPOW % 4) == 0 && (OFF_GRPPOW % 4) == 0 && (TAB_FLOATS % 16) == 0,
+static_assert(OFF_GRPPOW + 256 <= OFF_SCANPOW && OFF_SCANPOW + 512 <= TAB_FLOATS,
+              "table overlap");
+static_assert((OFF_LANEPOW % 4) == 0 && (OFF_GRPPOW % 4) == 0 && (OFF_SCANPOW % 4) == 0 &&
+                  (TAB_FLOATS % 16) == 0,
               "per-lane tables must be 16-byte aligned");
 
 // 2x2 row-major matrices (T acts on TDF-II states (z1, z2)).

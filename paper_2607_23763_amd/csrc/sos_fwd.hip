@@ -43,32 +43,107 @@ using namespace sosdev;
 namespace {
 
 struct FwdArgs {
+    // plain mode (B == 0): one signal x/y of n samples, K sections at tabs
     const float *x;
     float *y;
     int64_t n;
-    int64_t groups;
     const float *tabs;
     const float *zi;
     float *zf;
+    int K;                  // plain: sections; batched: descriptor stride (max sections)
+    // batched mode (B > 0): per-signal arrays (device) and the work table
+    int B;
+    const int32_t *Ks;      // sections per signal
+    const int32_t *sec_off; // B+1 section offsets (tables, zi, zf)
+    const int64_t *sig_off; // B+1 sample offsets
+    const int64_t *gpre;    // B+1 prefix of group counts
+    const int32_t *sigmap;  // ticket -> signal
+    const int64_t *total_dev;  // number of work items (batched)
+    // both modes
+    int64_t total;          // number of work items (plain)
     unsigned long long *desc;
     unsigned *ctrl;
-    int K;
-    int vec;   // x and y 16-byte aligned
     unsigned long long timeout_ticks;
 };
 
-__device__ __forceinline__ float lane_up(float v, int d, int lane)
+// One unit of work: group g of one signal, drawn as ticket t.
+struct Item {
+    const float *x;
+    float *y;
+    int64_t n;              // samples in the signal
+    int64_t g;              // group index within the signal
+    int64_t t;              // ticket (descriptor row)
+    const float *tabs;      // tables of the signal's sections
+    const float *zi;
+    float *zf;
+    int K;
+};
+
+// DPP move of a 32-bit value across lanes; lanes whose source is outside the
+// row (or whose row is masked off by ROWS) read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp0(float v)
 {
-    // value of lane (lane - d), 0 for lane < d
-    const float r = __shfl_up(v, d, 64);
-    return lane >= d ? r : 0.0f;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+enum : int {
+    DPP_ROW_SHR = 0x110,    // + d, d = 1..15: lane l reads l-d inside its 16-lane row
+    DPP_WAVE_SHR1 = 0x138,  // lane l reads l-1 across the whole wave
+    DPP_BCAST15 = 0x142,    // lane 15 of row r -> every lane of row r+1
+    DPP_BCAST31 = 0x143     // lane 31 -> every lane of rows 2 and 3
+};
+
+// Inclusive affine scan over the 64 lanes of a wave:
+//   P[l] = t[l] + T^N P[l-1]   (P[-1] = 0),
+// the cross-lane terminal-state recurrence (role of Eq. (13)). Within each
+// 16-lane row a Kogge-Stone ladder with the uniform powers T^(N 2^k), k < 4;
+// then rows 1 and 3 add lane 15 / 47 through T^(N((l%16)+1)) and rows 2 and 3
+// add lane 31 through T^(N(l-31)) (per-lane powers from the table).
+__device__ __forceinline__ void wave_scan(float &p1, float &p2, ctab_t *tab, const float *tabv,
+                                          int lane)
+{
+#define SOS_ROW_STEP(K)                                                                     \
+    {                                                                                       \
+        const float q1 = dpp0<DPP_ROW_SHR + (1 << K), 0xF>(p1);                             \
+        const float q2 = dpp0<DPP_ROW_SHR + (1 << K), 0xF>(p2);                             \
+        const float n1 = fmaf(tab[OFF_KS + 4 * K + 0], q1, fmaf(tab[OFF_KS + 4 * K + 1], q2, p1)); \
+        const float n2 = fmaf(tab[OFF_KS + 4 * K + 2], q1, fmaf(tab[OFF_KS + 4 * K + 3], q2, p2)); \
+        p1 = n1;                                                                            \
+        p2 = n2;                                                                            \
+    }
+    SOS_ROW_STEP(0)
+    SOS_ROW_STEP(1)
+    SOS_ROW_STEP(2)
+    SOS_ROW_STEP(3)
+#undef SOS_ROW_STEP
+    const float4 pa = *reinterpret_cast<const float4 *>(tabv + OFF_SCANPOW + 8 * lane);
+    const float4 pb = *reinterpret_cast<const float4 *>(tabv + OFF_SCANPOW + 8 * lane + 4);
+    {
+        const float q1 = dpp0<DPP_BCAST15, 0xA>(p1), q2 = dpp0<DPP_BCAST15, 0xA>(p2);
+        const float n1 = fmaf(pa.x, q1, fmaf(pa.y, q2, p1));
+        const float n2 = fmaf(pa.z, q1, fmaf(pa.w, q2, p2));
+        p1 = n1;
+        p2 = n2;
+    }
+    {
+        const float q1 = dpp0<DPP_BCAST31, 0xC>(p1), q2 = dpp0<DPP_BCAST31, 0xC>(p2);
+        const float n1 = fmaf(pb.x, q1, fmaf(pb.y, q2, p1));
+        const float n2 = fmaf(pb.z, q1, fmaf(pb.w, q2, p2));
+        p1 = n1;
+        p2 = n2;
+    }
 }
 
+// Sum over the 64 lanes of a wave (result valid in every lane).
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    v += dpp0<DPP_ROW_SHR + 1, 0xF>(v);
+    v += dpp0<DPP_ROW_SHR + 2, 0xF>(v);
+    v += dpp0<DPP_ROW_SHR + 4, 0xF>(v);
+    v += dpp0<DPP_ROW_SHR + 8, 0xF>(v);
+    v += dpp0<DPP_BCAST15, 0xA>(v);
+    v += dpp0<DPP_BCAST31, 0xC>(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ unsigned long long pack(float v, unsigned tag)
@@ -114,8 +189,8 @@ __device__ __forceinline__ float2 mv_add(ctab_t *p, float v1, float v2, float a1
 // lookback; executed by one whole wave. Returns a wave-uniform pair. On
 // timeout returns NaNs and sets the error bit (the caller still publishes, so
 // successors terminate).
-__device__ float2 lookback(const FwdArgs &a, const float *tabv, int64_t c, int s, unsigned epoch,
-                           int lane)
+__device__ float2 lookback(const FwdArgs &a, const Item &it, const float *tabv, int s,
+                           unsigned epoch, int lane)
 {
     ctab_t *tab = ctab(tabv);
     const float4 gp = *reinterpret_cast<const float4 *>(tabv + OFF_GRPPOW + 4 * lane);
@@ -123,12 +198,13 @@ __device__ float2 lookback(const FwdArgs &a, const float *tabv, int64_t c, int s
     const float w10 = tab[OFF_TW + 2], w11 = tab[OFF_TW + 3];
     float acc1 = 0.0f, acc2 = 0.0f;
     float m00 = 1.0f, m01 = 0.0f, m10 = 0.0f, m11 = 1.0f;   // window transform
-    int64_t base = c - 1;
+    const int64_t first = it.t - it.g;   // ticket of the signal's first group
+    int64_t base = it.t - 1;
     const unsigned long long t0 = wall_clock64();
     while (true) {
         const int64_t h = base - lane;
         unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
-        if (h >= 0) {
+        if (h >= first) {
             const unsigned long long *d = a.desc + ((size_t)h * a.K + s) * 4;
 #pragma unroll
             for (int i = 0; i < 4; ++i) w[i] = load_word(d + i);
@@ -185,9 +261,9 @@ struct Xch {
 
 template <int N, int W>
 __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *tl,
-                                            const FwdArgs &a, const float *tabv, int64_t c, int s,
-                                            unsigned epoch, int wv, int lane, bool has_last, int zl,
-                                            int zp)
+                                            const FwdArgs &a, const Item &it, const float *tabv,
+                                            int s, unsigned epoch, int wv, int lane, bool has_last,
+                                            int zl, int zp)
 {
     constexpr int LOG = __builtin_ctz(N);
     ctab_t *tab = ctab(tabv);
@@ -230,14 +306,7 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
     const float b1 = tab[OFF_B1], b2 = tab[OFF_B2], a1 = tab[OFF_A1], a2 = tab[OFF_A2];
     float p1 = b1 * xl1 + b2 * xl2 - a1 * u[N - 1] - a2 * u[N - 2];
     float p2 = b2 * xl1 - a2 * u[N - 1];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int d = 1 << k;
-        const float q1 = lane_up(p1, d, lane), q2 = lane_up(p2, d, lane);
-        const float2 r = mv_add(tab + OFF_KS + 4 * k, q1, q2, p1, p2);
-        p1 = r.x;
-        p2 = r.y;
-    }
+    wave_scan(p1, p2, tab, tabv, lane);
 
     //     ... and over the W waves of the group (zero group state)
     float e1w = 0.0f, e2w = 0.0f;      // zero-state incoming state of this wave
@@ -256,7 +325,8 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
     }
     if (wv == W - 1) {
         // group local carry = state after the last wave at zero group state
-        const float t1 = __shfl(p1, 63, 64), t2 = __shfl(p2, 63, 64);
+        const float t1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p1), 63));
+        const float t2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p2), 63));
         float g1 = t1, g2 = t2;
         if (W > 1) {
             const float2 r = mv_add(tab + OFF_TWAVE, e1w, e2w, t1, t2);
@@ -265,17 +335,17 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
         }
 
         // --- 4. decoupled lookback for the group's incoming state
-        unsigned long long *dsc = a.desc + ((size_t)c * a.K + s) * 4;
+        unsigned long long *dsc = a.desc + ((size_t)it.t * a.K + s) * 4;
         float sg1, sg2;
-        if (c == 0) {
-            sg1 = a.zi ? ctab(a.zi)[2 * s] : 0.0f;
-            sg2 = a.zi ? ctab(a.zi)[2 * s + 1] : 0.0f;
+        if (it.g == 0) {
+            sg1 = it.zi ? ctab(it.zi)[2 * s] : 0.0f;
+            sg2 = it.zi ? ctab(it.zi)[2 * s + 1] : 0.0f;
         } else {
             if (lane == 0) {
                 store_word(dsc + 0, pack(g1, epoch));
                 store_word(dsc + 1, pack(g2, epoch));
             }
-            const float2 sg = lookback(a, tabv, c, s, epoch, lane);
+            const float2 sg = lookback(a, it, tabv, s, epoch, lane);
             sg1 = sg.x;
             sg2 = sg.y;
         }
@@ -293,7 +363,7 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
     // --- 5. incoming state of every lane, then back substitution
     const float2 sw = mv_add(tab + OFF_WPOW + 4 * wv, sg1, sg2, e1w, e2w);
     const float4 lp = *reinterpret_cast<const float4 *>(tabv + OFF_LANEPOW + 4 * lane);
-    const float e1 = lane_up(p1, 1, lane), e2 = lane_up(p2, 1, lane);
+    const float e1 = dpp0<DPP_WAVE_SHR1, 0xF>(p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(p2);
     const float s1 = fmaf(lp.x, sw.x, fmaf(lp.y, sw.y, e1));
     const float s2 = fmaf(lp.z, sw.x, fmaf(lp.w, sw.y, e2));
     ctab_t *g = tab + OFF_G + 1;   // g[-1] is readable and 0
@@ -315,7 +385,7 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
     }
 
     // --- final state after sample n-1 (only the lane that holds it)
-    if (has_last && a.zf) {
+    if (has_last && it.zf) {
         float yo1, yo2;
         pick_two(u, tl, lane, zl, zp, yo1, yo2);
         if (lane == zl) {
@@ -324,36 +394,26 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
                 z1 = b1 * zx1 + b2 * zx2 - a1 * yo1 - a2 * yo2;
             else
                 z1 = b1 * zx1 - a1 * yo1 + s2;   // s2: this lane's incoming state
-            a.zf[2 * s] = z1;
-            a.zf[2 * s + 1] = b2 * zx1 - a2 * yo1;
+            it.zf[2 * s] = z1;
+            it.zf[2 * s + 1] = b2 * zx1 - a2 * yo1;
         }
     }
 }
 
 template <int N, int W>
-__global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
+__device__ __forceinline__ void process_group(const FwdArgs &a, const Item &it, float *tl,
+                                              Xch<W> &xch, unsigned epoch, int wv, int lane)
 {
     constexpr int CW = kLanes * N;   // samples per wave
     constexpr int C = CW * W;        // samples per group
     constexpr int RS = N + 4;        // LDS row stride: conflict-free 128-bit row reads
     constexpr int Q = N / 4;         // float4 per lane row
-    __shared__ float tile[W][kLanes * RS];
-    __shared__ Xch<W> xch;
-    __shared__ unsigned ticket;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
 
-    if (threadIdx.x == 0) ticket = atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
-    __syncthreads();
-    const int64_t c = (int64_t)ticket;
-    if (c >= a.groups) return;
-    const unsigned epoch = __hip_atomic_load(&a.ctrl[CTRL_EPOCH], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-
-    const int64_t g0 = c * C + (int64_t)wv * CW;   // first sample of this wave
-    const int64_t rem = a.n - g0;                  // may be <= 0 in the last group
+    const int64_t g0 = it.g * C + (int64_t)wv * CW;   // first sample of this wave
+    const int64_t rem = it.n - g0;                    // may be <= 0 in the last group
     const bool full = rem >= CW;
-    float *tl = tile[wv];
+    const bool vec = ((reinterpret_cast<uintptr_t>(it.x) | reinterpret_cast<uintptr_t>(it.y)) &
+                      15u) == 0;
 
     // --- load: coalesced 128-bit global loads -> LDS rows (transpose)
 #pragma unroll
@@ -361,14 +421,14 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
         const int v = kLanes * j + lane;           // float4 index inside the wave's part
         const int64_t q = 4 * (int64_t)v;
         float4 val;
-        if (full && a.vec) {
-            const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(a.x + g0) + v);
+        if (full && vec) {
+            const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(it.x + g0) + v);
             val = make_float4(t.x, t.y, t.z, t.w);
         } else {
-            val.x = q + 0 < rem ? a.x[g0 + q + 0] : 0.0f;
-            val.y = q + 1 < rem ? a.x[g0 + q + 1] : 0.0f;
-            val.z = q + 2 < rem ? a.x[g0 + q + 2] : 0.0f;
-            val.w = q + 3 < rem ? a.x[g0 + q + 3] : 0.0f;
+            val.x = q + 0 < rem ? it.x[g0 + q + 0] : 0.0f;
+            val.y = q + 1 < rem ? it.x[g0 + q + 1] : 0.0f;
+            val.z = q + 2 < rem ? it.x[g0 + q + 2] : 0.0f;
+            val.w = q + 3 < rem ? it.x[g0 + q + 3] : 0.0f;
         }
         *reinterpret_cast<float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]) = val;
     }
@@ -383,23 +443,23 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
         u[4 * k + 3] = v.w;
     }
 
-    // --- sections (any unusable section poisons the whole call)
+    // --- sections (an unusable section poisons its signal)
     bool bad = false;
-    for (int s = 0; s < a.K; ++s)
-        bad |= __float_as_uint(ctab(a.tabs)[(size_t)s * TAB_FLOATS + OFF_STATUS]) != 0u;
+    for (int s = 0; s < it.K; ++s)
+        bad |= __float_as_uint(ctab(it.tabs)[(size_t)s * TAB_FLOATS + OFF_STATUS]) != 0u;
     // position of the last real sample n-1 if this wave holds it
-    const int64_t lp = (a.n - 1) - g0;
+    const int64_t lp = (it.n - 1) - g0;
     const bool has_last = lp >= 0 && lp < CW;
     const int zl = has_last ? (int)(lp / N) : 0, zp = has_last ? (int)(lp % N) : 0;
     if (!bad) {
-        for (int s = 0; s < a.K; ++s)
-            run_section<N, W>(u, xch, tl, a, a.tabs + (size_t)s * TAB_FLOATS, c, s, epoch, wv,
+        for (int s = 0; s < it.K; ++s)
+            run_section<N, W>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s, epoch, wv,
                               lane, has_last, zl, zp);
     } else {
 #pragma unroll
         for (int k = 0; k < N; ++k) u[k] = __builtin_nanf("");
-        if (has_last && lane == 0 && a.zf)
-            for (int s = 0; s < a.K; ++s) a.zf[2 * s] = a.zf[2 * s + 1] = __builtin_nanf("");
+        if (has_last && lane == 0 && it.zf)
+            for (int s = 0; s < it.K; ++s) it.zf[2 * s] = it.zf[2 * s + 1] = __builtin_nanf("");
     }
 
     // --- store: registers -> LDS rows -> coalesced 128-bit global stores
@@ -414,63 +474,182 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
         const int v = kLanes * j + lane;
         const int64_t q = 4 * (int64_t)v;
         const float4 val = *reinterpret_cast<const float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]);
-        if (full && a.vec) {
+        if (full && vec) {
             const f4 t = {val.x, val.y, val.z, val.w};
-            __builtin_nontemporal_store(t, reinterpret_cast<f4 *>(a.y + g0) + v);
+            __builtin_nontemporal_store(t, reinterpret_cast<f4 *>(it.y + g0) + v);
         } else {
-            if (q + 0 < rem) a.y[g0 + q + 0] = val.x;
-            if (q + 1 < rem) a.y[g0 + q + 1] = val.y;
-            if (q + 2 < rem) a.y[g0 + q + 2] = val.z;
-            if (q + 3 < rem) a.y[g0 + q + 3] = val.w;
+            if (q + 0 < rem) it.y[g0 + q + 0] = val.x;
+            if (q + 1 < rem) it.y[g0 + q + 1] = val.y;
+            if (q + 2 < rem) it.y[g0 + q + 2] = val.z;
+            if (q + 3 < rem) it.y[g0 + q + 3] = val.w;
         }
     }
 }
 
+// The filter kernel: every workgroup draws tickets until the work runs out.
+// A ticket names one group of one signal; within a signal, tickets ascend with
+// the group index, so a group's predecessors were drawn (and are being worked
+// on) before it, which guarantees forward progress of the lookback whatever
+// the grid size (Sec. IV-A).
 template <int N, int W>
-hipError_t launch(const FwdArgs &a, hipStream_t stream)
+__global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
 {
-    hipLaunchKernelGGL((sos_fwd_kernel<N, W>), dim3((unsigned)a.groups), dim3(64 * W), 0, stream,
-                       a);
+    constexpr int RS = N + 4;
+    __shared__ float tile[W][kLanes * RS];
+    __shared__ Xch<W> xch;
+    __shared__ int64_t ticket;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const unsigned epoch = __hip_atomic_load(&a.ctrl[CTRL_EPOCH], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t total = a.B > 0 ? *a.total_dev : a.total;
+    float *tl = tile[wv];
+
+    for (;;) {
+        if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
+        __syncthreads();
+        const int64_t t = ticket;
+        __syncthreads();
+        if (t >= total) break;
+        Item it;
+        it.t = t;
+        if (a.B == 0) {
+            it.x = a.x;
+            it.y = a.y;
+            it.n = a.n;
+            it.g = t;
+            it.tabs = a.tabs;
+            it.zi = a.zi;
+            it.zf = a.zf;
+            it.K = a.K;
+        } else {
+            const int i = a.sigmap[t];
+            const int64_t so = a.sig_off[i];
+            const int32_t sc = a.sec_off[i];
+            it.x = a.x + so;
+            it.y = a.y + so;
+            it.n = a.sig_off[i + 1] - so;
+            it.g = t - a.gpre[i];
+            it.tabs = a.tabs + (size_t)sc * TAB_FLOATS;
+            it.zi = a.zi ? a.zi + 2 * (int64_t)sc : nullptr;
+            it.zf = a.zf ? a.zf + 2 * (int64_t)sc : nullptr;
+            it.K = a.Ks[i];
+        }
+        process_group<N, W>(a, it, tl, xch, epoch, wv, lane);
+        if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
+    }
+}
+
+template <int N, int W>
+hipError_t launch(const FwdArgs &a, int64_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL((sos_fwd_kernel<N, W>), dim3((unsigned)grid), dim3(64 * W), 0, stream, a);
     return hipGetLastError();
+}
+
+template <int N, int W>
+int capacity_of()
+{
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sos_fwd_kernel<N, W>, 64 * W, 0) !=
+        hipSuccess)
+        per_cu = 1;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    return (per_cu > 0 ? per_cu : 1) * cus;
+}
+
+#define SOS_SHAPES(X)                                                                     \
+    X(16, 1) X(32, 1) X(64, 1) X(16, 4) X(32, 4) X(64, 4) X(16, 8) X(32, 8) X(64, 8)    \
+        X(16, 16) X(32, 16)
+
+hipError_t dispatch(int L, int N, const FwdArgs &a, int64_t grid, hipStream_t stream)
+{
+    const int W = L / 64;
+#define SOS_CASE(NN, WW)                                                                  \
+    if (N == NN && W == WW) return launch<NN, WW>(a, grid, stream);
+    SOS_SHAPES(SOS_CASE)
+#undef SOS_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-// Host-side launcher (C linkage inside the library only). L = 64 * W lanes per
-// group, N samples per lane.
-extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int64_t n,
-                                     int64_t groups, const float *tabs, int K, const float *zi,
-                                     float *zf, unsigned long long *desc, unsigned *ctrl,
-                                     unsigned long long timeout_ticks, hipStream_t stream)
-{
-    const int vec =
-        ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) == 0 ? 1 : 0;
-    FwdArgs a{x, y, n, groups, tabs, zi, zf, desc, ctrl, K, vec, timeout_ticks};
-    const int W = L / 64;
-    switch (W * 1000 + N) {
-    case 1016: return launch<16, 1>(a, stream);
-    case 1032: return launch<32, 1>(a, stream);
-    case 1064: return launch<64, 1>(a, stream);
-    case 4016: return launch<16, 4>(a, stream);
-    case 4032: return launch<32, 4>(a, stream);
-    case 4064: return launch<64, 4>(a, stream);
-    case 8016: return launch<16, 8>(a, stream);
-    case 8032: return launch<32, 8>(a, stream);
-    case 8064: return launch<64, 8>(a, stream);
-    case 16016: return launch<16, 16>(a, stream);
-    case 16032: return launch<32, 16>(a, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-// Group shapes compiled into the library.
+// Group shapes compiled into the library: L = 64 W lanes, N samples per lane.
 extern "C" int sos_fwd_shape_supported(int L, int N)
 {
     if (L % 64) return 0;
-    switch ((L / 64) * 1000 + N) {
-    case 1016: case 1032: case 1064: case 4016: case 4032: case 4064:
-    case 8016: case 8032: case 8064: case 16016: case 16032:
-        return 1;
-    default: return 0;
-    }
+    const int W = L / 64;
+#define SOS_CASE(NN, WW)                                                                  \
+    if (N == NN && W == WW) return 1;
+    SOS_SHAPES(SOS_CASE)
+#undef SOS_CASE
+    return 0;
+}
+
+// Workgroups of shape (L, N) that can be resident on the whole device at once.
+extern "C" int sos_fwd_capacity(int L, int N)
+{
+    const int W = L / 64;
+#define SOS_CASE(NN, WW)                                                                  \
+    if (N == NN && W == WW) return capacity_of<NN, WW>();
+    SOS_SHAPES(SOS_CASE)
+#undef SOS_CASE
+    return 0;
+}
+
+// Plain filter of one signal; grid <= 0 means one workgroup per group.
+extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int64_t n,
+                                     int64_t groups, const float *tabs, int K, const float *zi,
+                                     float *zf, unsigned long long *desc, unsigned *ctrl,
+                                     unsigned long long timeout_ticks, int64_t grid,
+                                     hipStream_t stream)
+{
+    FwdArgs a{};
+    a.x = x;
+    a.y = y;
+    a.n = n;
+    a.tabs = tabs;
+    a.zi = zi;
+    a.zf = zf;
+    a.K = K;
+    a.B = 0;
+    a.total = groups;
+    a.desc = desc;
+    a.ctrl = ctrl;
+    a.timeout_ticks = timeout_ticks;
+    if (grid <= 0 || grid > groups) grid = groups;
+    return dispatch(L, N, a, grid, stream);
+}
+
+// Uneven batch in one persistent launch. The work table (gpre, sigmap,
+// *total_dev) is produced on the device by sos_launch_worktable.
+extern "C" hipError_t sos_launch_fwd_batched(int L, int N, int B, int kmax, const int32_t *Ks,
+                                             const int32_t *sec_off, const int64_t *sig_off,
+                                             const int64_t *gpre, const int32_t *sigmap,
+                                             const int64_t *total_dev, const float *x, float *y,
+                                             const float *tabs, const float *zi, float *zf,
+                                             unsigned long long *desc, unsigned *ctrl,
+                                             unsigned long long timeout_ticks, int64_t grid,
+                                             hipStream_t stream)
+{
+    FwdArgs a{};
+    a.x = x;
+    a.y = y;
+    a.tabs = tabs;
+    a.zi = zi;
+    a.zf = zf;
+    a.K = kmax;
+    a.B = B;
+    a.Ks = Ks;
+    a.sec_off = sec_off;
+    a.sig_off = sig_off;
+    a.gpre = gpre;
+    a.sigmap = sigmap;
+    a.total_dev = total_dev;
+    a.desc = desc;
+    a.ctrl = ctrl;
+    a.timeout_ticks = timeout_ticks;
+    return dispatch(L, N, a, grid, stream);
 }

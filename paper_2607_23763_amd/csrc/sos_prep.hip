@@ -27,18 +27,13 @@ __device__ inline void put(float *t, int off, const m2 &m)
 
 }  // namespace
 
-// sections: K x 6 rows; tabs: K x TAB_FLOATS; log2n = log2(N) samples per
-// lane, log2w = log2(W) waves per group (group C = 64 W N samples).
-// Grid = (K), block = 64.
-extern "C" __global__ void __launch_bounds__(64)
-sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
-                float *__restrict__ tabs, unsigned *__restrict__ ctrl)
+// Table of one section: row = [b0 b1 b2 a0 a1 a2], t = its table, log2n =
+// log2(N) samples per lane, log2w = log2(W) waves per group (C = 64 W N).
+// Called by all 64 lanes of one wave (lane l fills the per-lane entries).
+__device__ void prep_section(const float *row, float *t, int log2n, int log2w, unsigned *ctrl,
+                             int l)
 {
-    const int s = blockIdx.x;
-    const int l = threadIdx.x;
-    if (s >= K) return;
     const int N = 1 << log2n;
-    const float *row = sections + 6 * s;
     const double a0 = (double)row[3];
     unsigned status = 0u;
     if (a0 == 0.0) status |= ERRBIT_A0;
@@ -47,8 +42,6 @@ sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
     const double a1 = row[4] * inv, a2 = row[5] * inv;
     // closed stability triangle of z^2 + a1 z + a2 (NaN fails the test)
     if (!(fabs(a2) <= 1.0 && fabs(a1) <= 1.0 + a2)) status |= ERRBIT_UNSTABLE;
-
-    float *t = tabs + (size_t)s * TAB_FLOATS;
 
     // T maps the TDF-II state before a sample to the state after it at zero input.
     const m2 T1 = {-a1, 1.0, -a2, 0.0};
@@ -76,6 +69,18 @@ sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
     put(t, OFF_LANEPOW + 4 * l, lp);
     put(t, OFF_GRPPOW + 4 * l, gp);
     if (l < kMaxWaves) put(t, OFF_WPOW + 4 * l, wp);
+    // cross-row steps of the in-wave scan: distance (l%16)+1 from the end of
+    // the previous row, and l-31 from lane 31 (used by rows 2 and 3)
+    {
+        const int ea = (l & 15) + 1, eb = l >= 32 ? l - 31 : 0;
+        m2 pa = mident(), pb = mident();
+        for (int k = 0; k < 6; ++k) {
+            if ((ea >> k) & 1) pa = mmul(pa, ks[k]);
+            if ((eb >> k) & 1) pb = mmul(pb, ks[k]);
+        }
+        put(t, OFF_SCANPOW + 8 * l, pa);
+        put(t, OFF_SCANPOW + 8 * l + 4, pb);
+    }
 
     if (l == 0) {
         t[OFF_STATUS] = __uint_as_float(status);
@@ -115,12 +120,52 @@ sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
     }
 }
 
+// Plain filter: sections K x 6 -> tabs K x TAB_FLOATS. Grid = (K), block = 64.
+extern "C" __global__ void __launch_bounds__(64)
+sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
+                float *__restrict__ tabs, unsigned *__restrict__ ctrl)
+{
+    const int s = blockIdx.x;
+    if (s >= K) return;
+    prep_section(sections + 6 * s, tabs + (size_t)s * TAB_FLOATS, log2n, log2w, ctrl,
+                 threadIdx.x);
+}
+
+// Uneven batch: block i prepares the K[i] sections of signal i (rows and
+// tables at sec_off[i]); signals the work table marks invalid are skipped.
+extern "C" __global__ void __launch_bounds__(64)
+sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax,
+                        const int32_t *__restrict__ Ks, const int32_t *__restrict__ sec_off,
+                        int log2n, int log2w, float *__restrict__ tabs,
+                        unsigned *__restrict__ ctrl)
+{
+    const int i = blockIdx.x;
+    if (i >= B) return;
+    const int K = Ks[i];
+    const int64_t so = sec_off[i];
+    if (K < 0 || K > kmax || so < 0 || so + K > (int64_t)B * kmax) return;
+    for (int k = 0; k < K; ++k)
+        prep_section(sections + 6 * (so + k), tabs + (size_t)(so + k) * TAB_FLOATS, log2n, log2w,
+                     ctrl, threadIdx.x);
+}
+
 extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, int log2w,
                                       float *tabs, unsigned *ctrl, hipStream_t stream)
 {
     if (K <= 0) return hipSuccess;
     hipLaunchKernelGGL(sos_prep_kernel, dim3(K), dim3(64), 0, stream, sections, K, log2n, log2w,
                        tabs, ctrl);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t sos_launch_prep_batched(const float *sections, int B, int kmax,
+                                              const int32_t *Ks, const int32_t *sec_off,
+                                              int log2n, int log2w, float *tabs, unsigned *ctrl,
+                                              hipStream_t stream)
+{
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sos_prep_batched_kernel, dim3(B), dim3(64), 0, stream, sections, B, kmax,
+                       Ks, sec_off, log2n, log2w, tabs, ctrl);
     return hipGetLastError();
 }
 

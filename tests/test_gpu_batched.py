@@ -1,0 +1,110 @@
+"""GPU parity of the uneven-batch entry point (sos_filter_batched): every
+signal of the batch against the FP64 oracle, the same result alone and in the
+mix, empty and zero-section signals, and rejection of inconsistent entries."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import rel_l2, tol_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_23763_amd as P
+
+    P.lib()
+    return torch, P
+
+
+def dev(torch, a, dtype=None):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_batch(torch, P, Ks, rows, sig_off, x, zi, tile=None):
+    h = P.Handle(0, tile=tile)
+    y, zf = P.sosfilt_batched(dev(torch, x), dev(torch, rows), dev(torch, Ks.astype(np.int32)),
+                              dev(torch, sig_off.astype(np.int64)),
+                              zi=None if zi is None else dev(torch, zi), handle=h)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), zf.cpu().numpy(), h.last_error()
+
+
+@pytest.mark.parametrize("tile", [(64, 16), (256, 32), (512, 32), (1024, 32)])
+def test_uneven_batch_matches_oracle(env, tile):
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=96, log2_lo=2, log2_hi=17, seed=11)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=12)
+    y, zf, err = run_batch(torch, P, Ks, rows, sig_off, x, zi, tile)
+    assert err == P.SOS_OK
+    yr, zfr = oracle.sosfilt_batched(Ks, rows, sig_off, x, zi, nthreads=8)
+    so = np.r_[0, np.cumsum(Ks)]
+    for i in range(len(Ks)):
+        a, b = sig_off[i], sig_off[i + 1]
+        e = rel_l2(y[a:b], yr[a:b])
+        assert e <= tol_for(int(Ks[i])), (i, Ks[i], b - a, e)
+        ez = rel_l2(zf[so[i]:so[i + 1]], zfr[so[i]:so[i + 1]])
+        assert ez <= tol_for(int(Ks[i])), (i, Ks[i], b - a, ez)
+
+
+def test_alone_equals_in_the_mix(env):
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=40, log2_lo=8, log2_hi=16, seed=21)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=22)
+    y, zf, err = run_batch(torch, P, Ks, rows, sig_off, x, zi)
+    assert err == P.SOS_OK
+    so = np.r_[0, np.cumsum(Ks)]
+    for i in (0, 7, 19, 39):
+        a, b = sig_off[i], sig_off[i + 1]
+        y1, zf1 = P.sosfilt(dev(torch, x[a:b]), dev(torch, rows[so[i]:so[i + 1]]),
+                            dev(torch, zi[so[i]:so[i + 1]]))
+        torch.cuda.synchronize()
+        assert rel_l2(y[a:b], y1.cpu().numpy()) <= 1e-5
+        assert rel_l2(zf[so[i]:so[i + 1]], zf1.cpu().numpy()) <= 1e-5
+
+
+def test_empty_and_zero_section_signals(env):
+    torch, P = env
+    g = workloads.rng(5)
+    lens = np.array([0, 5000, 0, 1, 70000, 3], dtype=np.int64)
+    Ks = np.array([2, 0, 0, 3, 1, 2], dtype=np.int32)
+    rows = np.concatenate([workloads.random_stable_sos(int(k), g) for k in Ks])
+    zi = workloads.initial_state(int(Ks.sum()), g)
+    sig_off = np.r_[0, np.cumsum(lens)].astype(np.int64)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=6)
+    y, zf, err = run_batch(torch, P, Ks, rows, sig_off, x, zi)
+    assert err == P.SOS_OK
+    yr, zfr = oracle.sosfilt_batched(Ks, rows, sig_off, x, zi)
+    assert rel_l2(y, yr) <= 1e-5
+    assert np.allclose(zf, zfr, rtol=1e-5, atol=1e-6)
+    a, b = sig_off[1], sig_off[2]
+    assert np.array_equal(y[a:b], x[a:b])          # K = 0: copy
+
+
+def test_inconsistent_signal_is_skipped_and_reported(env):
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=6, log2_lo=10, log2_hi=12, seed=31,
+                                                   k_lo=1, k_hi=3)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=32)
+    h = P.Handle(0)
+    Kd = Ks.copy()
+    Kd[2] = 9                                      # above kmax = 3
+    yd = torch.full((x.size,), 7.0, device="cuda")
+    P.sosfilt_batched(dev(torch, x), dev(torch, rows), dev(torch, Kd),
+                      dev(torch, sig_off), zi=dev(torch, zi), y=yd, kmax=3,
+                      sec_off=dev(torch, np.r_[0, np.cumsum(Ks)].astype(np.int32)), handle=h)
+    assert h.last_error() == P.SOS_EINVAL
+    y = yd.cpu().numpy()
+    yr, _ = oracle.sosfilt_batched(Ks, rows, sig_off, x, zi)
+    for i in range(6):
+        a, b = sig_off[i], sig_off[i + 1]
+        if i == 2:
+            assert np.all(y[a:b] == 7.0)          # untouched
+        else:
+            assert rel_l2(y[a:b], yr[a:b]) <= 1e-5
