@@ -97,6 +97,18 @@ int sos_last_error(sos_handle_t h);
 int sos_set_tile(sos_handle_t h, int L, int N);
 int sos_get_tile(sos_handle_t h, int *L, int *N);
 
+/* Arithmetic type of the filter kernels: 32 (FP32, the default) or 64 (FP64;
+ * 0 restores the default). Data in memory stay FP32 either way. The solver
+ * applies derived coefficients (fold taps, level coefficients, state-map
+ * powers) that are rounded to the compute type; for cascades of lightly
+ * damped sections (poles within ~0.05 of the unit circle, high order) FP32
+ * rounding of those coefficients can cost more accuracy than a sequential
+ * FP32 filter loses, and FP64 removes it. MI355X issues FP64 FMAs at the
+ * unpacked-FP32 rate, so the cost is register pressure. Applies to later
+ * calls. */
+int sos_set_precision(sos_handle_t h, int bits);
+int sos_get_precision(sos_handle_t h);
+
 /*
  * Plain filter, one signal (Sec. IV-A/B; Eqs. (1)-(25)).
  *   y[0..n) = cascade(sections[0..K))(x[0..n)) starting from zi; zf receives
@@ -116,11 +128,15 @@ int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, flo
  * B independent signals; signal i is x[sig_off[i] .. sig_off[i+1]) -> y at the
  * same offsets, filtered by K[i] sections whose rows start at row sec_off[i]
  * of `sections` (so rows sec_off[i] .. sec_off[i]+K[i]-1), with TDF-II states
- * zi/zf at 2*sec_off[i] .. 2*(sec_off[i]+K[i]) - 1.
- *   K, sec_off (B+1 entries used: B), sig_off (B+1) are DEVICE int arrays;
+ * zi/zf at 2*sec_off[i] .. 2*(sec_off[i]+K[i]) - 1. Rows of different signals
+ * need not be contiguous or ordered (a server can keep one row table for all
+ * its streams), but two signals must not share zf rows.
+ *   K, sec_off (B entries), sig_off (B+1 entries) are DEVICE int arrays;
  *   sections, x, y, zi, zf are DEVICE float arrays (zi/zf nullable).
  *   kmax (host) bounds every K[i] (0 <= kmax <= SOS_MAX_SECTIONS);
- *   total_samples (host) = sig_off[B], the size of x and y.
+ *   total_rows (host) = rows in `sections` (and pairs in zi/zf);
+ *   total_samples (host) = the size of x and y (sig_off[B] <= total_samples).
+ *   zi may equal zf (state updated in place).
  * The work table (groups per signal, ticket -> signal) is built on the device,
  * so a sequence of calls with changing device-side contents can be captured
  * in a HIP graph. Groups of all signals are drawn as tickets by a grid sized
@@ -130,9 +146,10 @@ int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, flo
  * (a0 == 0, unstable) poison only their own signal. Signals with no samples
  * get zf = zi. Calls on one handle must be ordered, as for sos_filter.
  */
-int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_samples, const int32_t *K,
-                       const int32_t *sec_off, const float *sections, const int64_t *sig_off,
-                       const float *x, float *y, const float *zi, float *zf, hipStream_t stream);
+int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                       int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                       const float *sections, const int64_t *sig_off, const float *x, float *y,
+                       const float *zi, float *zf, hipStream_t stream);
 
 /* Two-step form of sos_filter for repeated calls with the same coefficients
  * (Sec. II-D: every table depends only on the filter and is precomputed).
@@ -144,6 +161,31 @@ int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_samples, c
 int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream);
 int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, const float *zi,
                         float *zf, hipStream_t stream);
+
+/*
+ * Differentiable form. sos_filter_train is sos_filter that also writes the
+ * outputs of sections 0..K-2 to `saved` ((K-1) x n floats, device; unused
+ * when K <= 1); x and y must be distinct buffers.
+ *
+ * sos_filter_vjp: vector-Jacobian product of that forward call. Given the
+ * upstream gradients gy (n) and gzf (K x 2, nullable = zeros) it writes
+ *   gx        (n)      d<gy,y>+<gzf,zf> / dx        (may alias gy)
+ *   gzi       (K x 2)  ... / dzi                   (nullable)
+ *   gsections (K x 6)  ... / d[b0 b1 b2 a0 a1 a2]  (nullable; raw rows,
+ *                      through the division by a0)
+ * from x, y and saved of the forward call (zi is not needed). Per section, last
+ * to first: the recursive part 1/A(z) runs in reversed time with the same
+ * multi-block machinery (carries = last two outputs), a 3-tap FIR of its
+ * output gives the gradient of the section input, and per-group correlations
+ * of that output with the section's input and output give the coefficient
+ * gradients, reduced over groups in FP64 in a fixed order. The paper does not
+ * treat gradients; this is the adjoint of its Eq. (1) cascade.
+ */
+int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *x, float *y,
+                     int64_t n, const float *zi, float *zf, float *saved, hipStream_t stream);
+int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x, const float *y,
+                   const float *saved, int64_t n, const float *gy, const float *gzf, float *gx,
+                   float *gzi, float *gsections, hipStream_t stream);
 
 /* Memory-floor reference (the t_mem = b_s / BW term of the cost model,
  * Eq. (28), with b_s = 8 bytes per sample): a plain streaming copy y = x of n

@@ -61,11 +61,17 @@ def lib():
             L.sos_prepare.argtypes = [vp, vp, i32, vp]
             L.sos_filter_prepared.argtypes = [vp, vp, vp, i64, vp, vp, vp]
             L.sos_bench_copy.argtypes = [vp, vp, i64, vp]
-            L.sos_filter_batched.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp,
-                                             vp]
+            L.sos_filter_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp, vp,
+                                             vp, vp]
+            L.sos_set_precision.argtypes = [vp, i32]
+            L.sos_get_precision.argtypes = [vp]
+            L.sos_filter_train.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp, vp]
+            L.sos_filter_vjp.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
             for name in ("sos_create", "sos_destroy", "sos_last_error", "sos_set_tile",
                          "sos_get_tile", "sos_filter", "sos_debug_carries", "sos_prepare",
-                         "sos_filter_prepared", "sos_bench_copy", "sos_filter_batched"):
+                         "sos_filter_prepared", "sos_bench_copy", "sos_filter_batched",
+                         "sos_filter_train", "sos_filter_vjp", "sos_set_precision",
+                         "sos_get_precision"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -92,12 +98,21 @@ def _stream_ptr(device=None):
 class Handle:
     """Owns a libsosfilt handle (workspace: tables, lookback descriptors)."""
 
-    def __init__(self, device: int = 0, tile=None):
+    def __init__(self, device: int = 0, tile=None, precision: int = 0):
         self._h = ctypes.c_void_p()
         self.device = int(device)
         _check(lib().sos_create(ctypes.byref(self._h), self.device), "sos_create")
         if tile:
             self.set_tile(*tile)
+        if precision:
+            self.set_precision(precision)
+
+    def set_precision(self, bits: int):
+        """Compute type of the kernels: 32 or 64 (0 = default)."""
+        _check(lib().sos_set_precision(self._h, int(bits)), "sos_set_precision")
+
+    def precision(self) -> int:
+        return int(lib().sos_get_precision(self._h))
 
     def close(self):
         if self._h:
@@ -258,8 +273,88 @@ def sosfilt_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=N
     if zf is None:
         zf = torch.empty((nsec, 2), dtype=torch.float32, device=x.device)
     h = handle or default_handle(x.device.index or 0)
-    _check(lib().sos_filter_batched(h.ptr, B, int(kmax), x.numel(), _p(K.contiguous()),
+    _check(lib().sos_filter_batched(h.ptr, B, int(kmax), nsec, x.numel(), _p(K.contiguous()),
                                     _p(sec_off.contiguous()), _p(sections), _p(sig_off.contiguous()),
                                     _p(x), _p(y), _p(zi), _p(zf), _stream_ptr(x.device)),
            "sos_filter_batched")
     return y, zf
+
+
+def sosfilt_train(x, sos, zi=None, handle: Handle | None = None):
+    """Forward pass that keeps what the adjoint needs: returns (y, zf, saved),
+    saved = outputs of sections 0..K-2 ((K-1) x n, empty for K <= 1)."""
+    import torch
+
+    x = _as_dev_f32(x, "x").reshape(-1)
+    sos = _as_dev_f32(sos, "sos").reshape(-1, 6)
+    K = sos.shape[0]
+    if zi is not None:
+        zi = _as_dev_f32(zi, "zi").reshape(K, 2)
+    y = torch.empty_like(x)
+    zf = torch.empty((K, 2), dtype=torch.float32, device=x.device)
+    saved = torch.empty((max(K - 1, 0), x.numel()), dtype=torch.float32, device=x.device)
+    h = handle or default_handle(x.device.index or 0)
+    _check(lib().sos_filter_train(h.ptr, _p(sos), K, _p(x), _p(y), x.numel(), _p(zi), _p(zf),
+                                  _p(saved) if saved.numel() else None, _stream_ptr(x.device)),
+           "sos_filter_train")
+    return y, zf, saved
+
+
+def sosfilt_vjp(sos, x, y, saved, gy, gzf=None, handle: Handle | None = None):
+    """(gx, gzi, gsos) for the forward call that produced y and saved."""
+    import torch
+
+    sos = _as_dev_f32(sos, "sos").reshape(-1, 6)
+    K = sos.shape[0]
+    gy = _as_dev_f32(gy, "gy").reshape(-1)
+    if gzf is not None:
+        gzf = _as_dev_f32(gzf, "gzf").reshape(K, 2)
+    gx = torch.empty_like(gy)
+    gzi = torch.empty((K, 2), dtype=torch.float32, device=gy.device)
+    gsos = torch.empty((K, 6), dtype=torch.float32, device=gy.device)
+    h = handle or default_handle(gy.device.index or 0)
+    _check(lib().sos_filter_vjp(h.ptr, _p(sos), K, _p(x), _p(y),
+                                _p(saved) if saved is not None and saved.numel() else None,
+                                gy.numel(), _p(gy), _p(gzf), _p(gx), _p(gzi), _p(gsos),
+                                _stream_ptr(gy.device)), "sos_filter_vjp")
+    return gx, gzi, gsos
+
+
+def _autograd_fn():
+    import torch
+
+    class SosFilterFn(torch.autograd.Function):
+        """Differentiable cascade: forward = sos_filter_train, backward =
+        sos_filter_vjp (hand-written adjoint kernel)."""
+
+        @staticmethod
+        def forward(ctx, x, sos, zi):
+            y, zf, saved = sosfilt_train(x, sos, zi)
+            ctx.save_for_backward(x, sos, y, saved)
+            return y, zf
+
+        @staticmethod
+        def backward(ctx, gy, gzf):
+            x, sos, y, saved = ctx.saved_tensors
+            if gy is None:
+                gy = torch.zeros_like(y)
+            gx, gzi, gsos = sosfilt_vjp(sos, x.contiguous(), y, saved, gy.contiguous(),
+                                        None if gzf is None else gzf.contiguous())
+            return gx, gsos, gzi
+
+    return SosFilterFn
+
+
+_fn = None
+
+
+def sosfilt_autograd(x, sos, zi=None):
+    """y, zf with gradients flowing to x, sos and zi through the adjoint kernel."""
+    import torch
+
+    global _fn
+    if _fn is None:
+        _fn = _autograd_fn()
+    if zi is None:
+        zi = torch.zeros((sos.shape[0], 2), dtype=torch.float32, device=x.device)
+    return _fn.apply(x, sos, zi)

@@ -12,37 +12,44 @@
 #include "sosfilt.h"
 #include "sos_device.h"
 
-extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, int log2w,
-                                      float *tabs, unsigned *ctrl, hipStream_t stream);
-extern "C" hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
-extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int64_t n,
-                                     int64_t groups, const float *tabs, int K, const float *zi,
-                                     float *zf, unsigned long long *desc, unsigned *ctrl,
-                                     unsigned long long timeout_ticks, int64_t grid,
-                                     hipStream_t stream);
-extern "C" hipError_t sos_launch_fwd_batched(int L, int N, int B, int kmax, const int32_t *Ks,
-                                             const int32_t *sec_off, const int64_t *sig_off,
-                                             const int64_t *gpre, const int32_t *sigmap,
-                                             const int64_t *total_dev, const float *x, float *y,
-                                             const float *tabs, const float *zi, float *zf,
-                                             unsigned long long *desc, unsigned *ctrl,
-                                             unsigned long long timeout_ticks, int64_t grid,
-                                             hipStream_t stream);
-extern "C" hipError_t sos_launch_prep_batched(const float *sections, int B, int kmax,
-                                              const int32_t *Ks, const int32_t *sec_off,
-                                              int log2n, int log2w, float *tabs, unsigned *ctrl,
-                                              hipStream_t stream);
-extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t C, int64_t total_samples,
-                                           int64_t max_groups, const int32_t *Ks,
-                                           const int32_t *sec_off, const int64_t *sig_off,
-                                           int64_t *gpre, int32_t *sigmap, int64_t *total_dev,
-                                           const float *zi, float *zf, unsigned *ctrl,
-                                           hipStream_t stream);
-extern "C" int sos_fwd_shape_supported(int L, int N);
-extern "C" int sos_fwd_capacity(int L, int N);
-extern "C" hipError_t sos_launch_fill(float *dst, const float *src, int64_t count,
-                                      hipStream_t stream);
-extern "C" hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
+extern "C" {
+hipError_t sos_launch_prep(int bits, const float *sections, int K, int log2n, int log2w,
+                           void *tabs, unsigned *ctrl, int pair, hipStream_t stream);
+hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int kmax, int64_t rows,
+                                   const int32_t *Ks, const int32_t *sec_off, int log2n,
+                                   int log2w, void *tabs, unsigned *ctrl, hipStream_t stream);
+hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
+hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, float *y, int64_t n,
+                          int64_t groups, const void *tabs, int K, const float *zi, float *zf,
+                          unsigned long long *desc, unsigned *ctrl,
+                          unsigned long long timeout_ticks, int64_t grid, float *saved,
+                          hipStream_t stream);
+hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax, const int32_t *Ks,
+                                  const int32_t *sec_off, const int64_t *sig_off,
+                                  const int64_t *gpre, const int32_t *sigmap,
+                                  const int64_t *total_dev, const float *x, float *y,
+                                  const void *tabs, const float *zi, float *zf,
+                                  unsigned long long *desc, unsigned *ctrl,
+                                  unsigned long long timeout_ticks, int64_t grid,
+                                  hipStream_t stream);
+hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
+                                int64_t max_groups, const int32_t *Ks, const int32_t *sec_off,
+                                const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
+                                int64_t *total_dev, const float *zi, float *zf, unsigned *ctrl,
+                                hipStream_t stream);
+hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx, int64_t n,
+                          int64_t groups, const void *tabs, int K, const float *x,
+                          const float *y, const float *saved, const float *gzf, float *gzi,
+                          double *partials, unsigned long long *desc, unsigned *ctrl,
+                          unsigned long long timeout_ticks, int64_t grid, hipStream_t stream);
+hipError_t sos_launch_bwd_reduce(const double *partials, int64_t groups, int K,
+                                 const float *sections, float *gsections, hipStream_t stream);
+hipError_t sos_launch_fill(float *dst, const float *src, int64_t count, hipStream_t stream);
+hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
+int sos_fwd_shape_supported(int L, int N);
+int sos_fwd_capacity(int bits, int L, int N);
+int sos_bwd_shape_supported(int L, int N);
+}
 
 using namespace sosdev;
 
@@ -50,30 +57,38 @@ struct sos_ctx {
     int device = 0;
     int tile_L = 0;                       // lanes per group L = 64 W; 0 = default
     int tile_N = 0;                       // samples per lane N; 0 = default
+    int bits = 0;                         // compute type: 32, 64; 0 = default
     unsigned *ctrl = nullptr;             // CTRL_WORDS
-    float *tabs = nullptr;
-    int tabs_cap = 0;                     // sections
-    unsigned long long *desc = nullptr;
+    unsigned char *tabs = nullptr;        // coefficient tables (bytes)
+    size_t tabs_cap = 0;
+    unsigned long long *desc = nullptr;   // lookback descriptors
     size_t desc_cap = 0;                  // 64-bit words
     unsigned long long timeout_ticks = 0;
     int64_t last_groups = 0;
     int last_K = 0;
-    int prep_K = -1;                      // tables currently prepared (K, tile L x N)
+    int prep_K = -1;                      // tables currently prepared (K, shape, type)
     int prep_L = 0;
     int prep_N = 0;
+    int prep_bits = 0;
     // uneven-batch work table
     int64_t *gpre = nullptr;
-    size_t gpre_cap = 0;                  // entries
+    size_t gpre_cap = 0;
     int32_t *sigmap = nullptr;
     size_t sigmap_cap = 0;
     int64_t *total_dev = nullptr;
+    // adjoint
+    unsigned char *tabs_bwd = nullptr;
+    size_t tabs_bwd_cap = 0;
+    double *partials = nullptr;
+    size_t partials_cap = 0;
     std::mutex mu;
 };
 
 namespace {
 
-constexpr int kDefaultL = 512;
-constexpr int kDefaultN = 32;
+constexpr int kDefaultL = 512;   // measured best at order 2 with a persistent grid
+constexpr int kDefaultN = 64;
+constexpr int kDefaultBits = 32;
 
 struct DeviceGuard {
     int prev = -1;
@@ -89,41 +104,10 @@ struct DeviceGuard {
     }
 };
 
-int ensure_tabs(sos_ctx *h, int K, hipStream_t stream)
-{
-    if (K <= h->tabs_cap) return SOS_OK;
-    if (h->tabs) {
-        if (hipStreamSynchronize(stream) != hipSuccess) return SOS_EHIP;
-        (void)hipFree(h->tabs);
-        h->tabs = nullptr;
-        h->tabs_cap = 0;
-    }
-    const int cap = K < 8 ? 8 : K;
-    if (hipMalloc(&h->tabs, sizeof(float) * (size_t)TAB_FLOATS * cap) != hipSuccess)
-        return SOS_ENOMEM;
-    h->tabs_cap = cap;
-    return SOS_OK;
-}
-
-int ensure_desc(sos_ctx *h, size_t words, hipStream_t stream)
-{
-    if (words <= h->desc_cap) return SOS_OK;
-    if (h->desc) {
-        if (hipStreamSynchronize(stream) != hipSuccess) return SOS_EHIP;
-        (void)hipFree(h->desc);
-        h->desc = nullptr;
-        h->desc_cap = 0;
-    }
-    size_t cap = words + words / 4 + 1024;
-    if (hipMalloc(&h->desc, cap * sizeof(unsigned long long)) != hipSuccess) return SOS_ENOMEM;
-    // Tag 0 never matches a launch epoch, so zeroed words read as "not published".
-    if (hipMemset(h->desc, 0, cap * sizeof(unsigned long long)) != hipSuccess) return SOS_EHIP;
-    h->desc_cap = cap;
-    return SOS_OK;
-}
-
+// Grow a device buffer to hold `need` elements (contents not preserved). The
+// previous buffer may still be read by queued work on `stream`: wait first.
 template <typename T>
-int ensure_buf(T *&p, size_t &cap, size_t need, hipStream_t stream)
+int ensure_buf(T *&p, size_t &cap, size_t need, hipStream_t stream, bool zero = false)
 {
     if (need <= cap) return SOS_OK;
     if (p) {
@@ -134,8 +118,21 @@ int ensure_buf(T *&p, size_t &cap, size_t need, hipStream_t stream)
     }
     const size_t c = need + need / 4 + 64;
     if (hipMalloc(&p, c * sizeof(T)) != hipSuccess) return SOS_ENOMEM;
+    // descriptors: tag 0 never matches a launch epoch, so zeroed words read as
+    // "not published"
+    if (zero && hipMemset(p, 0, c * sizeof(T)) != hipSuccess) return SOS_EHIP;
     cap = c;
     return SOS_OK;
+}
+
+int ensure_desc(sos_ctx *h, size_t words, hipStream_t stream)
+{
+    return ensure_buf(h->desc, h->desc_cap, words, stream, true);
+}
+
+size_t tab_bytes(int sections, int bits)
+{
+    return (size_t)sections * TAB_FLOATS * (bits == 64 ? 8 : 4);
 }
 
 struct Tile {
@@ -155,6 +152,96 @@ Tile tile_of(const sos_ctx *h)
     }
     if (h->tile_L) t = Tile{h->tile_L, h->tile_N};
     return t;
+}
+
+int bits_of(const sos_ctx *h)
+{
+    if (h->bits) return h->bits;
+    if (const char *e = std::getenv("SOS_PRECISION")) {
+        const int v = std::atoi(e);
+        if (v == 32 || v == 64) return v;
+    }
+    return kDefaultBits;
+}
+
+int64_t grid_of(int bits, int L, int N)
+{
+    // persistent grid: as many workgroups as can be resident, drawing tickets
+    // until the groups run out (measured faster than one workgroup per group)
+    int64_t grid = sos_fwd_capacity(bits, L, N);
+    if (const char *e = std::getenv("SOS_PERSISTENT")) {
+        const int f = std::atoi(e);
+        grid = f > 0 ? (int64_t)f * grid : 0;   // 0: one workgroup per group
+    }
+    return grid;
+}
+
+int check_signal(const float *x, const float *y, int64_t n)
+{
+    if (n < 0) return SOS_EINVAL;
+    if (n > 0 && (!x || !y)) return SOS_EINVAL;
+    if (n > 0 && x != y) {
+        // in place or disjoint only
+        const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, bytes = (uintptr_t)n * 4u;
+        if (xa < ya + bytes && ya < xa + bytes) return SOS_EINVAL;
+    }
+    return SOS_OK;
+}
+
+// Tables for `sections` at the handle's shape and type (caller holds the lock).
+int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream)
+{
+    const Tile t = tile_of(h);
+    const int bits = bits_of(h);
+    int rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes(K > 8 ? K : 8, bits), stream);
+    if (rc) return rc;
+    if (sos_launch_prep(bits, sections, K, __builtin_ctz((unsigned)t.N),
+                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl, 0,
+                        stream) != hipSuccess)
+        return SOS_EHIP;
+    h->prep_K = K;
+    h->prep_L = t.L;
+    h->prep_N = t.N;
+    h->prep_bits = bits;
+    return SOS_OK;
+}
+
+// Filter with the prepared tables (caller holds the lock).
+int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *zi, float *zf,
+                  hipStream_t stream, float *saved)
+{
+    const int K = h->prep_K;
+    if (n == 0) {
+        if (zf && K > 0 && sos_launch_fill(zf, zi, 2 * (int64_t)K, stream) != hipSuccess)
+            return SOS_EHIP;
+        return SOS_OK;
+    }
+    if (K == 0) {
+        if (x != y && sos_launch_fill(y, x, n, stream) != hipSuccess) return SOS_EHIP;
+        return SOS_OK;
+    }
+    const int L = h->prep_L, N = h->prep_N, bits = h->prep_bits;
+    const int64_t C = (int64_t)L * N;
+    const int64_t groups = (n + C - 1) / C;
+    if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
+    const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
+    if (rc) return rc;
+    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    if (sos_launch_fwd(bits, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
+                       h->timeout_ticks, grid_of(bits, L, N), saved, stream) != hipSuccess)
+        return SOS_EHIP;
+    h->last_groups = groups;
+    h->last_K = K;
+    return SOS_OK;
+}
+
+void mark_degenerate(sos_ctx *h, int K)
+{
+    const Tile t = tile_of(h);   // degenerate calls need no tables
+    h->prep_K = K;
+    h->prep_L = t.L;
+    h->prep_N = t.N;
+    h->prep_bits = bits_of(h);
 }
 
 }  // namespace
@@ -218,12 +305,10 @@ int sos_destroy(sos_handle_t h)
     {
         DeviceGuard g(h->device);
         (void)hipDeviceSynchronize();
-        if (h->desc) (void)hipFree(h->desc);
-        if (h->tabs) (void)hipFree(h->tabs);
-        if (h->ctrl) (void)hipFree(h->ctrl);
-        if (h->gpre) (void)hipFree(h->gpre);
-        if (h->sigmap) (void)hipFree(h->sigmap);
-        if (h->total_dev) (void)hipFree(h->total_dev);
+        for (void *p : {(void *)h->desc, (void *)h->tabs, (void *)h->ctrl, (void *)h->gpre,
+                        (void *)h->sigmap, (void *)h->total_dev, (void *)h->tabs_bwd,
+                        (void *)h->partials})
+            if (p) (void)hipFree(p);
     }
     delete h;
     return SOS_OK;
@@ -269,64 +354,17 @@ int sos_get_tile(sos_handle_t h, int *L, int *N)
     return SOS_OK;
 }
 
-static int check_signal(const float *x, float *y, int64_t n)
+int sos_set_precision(sos_handle_t h, int bits)
 {
-    if (n < 0) return SOS_EINVAL;
-    if (n > 0 && (!x || !y)) return SOS_EINVAL;
-    if (n > 0 && x != y) {
-        // in place or disjoint only
-        const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, bytes = (uintptr_t)n * 4u;
-        if (xa < ya + bytes && ya < xa + bytes) return SOS_EINVAL;
-    }
+    if (!h || (bits != 0 && bits != 32 && bits != 64)) return SOS_EINVAL;
+    h->bits = bits;
     return SOS_OK;
 }
 
-// Tables for `sections` at the handle's current tile (caller holds the lock).
-static int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream)
+int sos_get_precision(sos_handle_t h)
 {
-    const Tile t = tile_of(h);
-    int rc = ensure_tabs(h, K, stream);
-    if (rc) return rc;
-    if (sos_launch_prep(sections, K, __builtin_ctz((unsigned)t.N),
-                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl,
-                        stream) != hipSuccess)
-        return SOS_EHIP;
-    h->prep_K = K;
-    h->prep_L = t.L;
-    h->prep_N = t.N;
-    return SOS_OK;
-}
-
-// Filter with the prepared tables (caller holds the lock).
-static int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *zi,
-                         float *zf, hipStream_t stream)
-{
-    const int K = h->prep_K;
-    if (n == 0) {
-        if (zf && K > 0 && sos_launch_fill(zf, zi, 2 * (int64_t)K, stream) != hipSuccess)
-            return SOS_EHIP;
-        return SOS_OK;
-    }
-    if (K == 0) {
-        if (x != y && sos_launch_fill(y, x, n, stream) != hipSuccess) return SOS_EHIP;
-        return SOS_OK;
-    }
-    const int L = h->prep_L, N = h->prep_N;
-    const int64_t C = (int64_t)L * N;
-    const int64_t groups = (n + C - 1) / C;
-    if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
-    const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
-    if (rc) return rc;
-    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    int64_t grid = 0;   // one workgroup per group unless a persistent grid is asked for
-    if (const char *e = std::getenv("SOS_PERSISTENT"))
-        if (std::atoi(e) > 0) grid = (int64_t)std::atoi(e) * sos_fwd_capacity(L, N);
-    if (sos_launch_fwd(L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
-                       h->timeout_ticks, grid, stream) != hipSuccess)
-        return SOS_EHIP;
-    h->last_groups = groups;
-    h->last_K = K;
-    return SOS_OK;
+    if (!h) return SOS_EINVAL;
+    return bits_of(h);
 }
 
 int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream)
@@ -347,10 +385,11 @@ int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, con
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(h->mu);
     const Tile t = tile_of(h);
-    if (h->prep_K < 0 || h->prep_N != t.N || h->prep_L != t.L) return SOS_EINVAL;
+    if (h->prep_K < 0 || h->prep_N != t.N || h->prep_L != t.L || h->prep_bits != bits_of(h))
+        return SOS_EINVAL;
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
-    return filter_locked(h, x, y, n, zi, zf, stream);
+    return filter_locked(h, x, y, n, zi, zf, stream, nullptr);
 }
 
 int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y, int64_t n,
@@ -367,37 +406,35 @@ int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, flo
         rc = prepare_locked(h, sections, K, stream);
         if (rc) return rc;
     } else {
-        const Tile t = tile_of(h);   // degenerate calls need no tables
-        h->prep_K = K;
-        h->prep_L = t.L;
-        h->prep_N = t.N;
+        mark_degenerate(h, K);
     }
-    return filter_locked(h, x, y, n, zi, zf, stream);
+    return filter_locked(h, x, y, n, zi, zf, stream, nullptr);
 }
 
-int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_samples, const int32_t *K,
-                       const int32_t *sec_off, const float *sections, const int64_t *sig_off,
-                       const float *x, float *y, const float *zi, float *zf, hipStream_t stream)
+int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                       int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                       const float *sections, const int64_t *sig_off, const float *x, float *y,
+                       const float *zi, float *zf, hipStream_t stream)
 {
-    if (!h || B < 0 || kmax < 0 || kmax > SOS_MAX_SECTIONS || total_samples < 0)
+    if (!h || B < 0 || kmax < 0 || kmax > SOS_MAX_SECTIONS || total_samples < 0 ||
+        total_rows < 0)
         return SOS_EINVAL;
     if (B == 0) return SOS_OK;
     if (!K || !sec_off || !sig_off) return SOS_EINVAL;
-    if (kmax > 0 && !sections) return SOS_EINVAL;
-    if (total_samples > 0 && (!x || !y)) return SOS_EINVAL;
-    if (total_samples > 0 && x != y) {
-        const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, bytes = (uintptr_t)total_samples * 4u;
-        if (xa < ya + bytes && ya < xa + bytes) return SOS_EINVAL;
-    }
+    if (total_rows > 0 && !sections) return SOS_EINVAL;
+    int rc = check_signal(x, y, total_samples);
+    if (rc) return rc;
     std::lock_guard<std::mutex> lk(h->mu);
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     const Tile t = tile_of(h);
+    const int bits = bits_of(h);
     const int64_t C = (int64_t)t.L * t.N;
     const int64_t max_groups = total_samples / C + B;
-    if (max_groups >= (int64_t)1 << 31) return SOS_EINVAL;
+    if (max_groups >= (int64_t)1 << 31 || total_rows >= (int64_t)1 << 31) return SOS_EINVAL;
     const int kd = kmax > 0 ? kmax : 1;   // descriptor stride
-    int rc = ensure_tabs(h, B * kd, stream);
+    rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes((int)(total_rows > 8 ? total_rows : 8), bits),
+                    stream);
     if (rc) return rc;
     rc = ensure_desc(h, (size_t)max_groups * (size_t)kd * 4u, stream);
     if (rc) return rc;
@@ -408,21 +445,94 @@ int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_samples, c
     if (!h->total_dev && hipMalloc(&h->total_dev, sizeof(int64_t)) != hipSuccess)
         return SOS_ENOMEM;
     const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
-    if (kmax > 0 && sos_launch_prep_batched(sections, B, kmax, K, sec_off, log2n, log2w, h->tabs,
-                                            h->ctrl, stream) != hipSuccess)
+    if (total_rows > 0 &&
+        sos_launch_prep_batched(bits, sections, B, kmax, total_rows, K, sec_off, log2n, log2w,
+                                h->tabs, h->ctrl, stream) != hipSuccess)
         return SOS_EHIP;
-    if (sos_launch_worktable(B, kmax, C, total_samples, max_groups, K, sec_off, sig_off, h->gpre,
-                             h->sigmap, h->total_dev, zi, zf, h->ctrl, stream) != hipSuccess)
+    if (sos_launch_worktable(B, kmax, total_rows, C, total_samples, max_groups, K, sec_off,
+                             sig_off, h->gpre, h->sigmap, h->total_dev, zi, zf, h->ctrl,
+                             stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    int64_t grid = sos_fwd_capacity(t.L, t.N);
-    if (grid > max_groups) grid = max_groups;
-    if (grid < 1) grid = 1;
-    if (sos_launch_fwd_batched(t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre, h->sigmap,
+    int64_t grid = grid_of(bits, t.L, t.N);
+    if (grid <= 0 || grid > max_groups) grid = max_groups;
+    if (sos_launch_fwd_batched(bits, t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre, h->sigmap,
                                h->total_dev, x, y, h->tabs, zi, zf, h->desc, h->ctrl,
                                h->timeout_ticks, grid, stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = -1;        // the batch overwrote the plain tables
+    h->last_groups = 0;
+    h->last_K = 0;
+    return SOS_OK;
+}
+
+int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *x, float *y,
+                     int64_t n, const float *zi, float *zf, float *saved, hipStream_t stream)
+{
+    if (!h || K < 0 || K > SOS_MAX_SECTIONS) return SOS_EINVAL;
+    if (K > 0 && !sections) return SOS_EINVAL;
+    if (K > 1 && n > 0 && !saved) return SOS_EINVAL;
+    if (n > 0 && x == y) return SOS_EINVAL;   // the adjoint needs the forward input
+    int rc = check_signal(x, y, n);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    if (n > 0 && K > 0) {
+        rc = prepare_locked(h, sections, K, stream);
+        if (rc) return rc;
+    } else {
+        mark_degenerate(h, K);
+    }
+    return filter_locked(h, x, y, n, zi, zf, stream, K > 1 ? saved : nullptr);
+}
+
+int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x, const float *y,
+                   const float *saved, int64_t n, const float *gy, const float *gzf, float *gx,
+                   float *gzi, float *gsections, hipStream_t stream)
+{
+    if (!h || K < 0 || K > SOS_MAX_SECTIONS || n < 0) return SOS_EINVAL;
+    if (K > 0 && !sections) return SOS_EINVAL;
+    if (n > 0 && (!x || !y || !gy || !gx)) return SOS_EINVAL;
+    if (K > 1 && n > 0 && !saved) return SOS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    if (K == 0) {
+        if (n > 0 && gx != gy && sos_launch_fill(gx, gy, n, stream) != hipSuccess)
+            return SOS_EHIP;
+        return SOS_OK;
+    }
+    if (n == 0) {
+        // zf = zi: the adjoint of zi is gzf; no samples, no coefficient gradient
+        if (gzi && sos_launch_fill(gzi, gzf, 2 * (int64_t)K, stream) != hipSuccess) return SOS_EHIP;
+        if (gsections && sos_launch_fill(gsections, nullptr, 6 * (int64_t)K, stream) != hipSuccess)
+            return SOS_EHIP;
+        return SOS_OK;
+    }
+    Tile t = tile_of(h);
+    if (!sos_bwd_shape_supported(t.L, t.N)) t = Tile{256, 32};
+    const int bits = bits_of(h);
+    const int64_t C = (int64_t)t.L * t.N;
+    const int64_t groups = (n + C - 1) / C;
+    if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
+    int rc = ensure_buf(h->tabs_bwd, h->tabs_bwd_cap, tab_bytes(K, bits), stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->partials, h->partials_cap, (size_t)groups * K * 5, stream);
+    if (rc) return rc;
+    rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
+    if (rc) return rc;
+    if (sos_launch_prep(bits, sections, K, __builtin_ctz((unsigned)t.N),
+                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs_bwd, h->ctrl, 1,
+                        stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    if (sos_launch_bwd(bits, t.L, t.N, gy, gx, n, groups, h->tabs_bwd, K, x, y, saved, gzf, gzi,
+                       h->partials, h->desc, h->ctrl, h->timeout_ticks, 0, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (gsections &&
+        sos_launch_bwd_reduce(h->partials, groups, K, sections, gsections, stream) != hipSuccess)
+        return SOS_EHIP;
     h->last_groups = 0;
     h->last_K = 0;
     return SOS_OK;

@@ -15,19 +15,20 @@ namespace {
 
 constexpr int kScanThreads = 1024;
 
-__device__ inline bool signal_ok(int i, int B, int kmax, int64_t total_samples,
+__device__ inline bool signal_ok(int i, int kmax, int64_t rows, int64_t total_samples,
                                  const int32_t *Ks, const int32_t *sec_off,
                                  const int64_t *sig_off)
 {
     const int K = Ks[i];
     const int64_t so = sec_off[i], a = sig_off[i], b = sig_off[i + 1];
-    return K >= 0 && K <= kmax && so >= 0 && so + K <= (int64_t)B * kmax && a >= 0 && b >= a &&
+    return K >= 0 && K <= kmax && so >= 0 && so + K <= rows && a >= 0 && b >= a &&
            b <= total_samples;
 }
 
 // One block of kScanThreads threads: group counts and their exclusive prefix.
 __global__ void __launch_bounds__(kScanThreads)
-worktable_scan_kernel(int B, int kmax, int64_t C, int64_t total_samples, int64_t max_groups,
+worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
+                      int64_t max_groups,
                       const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                       int64_t *gpre, int64_t *total_dev, unsigned *ctrl)
 {
@@ -40,7 +41,7 @@ worktable_scan_kernel(int B, int kmax, int64_t C, int64_t total_samples, int64_t
         const int i = base + tid;
         int64_t gi = 0;
         if (i < B) {
-            if (signal_ok(i, B, kmax, total_samples, Ks, sec_off, sig_off)) {
+            if (signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off)) {
                 const int64_t n = sig_off[i + 1] - sig_off[i];
                 gi = (n + C - 1) / C;
             } else {
@@ -93,15 +94,17 @@ worktable_fill_kernel(int B, const int64_t *gpre, const int64_t *total_dev, int3
 
 }  // namespace
 
-extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t C, int64_t total_samples,
+extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C,
+                                           int64_t total_samples,
                                            int64_t max_groups, const int32_t *Ks,
                                            const int32_t *sec_off, const int64_t *sig_off,
                                            int64_t *gpre, int32_t *sigmap, int64_t *total_dev,
                                            const float *zi, float *zf, unsigned *ctrl,
                                            hipStream_t stream)
 {
-    hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax, C,
-                       total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev, ctrl);
+    hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax,
+                       rows, C, total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev,
+                       ctrl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (B > 0)

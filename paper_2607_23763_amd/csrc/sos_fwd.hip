@@ -1,4 +1,4 @@
-// Single-kernel multi-block cascade filter for gfx950.
+// Single-kernel multi-block cascade filter for gfx950, and its adjoint.
 //
 // Mapping (Zhai & Paris Part II, Sec. IV-A): one workgroup of W wavefronts
 // owns one group of C = L*N samples, L = 64*W lanes; lane l holds the N
@@ -15,20 +15,24 @@
 //      r_{i+1}[n] = r_i[n] - e_i r_i[n-2^i] + f_i r_i[n-2^{i+1}] on the
 //      positions that stay (odd chain n = -1, even chain n = -2 mod 2^{i+1}),
 //      which exposes the lane's zero-state terminal pair y[N-2], y[N-1];
-//   3. that pair becomes the lane's zero-state terminal TDF-II state; a
-//      Kogge-Stone scan over the wave's 64 lanes (constant matrices
-//      T^(N 2^k)) gives every lane's zero-state state and the wave's total,
-//      and the W wave totals are combined through LDS (one barrier) into
-//      every wave's zero-state incoming state and the group's local carry;
+//   3. that pair becomes the lane's zero-state terminal state; a scan over the
+//      wave's 64 lanes (DPP row shifts and row broadcasts with powers of the
+//      state map) gives every lane's zero-state state and the wave's total,
+//      and the W wave totals are combined through LDS (one barrier) into every
+//      wave's zero-state incoming state and the group's local carry;
 //   4. decoupled lookback (last wave): publish the local carry, walk the
-//      predecessors' descriptors (64 per round, one per lane) until a
-//      resolved carry is found, compose through T^(C j), publish this group's
-//      resolved carry and hand the group state to all waves (second barrier);
+//      predecessors' descriptors (64 per round, one per lane) until a resolved
+//      carry is found, compose through T^(C j), publish this group's resolved
+//      carry and hand the group state to all waves (second barrier);
 //   5. each lane's true incoming state = T^(N l) (T^(64 N w) s_group + wave
 //      prefix) + lane prefix; back substitution level by level, the single
 //      initial-condition row per level and parity receiving g[n] s1 +
 //      g[n-1] s2 (no divisions).
 // The section output stays in registers as the next section's input.
+//
+// Compute type T: float, or double for lightly damped / high-order cascades
+// (MI355X issues FP64 FMAs at the same rate as unpacked FP32 FMAs; the cost
+// is registers). Data in HBM, LDS staging and descriptor values are FP32.
 //
 // Descriptors: per (group, section) four 64-bit words {agg.z1, agg.z2,
 // inc.z1, inc.z2}, each {float value | 32-bit epoch tag}. A word is valid when
@@ -47,7 +51,7 @@ struct FwdArgs {
     const float *x;
     float *y;
     int64_t n;
-    const float *tabs;
+    const void *tabs;       // K x TAB_FLOATS entries of the compute type
     const float *zi;
     float *zf;
     int K;                  // plain: sections; batched: descriptor stride (max sections)
@@ -60,6 +64,7 @@ struct FwdArgs {
     const int32_t *sigmap;  // ticket -> signal
     const int64_t *total_dev;  // number of work items (batched)
     // both modes
+    float *saved;           // plain mode, optional: outputs of sections 0..K-2 ((K-1) x n)
     int64_t total;          // number of work items (plain)
     unsigned long long *desc;
     unsigned *ctrl;
@@ -67,25 +72,21 @@ struct FwdArgs {
 };
 
 // One unit of work: group g of one signal, drawn as ticket t.
+template <typename T>
 struct Item {
     const float *x;
     float *y;
     int64_t n;              // samples in the signal
     int64_t g;              // group index within the signal
     int64_t t;              // ticket (descriptor row)
-    const float *tabs;      // tables of the signal's sections
+    const T *tabs;          // tables of the signal's sections
     const float *zi;
     float *zf;
     int K;
 };
 
-// DPP move of a 32-bit value across lanes; lanes whose source is outside the
-// row (or whose row is masked off by ROWS) read 0.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp0(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
-}
+// ----------------------------------------------------------------- lane ops
+
 enum : int {
     DPP_ROW_SHR = 0x110,    // + d, d = 1..15: lane l reads l-d inside its 16-lane row
     DPP_WAVE_SHR1 = 0x138,  // lane l reads l-1 across the whole wave
@@ -93,49 +94,113 @@ enum : int {
     DPP_BCAST31 = 0x143     // lane 31 -> every lane of rows 2 and 3
 };
 
-// Inclusive affine scan over the 64 lanes of a wave:
-//   P[l] = t[l] + T^N P[l-1]   (P[-1] = 0),
-// the cross-lane terminal-state recurrence (role of Eq. (13)). Within each
-// 16-lane row a Kogge-Stone ladder with the uniform powers T^(N 2^k), k < 4;
-// then rows 1 and 3 add lane 15 / 47 through T^(N((l%16)+1)) and rows 2 and 3
-// add lane 31 through T^(N(l-31)) (per-lane powers from the table).
-__device__ __forceinline__ void wave_scan(float &p1, float &p2, ctab_t *tab, const float *tabv,
-                                          int lane)
+// DPP move across lanes; lanes whose source is outside the row (or whose row
+// is masked off by ROWS) read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp0(float v)
 {
-#define SOS_ROW_STEP(K)                                                                     \
-    {                                                                                       \
-        const float q1 = dpp0<DPP_ROW_SHR + (1 << K), 0xF>(p1);                             \
-        const float q2 = dpp0<DPP_ROW_SHR + (1 << K), 0xF>(p2);                             \
-        const float n1 = fmaf(tab[OFF_KS + 4 * K + 0], q1, fmaf(tab[OFF_KS + 4 * K + 1], q2, p1)); \
-        const float n2 = fmaf(tab[OFF_KS + 4 * K + 2], q1, fmaf(tab[OFF_KS + 4 * K + 3], q2, p2)); \
-        p1 = n1;                                                                            \
-        p2 = n2;                                                                            \
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp0(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float readlane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
+// A per-lane 2x2 matrix (4 consecutive entries of the compute type).
+template <typename T>
+struct M2 {
+    T a, b, c, d;
+};
+__device__ __forceinline__ M2<float> load_m2(const float *p)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    return {v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ M2<double> load_m2(const double *p)
+{
+    const double2 u = *reinterpret_cast<const double2 *>(p);
+    const double2 v = *reinterpret_cast<const double2 *>(p + 2);
+    return {u.x, u.y, v.x, v.y};
+}
+
+// Read-only constant-space view of a table of the compute type (uniform
+// indexes become scalar loads).
+template <typename T>
+using ctabT = const __attribute__((address_space(4))) T;
+template <typename T>
+__device__ __forceinline__ ctabT<T> *ctabp(const T *p) { return (ctabT<T> *)p; }
+
+// 2x2 (row-major, 4 entries at p) times vector, plus addend.
+template <typename T>
+__device__ __forceinline__ void mv_add(ctabT<T> *p, T v1, T v2, T &o1, T &o2)
+{
+    const T n1 = fmaT(p[0], v1, fmaT(p[1], v2, o1));
+    const T n2 = fmaT(p[2], v1, fmaT(p[3], v2, o2));
+    o1 = n1;
+    o2 = n2;
+}
+
+// Inclusive affine scan over the 64 lanes of a wave:
+//   P[l] = t[l] + S P[l-1]   (P[-1] = 0),  S = the state map across one lane,
+// the cross-lane terminal-state recurrence (role of Eq. (13)). Within each
+// 16-lane row a Kogge-Stone ladder with the uniform powers S^(2^k), k < 4;
+// then rows 1 and 3 add lane 15 / 47 through S^((l%16)+1) and rows 2 and 3
+// add lane 31 through S^(l-31) (per-lane powers from the table).
+template <typename T>
+__device__ __forceinline__ void wave_scan(T &p1, T &p2, const T *tabv, int lane)
+{
+    ctabT<T> *tab = ctabp(tabv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T q1, q2;
+        switch (k) {
+        case 0: q1 = dpp0<DPP_ROW_SHR + 1, 0xF>(p1); q2 = dpp0<DPP_ROW_SHR + 1, 0xF>(p2); break;
+        case 1: q1 = dpp0<DPP_ROW_SHR + 2, 0xF>(p1); q2 = dpp0<DPP_ROW_SHR + 2, 0xF>(p2); break;
+        case 2: q1 = dpp0<DPP_ROW_SHR + 4, 0xF>(p1); q2 = dpp0<DPP_ROW_SHR + 4, 0xF>(p2); break;
+        default: q1 = dpp0<DPP_ROW_SHR + 8, 0xF>(p1); q2 = dpp0<DPP_ROW_SHR + 8, 0xF>(p2); break;
+        }
+        mv_add<T>(tab + OFF_KS + 4 * k, q1, q2, p1, p2);
     }
-    SOS_ROW_STEP(0)
-    SOS_ROW_STEP(1)
-    SOS_ROW_STEP(2)
-    SOS_ROW_STEP(3)
-#undef SOS_ROW_STEP
-    const float4 pa = *reinterpret_cast<const float4 *>(tabv + OFF_SCANPOW + 8 * lane);
-    const float4 pb = *reinterpret_cast<const float4 *>(tabv + OFF_SCANPOW + 8 * lane + 4);
+    const M2<T> pa = load_m2(tabv + OFF_SCANPOW + 8 * lane);
+    const M2<T> pb = load_m2(tabv + OFF_SCANPOW + 8 * lane + 4);
     {
-        const float q1 = dpp0<DPP_BCAST15, 0xA>(p1), q2 = dpp0<DPP_BCAST15, 0xA>(p2);
-        const float n1 = fmaf(pa.x, q1, fmaf(pa.y, q2, p1));
-        const float n2 = fmaf(pa.z, q1, fmaf(pa.w, q2, p2));
+        const T q1 = dpp0<DPP_BCAST15, 0xA>(p1), q2 = dpp0<DPP_BCAST15, 0xA>(p2);
+        const T n1 = fmaT(pa.a, q1, fmaT(pa.b, q2, p1));
+        const T n2 = fmaT(pa.c, q1, fmaT(pa.d, q2, p2));
         p1 = n1;
         p2 = n2;
     }
     {
-        const float q1 = dpp0<DPP_BCAST31, 0xC>(p1), q2 = dpp0<DPP_BCAST31, 0xC>(p2);
-        const float n1 = fmaf(pb.x, q1, fmaf(pb.y, q2, p1));
-        const float n2 = fmaf(pb.z, q1, fmaf(pb.w, q2, p2));
+        const T q1 = dpp0<DPP_BCAST31, 0xC>(p1), q2 = dpp0<DPP_BCAST31, 0xC>(p2);
+        const T n1 = fmaT(pb.a, q1, fmaT(pb.b, q2, p1));
+        const T n2 = fmaT(pb.c, q1, fmaT(pb.d, q2, p2));
         p1 = n1;
         p2 = n2;
     }
 }
 
 // Sum over the 64 lanes of a wave (result valid in every lane).
-__device__ __forceinline__ float wave_sum(float v)
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
 {
     v += dpp0<DPP_ROW_SHR + 1, 0xF>(v);
     v += dpp0<DPP_ROW_SHR + 2, 0xF>(v);
@@ -143,8 +208,10 @@ __device__ __forceinline__ float wave_sum(float v)
     v += dpp0<DPP_ROW_SHR + 8, 0xF>(v);
     v += dpp0<DPP_BCAST15, 0xA>(v);
     v += dpp0<DPP_BCAST31, 0xC>(v);
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    return readlane(v, 63);
 }
+
+// ------------------------------------------------------------- descriptors
 
 __device__ __forceinline__ unsigned long long pack(float v, unsigned tag)
 {
@@ -161,44 +228,40 @@ __device__ __forceinline__ unsigned long long load_word(const unsigned long long
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Lane `zl` reads samples zp and zp-1 of its row after the whole wave has
-// written its registers to its LDS rows (only the wave holding sample n-1
-// does this, once per section; LDS operations of one wave complete in order).
-template <int N>
-__device__ __forceinline__ void pick_two(const float (&u)[N], float *tl, int lane, int zl, int zp,
-                                         float &v0, float &v1)
+// Lane `zl` (only) writes its N registers to scratch LDS and reads back
+// positions zp and zp-1 (0 if zp == 0). tl must hold 2N floats.
+template <typename T, int N>
+__device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, int zl, int zp,
+                                         T &v0, T &v1)
 {
-    constexpr int RS = N + 4;
+    T *sc = reinterpret_cast<T *>(tl);
+    if (lane == zl) {
 #pragma unroll
-    for (int k = 0; k < N / 4; ++k)
-        *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
-            make_float4(u[4 * k + 0], u[4 * k + 1], u[4 * k + 2], u[4 * k + 3]);
+        for (int k = 0; k < N; ++k) sc[k] = u[k];
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    v0 = tl[zl * RS + zp];
-    v1 = zp >= 1 ? tl[zl * RS + zp - 1] : 0.0f;
+    if (lane == zl) {
+        v0 = sc[zp];
+        v1 = zp >= 1 ? sc[zp - 1] : T(0);
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// 2x2 (row-major, 4 floats at p) times vector, plus addend.
-__device__ __forceinline__ float2 mv_add(ctab_t *p, float v1, float v2, float a1, float a2)
+// Resolve the incoming state of group it.g (> 0) of a signal for section s by
+// decoupled lookback; executed by one whole wave. Returns wave-uniform values.
+// On timeout returns NaNs and sets the error bit (the caller still publishes,
+// so successors terminate).
+template <typename T>
+__device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int s,
+                         unsigned epoch, int lane, T &r1, T &r2)
 {
-    return make_float2(fmaf(p[0], v1, fmaf(p[1], v2, a1)), fmaf(p[2], v1, fmaf(p[3], v2, a2)));
-}
-
-// Resolve the incoming state of group c (> 0) for section s by decoupled
-// lookback; executed by one whole wave. Returns a wave-uniform pair. On
-// timeout returns NaNs and sets the error bit (the caller still publishes, so
-// successors terminate).
-__device__ float2 lookback(const FwdArgs &a, const Item &it, const float *tabv, int s,
-                           unsigned epoch, int lane)
-{
-    ctab_t *tab = ctab(tabv);
-    const float4 gp = *reinterpret_cast<const float4 *>(tabv + OFF_GRPPOW + 4 * lane);
-    const float w00 = tab[OFF_TW + 0], w01 = tab[OFF_TW + 1];
-    const float w10 = tab[OFF_TW + 2], w11 = tab[OFF_TW + 3];
-    float acc1 = 0.0f, acc2 = 0.0f;
-    float m00 = 1.0f, m01 = 0.0f, m10 = 0.0f, m11 = 1.0f;   // window transform
-    const int64_t first = it.t - it.g;   // ticket of the signal's first group
+    ctabT<T> *tab = ctabp(tabv);
+    const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);
+    const T w00 = tab[OFF_TW + 0], w01 = tab[OFF_TW + 1];
+    const T w10 = tab[OFF_TW + 2], w11 = tab[OFF_TW + 3];
+    T acc1 = 0, acc2 = 0;
+    T m00 = 1, m01 = 0, m10 = 0, m11 = 1;   // window transform
+    const int64_t first = it.t - it.g;      // ticket of the signal's first group
     int64_t base = it.t - 1;
     const unsigned long long t0 = wall_clock64();
     while (true) {
@@ -225,12 +288,13 @@ __device__ float2 lookback(const FwdArgs &a, const Item &it, const float *tabv, 
         if ((rdym & need) != need) {
             if (wall_clock64() - t0 > a.timeout_ticks) {
                 if (lane == 0) atomicOr(&a.ctrl[CTRL_ERR], ERRBIT_TIMEOUT);
-                return make_float2(__builtin_nanf(""), __builtin_nanf(""));
+                r1 = r2 = T(__builtin_nanf(""));
+                return;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        float v1 = 0.0f, v2 = 0.0f;
+        T v1 = 0, v2 = 0;
         if (lane < jstar) {
             v1 = __uint_as_float((unsigned)w[0]);
             v2 = __uint_as_float((unsigned)w[1]);
@@ -238,51 +302,59 @@ __device__ float2 lookback(const FwdArgs &a, const Item &it, const float *tabv, 
             v1 = __uint_as_float((unsigned)w[2]);
             v2 = __uint_as_float((unsigned)w[3]);
         }
-        const float s1 = wave_sum(gp.x * v1 + gp.y * v2);
-        const float s2 = wave_sum(gp.z * v1 + gp.w * v2);
+        const T s1 = wave_sum<T>(gp.a * v1 + gp.b * v2);
+        const T s2 = wave_sum<T>(gp.c * v1 + gp.d * v2);
         acc1 += m00 * s1 + m01 * s2;
         acc2 += m10 * s1 + m11 * s2;
         if (jstar < 64) break;
         // slide the window 64 groups further back
-        const float n00 = m00 * w00 + m01 * w10, n01 = m00 * w01 + m01 * w11;
-        const float n10 = m10 * w00 + m11 * w10, n11 = m10 * w01 + m11 * w11;
+        const T n00 = m00 * w00 + m01 * w10, n01 = m00 * w01 + m01 * w11;
+        const T n10 = m10 * w00 + m11 * w10, n11 = m10 * w01 + m11 * w11;
         m00 = n00; m01 = n01; m10 = n10; m11 = n11;
         base -= 64;
     }
-    return make_float2(acc1, acc2);
+    r1 = acc1;
+    r2 = acc2;
 }
 
 // Exchange area of one workgroup in LDS.
-template <int W>
+template <typename T, int W>
 struct Xch {
-    float wave_tot[W][2];   // zero-state totals of the waves
-    float grp[2];           // resolved incoming state of the group
+    T wave_tot[W][2];   // zero-state totals of the waves
+    T grp[2];           // resolved incoming state of the group
 };
 
-template <int N, int W>
-__device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *tl,
-                                            const FwdArgs &a, const Item &it, const float *tabv,
+// ------------------------------------------------------------- one section
+
+// One section of the cascade on the group held by the workgroup.
+// PAIR = false: the forward filter; carries are TDF-II states.
+// PAIR = true: a pure recursive section 1/A(z) (the adjoint's reversed-time
+//   pass); carries are the last two outputs (y[-2], y[-1]), and the tables hold
+//   the matching state map. On return (q1, q2) is the lane's incoming carry.
+template <typename T, int N, int W, bool PAIR>
+__device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl,
+                                            const FwdArgs &a, const Item<T> &it, const T *tabv,
                                             int s, unsigned epoch, int wv, int lane, bool has_last,
-                                            int zl, int zp)
+                                            int zl, int zp, T &q1, T &q2)
 {
     constexpr int LOG = __builtin_ctz(N);
-    ctab_t *tab = ctab(tabv);
+    ctabT<T> *tab = ctabp(tabv);
 
     // --- inputs kept for the terminal state (and for zf at sample n-1)
-    const float xl1 = u[N - 1], xl2 = u[N - 2];
-    float zx1 = 0.0f, zx2 = 0.0f;
-    if (has_last) pick_two(u, tl, lane, zl, zp, zx1, zx2);
+    const T xl1 = u[N - 1], xl2 = u[N - 2];
+    T zx1 = 0, zx2 = 0;
+    if (!PAIR && has_last) pick_two<T, N>(u, tl, lane, zl, zp, zx1, zx2);
 
     // --- 1. level-1 right-hand side, in place from the end
-    const float c0 = tab[OFF_TAPS + 0], c1 = tab[OFF_TAPS + 1], c2 = tab[OFF_TAPS + 2];
-    const float c3 = tab[OFF_TAPS + 3], c4 = tab[OFF_TAPS + 4];
+    const T c0 = tab[OFF_TAPS + 0], c1 = tab[OFF_TAPS + 1], c2 = tab[OFF_TAPS + 2];
+    const T c3 = tab[OFF_TAPS + 3], c4 = tab[OFF_TAPS + 4];
 #pragma unroll
     for (int m = N - 1; m >= 0; --m) {
-        float r = c0 * u[m];
-        if (m >= 1) r = fmaf(c1, u[m - 1], r);
-        if (m >= 2) r = fmaf(c2, u[m - 2], r);
-        if (m >= 3) r = fmaf(c3, u[m - 3], r);
-        if (m >= 4) r = fmaf(c4, u[m - 4], r);
+        T r = c0 * u[m];
+        if (m >= 1) r = fmaT(c1, u[m - 1], r);
+        if (m >= 2) r = fmaT(c2, u[m - 2], r);
+        if (m >= 3) r = fmaT(c3, u[m - 3], r);
+        if (m >= 4) r = fmaT(c4, u[m - 4], r);
         u[m] = r;
     }
 
@@ -290,26 +362,32 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
 #pragma unroll
     for (int i = 1; i < LOG; ++i) {
         const int st = 1 << i;
-        const float e = tab[OFF_E + i], f = tab[OFF_F + i];
+        const T e = tab[OFF_E + i], f = tab[OFF_F + i];
 #pragma unroll
         for (int m = N - 1; m >= 0; --m) {
             if (((m + 1) % (2 * st)) == 0 || ((m + 2) % (2 * st)) == 0) {
-                float r = u[m];
-                if (m - st >= 0) r = fmaf(-e, u[m - st], r);
-                if (m - 2 * st >= 0) r = fmaf(f, u[m - 2 * st], r);
+                T r = u[m];
+                if (m - st >= 0) r = fmaT(-e, u[m - st], r);
+                if (m - 2 * st >= 0) r = fmaT(f, u[m - 2 * st], r);
                 u[m] = r;
             }
         }
     }
 
-    // --- 3. zero-state terminal TDF-II state of the lane, scan over the wave
-    const float b1 = tab[OFF_B1], b2 = tab[OFF_B2], a1 = tab[OFF_A1], a2 = tab[OFF_A2];
-    float p1 = b1 * xl1 + b2 * xl2 - a1 * u[N - 1] - a2 * u[N - 2];
-    float p2 = b2 * xl1 - a2 * u[N - 1];
-    wave_scan(p1, p2, tab, tabv, lane);
+    // --- 3. zero-state terminal state of the lane, scan over the wave
+    const T b1 = tab[OFF_B1], b2 = tab[OFF_B2], a1 = tab[OFF_A1], a2 = tab[OFF_A2];
+    T p1, p2;
+    if (PAIR) {
+        p1 = u[N - 2];
+        p2 = u[N - 1];
+    } else {
+        p1 = b1 * xl1 + b2 * xl2 - a1 * u[N - 1] - a2 * u[N - 2];
+        p2 = b2 * xl1 - a2 * u[N - 1];
+    }
+    wave_scan<T>(p1, p2, tabv, lane);
 
     //     ... and over the W waves of the group (zero group state)
-    float e1w = 0.0f, e2w = 0.0f;      // zero-state incoming state of this wave
+    T e1w = 0, e2w = 0;      // zero-state incoming state of this wave
     if (W > 1) {
         if (lane == 63) {
             xch.wave_tot[wv][0] = p1;
@@ -317,92 +395,119 @@ __device__ __forceinline__ void run_section(float (&u)[N], Xch<W> &xch, float *t
         }
         __syncthreads();
         for (int v = 0; v < wv; ++v) {
-            const float2 r = mv_add(tab + OFF_TWAVE, e1w, e2w, xch.wave_tot[v][0],
-                                    xch.wave_tot[v][1]);
-            e1w = r.x;
-            e2w = r.y;
+            T o1 = xch.wave_tot[v][0], o2 = xch.wave_tot[v][1];
+            mv_add<T>(tab + OFF_TWAVE, e1w, e2w, o1, o2);
+            e1w = o1;
+            e2w = o2;
         }
     }
     if (wv == W - 1) {
         // group local carry = state after the last wave at zero group state
-        const float t1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p1), 63));
-        const float t2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p2), 63));
-        float g1 = t1, g2 = t2;
-        if (W > 1) {
-            const float2 r = mv_add(tab + OFF_TWAVE, e1w, e2w, t1, t2);
-            g1 = r.x;
-            g2 = r.y;
-        }
+        T g1 = readlane(p1, 63), g2 = readlane(p2, 63);
+        if (W > 1) mv_add<T>(tab + OFF_TWAVE, e1w, e2w, g1, g2);
 
         // --- 4. decoupled lookback for the group's incoming state
         unsigned long long *dsc = a.desc + ((size_t)it.t * a.K + s) * 4;
-        float sg1, sg2;
+        T sg1, sg2;
         if (it.g == 0) {
-            sg1 = it.zi ? ctab(it.zi)[2 * s] : 0.0f;
-            sg2 = it.zi ? ctab(it.zi)[2 * s + 1] : 0.0f;
+            // PAIR: the initial carry arrives as (y[-1], y[-2]) (the adjoint of zf)
+            sg1 = it.zi ? T(ctab(it.zi)[2 * s + (PAIR ? 1 : 0)]) : T(0);
+            sg2 = it.zi ? T(ctab(it.zi)[2 * s + (PAIR ? 0 : 1)]) : T(0);
         } else {
             if (lane == 0) {
-                store_word(dsc + 0, pack(g1, epoch));
-                store_word(dsc + 1, pack(g2, epoch));
+                store_word(dsc + 0, pack((float)g1, epoch));
+                store_word(dsc + 1, pack((float)g2, epoch));
             }
-            const float2 sg = lookback(a, it, tabv, s, epoch, lane);
-            sg1 = sg.x;
-            sg2 = sg.y;
+            lookback<T>(a, it, tabv, s, epoch, lane, sg1, sg2);
         }
-        const float2 inc = mv_add(tab + OFF_TC, sg1, sg2, g1, g2);
+        T i1 = g1, i2 = g2;
+        mv_add<T>(tab + OFF_TC, sg1, sg2, i1, i2);
         if (lane == 0) {
-            store_word(dsc + 2, pack(inc.x, epoch));
-            store_word(dsc + 3, pack(inc.y, epoch));
+            store_word(dsc + 2, pack((float)i1, epoch));
+            store_word(dsc + 3, pack((float)i2, epoch));
             xch.grp[0] = sg1;
             xch.grp[1] = sg2;
         }
     }
     __syncthreads();
-    const float sg1 = xch.grp[0], sg2 = xch.grp[1];
+    const T sg1 = xch.grp[0], sg2 = xch.grp[1];
 
     // --- 5. incoming state of every lane, then back substitution
-    const float2 sw = mv_add(tab + OFF_WPOW + 4 * wv, sg1, sg2, e1w, e2w);
-    const float4 lp = *reinterpret_cast<const float4 *>(tabv + OFF_LANEPOW + 4 * lane);
-    const float e1 = dpp0<DPP_WAVE_SHR1, 0xF>(p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(p2);
-    const float s1 = fmaf(lp.x, sw.x, fmaf(lp.y, sw.y, e1));
-    const float s2 = fmaf(lp.z, sw.x, fmaf(lp.w, sw.y, e2));
-    ctab_t *g = tab + OFF_G + 1;   // g[-1] is readable and 0
+    T sw1 = e1w, sw2 = e2w;
+    mv_add<T>(tab + OFF_WPOW + 4 * wv, sg1, sg2, sw1, sw2);
+    const M2<T> lp = load_m2(tabv + OFF_LANEPOW + 4 * lane);
+    const T e1 = dpp0<DPP_WAVE_SHR1, 0xF>(p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(p2);
+    q1 = fmaT(lp.a, sw1, fmaT(lp.b, sw2, e1));
+    q2 = fmaT(lp.c, sw1, fmaT(lp.d, sw2, e2));
+    // TDF-II injection (s1, s2) of the lane's incoming carry
+    const T s1 = PAIR ? -(a1 * q2 + a2 * q1) : q1;
+    const T s2 = PAIR ? -a2 * q2 : q2;
+    ctabT<T> *g = tab + OFF_G + 1;   // g[-1] is readable and 0
 
-    u[N - 1] = fmaf(g[N - 1], s1, fmaf(g[N - 2], s2, u[N - 1]));
-    u[N - 2] = fmaf(g[N - 2], s1, fmaf(g[N - 3], s2, u[N - 2]));
+    u[N - 1] = fmaT(g[N - 1], s1, fmaT(g[N - 2], s2, u[N - 1]));
+    u[N - 2] = fmaT(g[N - 2], s1, fmaT(g[N - 3], s2, u[N - 2]));
 #pragma unroll
     for (int i = LOG - 1; i >= 1; --i) {
         const int st = 1 << i;
-        const float e = tab[OFF_E + i], f = tab[OFF_F + i];
+        const T e = tab[OFF_E + i], f = tab[OFF_F + i];
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
             const int m0 = st - 1 - par;                 // odd chain, then even chain
-            u[m0] = fmaf(g[m0], s1, fmaf(g[m0 - 1], s2, u[m0]));
+            u[m0] = fmaT(g[m0], s1, fmaT(g[m0 - 1], s2, u[m0]));
 #pragma unroll
             for (int m = m0 + 2 * st; m < N; m += 2 * st)
-                u[m] = fmaf(-e, u[m - st], fmaf(-f, u[m - 2 * st], u[m]));
+                u[m] = fmaT(-e, u[m - st], fmaT(-f, u[m - 2 * st], u[m]));
         }
     }
 
     // --- final state after sample n-1 (only the lane that holds it)
-    if (has_last && it.zf) {
-        float yo1, yo2;
-        pick_two(u, tl, lane, zl, zp, yo1, yo2);
+    if (!PAIR && has_last && it.zf) {
+        T yo1 = 0, yo2 = 0;
+        pick_two<T, N>(u, tl, lane, zl, zp, yo1, yo2);
         if (lane == zl) {
-            float z1;
+            T z1;
             if (zp >= 1)
                 z1 = b1 * zx1 + b2 * zx2 - a1 * yo1 - a2 * yo2;
             else
                 z1 = b1 * zx1 - a1 * yo1 + s2;   // s2: this lane's incoming state
-            it.zf[2 * s] = z1;
-            it.zf[2 * s + 1] = b2 * zx1 - a2 * yo1;
+            it.zf[2 * s] = (float)z1;
+            it.zf[2 * s + 1] = (float)(b2 * zx1 - a2 * yo1);
         }
     }
 }
 
-template <int N, int W>
-__device__ __forceinline__ void process_group(const FwdArgs &a, const Item &it, float *tl,
-                                              Xch<W> &xch, unsigned epoch, int wv, int lane)
+// Write the wave's registers (lane rows) to dst[g0 .. g0 + 64N) through the
+// wave's LDS rows with coalesced stores, masked at the signal end n.
+template <typename T, int N>
+__device__ __forceinline__ void store_rows(const T (&u)[N], float *tl, int lane, int64_t n,
+                                           int64_t g0, float *dst)
+{
+    constexpr int RS = N + 4, Q = N / 4;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
+            make_float4((float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
+                        (float)u[4 * k + 3]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int64_t rem = n - g0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        const int v = kLanes * j + lane;
+        const float4 val = *reinterpret_cast<const float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]);
+        const int64_t q = 4 * (int64_t)v;
+        if (q + 0 < rem) dst[g0 + q + 0] = val.x;
+        if (q + 1 < rem) dst[g0 + q + 1] = val.y;
+        if (q + 2 < rem) dst[g0 + q + 2] = val.z;
+        if (q + 3 < rem) dst[g0 + q + 3] = val.w;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// --------------------------------------------------------- forward kernel
+
+template <typename T, int N, int W>
+__device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &it, float *tl,
+                                              Xch<T, W> &xch, unsigned epoch, int wv, int lane)
 {
     constexpr int CW = kLanes * N;   // samples per wave
     constexpr int C = CW * W;        // samples per group
@@ -433,7 +538,7 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item &it, 
         *reinterpret_cast<float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]) = val;
     }
     __syncthreads();
-    float u[N];
+    T u[N];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         const float4 v = *reinterpret_cast<const float4 *>(&tl[lane * RS + 4 * k]);
@@ -446,18 +551,23 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item &it, 
     // --- sections (an unusable section poisons its signal)
     bool bad = false;
     for (int s = 0; s < it.K; ++s)
-        bad |= __float_as_uint(ctab(it.tabs)[(size_t)s * TAB_FLOATS + OFF_STATUS]) != 0u;
+        bad |= __float_as_uint((float)ctabp(it.tabs)[(size_t)s * TAB_FLOATS + OFF_STATUS]) != 0u;
     // position of the last real sample n-1 if this wave holds it
     const int64_t lp = (it.n - 1) - g0;
     const bool has_last = lp >= 0 && lp < CW;
     const int zl = has_last ? (int)(lp / N) : 0, zp = has_last ? (int)(lp % N) : 0;
+    __syncthreads();   // the rows were read; the tile is scratch from here on
     if (!bad) {
-        for (int s = 0; s < it.K; ++s)
-            run_section<N, W>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s, epoch, wv,
-                              lane, has_last, zl, zp);
+        for (int s = 0; s < it.K; ++s) {
+            T q1, q2;
+            run_section<T, N, W, false>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s,
+                                        epoch, wv, lane, has_last, zl, zp, q1, q2);
+            if (a.saved && s + 1 < it.K)
+                store_rows<T, N>(u, tl, lane, it.n, g0, a.saved + (size_t)s * it.n);
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < N; ++k) u[k] = __builtin_nanf("");
+        for (int k = 0; k < N; ++k) u[k] = T(__builtin_nanf(""));
         if (has_last && lane == 0 && it.zf)
             for (int s = 0; s < it.K; ++s) it.zf[2 * s] = it.zf[2 * s + 1] = __builtin_nanf("");
     }
@@ -467,7 +577,8 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item &it, 
 #pragma unroll
     for (int k = 0; k < Q; ++k)
         *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
-            make_float4(u[4 * k + 0], u[4 * k + 1], u[4 * k + 2], u[4 * k + 3]);
+            make_float4((float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
+                        (float)u[4 * k + 3]);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -491,12 +602,12 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item &it, 
 // the group index, so a group's predecessors were drawn (and are being worked
 // on) before it, which guarantees forward progress of the lookback whatever
 // the grid size (Sec. IV-A).
-template <int N, int W>
+template <typename T, int N, int W>
 __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
 {
     constexpr int RS = N + 4;
     __shared__ float tile[W][kLanes * RS];
-    __shared__ Xch<W> xch;
+    __shared__ Xch<T, W> xch;
     __shared__ int64_t ticket;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -504,6 +615,7 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
                                              __HIP_MEMORY_SCOPE_AGENT);
     const int64_t total = a.B > 0 ? *a.total_dev : a.total;
     float *tl = tile[wv];
+    const T *tabs = reinterpret_cast<const T *>(a.tabs);
 
     for (;;) {
         if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
@@ -511,14 +623,14 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
         const int64_t t = ticket;
         __syncthreads();
         if (t >= total) break;
-        Item it;
+        Item<T> it;
         it.t = t;
         if (a.B == 0) {
             it.x = a.x;
             it.y = a.y;
             it.n = a.n;
             it.g = t;
-            it.tabs = a.tabs;
+            it.tabs = tabs;
             it.zi = a.zi;
             it.zf = a.zf;
             it.K = a.K;
@@ -530,29 +642,252 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
             it.y = a.y + so;
             it.n = a.sig_off[i + 1] - so;
             it.g = t - a.gpre[i];
-            it.tabs = a.tabs + (size_t)sc * TAB_FLOATS;
+            it.tabs = tabs + (size_t)sc * TAB_FLOATS;
             it.zi = a.zi ? a.zi + 2 * (int64_t)sc : nullptr;
             it.zf = a.zf ? a.zf + 2 * (int64_t)sc : nullptr;
             it.K = a.Ks[i];
         }
-        process_group<N, W>(a, it, tl, xch, epoch, wv, lane);
+        process_group<T, N, W>(a, it, tl, xch, epoch, wv, lane);
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
     }
 }
 
-template <int N, int W>
-hipError_t launch(const FwdArgs &a, int64_t grid, hipStream_t stream)
+// ---------------------------------------------------------------------------
+// Adjoint (vector-Jacobian product) of the cascade.
+//
+// For section k (last to first), in reversed time r = n-1-t:
+//   lam'[r]  = g'[r] - a1 lam'[r-1] - a2 lam'[r-2]    (lam'[-1], lam'[-2]) = gzf[k]
+//   g_prev'[r] = b0 lam'[r] + b1 lam'[r-1] + b2 lam'[r-2]
+//   d/db_i  = sum_r lam'[r-i] u'[r],  d/da_i = -sum_r lam'[r-i] v'[r]
+//   d/dzi   = (lam'[n-1], lam'[n-2])
+// with u, v the section's forward input and output. The first line is a plain
+// recursive section run by the same multi-block machinery (PAIR carries) on
+// groups aligned to the end of the signal, so the initial carry enters at the
+// last real sample and the zero padding falls before sample 0.
+struct BwdArgs {
+    const float *gy;
+    float *gx;
+    int64_t n;
+    const void *tabs;        // PAIR tables of the K sections (compute type)
+    const float *x;          // forward input
+    const float *y;          // forward output
+    const float *saved;      // outputs of sections 0..K-2, (K-1) x n
+    const float *gzf;        // K x 2 or null
+    float *gzi;              // K x 2 or null
+    double *partials;        // total x K x 5 per-group coefficient sums
+    unsigned long long *desc;
+    unsigned *ctrl;
+    int K;
+    int64_t total;
+    unsigned long long timeout_ticks;
+};
+
+// Stage the wave's part of a signal in reversed time into its LDS rows:
+// element e of the wave (reversed index r0 + e) is src[n-1-r0-e], 0 past the end.
+template <int N>
+__device__ __forceinline__ void stage_reversed(const float *src, int64_t n, int64_t r0, float *tl,
+                                               int lane)
 {
-    hipLaunchKernelGGL((sos_fwd_kernel<N, W>), dim3((unsigned)grid), dim3(64 * W), 0, stream, a);
+    constexpr int RS = N + 4;
+#pragma unroll 4
+    for (int j = 0; j < N; ++j) {
+        const int e = kLanes * j + lane;
+        const int64_t r = r0 + e;
+        tl[(e / N) * RS + (e % N)] = r < n ? src[n - 1 - r] : 0.0f;
+    }
+}
+
+template <typename T, int N, int W>
+__global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
+{
+    constexpr int RS = N + 4;
+    constexpr int CW = kLanes * N;
+    constexpr int C = CW * W;
+    __shared__ float tile[W][kLanes * RS];
+    __shared__ float tile2[W][kLanes * RS];
+    __shared__ Xch<T, W> xch;
+    __shared__ int64_t ticket;
+    __shared__ double red[W][5];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const unsigned epoch = __hip_atomic_load(&b.ctrl[CTRL_EPOCH], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    float *tl = tile[wv];
+    float *tl2 = tile2[wv];
+    const T *tabs = reinterpret_cast<const T *>(b.tabs);
+    FwdArgs a{};                 // the fields the section step and lookback use
+    a.K = b.K;
+    a.desc = b.desc;
+    a.ctrl = b.ctrl;
+    a.timeout_ticks = b.timeout_ticks;
+
+    bool bad = false;
+    for (int k = 0; k < b.K; ++k)
+        bad |= __float_as_uint((float)ctabp(tabs)[(size_t)k * TAB_FLOATS + OFF_STATUS]) != 0u;
+
+    for (;;) {
+        if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&b.ctrl[CTRL_TICKET], 1u);
+        __syncthreads();
+        const int64_t t = ticket;
+        __syncthreads();
+        if (t >= b.total) break;
+        Item<T> it{};
+        it.n = b.n;
+        it.g = t;
+        it.t = t;
+        it.zi = b.gzf;
+        it.K = b.K;
+        const int64_t r0 = t * C + (int64_t)wv * CW;   // reversed index of the wave's start
+
+        stage_reversed<N>(b.gy, b.n, r0, tl, lane);
+        __syncthreads();
+        T u[N];
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k) {
+            const float4 v = *reinterpret_cast<const float4 *>(&tl[lane * RS + 4 * k]);
+            u[4 * k + 0] = v.x;
+            u[4 * k + 1] = v.y;
+            u[4 * k + 2] = v.z;
+            u[4 * k + 3] = v.w;
+        }
+        // lane / position of reversed index n-1 (forward sample 0) if this wave holds it
+        const int64_t pz = (b.n - 1) - r0;
+        const bool has_first = pz >= 0 && pz < CW;
+        const int zl = has_first ? (int)(pz / N) : 0, zp = has_first ? (int)(pz % N) : 0;
+
+        for (int k = b.K - 1; k >= 0 && !bad; --k) {
+            const T *tabv = tabs + (size_t)k * TAB_FLOATS;
+            ctabT<T> *tab = ctabp(tabv);
+            __syncthreads();
+            stage_reversed<N>(k == 0 ? b.x : b.saved + (size_t)(k - 1) * b.n, b.n, r0, tl, lane);
+            stage_reversed<N>(k == b.K - 1 ? b.y : b.saved + (size_t)k * b.n, b.n, r0, tl2, lane);
+            __syncthreads();
+            T q1, q2;   // lam'[-2], lam'[-1] of this lane
+            run_section<T, N, W, true>(u, xch, tl, a, it, tabv, k, epoch, wv, lane, false, 0, 0,
+                                       q1, q2);
+            // coefficient sums over the lane
+            T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const T L0 = u[m];
+                const T L1 = m >= 1 ? u[m - 1] : q2;
+                const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
+                const T uu = tl[lane * RS + m], vv = tl2[lane * RS + m];
+                s0 = fmaT(L0, uu, s0);
+                s1 = fmaT(L1, uu, s1);
+                s2 = fmaT(L2, uu, s2);
+                s3 = fmaT(-L1, vv, s3);
+                s4 = fmaT(-L2, vv, s4);
+            }
+            // d/dzi = (lam'[n-1], lam'[n-2])
+            if (has_first && b.gzi) {
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                T l1 = 0, l2 = 0;
+                pick_two<T, N>(u, tl, lane, zl, zp, l1, l2);
+                if (lane == zl) {
+                    b.gzi[2 * k] = (float)l1;
+                    b.gzi[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
+                }
+            }
+            // gradient for the section below: 3-tap FIR of lam' (descending, in place)
+            const T f0 = tab[OFF_FIR + 0], f1 = tab[OFF_FIR + 1], f2 = tab[OFF_FIR + 2];
+#pragma unroll
+            for (int m = N - 1; m >= 0; --m) {
+                const T L1 = m >= 1 ? u[m - 1] : q2;
+                const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
+                u[m] = fmaT(f0, u[m], fmaT(f1, L1, f2 * L2));
+            }
+            // group partial sums (waves combined in FP64)
+            const T w0 = wave_sum<T>(s0), w1 = wave_sum<T>(s1), w2 = wave_sum<T>(s2);
+            const T w3 = wave_sum<T>(s3), w4 = wave_sum<T>(s4);
+            if (lane == 0) {
+                red[wv][0] = w0;
+                red[wv][1] = w1;
+                red[wv][2] = w2;
+                red[wv][3] = w3;
+                red[wv][4] = w4;
+            }
+            __syncthreads();
+            if (threadIdx.x < 5) {
+                double acc = 0.0;
+                for (int v = 0; v < W; ++v) acc += red[v][threadIdx.x];
+                b.partials[((size_t)t * b.K + k) * 5 + threadIdx.x] = acc;
+            }
+        }
+        if (bad) {
+#pragma unroll
+            for (int m = 0; m < N; ++m) u[m] = T(__builtin_nanf(""));
+            for (int i = threadIdx.x; i < 5 * b.K; i += blockDim.x)
+                b.partials[(size_t)t * b.K * 5 + i] = __builtin_nan("");
+        }
+        // store dL/dx in forward order
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < N / 4; ++k)
+            *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
+                make_float4((float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
+                            (float)u[4 * k + 3]);
+        __syncthreads();
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) {
+            const int e = kLanes * j + lane;
+            const int64_t r = r0 + e;
+            if (r < b.n) b.gx[b.n - 1 - r] = tl[(e / N) * RS + (e % N)];
+        }
+        if ((int64_t)gridDim.x >= b.total) break;
+    }
+}
+
+// Sum the per-group coefficient partials of section k in FP64 (fixed order)
+// and apply the chain rule through the division by a0. Grid = (K), block 256.
+__global__ void __launch_bounds__(256)
+sos_bwd_reduce_kernel(const double *partials, int64_t total, int K, const float *sections,
+                      float *gsections)
+{
+    __shared__ double sh[256][5];
+    const int k = blockIdx.x;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t t = threadIdx.x; t < total; t += 256)
+        for (int i = 0; i < 5; ++i) acc[i] += partials[((size_t)t * K + k) * 5 + i];
+    for (int i = 0; i < 5; ++i) sh[threadIdx.x][i] = acc[i];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d)
+            for (int i = 0; i < 5; ++i) sh[threadIdx.x][i] += sh[threadIdx.x + d][i];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float *row = sections + 6 * k;
+        const double a0 = row[3];
+        const double bn0 = row[0] / a0, bn1 = row[1] / a0, bn2 = row[2] / a0;
+        const double an1 = row[4] / a0, an2 = row[5] / a0;
+        const double *g = sh[0];
+        float *o = gsections + 6 * k;
+        o[0] = (float)(g[0] / a0);
+        o[1] = (float)(g[1] / a0);
+        o[2] = (float)(g[2] / a0);
+        o[4] = (float)(g[3] / a0);
+        o[5] = (float)(g[4] / a0);
+        o[3] = (float)(-(g[0] * bn0 + g[1] * bn1 + g[2] * bn2 + g[3] * an1 + g[4] * an2) / a0);
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+template <typename T, int N, int W>
+hipError_t launch_fwd(const FwdArgs &a, int64_t grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL((sos_fwd_kernel<T, N, W>), dim3((unsigned)grid), dim3(64 * W), 0, stream,
+                       a);
     return hipGetLastError();
 }
 
-template <int N, int W>
+template <typename T, int N, int W>
 int capacity_of()
 {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sos_fwd_kernel<N, W>, 64 * W, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sos_fwd_kernel<T, N, W>, 64 * W,
+                                                     0) != hipSuccess)
         per_cu = 1;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -560,15 +895,19 @@ int capacity_of()
     return (per_cu > 0 ? per_cu : 1) * cus;
 }
 
+// Group shapes compiled into the library (N samples per lane, W waves).
 #define SOS_SHAPES(X)                                                                     \
     X(16, 1) X(32, 1) X(64, 1) X(16, 4) X(32, 4) X(64, 4) X(16, 8) X(32, 8) X(64, 8)    \
         X(16, 16) X(32, 16)
 
-hipError_t dispatch(int L, int N, const FwdArgs &a, int64_t grid, hipStream_t stream)
+hipError_t dispatch_fwd(int bits, int L, int N, const FwdArgs &a, int64_t grid,
+                        hipStream_t stream)
 {
     const int W = L / 64;
 #define SOS_CASE(NN, WW)                                                                  \
-    if (N == NN && W == WW) return launch<NN, WW>(a, grid, stream);
+    if (N == NN && W == WW)                                                               \
+        return bits == 64 ? launch_fwd<double, NN, WW>(a, grid, stream)                   \
+                          : launch_fwd<float, NN, WW>(a, grid, stream);
     SOS_SHAPES(SOS_CASE)
 #undef SOS_CASE
     return hipErrorInvalidValue;
@@ -576,7 +915,6 @@ hipError_t dispatch(int L, int N, const FwdArgs &a, int64_t grid, hipStream_t st
 
 }  // namespace
 
-// Group shapes compiled into the library: L = 64 W lanes, N samples per lane.
 extern "C" int sos_fwd_shape_supported(int L, int N)
 {
     if (L % 64) return 0;
@@ -589,24 +927,26 @@ extern "C" int sos_fwd_shape_supported(int L, int N)
 }
 
 // Workgroups of shape (L, N) that can be resident on the whole device at once.
-extern "C" int sos_fwd_capacity(int L, int N)
+extern "C" int sos_fwd_capacity(int bits, int L, int N)
 {
     const int W = L / 64;
 #define SOS_CASE(NN, WW)                                                                  \
-    if (N == NN && W == WW) return capacity_of<NN, WW>();
+    if (N == NN && W == WW) return bits == 64 ? capacity_of<double, NN, WW>()              \
+                                              : capacity_of<float, NN, WW>();
     SOS_SHAPES(SOS_CASE)
 #undef SOS_CASE
     return 0;
 }
 
 // Plain filter of one signal; grid <= 0 means one workgroup per group.
-extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int64_t n,
-                                     int64_t groups, const float *tabs, int K, const float *zi,
+extern "C" hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, float *y, int64_t n,
+                                     int64_t groups, const void *tabs, int K, const float *zi,
                                      float *zf, unsigned long long *desc, unsigned *ctrl,
-                                     unsigned long long timeout_ticks, int64_t grid,
+                                     unsigned long long timeout_ticks, int64_t grid, float *saved,
                                      hipStream_t stream)
 {
     FwdArgs a{};
+    a.saved = saved;
     a.x = x;
     a.y = y;
     a.n = n;
@@ -620,16 +960,17 @@ extern "C" hipError_t sos_launch_fwd(int L, int N, const float *x, float *y, int
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
     if (grid <= 0 || grid > groups) grid = groups;
-    return dispatch(L, N, a, grid, stream);
+    return dispatch_fwd(bits, L, N, a, grid, stream);
 }
 
 // Uneven batch in one persistent launch. The work table (gpre, sigmap,
 // *total_dev) is produced on the device by sos_launch_worktable.
-extern "C" hipError_t sos_launch_fwd_batched(int L, int N, int B, int kmax, const int32_t *Ks,
-                                             const int32_t *sec_off, const int64_t *sig_off,
-                                             const int64_t *gpre, const int32_t *sigmap,
-                                             const int64_t *total_dev, const float *x, float *y,
-                                             const float *tabs, const float *zi, float *zf,
+extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax,
+                                             const int32_t *Ks, const int32_t *sec_off,
+                                             const int64_t *sig_off, const int64_t *gpre,
+                                             const int32_t *sigmap, const int64_t *total_dev,
+                                             const float *x, float *y, const void *tabs,
+                                             const float *zi, float *zf,
                                              unsigned long long *desc, unsigned *ctrl,
                                              unsigned long long timeout_ticks, int64_t grid,
                                              hipStream_t stream)
@@ -651,5 +992,53 @@ extern "C" hipError_t sos_launch_fwd_batched(int L, int N, int B, int kmax, cons
     a.desc = desc;
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
-    return dispatch(L, N, a, grid, stream);
+    return dispatch_fwd(bits, L, N, a, grid, stream);
+}
+
+// Adjoint of the plain filter: grid <= 0 means one workgroup per group.
+extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx,
+                                     int64_t n, int64_t groups, const void *tabs, int K,
+                                     const float *x, const float *y, const float *saved,
+                                     const float *gzf, float *gzi, double *partials,
+                                     unsigned long long *desc, unsigned *ctrl,
+                                     unsigned long long timeout_ticks, int64_t grid,
+                                     hipStream_t stream)
+{
+    BwdArgs b{gy, gx, n, tabs, x, y, saved, gzf, gzi, partials, desc, ctrl, K, groups,
+              timeout_ticks};
+    if (grid <= 0 || grid > groups) grid = groups;
+    const int W = L / 64;
+#define SOS_BWD_CASE(NN, WW)                                                                   \
+    if (N == NN && W == WW) {                                                                  \
+        if (bits == 64)                                                                        \
+            hipLaunchKernelGGL((sos_bwd_kernel<double, NN, WW>), dim3((unsigned)grid),        \
+                               dim3(64 * WW), 0, stream, b);                                   \
+        else                                                                                   \
+            hipLaunchKernelGGL((sos_bwd_kernel<float, NN, WW>), dim3((unsigned)grid),         \
+                               dim3(64 * WW), 0, stream, b);                                   \
+        return hipGetLastError();                                                              \
+    }
+    SOS_BWD_CASE(16, 1)
+    SOS_BWD_CASE(32, 1)
+    SOS_BWD_CASE(16, 4)
+    SOS_BWD_CASE(32, 4)
+    SOS_BWD_CASE(16, 8)
+    SOS_BWD_CASE(32, 8)
+#undef SOS_BWD_CASE
+    return hipErrorInvalidValue;
+}
+
+extern "C" int sos_bwd_shape_supported(int L, int N)
+{
+    return (L == 64 || L == 256 || L == 512) && (N == 16 || N == 32);
+}
+
+extern "C" hipError_t sos_launch_bwd_reduce(const double *partials, int64_t groups, int K,
+                                            const float *sections, float *gsections,
+                                            hipStream_t stream)
+{
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sos_bwd_reduce_kernel, dim3(K), dim3(256), 0, stream, partials, groups, K,
+                       sections, gsections);
+    return hipGetLastError();
 }

@@ -17,34 +17,40 @@ __device__ inline m2 mpow_pow2(m2 m, int log2e)
     return m;
 }
 
-__device__ inline void put(float *t, int off, const m2 &m)
+template <typename T>
+__device__ inline void put(T *t, int off, const m2 &m)
 {
-    t[off + 0] = (float)m.a;
-    t[off + 1] = (float)m.b;
-    t[off + 2] = (float)m.c;
-    t[off + 3] = (float)m.d;
+    t[off + 0] = (T)m.a;
+    t[off + 1] = (T)m.b;
+    t[off + 2] = (T)m.c;
+    t[off + 3] = (T)m.d;
 }
 
 }  // namespace
 
 // Table of one section: row = [b0 b1 b2 a0 a1 a2], t = its table, log2n =
 // log2(N) samples per lane, log2w = log2(W) waves per group (C = 64 W N).
-// Called by all 64 lanes of one wave (lane l fills the per-lane entries).
-__device__ void prep_section(const float *row, float *t, int log2n, int log2w, unsigned *ctrl,
-                             int l)
+// pair = false: the section itself, carries are TDF-II states (state map T).
+// pair = true: the pure recursive part 1/A(z) with the last two outputs as the
+// carry (state map Phi = [[0, 1], [-a2, -a1]] on (y[-2], y[-1])), used by the
+// adjoint. Called by all 64 lanes of one wave (lane l fills per-lane entries).
+template <typename T>
+__device__ void prep_section(const float *row, T *t, int log2n, int log2w, unsigned *ctrl, int l,
+                             bool pair)
 {
     const int N = 1 << log2n;
     const double a0 = (double)row[3];
     unsigned status = 0u;
     if (a0 == 0.0) status |= ERRBIT_A0;
     const double inv = (a0 == 0.0) ? 0.0 : 1.0 / a0;
-    const double b0 = row[0] * inv, b1 = row[1] * inv, b2 = row[2] * inv;
+    const double b0 = pair ? 1.0 : row[0] * inv, b1 = pair ? 0.0 : row[1] * inv;
+    const double b2 = pair ? 0.0 : row[2] * inv;
     const double a1 = row[4] * inv, a2 = row[5] * inv;
     // closed stability triangle of z^2 + a1 z + a2 (NaN fails the test)
     if (!(fabs(a2) <= 1.0 && fabs(a1) <= 1.0 + a2)) status |= ERRBIT_UNSTABLE;
 
     // T maps the TDF-II state before a sample to the state after it at zero input.
-    const m2 T1 = {-a1, 1.0, -a2, 0.0};
+    const m2 T1 = pair ? m2{0.0, 1.0, -a2, -a1} : m2{-a1, 1.0, -a2, 0.0};
     const m2 TN = mpow_pow2(T1, log2n);     // across one lane (N samples)
     m2 ks[6];
     ks[0] = TN;
@@ -83,32 +89,37 @@ __device__ void prep_section(const float *row, float *t, int log2n, int log2w, u
     }
 
     if (l == 0) {
-        t[OFF_STATUS] = __uint_as_float(status);
+        t[OFF_STATUS] = (T)status;   // 0 = usable
+        if (pair) {
+            t[OFF_FIR + 0] = (T)(row[0] * inv);
+            t[OFF_FIR + 1] = (T)(row[1] * inv);
+            t[OFF_FIR + 2] = (T)(row[2] * inv);
+        }
         // level-1 right-hand side taps: B(z) A(-z) (Eq. (23) with a general b0)
-        t[OFF_TAPS + 0] = (float)b0;
-        t[OFF_TAPS + 1] = (float)(b1 - a1 * b0);
-        t[OFF_TAPS + 2] = (float)(b2 - a1 * b1 + a2 * b0);
-        t[OFF_TAPS + 3] = (float)(a2 * b1 - a1 * b2);
-        t[OFF_TAPS + 4] = (float)(a2 * b2);
-        t[OFF_B1] = (float)b1;
-        t[OFF_B2] = (float)b2;
-        t[OFF_A1] = (float)a1;
-        t[OFF_A2] = (float)a2;
+        t[OFF_TAPS + 0] = (T)b0;
+        t[OFF_TAPS + 1] = (T)(b1 - a1 * b0);
+        t[OFF_TAPS + 2] = (T)(b2 - a1 * b1 + a2 * b0);
+        t[OFF_TAPS + 3] = (T)(a2 * b1 - a1 * b2);
+        t[OFF_TAPS + 4] = (T)(a2 * b2);
+        t[OFF_B1] = (T)b1;
+        t[OFF_B2] = (T)b2;
+        t[OFF_A1] = (T)a1;
+        t[OFF_A2] = (T)a2;
         // reduction levels: A_{i+1}(w^2) = A_i(w) A_i(-w)
         double e = a1, f = a2;
         for (int i = 0; i < 8; ++i) {
-            t[OFF_E + i] = (float)e;
-            t[OFF_F + i] = (float)f;
+            t[OFF_E + i] = (T)e;
+            t[OFF_F + i] = (T)f;
             const double en = 2.0 * f - e * e;
             f = f * f;
             e = en;
         }
         // impulse response of 1/A(z), stored with g[-1] = 0 first
-        t[OFF_G] = 0.0f;
+        t[OFF_G] = T(0);
         double gm2 = 0.0, gm1 = 0.0;
         for (int m = 0; m < kMaxN; ++m) {
             const double g = (m == 0) ? 1.0 : (-a1 * gm1 - a2 * gm2);
-            t[OFF_G + 1 + m] = (m < N) ? (float)g : 0.0f;
+            t[OFF_G + 1 + m] = (m < N) ? (T)g : T(0);
             gm2 = gm1;
             gm1 = g;
         }
@@ -121,51 +132,65 @@ __device__ void prep_section(const float *row, float *t, int log2n, int log2w, u
 }
 
 // Plain filter: sections K x 6 -> tabs K x TAB_FLOATS. Grid = (K), block = 64.
-extern "C" __global__ void __launch_bounds__(64)
+template <typename T>
+__global__ void __launch_bounds__(64)
 sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
-                float *__restrict__ tabs, unsigned *__restrict__ ctrl)
+                T *__restrict__ tabs, unsigned *__restrict__ ctrl, int pair)
 {
     const int s = blockIdx.x;
     if (s >= K) return;
-    prep_section(sections + 6 * s, tabs + (size_t)s * TAB_FLOATS, log2n, log2w, ctrl,
-                 threadIdx.x);
+    prep_section<T>(sections + 6 * s, tabs + (size_t)s * TAB_FLOATS, log2n, log2w, ctrl,
+                    threadIdx.x, pair != 0);
 }
 
 // Uneven batch: block i prepares the K[i] sections of signal i (rows and
-// tables at sec_off[i]); signals the work table marks invalid are skipped.
-extern "C" __global__ void __launch_bounds__(64)
-sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax,
+// tables at sec_off[i]); signals with inconsistent entries are skipped.
+template <typename T>
+__global__ void __launch_bounds__(64)
+sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax, int64_t rows,
                         const int32_t *__restrict__ Ks, const int32_t *__restrict__ sec_off,
-                        int log2n, int log2w, float *__restrict__ tabs,
-                        unsigned *__restrict__ ctrl)
+                        int log2n, int log2w, T *__restrict__ tabs, unsigned *__restrict__ ctrl)
 {
     const int i = blockIdx.x;
     if (i >= B) return;
     const int K = Ks[i];
     const int64_t so = sec_off[i];
-    if (K < 0 || K > kmax || so < 0 || so + K > (int64_t)B * kmax) return;
+    if (K < 0 || K > kmax || so < 0 || so + K > rows) return;
     for (int k = 0; k < K; ++k)
-        prep_section(sections + 6 * (so + k), tabs + (size_t)(so + k) * TAB_FLOATS, log2n, log2w,
-                     ctrl, threadIdx.x);
+        prep_section<T>(sections + 6 * (so + k), tabs + (size_t)(so + k) * TAB_FLOATS, log2n,
+                        log2w, ctrl, threadIdx.x, false);
 }
 
-extern "C" hipError_t sos_launch_prep(const float *sections, int K, int log2n, int log2w,
-                                      float *tabs, unsigned *ctrl, hipStream_t stream)
+// K sections -> tables of the compute type `bits` (32 or 64). pair != 0: the
+// adjoint's tables (recursive parts with output-pair carries).
+extern "C" hipError_t sos_launch_prep(int bits, const float *sections, int K, int log2n,
+                                      int log2w, void *tabs, unsigned *ctrl, int pair,
+                                      hipStream_t stream)
 {
     if (K <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sos_prep_kernel, dim3(K), dim3(64), 0, stream, sections, K, log2n, log2w,
-                       tabs, ctrl);
+    if (bits == 64)
+        hipLaunchKernelGGL(sos_prep_kernel<double>, dim3(K), dim3(64), 0, stream, sections, K,
+                           log2n, log2w, (double *)tabs, ctrl, pair);
+    else
+        hipLaunchKernelGGL(sos_prep_kernel<float>, dim3(K), dim3(64), 0, stream, sections, K,
+                           log2n, log2w, (float *)tabs, ctrl, pair);
     return hipGetLastError();
 }
 
-extern "C" hipError_t sos_launch_prep_batched(const float *sections, int B, int kmax,
-                                              const int32_t *Ks, const int32_t *sec_off,
-                                              int log2n, int log2w, float *tabs, unsigned *ctrl,
-                                              hipStream_t stream)
+extern "C" hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int kmax,
+                                              int64_t rows, const int32_t *Ks,
+                                              const int32_t *sec_off, int log2n, int log2w,
+                                              void *tabs, unsigned *ctrl, hipStream_t stream)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sos_prep_batched_kernel, dim3(B), dim3(64), 0, stream, sections, B, kmax,
-                       Ks, sec_off, log2n, log2w, tabs, ctrl);
+    if (bits == 64)
+        hipLaunchKernelGGL(sos_prep_batched_kernel<double>, dim3(B), dim3(64), 0, stream,
+                           sections, B, kmax, rows, Ks, sec_off, log2n, log2w, (double *)tabs,
+                           ctrl);
+    else
+        hipLaunchKernelGGL(sos_prep_batched_kernel<float>, dim3(B), dim3(64), 0, stream,
+                           sections, B, kmax, rows, Ks, sec_off, log2n, log2w, (float *)tabs,
+                           ctrl);
     return hipGetLastError();
 }
 

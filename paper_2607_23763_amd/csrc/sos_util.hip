@@ -18,11 +18,12 @@ __global__ void __launch_bounds__(256) fill_kernel(float *dst, const float *src,
 // filter uses: 8 bytes of HBM traffic per sample and no arithmetic. It is the
 // achievable memory floor t_mem = b_s / BW of the cost model (Eq. (28)) and
 // the reference for scaling the HBM byte counters.
+// One 128-bit element per thread, one wave of blocks over the whole array
+// (measured faster on MI355X than a grid-stride loop).
 __global__ void __launch_bounds__(256) copy_kernel(const f4 *x, f4 *y, int64_t n4)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
 }
 
 }  // namespace
@@ -43,8 +44,8 @@ extern "C" hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipSt
     const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15u) == 0;
     const int64_t n4 = vec ? n / 4 : 0;
     if (n4 > 0) {
-        int64_t blocks = (n4 + 255) / 256;
-        if (blocks > 256 * 64) blocks = 256 * 64;
+        const int64_t blocks = (n4 + 255) / 256;
+        if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
                            reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(y), n4);
         const hipError_t e = hipGetLastError();

@@ -225,3 +225,51 @@ def filter_model(sos, x, zi=None, N=8, L=4, window=3, seed=0):
         pc[g] = [s + 1, 0]
     y = np.concatenate([d.reshape(-1) for d in data])[:n]
     return y, zf
+
+
+def vjp_model(sos, x, zi, gy, gzf):
+    """The adjoint as the backward kernel computes it: per section, from the
+    last to the first, in reversed time r = n-1-t:
+      lam'[r] = g'[r] - a1 lam'[r-1] - a2 lam'[r-2],  (lam'[-1], lam'[-2]) = gzf[k]
+      g_prev'[r] = b0 lam'[r] + b1 lam'[r-1] + b2 lam'[r-2]
+      gb_i = sum_r lam'[r-i] u'[r],  ga_i = -sum_r lam'[r-i] v'[r]   (i = 0, 1, 2)
+      gzi = (lam'[n-1], lam'[n-2])
+    u, v = the section's forward input and output. Gradients w.r.t. raw rows
+    follow from the normalised ones through the division by a0."""
+    sos = np.asarray(sos, dtype=np.float64).reshape(-1, 6)
+    K = sos.shape[0]
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    zi = np.zeros((K, 2)) if zi is None else np.asarray(zi, dtype=np.float64)
+    gzf = np.zeros((K, 2)) if gzf is None else np.asarray(gzf, dtype=np.float64)
+    acts = [x.copy()]
+    for k in range(K):
+        b0, b1, b2, a1, a2 = normalized(sos[k])
+        z1, z2 = zi[k]
+        out = np.empty(n)
+        for t in range(n):
+            y = b0 * acts[-1][t] + z1
+            z1 = b1 * acts[-1][t] - a1 * y + z2
+            z2 = b2 * acts[-1][t] - a2 * y
+            out[t] = y
+        acts.append(out)
+    g = np.asarray(gy, dtype=np.float64)[::-1].copy()
+    gzi = np.zeros((K, 2))
+    gsos = np.zeros((K, 6))
+    for k in range(K - 1, -1, -1):
+        b0, b1, b2, a1, a2 = normalized(sos[k])
+        up, vp = acts[k][::-1], acts[k + 1][::-1]
+        lam = np.zeros(n + 2)              # lam[j + 2] holds lam'[j]; lam'[-1], lam'[-2] first
+        lam[1], lam[0] = gzf[k][0], gzf[k][1]
+        for r in range(n):
+            lam[r + 2] = g[r] - a1 * lam[r + 1] - a2 * lam[r]
+        L0, L1, L2 = lam[2:], lam[1:-1], lam[:-2]
+        gb = np.array([L0 @ up, L1 @ up, L2 @ up])
+        ga = np.array([-(L1 @ vp), -(L2 @ vp)])
+        gzi[k] = [L0[n - 1], L0[n - 2] if n >= 2 else gzf[k][0]]
+        a0 = sos[k, 3]
+        gsos[k, :3] = gb / a0
+        gsos[k, 4:] = ga / a0
+        gsos[k, 3] = -(gb @ np.array([b0, b1, b2]) + ga @ np.array([a1, a2])) / a0
+        g = b0 * L0 + b1 * L1 + b2 * L2
+    return g[::-1].copy(), gzi, gsos

@@ -45,6 +45,14 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_filter(None, None, 1, None, None, 10, None, None, None) == P.SOS_EINVAL
     assert lib.sos_set_tile(None, 64, 32) == P.SOS_EINVAL
     assert lib.sos_get_tile(None, None, None) == P.SOS_EINVAL
+    assert lib.sos_set_precision(None, 64) == P.SOS_EINVAL
+    assert lib.sos_get_precision(None) == P.SOS_EINVAL
+    assert lib.sos_filter_batched(None, 1, 1, 1, 10, None, None, None, None, None, None, None,
+                                  None, None) == P.SOS_EINVAL
+    assert lib.sos_filter_train(None, None, 1, None, None, 10, None, None, None,
+                                None) == P.SOS_EINVAL
+    assert lib.sos_filter_vjp(None, None, 1, None, None, None, 10, None, None, None, None, None,
+                              None) == P.SOS_EINVAL
     assert lib.sos_prepare(None, None, 1, None) == P.SOS_EINVAL
     assert lib.sos_filter_prepared(None, None, None, 10, None, None, None) == P.SOS_EINVAL
     assert lib.sos_bench_copy(None, None, 10, None) == P.SOS_EINVAL

@@ -27,8 +27,8 @@ def dev(torch, a, dtype=None):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def run_batch(torch, P, Ks, rows, sig_off, x, zi, tile=None):
-    h = P.Handle(0, tile=tile)
+def run_batch(torch, P, Ks, rows, sig_off, x, zi, tile=None, precision=0):
+    h = P.Handle(0, tile=tile, precision=precision)
     y, zf = P.sosfilt_batched(dev(torch, x), dev(torch, rows), dev(torch, Ks.astype(np.int32)),
                               dev(torch, sig_off.astype(np.int64)),
                               zi=None if zi is None else dev(torch, zi), handle=h)
@@ -36,12 +36,13 @@ def run_batch(torch, P, Ks, rows, sig_off, x, zi, tile=None):
     return y.cpu().numpy(), zf.cpu().numpy(), h.last_error()
 
 
-@pytest.mark.parametrize("tile", [(64, 16), (256, 32), (512, 32), (1024, 32)])
-def test_uneven_batch_matches_oracle(env, tile):
+@pytest.mark.parametrize("tile,precision", [((64, 16), 32), ((256, 32), 32), ((512, 32), 32),
+                                            ((1024, 32), 32), ((512, 32), 64)])
+def test_uneven_batch_matches_oracle(env, tile, precision):
     torch, P = env
     Ks, rows, sig_off, zi = workloads.uneven_batch(B=96, log2_lo=2, log2_hi=17, seed=11)
     x = workloads.batch_signal(int(sig_off[-1]), seed=12)
-    y, zf, err = run_batch(torch, P, Ks, rows, sig_off, x, zi, tile)
+    y, zf, err = run_batch(torch, P, Ks, rows, sig_off, x, zi, tile, precision)
     assert err == P.SOS_OK
     yr, zfr = oracle.sosfilt_batched(Ks, rows, sig_off, x, zi, nthreads=8)
     so = np.r_[0, np.cumsum(Ks)]

@@ -191,3 +191,63 @@ def test_full_size_2p28(torch_cuda, P, K):
     print("2^28 K", K, "rel_l2", e, "max/peak", max_over_peak(yh, yr))
     assert e <= tol_for(K)
     assert rel_l2(zf.cpu().numpy(), zfr) <= tol_for(K)
+
+
+def lightly_damped_sections(K=8, r=0.995, seed=9):
+    """K sections with every pole at radius r (random angles and zeros), the
+    first section scaled so the cascade has unit white-noise gain (sum of the
+    squared impulse response, computed by the oracle, equals 1)."""
+    sos = workloads.random_stable_sos(K, workloads.rng(seed), r_fixed=r)
+    imp = np.zeros(40000)
+    imp[0] = 1.0
+    h, _ = oracle.sosfilt(sos, imp)
+    sos[0, :3] /= np.sqrt(np.sum(h ** 2))
+    return sos.astype(np.float32)
+
+
+def fp32_sequential_error(sos, x, zi, yr):
+    """Relative L2 error of a sequential FP32 cascade (scipy's direct-form
+    sosfilt run in float32): the accuracy floor of any FP32 filter."""
+    import scipy.signal
+
+    y32 = scipy.signal.sosfilt(sos.astype(np.float32), x.astype(np.float32),
+                               zi=None if zi is None else zi.astype(np.float32))
+    y32 = y32[0] if zi is not None else y32
+    return rel_l2(y32, yr)
+
+
+@pytest.mark.parametrize("tile", [(64, 16), (512, 16), (512, 64), (1024, 32)])
+@pytest.mark.parametrize("K", [1, 4, 8])
+def test_precision64_matches_oracle(torch_cuda, P, K, tile):
+    """FP64 compute type: same layout and launch, errors from FP32 data only."""
+    sos = workloads.sweep_sections(K, "random")
+    n = (1 << 17) + 999
+    x = workloads.signal(n, seed=12)
+    zi = workloads.initial_state(K, workloads.rng(50 + K))
+    h = P.Handle(0, tile=tile, precision=64)
+    assert h.precision() == 64
+    y, zf, _ = run(torch_cuda, P, sos, x, zi, handle=h)
+    yr, zfr = oracle.sosfilt(sos, x, zi)
+    print("fp64 K", K, "tile", tile, "rel_l2", rel_l2(y, yr), "zf", rel_l2(zf, zfr))
+    assert rel_l2(y, yr) <= 1e-6
+    assert rel_l2(zf, zfr) <= 1e-6
+
+
+@pytest.mark.parametrize("tile", [(64, 16), (512, 32), (512, 64)])
+def test_lightly_damped_order16(torch_cuda, P, tile):
+    """Order 16, all poles at radius 0.995: the FP64 compute type meets the
+    order-16 bound; the FP32 one is reported beside the FP32 sequential floor."""
+    sos = lightly_damped_sections()
+    n = 1 << 18
+    x = workloads.signal(n, seed=13)
+    yr, zfr = oracle.sosfilt(sos, x)
+    h64 = P.Handle(0, tile=tile, precision=64)
+    y64, zf64, _ = run(torch_cuda, P, sos, x, handle=h64)
+    h32 = P.Handle(0, tile=tile, precision=32)
+    y32, _, _ = run(torch_cuda, P, sos, x, handle=h32)
+    floor = fp32_sequential_error(sos, x, None, yr)
+    print("order16 r=0.995 tile", tile, "fp64", rel_l2(y64, yr), "fp32", rel_l2(y32, yr),
+          "fp32 sequential floor", floor)
+    assert rel_l2(y64, yr) <= 1e-5
+    assert rel_l2(zf64, zfr) <= 1e-5
+    assert np.isfinite(y32).all()

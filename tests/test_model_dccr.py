@@ -97,3 +97,21 @@ def test_printed_sign_of_state_correction_is_wrong():
     corrected = np.stack([ye0[l] + np.linalg.matrix_power(-C, l + 1) @ ym1 for l in range(L)])
     assert np.max(np.abs(corrected - ye)) < 1e-12
     assert np.max(np.abs(printed - ye)) > 1e-3
+
+
+def test_vjp_model_matches_oracle():
+    """The backward kernel's formulation (reversed-time 1/A, 3-tap FIR, lambda
+    correlations) reproduces the oracle's reverse sweep."""
+    g = np.random.default_rng(50)
+    for K, n in ((1, 40), (3, 57), (4, 2), (2, 1)):
+        rows = _rows(K, 60 + K)
+        rows[0] *= 1.3                         # a0 != 1
+        x = g.normal(size=n)
+        zi = g.normal(size=(K, 2))
+        gy = g.normal(size=n)
+        gzf = g.normal(size=(K, 2))
+        gx, gzi, gs = M.vjp_model(rows, x, zi, gy, gzf)
+        rx, rzi, rs = oracle.sosfilt_vjp(rows, x, zi, gy, gzf)
+        assert np.max(np.abs(gx - rx)) < 1e-10 * max(1, np.max(np.abs(rx)))
+        assert np.max(np.abs(gzi - rzi)) < 1e-10 * max(1, np.max(np.abs(rzi)))
+        assert np.max(np.abs(gs - rs)) < 1e-10 * max(1, np.max(np.abs(rs)))
