@@ -109,6 +109,16 @@ int sos_get_tile(sos_handle_t h, int *L, int *N);
 int sos_set_precision(sos_handle_t h, int bits);
 int sos_get_precision(sos_handle_t h);
 
+/* Bound on each lookback wait (Sec. IV-A's decoupled lookback spins on its
+ * predecessors' descriptors): `ms` milliseconds of the device wall clock
+ * (0 restores the default, 2000 ms, or SOS_TIMEOUT_MS at sos_create). A wait
+ * that exceeds it poisons the group's outputs with NaN, still publishes so
+ * successors terminate, and makes sos_last_error report SOS_ETIMEOUT.
+ * Returns SOS_EINVAL for a negative or non-finite value or more than one hour. */
+int sos_set_timeout(sos_handle_t h, double ms);
+/* The device wall-clock rate in kHz the timeout is converted with. */
+int sos_wall_clock_khz(sos_handle_t h);
+
 /*
  * Plain filter, one signal (Sec. IV-A/B; Eqs. (1)-(25)).
  *   y[0..n) = cascade(sections[0..K))(x[0..n)) starting from zi; zf receives

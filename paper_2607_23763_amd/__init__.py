@@ -64,6 +64,8 @@ def lib():
             L.sos_filter_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp, vp,
                                              vp, vp]
             L.sos_set_precision.argtypes = [vp, i32]
+            L.sos_set_timeout.argtypes = [vp, ctypes.c_double]
+            L.sos_wall_clock_khz.argtypes = [vp]
             L.sos_get_precision.argtypes = [vp]
             L.sos_filter_train.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp, vp]
             L.sos_filter_vjp.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -71,7 +73,7 @@ def lib():
                          "sos_get_tile", "sos_filter", "sos_debug_carries", "sos_prepare",
                          "sos_filter_prepared", "sos_bench_copy", "sos_filter_batched",
                          "sos_filter_train", "sos_filter_vjp", "sos_set_precision",
-                         "sos_get_precision"):
+                         "sos_get_precision", "sos_set_timeout", "sos_wall_clock_khz"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -113,6 +115,13 @@ class Handle:
 
     def precision(self) -> int:
         return int(lib().sos_get_precision(self._h))
+
+    def set_timeout(self, ms: float):
+        """Bound on each lookback wait in milliseconds (0 = default)."""
+        _check(lib().sos_set_timeout(self._h, float(ms)), "sos_set_timeout")
+
+    def wall_clock_khz(self) -> int:
+        return int(lib().sos_wall_clock_khz(self._h))
 
     def close(self):
         if self._h:

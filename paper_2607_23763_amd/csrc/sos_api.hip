@@ -63,7 +63,8 @@ struct sos_ctx {
     size_t tabs_cap = 0;
     unsigned long long *desc = nullptr;   // lookback descriptors
     size_t desc_cap = 0;                  // 64-bit words
-    unsigned long long timeout_ticks = 0;
+    unsigned long long timeout_ticks = 0;  // lookback wait bound, in wall-clock ticks
+    int wall_khz = 0;                     // device wall clock (s_memrealtime) rate
     int64_t last_groups = 0;
     int last_K = 0;
     int prep_K = -1;                      // tables currently prepared (K, shape, type)
@@ -235,6 +236,14 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     return SOS_OK;
 }
 
+// Lookback wait bound: ms milliseconds of the device wall clock, at least one
+// tick.
+void set_timeout_ms(sos_ctx *h, double ms)
+{
+    const double t = ms * (double)h->wall_khz;
+    h->timeout_ticks = t < 1.0 ? 1ull : (unsigned long long)t;
+}
+
 void mark_degenerate(sos_ctx *h, int K)
 {
     const Tile t = tile_of(h);   // degenerate calls need no tables
@@ -291,12 +300,25 @@ int sos_create(sos_handle_t *out, int hip_device)
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) != hipSuccess ||
         khz <= 0)
         khz = 100000;
+    h->wall_khz = khz;
     double ms = 2000.0;
     if (const char *e = std::getenv("SOS_TIMEOUT_MS")) ms = std::atof(e);
-    if (ms < 1.0) ms = 1.0;
-    h->timeout_ticks = (unsigned long long)(ms * (double)khz);
+    set_timeout_ms(h, ms);
     *out = h;
     return SOS_OK;
+}
+
+int sos_set_timeout(sos_handle_t h, double ms)
+{
+    if (!h || !(ms >= 0.0) || ms > 3.6e6) return SOS_EINVAL;
+    set_timeout_ms(h, ms == 0.0 ? 2000.0 : ms);
+    return SOS_OK;
+}
+
+int sos_wall_clock_khz(sos_handle_t h)
+{
+    if (!h) return SOS_EINVAL;
+    return h->wall_khz;
 }
 
 int sos_destroy(sos_handle_t h)

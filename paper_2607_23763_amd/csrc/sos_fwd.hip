@@ -249,25 +249,33 @@ __device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, i
 
 // Resolve the incoming state of group it.g (> 0) of a signal for section s by
 // decoupled lookback; executed by one whole wave. Returns wave-uniform values.
-// On timeout returns NaNs and sets the error bit (the caller still publishes,
-// so successors terminate).
+//
+// Each round the wave reads up to 64 of the newest predecessors not yet
+// consumed, one per lane. It consumes the longest prefix that is ready: if a
+// resolved carry (inclusive) lies in that prefix at lane j*, the result is
+// inc[j*] propagated over j* groups plus the local carries (aggregates) of
+// the j* groups in front of it, and the walk ends; otherwise the prefix's
+// aggregates are added and the walk slides past them. When the newest
+// unconsumed predecessor is not ready yet, the wave waits on that single
+// descriptor with exponential backoff, so waiting waves issue one request per
+// poll. On timeout it returns NaNs and sets the error bit (the caller still
+// publishes, so successors terminate).
 template <typename T>
 __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int s,
                          unsigned epoch, int lane, T &r1, T &r2)
 {
-    ctabT<T> *tab = ctabp(tabv);
-    const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);
-    const T w00 = tab[OFF_TW + 0], w01 = tab[OFF_TW + 1];
-    const T w10 = tab[OFF_TW + 2], w11 = tab[OFF_TW + 3];
+    const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);   // T^(C lane)
     T acc1 = 0, acc2 = 0;
-    T m00 = 1, m01 = 0, m10 = 0, m11 = 1;   // window transform
+    T m00 = 1, m01 = 0, m10 = 0, m11 = 1;   // transform from the newest unconsumed group
     const int64_t first = it.t - it.g;      // ticket of the signal's first group
-    int64_t base = it.t - 1;
+    int64_t base = it.t - 1;                // newest unconsumed predecessor
+    int span = 64;                          // lanes reading this round
+    int nap = 0;
     const unsigned long long t0 = wall_clock64();
     while (true) {
         const int64_t h = base - lane;
         unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
-        if (h >= first) {
+        if (lane < span && h >= first) {
             const unsigned long long *d = a.desc + ((size_t)h * a.K + s) * 4;
 #pragma unroll
             for (int i = 0; i < 4; ++i) w[i] = load_word(d + i);
@@ -276,29 +284,29 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
         const bool agg_ok = (unsigned)(w[0] >> 32) == epoch && (unsigned)(w[1] >> 32) == epoch;
         const unsigned long long incm = __ballot(inc_ok);
         const unsigned long long rdym = __ballot(inc_ok || agg_ok);
-        int jstar = 64;
-        unsigned long long need;
-        if (incm) {
-            jstar = __builtin_ctzll(incm);
-            need = (jstar == 63) ? ~0ull : ((2ull << jstar) - 1ull);
-        } else {
-            // no resolved carry in this window: all 64 must hold local carries
-            need = ~0ull;
-        }
-        if ((rdym & need) != need) {
+        const unsigned long long spanm = span == 64 ? ~0ull : ((1ull << span) - 1ull);
+        const unsigned long long notr = ~rdym & spanm;
+        const int nr = notr ? __builtin_ctzll(notr) : span;   // ready prefix
+        const int jstar = incm ? __builtin_ctzll(incm) : 64;
+        const bool done = jstar < nr;
+        const int c = done ? jstar : nr;                       // aggregates consumed
+        if (c == 0 && !done) {
             if (wall_clock64() - t0 > a.timeout_ticks) {
                 if (lane == 0) atomicOr(&a.ctrl[CTRL_ERR], ERRBIT_TIMEOUT);
                 r1 = r2 = T(__builtin_nanf(""));
                 return;
             }
-            __builtin_amdgcn_s_sleep(1);
+            for (int i = 0; i < (1 << nap); ++i) __builtin_amdgcn_s_sleep(2);
+            if (nap < 4) ++nap;
+            span = 1;
             continue;
         }
+        nap = 0;
         T v1 = 0, v2 = 0;
-        if (lane < jstar) {
+        if (lane < c) {
             v1 = __uint_as_float((unsigned)w[0]);
             v2 = __uint_as_float((unsigned)w[1]);
-        } else if (lane == jstar) {
+        } else if (done && lane == jstar) {
             v1 = __uint_as_float((unsigned)w[2]);
             v2 = __uint_as_float((unsigned)w[3]);
         }
@@ -306,12 +314,22 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
         const T s2 = wave_sum<T>(gp.c * v1 + gp.d * v2);
         acc1 += m00 * s1 + m01 * s2;
         acc2 += m10 * s1 + m11 * s2;
-        if (jstar < 64) break;
-        // slide the window 64 groups further back
-        const T n00 = m00 * w00 + m01 * w10, n01 = m00 * w01 + m01 * w11;
-        const T n10 = m10 * w00 + m11 * w10, n11 = m10 * w01 + m11 * w11;
+        if (done) break;
+        // slide past the c consumed groups: m <- m T^(C c)
+        T p00, p01, p10, p11;
+        if (c == 64) {
+            ctabT<T> *tab = ctabp(tabv);
+            p00 = tab[OFF_TW + 0]; p01 = tab[OFF_TW + 1];
+            p10 = tab[OFF_TW + 2]; p11 = tab[OFF_TW + 3];
+        } else {
+            p00 = readlane(gp.a, c); p01 = readlane(gp.b, c);
+            p10 = readlane(gp.c, c); p11 = readlane(gp.d, c);
+        }
+        const T n00 = m00 * p00 + m01 * p10, n01 = m00 * p01 + m01 * p11;
+        const T n10 = m10 * p00 + m11 * p10, n11 = m10 * p01 + m11 * p11;
         m00 = n00; m01 = n01; m10 = n10; m11 = n11;
-        base -= 64;
+        base -= c;
+        span = 64;
     }
     r1 = acc1;
     r2 = acc2;
@@ -476,30 +494,129 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
     }
 }
 
+// ---------------------------------------------------------------- wave tile
+// A wave's part of a group (64 N consecutive samples) staged in LDS as 64 rows
+// of N floats, row l holding lane l's samples, with row stride RS = N + 4 so
+// that the 128-bit row accesses of 64 lanes are free of bank conflicts.
+// Coalesced slot j of lane l is float4 number v = 64 j + l of the part, i.e.
+// row v / Q, column 4 (v % Q) with Q = N / 4; since Q divides 64 this is a
+// per-lane base plus the compile-time offset j (64 / Q) RS, so the addresses
+// are one register and immediates.
+template <int N>
+struct WaveTile {
+    static constexpr int Q = N / 4;
+    static constexpr int RS = N + 4;
+    static constexpr int STEP = (kLanes / Q) * RS;
+    static __device__ __forceinline__ int slot_base(int lane)
+    {
+        return (lane / Q) * RS + (lane % Q) * 4;
+    }
+};
+
+// src[0 .. 64N) -> tile; `rem` samples are valid (zeros past them); `vec`
+// says src is 16-byte aligned. All loads of a lane are issued before the
+// first LDS write.
+template <int N>
+__device__ __forceinline__ void tile_load(const float *src, int64_t rem, bool vec, float *tl,
+                                          int lane)
+{
+    using TT = WaveTile<N>;
+    float *p = tl + TT::slot_base(lane);
+    if (vec && rem >= kLanes * N) {
+        const f4 *s4 = reinterpret_cast<const f4 *>(src) + lane;
+        f4 t[TT::Q];
+#pragma unroll
+        for (int j = 0; j < TT::Q; ++j) t[j] = __builtin_nontemporal_load(s4 + kLanes * j);
+#pragma unroll
+        for (int j = 0; j < TT::Q; ++j) *reinterpret_cast<f4 *>(p + j * TT::STEP) = t[j];
+    } else {
+        const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+#pragma unroll
+        for (int j = 0; j < TT::Q; ++j) {
+            const int q = 4 * (kLanes * j + lane);
+            f4 t;
+            t.x = q + 0 < r ? src[q + 0] : 0.0f;
+            t.y = q + 1 < r ? src[q + 1] : 0.0f;
+            t.z = q + 2 < r ? src[q + 2] : 0.0f;
+            t.w = q + 3 < r ? src[q + 3] : 0.0f;
+            *reinterpret_cast<f4 *>(p + j * TT::STEP) = t;
+        }
+    }
+}
+
+// tile -> dst[0 .. min(rem, 64N)). NT: nontemporal stores, all LDS reads
+// first (for the final output, when the lane's registers are free); otherwise
+// each slot is stored as it is read, holding 4 registers instead of N (for
+// the intermediate outputs kept for the adjoint, while the lane's N
+// registers are live).
+template <int N, bool NT>
+__device__ __forceinline__ void tile_store(float *dst, int64_t rem, bool vec, const float *tl,
+                                           int lane)
+{
+    using TT = WaveTile<N>;
+    const float *p = tl + TT::slot_base(lane);
+    if (vec && rem >= kLanes * N) {
+        f4 *d4 = reinterpret_cast<f4 *>(dst) + lane;
+        if (NT) {
+            f4 t[TT::Q];
+#pragma unroll
+            for (int j = 0; j < TT::Q; ++j) t[j] = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
+#pragma unroll
+            for (int j = 0; j < TT::Q; ++j) __builtin_nontemporal_store(t[j], d4 + kLanes * j);
+        } else {
+#pragma unroll
+            for (int j = 0; j < TT::Q; ++j) d4[kLanes * j] = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
+        }
+    } else {
+        const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+#pragma unroll
+        for (int j = 0; j < TT::Q; ++j) {
+            const int q = 4 * (kLanes * j + lane);
+            const f4 t = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
+            if (q + 0 < r) dst[q + 0] = t.x;
+            if (q + 1 < r) dst[q + 1] = t.y;
+            if (q + 2 < r) dst[q + 2] = t.z;
+            if (q + 3 < r) dst[q + 3] = t.w;
+        }
+    }
+}
+
+// lane rows of the tile <-> the lane's N registers
+template <typename T, int N>
+__device__ __forceinline__ void regs_from_rows(T (&u)[N], const float *tl, int lane)
+{
+    const float *row = tl + lane * WaveTile<N>::RS;
+#pragma unroll
+    for (int k = 0; k < N / 4; ++k) {
+        const f4 v = *reinterpret_cast<const f4 *>(row + 4 * k);
+        u[4 * k + 0] = v.x;
+        u[4 * k + 1] = v.y;
+        u[4 * k + 2] = v.z;
+        u[4 * k + 3] = v.w;
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void rows_from_regs(const T (&u)[N], float *tl, int lane)
+{
+    float *row = tl + lane * WaveTile<N>::RS;
+#pragma unroll
+    for (int k = 0; k < N / 4; ++k) {
+        const f4 v = {(float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
+                      (float)u[4 * k + 3]};
+        *reinterpret_cast<f4 *>(row + 4 * k) = v;
+    }
+}
+
 // Write the wave's registers (lane rows) to dst[g0 .. g0 + 64N) through the
 // wave's LDS rows with coalesced stores, masked at the signal end n.
 template <typename T, int N>
 __device__ __forceinline__ void store_rows(const T (&u)[N], float *tl, int lane, int64_t n,
                                            int64_t g0, float *dst)
 {
-    constexpr int RS = N + 4, Q = N / 4;
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-        *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
-            make_float4((float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
-                        (float)u[4 * k + 3]);
+    rows_from_regs<T, N>(u, tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int64_t rem = n - g0;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        const int v = kLanes * j + lane;
-        const float4 val = *reinterpret_cast<const float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]);
-        const int64_t q = 4 * (int64_t)v;
-        if (q + 0 < rem) dst[g0 + q + 0] = val.x;
-        if (q + 1 < rem) dst[g0 + q + 1] = val.y;
-        if (q + 2 < rem) dst[g0 + q + 2] = val.z;
-        if (q + 3 < rem) dst[g0 + q + 3] = val.w;
-    }
+    tile_store<N, false>(dst + g0, n - g0, (reinterpret_cast<uintptr_t>(dst + g0) & 15u) == 0, tl,
+                         lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
@@ -511,42 +628,19 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &i
 {
     constexpr int CW = kLanes * N;   // samples per wave
     constexpr int C = CW * W;        // samples per group
-    constexpr int RS = N + 4;        // LDS row stride: conflict-free 128-bit row reads
-    constexpr int Q = N / 4;         // float4 per lane row
 
     const int64_t g0 = it.g * C + (int64_t)wv * CW;   // first sample of this wave
     const int64_t rem = it.n - g0;                    // may be <= 0 in the last group
-    const bool full = rem >= CW;
     const bool vec = ((reinterpret_cast<uintptr_t>(it.x) | reinterpret_cast<uintptr_t>(it.y)) &
                       15u) == 0;
 
-    // --- load: coalesced 128-bit global loads -> LDS rows (transpose)
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        const int v = kLanes * j + lane;           // float4 index inside the wave's part
-        const int64_t q = 4 * (int64_t)v;
-        float4 val;
-        if (full && vec) {
-            const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(it.x + g0) + v);
-            val = make_float4(t.x, t.y, t.z, t.w);
-        } else {
-            val.x = q + 0 < rem ? it.x[g0 + q + 0] : 0.0f;
-            val.y = q + 1 < rem ? it.x[g0 + q + 1] : 0.0f;
-            val.z = q + 2 < rem ? it.x[g0 + q + 2] : 0.0f;
-            val.w = q + 3 < rem ? it.x[g0 + q + 3] : 0.0f;
-        }
-        *reinterpret_cast<float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]) = val;
-    }
-    __syncthreads();
+    // --- load: coalesced 128-bit global loads -> the wave's LDS rows -> registers.
+    //     The tile is the wave's own, so wave-scope ordering suffices.
+    tile_load<N>(it.x + g0, rem, vec, tl, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     T u[N];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        const float4 v = *reinterpret_cast<const float4 *>(&tl[lane * RS + 4 * k]);
-        u[4 * k + 0] = v.x;
-        u[4 * k + 1] = v.y;
-        u[4 * k + 2] = v.z;
-        u[4 * k + 3] = v.w;
-    }
+    regs_from_rows<T, N>(u, tl, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
     // --- sections (an unusable section poisons its signal)
     bool bad = false;
@@ -556,7 +650,6 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &i
     const int64_t lp = (it.n - 1) - g0;
     const bool has_last = lp >= 0 && lp < CW;
     const int zl = has_last ? (int)(lp / N) : 0, zp = has_last ? (int)(lp % N) : 0;
-    __syncthreads();   // the rows were read; the tile is scratch from here on
     if (!bad) {
         for (int s = 0; s < it.K; ++s) {
             T q1, q2;
@@ -572,29 +665,11 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &i
             for (int s = 0; s < it.K; ++s) it.zf[2 * s] = it.zf[2 * s + 1] = __builtin_nanf("");
     }
 
-    // --- store: registers -> LDS rows -> coalesced 128-bit global stores
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-        *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
-            make_float4((float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
-                        (float)u[4 * k + 3]);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        const int v = kLanes * j + lane;
-        const int64_t q = 4 * (int64_t)v;
-        const float4 val = *reinterpret_cast<const float4 *>(&tl[(v / Q) * RS + (v % Q) * 4]);
-        if (full && vec) {
-            const f4 t = {val.x, val.y, val.z, val.w};
-            __builtin_nontemporal_store(t, reinterpret_cast<f4 *>(it.y + g0) + v);
-        } else {
-            if (q + 0 < rem) it.y[g0 + q + 0] = val.x;
-            if (q + 1 < rem) it.y[g0 + q + 1] = val.y;
-            if (q + 2 < rem) it.y[g0 + q + 2] = val.z;
-            if (q + 3 < rem) it.y[g0 + q + 3] = val.w;
-        }
-    }
+    // --- store: registers -> the wave's LDS rows -> coalesced 128-bit global stores
+    rows_from_regs<T, N>(u, tl, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    tile_store<N, true>(it.y + g0, rem, vec, tl, lane);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
 // The filter kernel: every workgroup draws tickets until the work runs out.

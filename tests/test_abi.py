@@ -47,6 +47,8 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_get_tile(None, None, None) == P.SOS_EINVAL
     assert lib.sos_set_precision(None, 64) == P.SOS_EINVAL
     assert lib.sos_get_precision(None) == P.SOS_EINVAL
+    assert lib.sos_set_timeout(None, 1.0) == P.SOS_EINVAL
+    assert lib.sos_wall_clock_khz(None) == P.SOS_EINVAL
     assert lib.sos_filter_batched(None, 1, 1, 1, 10, None, None, None, None, None, None, None,
                                   None, None) == P.SOS_EINVAL
     assert lib.sos_filter_train(None, None, 1, None, None, 10, None, None, None,

@@ -251,3 +251,32 @@ def test_lightly_damped_order16(torch_cuda, P, tile):
     assert rel_l2(y64, yr) <= 1e-5
     assert rel_l2(zf64, zfr) <= 1e-5
     assert np.isfinite(y32).all()
+
+
+def test_lookback_timeout_is_bounded_and_reported(torch_cuda, P):
+    """A one-tick bound on each lookback wait, forced from the host: the launch
+    still ends, any group whose wait ran out is NaN and the handle reports
+    SOS_ETIMEOUT; with the default bound restored the same handle is exact."""
+    torch = torch_cuda
+    K = 4
+    sos = workloads.sweep_sections(K, "random")
+    n = 1 << 22
+    x = workloads.signal(n, seed=31)
+    h = P.Handle(0, tile=(256, 16))
+    print("device wall clock kHz", h.wall_clock_khz())
+    xd = torch.from_numpy(x).cuda()
+    sd = torch.from_numpy(sos).cuda()
+    h.set_timeout(1e-6)
+    y, _ = P.sosfilt(xd, sd, handle=h)
+    torch.cuda.synchronize()
+    err = h.last_error()
+    has_nan = bool(torch.isnan(y).any().item())
+    print("one-tick bound: status", err, "NaN outputs", has_nan)
+    assert err in (P.SOS_OK, P.SOS_ETIMEOUT)
+    assert has_nan == (err == P.SOS_ETIMEOUT)
+    h.set_timeout(0)
+    y, _ = P.sosfilt(xd, sd, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    yr, _ = oracle.sosfilt(sos, x)
+    assert rel_l2(y.cpu().numpy(), yr) <= 1e-5
