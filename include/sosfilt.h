@@ -216,6 +216,76 @@ int sos_bench_copy(const float *x, float *y, int64_t n, hipStream_t stream);
 int sos_debug_carries(sos_handle_t h, float *out, int64_t capacity_floats, int64_t *groups,
                       int *K);
 
+/* ------------------------------------------------------------------ serving
+ * Many long signals ("streams") that arrive in chunks, each filtered by its
+ * own cascade as one continuous signal (the problem of Sec. II per stream;
+ * chunked filtering with carried state is exact by the superposition of
+ * Sec. II-F: a chunk's output is its zero-state response plus the response to
+ * the state the previous chunk left). A server keeps every open stream's
+ * sections, their prepared tables and its K TDF-II states in device memory
+ * between chunks, and batches pending chunks continuously: one scheduler
+ * thread forms steps of at most one chunk per stream (oldest first), each
+ * step one persistent launch of the uneven-batch path, queued in order on
+ * one HIP stream so a stream's chunks run in FIFO order, while chunks that
+ * arrive during a step join the next one.
+ *
+ * Chunk and output buffers are DEVICE pointers owned by the caller, who keeps
+ * them alive until sos_stream_wait returns for that chunk; out may equal
+ * chunk. Operations on one server may come from any host thread. */
+typedef struct sos_srv *sos_server_t;
+
+/* Create a server on the device of `h`, with h's tile (L, N), compute type
+ * and lookback bound (h itself is not used afterwards; the server has its own
+ * workspace). device_mem_budget bytes (0 = 256 MiB) are split between stream
+ * rows (sections, states and tables: K rows per stream) and one step's work
+ * table and descriptors, which bounds the samples of a step and of a chunk
+ * (sos_server_limits). max_slots (>= 1) bounds the chunks of one step.
+ * Allocates everything up front; no device allocation happens while serving. */
+int sos_server_create(sos_server_t *s, sos_handle_t h, size_t device_mem_budget, int max_slots);
+/* Stop the scheduler, let steps on the device finish, fail chunks not yet in
+ * a step with SOS_ECLOSED, free everything. */
+int sos_server_destroy(sos_server_t s);
+/* Capacity: stream rows in total, largest chunk (samples), and the tile. */
+int sos_server_limits(sos_server_t s, int64_t *max_rows, int64_t *max_chunk, int *L, int *N);
+
+/* Open a stream with K sections (HOST array K x 6, same layout and
+ * normalisation as sos_filter) and initial TDF-II states zi (HOST K x 2, NULL
+ * = zeros). Synchronous: copies and prepares the tables and checks them;
+ * returns SOS_EA0 / SOS_EUNSTABLE for unusable sections, SOS_EBUSY when the
+ * stream rows are used up. *stream_id receives the stream's id. */
+int sos_stream_open(sos_server_t s, const float *sections_host, int K, const float *zi_host,
+                    int64_t *stream_id);
+/* Enqueue the next chunk of a stream: n samples at `chunk`, output to `out`.
+ * Returns at once with a ticket for sos_stream_wait. SOS_EINVAL for n < 0 or
+ * n above the largest chunk, SOS_ECLOSED for an unknown or closing stream. */
+int sos_stream_push(sos_server_t s, int64_t stream_id, const float *chunk, int64_t n, float *out,
+                    uint64_t *ticket);
+/* The same for `count` chunks at once (one lock; arrays of count entries). */
+int sos_stream_push_many(sos_server_t s, int count, const int64_t *stream_ids,
+                         const float *const *chunks, const int64_t *n, float *const *outs,
+                         uint64_t *tickets);
+/* Block until the chunk is filtered; returns its status (SOS_OK, or
+ * SOS_ETIMEOUT / SOS_EINVAL / SOS_EHIP for its step, SOS_ECLOSED if the server
+ * was destroyed first) and, if latency_s is not NULL, the time in seconds from
+ * its push to the host's observation that its step completed. A ticket can be
+ * waited on once. */
+int sos_stream_wait(sos_server_t s, uint64_t ticket, double *latency_s);
+/* After all chunks pushed so far on the stream are finished, copy its K x 2
+ * TDF-II state to HOST memory zf_host (a checkpoint: reopening a stream with
+ * these states continues it exactly). */
+int sos_stream_state(sos_server_t s, int64_t stream_id, float *zf_host);
+/* Wait for the stream's outstanding chunks, then release its rows. */
+int sos_stream_close(sos_server_t s, int64_t stream_id);
+/* Load driver for measurement: push chunk r (n = lens[r] samples at
+ * x + offs[r], output at y + offs[r], DEVICE memory) of stream stream_ids[r]
+ * at arrival_s[r] seconds after the call (arrival times ascending), from
+ * the calling thread, then wait for all; latency_s[r] (nullable) receives each
+ * chunk's latency and *wall_s the time from the start to the last completion.
+ * Returns the first failing status. */
+int sos_server_replay(sos_server_t s, int64_t R, const int64_t *stream_ids, const int64_t *offs,
+                      const int64_t *lens, const double *arrival_s, const float *x, float *y,
+                      double *latency_s, double *wall_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,24 @@ def lib():
             L.sos_get_precision.argtypes = [vp]
             L.sos_filter_train.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp, vp]
             L.sos_filter_vjp.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+            u64p = ctypes.POINTER(ctypes.c_uint64)
+            dp = ctypes.POINTER(ctypes.c_double)
+            L.sos_server_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_size_t, i32]
+            L.sos_server_destroy.argtypes = [vp]
+            L.sos_server_limits.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                            ctypes.POINTER(i32), ctypes.POINTER(i32)]
+            L.sos_stream_open.argtypes = [vp, vp, i32, vp, ctypes.POINTER(i64)]
+            L.sos_stream_push.argtypes = [vp, i64, vp, i64, vp, u64p]
+            L.sos_stream_push_many.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+            L.sos_stream_wait.argtypes = [vp, ctypes.c_uint64, dp]
+            L.sos_stream_state.argtypes = [vp, i64, vp]
+            L.sos_stream_close.argtypes = [vp, i64]
+            L.sos_server_replay.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, dp]
+            for name in ("sos_server_create", "sos_server_destroy", "sos_server_limits",
+                         "sos_stream_open", "sos_stream_push", "sos_stream_push_many",
+                         "sos_stream_wait", "sos_stream_state", "sos_stream_close",
+                         "sos_server_replay"):
+                getattr(L, name).restype = i32
             for name in ("sos_create", "sos_destroy", "sos_last_error", "sos_set_tile",
                          "sos_get_tile", "sos_filter", "sos_debug_carries", "sos_prepare",
                          "sos_filter_prepared", "sos_bench_copy", "sos_filter_batched",
@@ -367,3 +385,117 @@ def sosfilt_autograd(x, sos, zi=None):
     if zi is None:
         zi = torch.zeros((sos.shape[0], 2), dtype=torch.float32, device=x.device)
     return _fn.apply(x, sos, zi)
+
+
+class Server:
+    """Continuous-batching server over the C ABI (sos_server_* / sos_stream_*).
+
+    Streams keep their sections, tables and TDF-II state on the device; chunks
+    are float32 CUDA tensors that must stay alive until `wait` returns for
+    them (the server keeps a reference to each pushed chunk and output until
+    then). The tile, compute type and lookback bound come from `handle` (or a
+    new handle made with `tile` / `precision`)."""
+
+    def __init__(self, handle: Handle | None = None, budget: int = 0, max_slots: int = 1024,
+                 device: int = 0, tile=None, precision: int = 0):
+        h = handle or Handle(device, tile=tile, precision=precision)
+        self.device = h.device
+        self._s = ctypes.c_void_p()
+        _check(lib().sos_server_create(ctypes.byref(self._s), h.ptr, int(budget), int(max_slots)),
+               "sos_server_create")
+        self._keep = {}
+        self._K = {}
+
+    @property
+    def ptr(self):
+        if not self._s:
+            raise SosError(SOS_ECLOSED, "server is closed")
+        return self._s
+
+    def limits(self):
+        r, c = ctypes.c_int64(), ctypes.c_int64()
+        L, N = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sos_server_limits(self.ptr, ctypes.byref(r), ctypes.byref(c), ctypes.byref(L),
+                                       ctypes.byref(N)), "sos_server_limits")
+        return {"max_rows": r.value, "max_chunk": c.value, "tile": (L.value, N.value)}
+
+    def open(self, sections, zi=None) -> int:
+        """Open a stream; sections (K x 6) and zi (K x 2) are host arrays."""
+        import numpy as np
+
+        sec = np.ascontiguousarray(np.asarray(sections, dtype=np.float32).reshape(-1, 6))
+        z = None if zi is None else np.ascontiguousarray(np.asarray(zi, dtype=np.float32))
+        if z is not None and z.size != 2 * sec.shape[0]:
+            raise ValueError("zi must hold K x 2 values")
+        sid = ctypes.c_int64()
+        _check(lib().sos_stream_open(self.ptr, sec.ctypes.data if sec.size else None, sec.shape[0],
+                                     None if z is None else z.ctypes.data, ctypes.byref(sid)),
+               "sos_stream_open")
+        self._K[sid.value] = sec.shape[0]
+        return sid.value
+
+    def push(self, stream_id: int, chunk, out=None):
+        """Enqueue a chunk (1-D float32 CUDA tensor); returns (ticket, out)."""
+        import torch
+
+        if chunk.dtype != torch.float32 or not chunk.is_cuda or not chunk.is_contiguous():
+            raise TypeError("chunk must be a contiguous float32 CUDA tensor")
+        if out is None:
+            out = torch.empty_like(chunk)
+        tk = ctypes.c_uint64()
+        # the caller's stream must have produced `chunk` before the server reads it
+        torch.cuda.current_stream(chunk.device).synchronize()
+        _check(lib().sos_stream_push(self.ptr, int(stream_id), _p(chunk), chunk.numel(), _p(out),
+                                     ctypes.byref(tk)), "sos_stream_push")
+        self._keep[tk.value] = (chunk, out)
+        return tk.value, out
+
+    def wait(self, ticket: int) -> float:
+        """Block until the chunk is done; returns its latency in seconds."""
+        lat = ctypes.c_double()
+        rc = lib().sos_stream_wait(self.ptr, ctypes.c_uint64(ticket), ctypes.byref(lat))
+        self._keep.pop(ticket, None)
+        _check(rc, "sos_stream_wait")
+        return lat.value
+
+    def state(self, stream_id: int):
+        import numpy as np
+
+        buf = np.zeros((max(self._K.get(int(stream_id), 0), 1), 2), dtype=np.float32)
+        _check(lib().sos_stream_state(self.ptr, int(stream_id), buf.ctypes.data),
+               "sos_stream_state")
+        return buf[:self._K.get(int(stream_id), 0)]
+
+    def close_stream(self, stream_id: int):
+        _check(lib().sos_stream_close(self.ptr, int(stream_id)), "sos_stream_close")
+        self._K.pop(int(stream_id), None)
+
+    def replay(self, stream_ids, offs, lens, arrival_s, x, y):
+        """Native load driver; returns (latencies [s] per chunk, wall seconds)."""
+        import numpy as np
+
+        ids = np.ascontiguousarray(stream_ids, dtype=np.int64)
+        o = np.ascontiguousarray(offs, dtype=np.int64)
+        n = np.ascontiguousarray(lens, dtype=np.int64)
+        t = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        lat = np.zeros(len(ids), dtype=np.float64)
+        wall = ctypes.c_double()
+        import torch
+
+        torch.cuda.current_stream(x.device).synchronize()
+        _check(lib().sos_server_replay(self.ptr, len(ids), ids.ctypes.data, o.ctypes.data,
+                                       n.ctypes.data, t.ctypes.data, _p(x), _p(y), lat.ctypes.data,
+                                       ctypes.byref(wall)), "sos_server_replay")
+        return lat, wall.value
+
+    def close(self):
+        if self._s:
+            lib().sos_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -63,6 +63,8 @@ struct FwdArgs {
     const int64_t *gpre;    // B+1 prefix of group counts
     const int32_t *sigmap;  // ticket -> signal
     const int64_t *total_dev;  // number of work items (batched)
+    const float *const *xp; // batched, optional: per-signal input pointers (else x + sig_off)
+    float *const *yp;       //   and output pointers (else y + sig_off)
     // both modes
     float *saved;           // plain mode, optional: outputs of sections 0..K-2 ((K-1) x n)
     int64_t total;          // number of work items (plain)
@@ -713,8 +715,8 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
             const int i = a.sigmap[t];
             const int64_t so = a.sig_off[i];
             const int32_t sc = a.sec_off[i];
-            it.x = a.x + so;
-            it.y = a.y + so;
+            it.x = a.xp ? a.xp[i] : a.x + so;
+            it.y = a.yp ? a.yp[i] : a.y + so;
             it.n = a.sig_off[i + 1] - so;
             it.g = t - a.gpre[i];
             it.tabs = tabs + (size_t)sc * TAB_FLOATS;
@@ -1048,11 +1050,14 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
                                              const float *zi, float *zf,
                                              unsigned long long *desc, unsigned *ctrl,
                                              unsigned long long timeout_ticks, int64_t grid,
+                                             const float *const *xp, float *const *yp,
                                              hipStream_t stream)
 {
     FwdArgs a{};
     a.x = x;
     a.y = y;
+    a.xp = xp;
+    a.yp = yp;
     a.tabs = tabs;
     a.zi = zi;
     a.zf = zf;

@@ -1,0 +1,147 @@
+// Internal declarations shared by the host-side sources of the library: the
+// kernel launchers, the handle structure and its shape/precision helpers.
+// Not part of the public ABI (include/sosfilt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+#include <mutex>
+
+#include "sosfilt.h"
+#include "sos_device.h"
+
+extern "C" {
+hipError_t sos_launch_prep(int bits, const float *sections, int K, int log2n, int log2w,
+                           void *tabs, unsigned *ctrl, int pair, hipStream_t stream);
+hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int kmax, int64_t rows,
+                                   const int32_t *Ks, const int32_t *sec_off, int log2n,
+                                   int log2w, void *tabs, unsigned *ctrl, hipStream_t stream);
+hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
+hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, float *y, int64_t n,
+                          int64_t groups, const void *tabs, int K, const float *zi, float *zf,
+                          unsigned long long *desc, unsigned *ctrl,
+                          unsigned long long timeout_ticks, int64_t grid, float *saved,
+                          hipStream_t stream);
+hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax, const int32_t *Ks,
+                                  const int32_t *sec_off, const int64_t *sig_off,
+                                  const int64_t *gpre, const int32_t *sigmap,
+                                  const int64_t *total_dev, const float *x, float *y,
+                                  const void *tabs, const float *zi, float *zf,
+                                  unsigned long long *desc, unsigned *ctrl,
+                                  unsigned long long timeout_ticks, int64_t grid,
+                                  const float *const *xp, float *const *yp, hipStream_t stream);
+hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
+                                int64_t max_groups, const int32_t *Ks, const int32_t *sec_off,
+                                const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
+                                int64_t *total_dev, const float *zi, float *zf, unsigned *ctrl,
+                                hipStream_t stream);
+hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx, int64_t n,
+                          int64_t groups, const void *tabs, int K, const float *x,
+                          const float *y, const float *saved, const float *gzf, float *gzi,
+                          double *partials, unsigned long long *desc, unsigned *ctrl,
+                          unsigned long long timeout_ticks, int64_t grid, hipStream_t stream);
+hipError_t sos_launch_bwd_reduce(const double *partials, int64_t groups, int K,
+                                 const float *sections, float *gsections, hipStream_t stream);
+hipError_t sos_launch_fill(float *dst, const float *src, int64_t count, hipStream_t stream);
+hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
+int sos_fwd_shape_supported(int L, int N);
+int sos_fwd_capacity(int bits, int L, int N);
+int sos_bwd_shape_supported(int L, int N);
+}
+
+struct sos_ctx {
+    int device = 0;
+    int tile_L = 0;                       // lanes per group L = 64 W; 0 = default
+    int tile_N = 0;                       // samples per lane N; 0 = default
+    int bits = 0;                         // compute type: 32, 64; 0 = default
+    unsigned *ctrl = nullptr;             // CTRL_WORDS
+    unsigned char *tabs = nullptr;        // coefficient tables (bytes)
+    size_t tabs_cap = 0;
+    unsigned long long *desc = nullptr;   // lookback descriptors
+    size_t desc_cap = 0;                  // 64-bit words
+    unsigned long long timeout_ticks = 0;  // lookback wait bound, in wall-clock ticks
+    int wall_khz = 0;                     // device wall clock (s_memrealtime) rate
+    int64_t last_groups = 0;
+    int last_K = 0;
+    int prep_K = -1;                      // tables currently prepared (K, shape, type)
+    int prep_L = 0;
+    int prep_N = 0;
+    int prep_bits = 0;
+    // uneven-batch work table
+    int64_t *gpre = nullptr;
+    size_t gpre_cap = 0;
+    int32_t *sigmap = nullptr;
+    size_t sigmap_cap = 0;
+    int64_t *total_dev = nullptr;
+    // adjoint
+    unsigned char *tabs_bwd = nullptr;
+    size_t tabs_bwd_cap = 0;
+    double *partials = nullptr;
+    size_t partials_cap = 0;
+    std::mutex mu;
+};
+
+namespace sosint {
+
+constexpr int kDefaultL = 512;   // measured best at order 2 with a persistent grid
+constexpr int kDefaultN = 64;
+constexpr int kDefaultBits = 32;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct Tile {
+    int L, N;
+};
+
+inline Tile tile_of(const sos_ctx *h)
+{
+    Tile t{kDefaultL, kDefaultN};
+    if (const char *e = std::getenv("SOS_TILE_L")) {
+        const int v = std::atoi(e);
+        if (sos_fwd_shape_supported(v, t.N)) t.L = v;
+    }
+    if (const char *e = std::getenv("SOS_TILE_N")) {
+        const int v = std::atoi(e);
+        if (sos_fwd_shape_supported(t.L, v)) t.N = v;
+    }
+    if (h->tile_L) t = Tile{h->tile_L, h->tile_N};
+    return t;
+}
+
+inline int bits_of(const sos_ctx *h)
+{
+    if (h->bits) return h->bits;
+    if (const char *e = std::getenv("SOS_PRECISION")) {
+        const int v = std::atoi(e);
+        if (v == 32 || v == 64) return v;
+    }
+    return kDefaultBits;
+}
+
+inline int64_t grid_of(int bits, int L, int N)
+{
+    // persistent grid: as many workgroups as can be resident, drawing tickets
+    // until the groups run out (measured faster than one workgroup per group)
+    int64_t grid = sos_fwd_capacity(bits, L, N);
+    if (const char *e = std::getenv("SOS_PERSISTENT")) {
+        const int f = std::atoi(e);
+        grid = f > 0 ? (int64_t)f * grid : 0;   // 0: one workgroup per group
+    }
+    return grid;
+}
+
+}  // namespace sosint

@@ -1,0 +1,640 @@
+// Serving layer: continuous batching of per-stream filtering requests.
+//
+// A stream is one long signal that arrives in chunks, filtered by its own
+// cascade (Sec. II's problem per stream). Its sections, their coefficient
+// tables and its K TDF-II states live in device tables for the life of the
+// stream, so a chunk is filtered from the state the previous chunk left, in
+// place (zi = zf = the stream's state rows).
+//
+// One scheduler thread forms steps. A step is one persistent batched launch
+// (the uneven-batch path: work table, arm, filter) over at most one chunk of
+// each stream with work pending, taken in arrival order of the streams, up
+// to `max_slots` chunks and a sample budget derived from the device memory
+// budget. Steps are queued on one HIP stream, so a stream's next chunk may
+// enter the next step while the current one runs: HIP stream order keeps
+// each stream's chunks in FIFO order, and chunks that arrive while steps are
+// on the device join the next step as soon as a step slot frees up. Chunk
+// buffers are the caller's device memory, addressed through per-signal
+// pointer tables (no gather copies).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "sos_internal.h"
+
+using namespace sosdev;
+using namespace sosint;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr int kSteps = 3;                        // steps in flight
+constexpr size_t kDefaultBudget = 256ull << 20;  // bytes
+constexpr int kPending = 1;                      // request status while not finished
+
+// First-fit allocator of contiguous row ranges [0, n).
+struct RowPool {
+    std::vector<std::pair<int64_t, int64_t>> free_;   // (offset, length), sorted
+    void init(int64_t n)
+    {
+        free_.clear();
+        if (n > 0) free_.push_back({0, n});
+    }
+    int64_t alloc(int64_t k)
+    {
+        for (size_t i = 0; i < free_.size(); ++i) {
+            if (free_[i].second >= k) {
+                const int64_t off = free_[i].first;
+                free_[i].first += k;
+                free_[i].second -= k;
+                if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t k)
+    {
+        if (k <= 0) return;
+        auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (int64_t)0));
+        it = free_.insert(it, {off, k});
+        size_t i = (size_t)(it - free_.begin());
+        if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+            free_[i].second += free_[i + 1].second;
+            free_.erase(free_.begin() + (long)i + 1);
+        }
+        if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+            free_[i - 1].second += free_[i].second;
+            free_.erase(free_.begin() + (long)i);
+        }
+    }
+};
+
+struct Request {
+    int64_t stream;
+    const float *x;
+    float *y;
+    int64_t n;
+    Clock::time_point t_push;
+    int status = kPending;
+    double latency = 0.0;
+};
+
+struct Stream {
+    int K = 0;
+    int64_t row = 0;
+    std::deque<uint64_t> pending;   // pushed, not yet in a step
+    int64_t outstanding = 0;        // pushed, not yet retired
+    bool in_ready = false;
+    bool closing = false;
+};
+
+// Per-step argument arrays, laid out identically in pinned host memory and
+// in the device copy: K | sec_off | sig_off | xp | yp (| err word, host only).
+struct ArgLayout {
+    size_t k, sec, sig, xp, yp, bytes, err;
+    explicit ArgLayout(int slots = 0)
+    {
+        auto up8 = [](size_t v) { return (v + 7) & ~(size_t)7; };
+        k = 0;
+        sec = up8(k + 4 * (size_t)slots);
+        sig = up8(sec + 4 * (size_t)slots);
+        xp = sig + 8 * ((size_t)slots + 1);
+        yp = xp + 8 * (size_t)slots;
+        bytes = yp + 8 * (size_t)slots;
+        err = bytes;
+    }
+};
+
+struct Step {
+    bool busy = false;
+    hipEvent_t done = nullptr;
+    unsigned char *host = nullptr;   // pinned, ArgLayout::bytes + 8
+    std::vector<uint64_t> tickets;
+};
+
+}  // namespace
+
+struct sos_srv {
+    sos_ctx *h = nullptr;             // own workspace: ctrl, descriptors, work table
+    hipStream_t stream = nullptr;     // steps
+    hipStream_t ostream = nullptr;    // stream opening (table preparation)
+    unsigned *octrl = nullptr;        // error word of the preparation launches
+    int device = 0, L = 0, N = 0, bits = 32;
+    int64_t C = 0;
+    int max_slots = 0;
+    int64_t max_rows = 0, max_groups = 0, max_step_samples = 0;
+    size_t tab_row_bytes = 0;
+    float *sections = nullptr;        // max_rows x 6
+    float *state = nullptr;           // max_rows x 2
+    unsigned char *tabs = nullptr;    // max_rows x tab_row_bytes
+    unsigned char *dargs = nullptr;   // device copy of a step's arguments
+    ArgLayout lay;
+    Step steps[kSteps];
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    std::unordered_map<int64_t, Stream> streams;
+    int64_t next_stream = 1;
+    std::unordered_map<uint64_t, Request> reqs;
+    uint64_t next_ticket = 1;
+    std::deque<int64_t> ready;        // streams with pending chunks
+    RowPool rows;
+};
+
+namespace {
+
+int status_of_bits(unsigned b)
+{
+    if (b & ERRBIT_TIMEOUT) return SOS_ETIMEOUT;
+    if (b & ERRBIT_BADARG) return SOS_EINVAL;
+    if (b & ERRBIT_A0) return SOS_EA0;
+    if (b & ERRBIT_UNSTABLE) return SOS_EUNSTABLE;
+    return SOS_OK;
+}
+
+void retire(sos_srv *s, Step &st, int status)
+{
+    const Clock::time_point now = Clock::now();
+    for (uint64_t tk : st.tickets) {
+        auto it = s->reqs.find(tk);
+        if (it == s->reqs.end()) continue;
+        Request &rq = it->second;
+        rq.status = status;
+        rq.latency = std::chrono::duration<double>(now - rq.t_push).count();
+        auto si = s->streams.find(rq.stream);
+        if (si != s->streams.end()) --si->second.outstanding;
+    }
+    st.tickets.clear();
+    st.busy = false;
+    s->cv_done.notify_all();
+}
+
+// Form a step from the ready streams and enqueue it (lock held).
+void launch_step(sos_srv *s, Step &st)
+{
+    unsigned char *hb = st.host;
+    int32_t *K = reinterpret_cast<int32_t *>(hb + s->lay.k);
+    int32_t *sec = reinterpret_cast<int32_t *>(hb + s->lay.sec);
+    int64_t *sig = reinterpret_cast<int64_t *>(hb + s->lay.sig);
+    const float **xp = reinterpret_cast<const float **>(hb + s->lay.xp);
+    float **yp = reinterpret_cast<float **>(hb + s->lay.yp);
+    unsigned *err = reinterpret_cast<unsigned *>(hb + s->lay.err);
+    int B = 0, kmax = 0;
+    int64_t total = 0;
+    std::deque<int64_t> deferred;
+    while (!s->ready.empty() && B < s->max_slots) {
+        const int64_t sid = s->ready.front();
+        s->ready.pop_front();
+        Stream &str = s->streams[sid];
+        str.in_ready = false;
+        if (str.pending.empty()) continue;
+        const uint64_t tk = str.pending.front();
+        Request &rq = s->reqs[tk];
+        if (B > 0 && total + rq.n > s->max_step_samples) {
+            deferred.push_back(sid);        // does not fit this step
+            continue;
+        }
+        str.pending.pop_front();
+        K[B] = str.K;
+        sec[B] = (int32_t)str.row;
+        sig[B] = total;
+        xp[B] = rq.x;
+        yp[B] = rq.y;
+        total += rq.n;
+        kmax = std::max(kmax, str.K);
+        st.tickets.push_back(tk);
+        ++B;
+        if (!str.pending.empty()) deferred.push_back(sid);   // its next chunk: a later step
+    }
+    for (int64_t sid : deferred) {
+        Stream &str = s->streams[sid];
+        if (!str.in_ready) {
+            str.in_ready = true;
+            s->ready.push_back(sid);
+        }
+    }
+    if (B == 0) return;
+    sig[B] = total;
+    *err = 0;
+    st.busy = true;
+    sos_ctx *h = s->h;
+    const unsigned char *d = s->dargs;
+    const int32_t *dK = reinterpret_cast<const int32_t *>(d + s->lay.k);
+    const int32_t *dsec = reinterpret_cast<const int32_t *>(d + s->lay.sec);
+    const int64_t *dsig = reinterpret_cast<const int64_t *>(d + s->lay.sig);
+    const float *const *dxp = reinterpret_cast<const float *const *>(d + s->lay.xp);
+    float *const *dyp = reinterpret_cast<float *const *>(d + s->lay.yp);
+    int64_t grid = grid_of(s->bits, s->L, s->N);
+    if (grid <= 0 || grid > s->max_groups) grid = s->max_groups;
+    bool ok =
+        hipMemcpyAsync(s->dargs, hb, s->lay.bytes, hipMemcpyHostToDevice, s->stream) ==
+            hipSuccess &&
+        sos_launch_worktable(B, kmax, s->max_rows, s->C, total, s->max_groups, dK, dsec, dsig,
+                             h->gpre, h->sigmap, h->total_dev, s->state, s->state, h->ctrl,
+                             s->stream) == hipSuccess &&
+        sos_launch_arm(h->ctrl, s->stream) == hipSuccess &&
+        sos_launch_fwd_batched(s->bits, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
+                               h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
+                               s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
+                               s->stream) == hipSuccess &&
+        hipMemcpyAsync(err, h->ctrl + CTRL_ERR, sizeof(unsigned), hipMemcpyDeviceToHost,
+                       s->stream) == hipSuccess &&
+        sos_launch_fill(reinterpret_cast<float *>(h->ctrl + CTRL_ERR), nullptr, 1, s->stream) ==
+            hipSuccess &&
+        hipEventRecord(st.done, s->stream) == hipSuccess;
+    if (!ok) retire(s, st, SOS_EHIP);
+}
+
+void worker_main(sos_srv *s)
+{
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool busy = false;
+        for (Step &st : s->steps) {
+            if (!st.busy) continue;
+            const hipError_t q = hipEventQuery(st.done);
+            if (q == hipErrorNotReady) {
+                busy = true;
+                continue;
+            }
+            const unsigned bits = *reinterpret_cast<unsigned *>(st.host + s->lay.err);
+            retire(s, st, q == hipSuccess ? status_of_bits(bits) : SOS_EHIP);
+        }
+        if (s->stop && !busy) break;
+        Step *freeslot = nullptr;
+        for (Step &st : s->steps)
+            if (!st.busy) {
+                freeslot = &st;
+                break;
+            }
+        if (!s->stop && freeslot && !s->ready.empty()) {
+            launch_step(s, *freeslot);
+            continue;
+        }
+        if (busy)
+            s->cv_work.wait_for(lk, std::chrono::microseconds(5));
+        else
+            s->cv_work.wait(lk);
+    }
+}
+
+void free_server(sos_srv *s)
+{
+    for (Step &st : s->steps) {
+        if (st.done) (void)hipEventDestroy(st.done);
+        if (st.host) (void)hipHostFree(st.host);
+    }
+    for (void *p : {(void *)s->sections, (void *)s->state, (void *)s->tabs, (void *)s->dargs,
+                    (void *)s->octrl})
+        if (p) (void)hipFree(p);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->ostream) (void)hipStreamDestroy(s->ostream);
+    if (s->h) (void)sos_destroy(s->h);
+    delete s;
+}
+
+// Push `count` chunks (lock not held). Returns the first failing code.
+int push_many(sos_srv *s, int count, const int64_t *ids, const float *const *x,
+              float *const *y, const int64_t *n, uint64_t *tickets)
+{
+    const Clock::time_point now = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return SOS_ECLOSED;
+    for (int r = 0; r < count; ++r) {
+        auto it = s->streams.find(ids[r]);
+        if (it == s->streams.end() || it->second.closing) return SOS_ECLOSED;
+        if (n[r] < 0 || n[r] > s->max_step_samples || (n[r] > 0 && (!x[r] || !y[r])))
+            return SOS_EINVAL;
+    }
+    for (int r = 0; r < count; ++r) {
+        Stream &str = s->streams[ids[r]];
+        const uint64_t tk = s->next_ticket++;
+        Request rq;
+        rq.stream = ids[r];
+        rq.x = x[r];
+        rq.y = y[r];
+        rq.n = n[r];
+        rq.t_push = now;
+        s->reqs.emplace(tk, rq);
+        str.pending.push_back(tk);
+        ++str.outstanding;
+        if (!str.in_ready) {
+            str.in_ready = true;
+            s->ready.push_back(ids[r]);
+        }
+        tickets[r] = tk;
+    }
+    s->cv_work.notify_one();
+    return SOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budget,
+                      int max_slots)
+{
+    if (!out || !hu || max_slots < 1 || max_slots > (1 << 20)) return SOS_EINVAL;
+    *out = nullptr;
+    sos_srv *s = new (std::nothrow) sos_srv();
+    if (!s) return SOS_ENOMEM;
+    s->device = hu->device;
+    DeviceGuard g(s->device);
+    if (!g.ok) {
+        delete s;
+        return SOS_EHIP;
+    }
+    int rc = sos_create(&s->h, s->device);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    const Tile t = tile_of(hu);
+    s->L = t.L;
+    s->N = t.N;
+    s->bits = bits_of(hu);
+    s->h->timeout_ticks = hu->timeout_ticks;
+    s->C = (int64_t)t.L * t.N;
+    s->max_slots = max_slots;
+    s->lay = ArgLayout(max_slots);
+    s->tab_row_bytes = (size_t)TAB_FLOATS * (s->bits == 64 ? 8 : 4);
+    const size_t budget = device_mem_budget ? device_mem_budget : kDefaultBudget;
+    // half for per-stream rows (sections, state, tables), half for a step's
+    // work table and descriptors (stride up to SOS_MAX_SECTIONS)
+    const size_t row_bytes = 6 * 4 + 2 * 4 + s->tab_row_bytes;
+    s->max_rows = (int64_t)((budget / 2) / row_bytes);
+    const size_t group_bytes = (size_t)SOS_MAX_SECTIONS * 4 * 8 + 4;
+    s->max_groups = (int64_t)((budget / 2) / group_bytes);
+    s->max_step_samples = (s->max_groups - max_slots) * s->C;
+    if (s->max_rows < 1 || s->max_step_samples < s->C || s->max_rows >= ((int64_t)1 << 31) ||
+        s->max_groups >= ((int64_t)1 << 31)) {
+        free_server(s);
+        return SOS_EINVAL;
+    }
+    s->rows.init(s->max_rows);
+    bool ok =
+        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
+        hipStreamCreateWithFlags(&s->ostream, hipStreamNonBlocking) == hipSuccess &&
+        hipMalloc(&s->sections, (size_t)s->max_rows * 6 * 4) == hipSuccess &&
+        hipMalloc(&s->state, (size_t)s->max_rows * 2 * 4) == hipSuccess &&
+        hipMalloc(&s->tabs, (size_t)s->max_rows * s->tab_row_bytes) == hipSuccess &&
+        hipMalloc(&s->dargs, s->lay.bytes) == hipSuccess &&
+        hipMalloc(&s->octrl, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
+        hipMemset(s->octrl, 0, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
+        hipMalloc(&s->h->gpre, sizeof(int64_t) * ((size_t)max_slots + 1)) == hipSuccess &&
+        hipMalloc(&s->h->sigmap, sizeof(int32_t) * (size_t)s->max_groups) == hipSuccess &&
+        hipMalloc(&s->h->total_dev, sizeof(int64_t)) == hipSuccess &&
+        hipMalloc(&s->h->desc, (size_t)s->max_groups * SOS_MAX_SECTIONS * 4 * 8) == hipSuccess &&
+        hipMemset(s->h->desc, 0, (size_t)s->max_groups * SOS_MAX_SECTIONS * 4 * 8) ==
+            hipSuccess;
+    for (Step &st : s->steps) {
+        ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc(&st.host, s->lay.bytes + 8, hipHostMallocDefault) == hipSuccess;
+    }
+    if (!ok) {
+        free_server(s);
+        return SOS_ENOMEM;
+    }
+    s->h->gpre_cap = (size_t)max_slots + 1;
+    s->h->sigmap_cap = (size_t)s->max_groups;
+    s->h->desc_cap = (size_t)s->max_groups * SOS_MAX_SECTIONS * 4;
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        free_server(s);
+        return SOS_ENOMEM;
+    }
+    *out = s;
+    return SOS_OK;
+}
+
+int sos_server_destroy(sos_server_t s)
+{
+    if (!s) return SOS_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        // chunks not yet in a step are not run
+        for (auto &kv : s->streams) {
+            for (uint64_t tk : kv.second.pending) {
+                auto it = s->reqs.find(tk);
+                if (it != s->reqs.end()) it->second.status = SOS_ECLOSED;
+            }
+            kv.second.pending.clear();
+        }
+        s->ready.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    DeviceGuard g(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    free_server(s);
+    return SOS_OK;
+}
+
+int sos_server_limits(sos_server_t s, int64_t *max_rows, int64_t *max_chunk, int *L, int *N)
+{
+    if (!s) return SOS_EINVAL;
+    if (max_rows) *max_rows = s->max_rows;
+    if (max_chunk) *max_chunk = s->max_step_samples;
+    if (L) *L = s->L;
+    if (N) *N = s->N;
+    return SOS_OK;
+}
+
+int sos_stream_open(sos_server_t s, const float *sections_host, int K, const float *zi_host,
+                    int64_t *stream_id)
+{
+    if (!s || !stream_id || K < 0 || K > SOS_MAX_SECTIONS || (K > 0 && !sections_host))
+        return SOS_EINVAL;
+    *stream_id = 0;
+    int64_t row = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return SOS_ECLOSED;
+        if (K > 0) {
+            row = s->rows.alloc(K);
+            if (row < 0) return SOS_EBUSY;
+        }
+    }
+    int rc = SOS_OK;
+    if (K > 0) {
+        DeviceGuard g(s->device);
+        std::vector<float> st(2 * (size_t)K, 0.0f);
+        if (zi_host) std::memcpy(st.data(), zi_host, st.size() * sizeof(float));
+        std::vector<unsigned char> tab(s->tab_row_bytes * (size_t)K);
+        const bool ok =
+            g.ok &&
+            hipMemcpyAsync(s->sections + 6 * row, sections_host, 6 * sizeof(float) * (size_t)K,
+                           hipMemcpyHostToDevice, s->ostream) == hipSuccess &&
+            hipMemcpyAsync(s->state + 2 * row, st.data(), st.size() * sizeof(float),
+                           hipMemcpyHostToDevice, s->ostream) == hipSuccess &&
+            sos_launch_prep(s->bits, s->sections + 6 * row, K, __builtin_ctz((unsigned)s->N),
+                            __builtin_ctz((unsigned)(s->L / 64)),
+                            s->tabs + (size_t)row * s->tab_row_bytes, s->octrl, 0,
+                            s->ostream) == hipSuccess &&
+            hipMemcpyAsync(tab.data(), s->tabs + (size_t)row * s->tab_row_bytes, tab.size(),
+                           hipMemcpyDeviceToHost, s->ostream) == hipSuccess &&
+            hipStreamSynchronize(s->ostream) == hipSuccess;
+        if (!ok) {
+            rc = SOS_EHIP;
+        } else {
+            unsigned bad = 0;
+            for (int k = 0; k < K; ++k) {
+                const unsigned char *p = tab.data() + (size_t)k * s->tab_row_bytes;
+                double v;
+                if (s->bits == 64) {
+                    std::memcpy(&v, p + 8 * OFF_STATUS, 8);
+                } else {
+                    float f;
+                    std::memcpy(&f, p + 4 * OFF_STATUS, 4);
+                    v = f;
+                }
+                bad |= (unsigned)v;
+            }
+            rc = status_of_bits(bad);
+        }
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc == SOS_OK && s->stop) rc = SOS_ECLOSED;
+    if (rc != SOS_OK) {
+        if (K > 0) s->rows.release(row, K);
+        return rc;
+    }
+    const int64_t sid = s->next_stream++;
+    Stream &str = s->streams[sid];
+    str.K = K;
+    str.row = row;
+    *stream_id = sid;
+    return SOS_OK;
+}
+
+int sos_stream_push(sos_server_t s, int64_t stream_id, const float *chunk, int64_t n, float *out,
+                    uint64_t *ticket)
+{
+    if (!s || !ticket) return SOS_EINVAL;
+    *ticket = 0;
+    return push_many(s, 1, &stream_id, &chunk, &out, &n, ticket);
+}
+
+int sos_stream_push_many(sos_server_t s, int count, const int64_t *stream_ids,
+                         const float *const *chunks, const int64_t *n, float *const *outs,
+                         uint64_t *tickets)
+{
+    if (!s || count < 0 || (count > 0 && (!stream_ids || !chunks || !n || !outs || !tickets)))
+        return SOS_EINVAL;
+    if (count == 0) return SOS_OK;
+    return push_many(s, count, stream_ids, chunks, outs, n, tickets);
+}
+
+int sos_stream_wait(sos_server_t s, uint64_t ticket, double *latency_s)
+{
+    if (!s) return SOS_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return SOS_EINVAL;
+    s->cv_done.wait(lk, [&] { return it->second.status != kPending; });
+    const int rc = it->second.status;
+    if (latency_s) *latency_s = it->second.latency;
+    s->reqs.erase(it);
+    return rc;
+}
+
+int sos_stream_state(sos_server_t s, int64_t stream_id, float *zf_host)
+{
+    if (!s) return SOS_EINVAL;
+    int K = 0;
+    int64_t row = 0;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->streams.find(stream_id);
+        if (it == s->streams.end()) return SOS_ECLOSED;
+        s->cv_done.wait(lk, [&] { return it->second.outstanding == 0 || s->stop; });
+        K = it->second.K;
+        row = it->second.row;
+    }
+    if (K == 0) return SOS_OK;
+    if (!zf_host) return SOS_EINVAL;
+    DeviceGuard g(s->device);
+    if (!g.ok) return SOS_EHIP;
+    if (hipMemcpyAsync(zf_host, s->state + 2 * row, 2 * sizeof(float) * (size_t)K,
+                       hipMemcpyDeviceToHost, s->ostream) != hipSuccess ||
+        hipStreamSynchronize(s->ostream) != hipSuccess)
+        return SOS_EHIP;
+    return SOS_OK;
+}
+
+int sos_stream_close(sos_server_t s, int64_t stream_id)
+{
+    if (!s) return SOS_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->streams.find(stream_id);
+    if (it == s->streams.end() || it->second.closing) return SOS_ECLOSED;
+    it->second.closing = true;
+    s->cv_done.wait(lk, [&] { return it->second.outstanding == 0 || s->stop; });
+    if (it->second.K > 0) s->rows.release(it->second.row, it->second.K);
+    s->streams.erase(it);
+    return SOS_OK;
+}
+
+int sos_server_replay(sos_server_t s, int64_t R, const int64_t *stream_ids, const int64_t *offs,
+                      const int64_t *lens, const double *arrival_s, const float *x, float *y,
+                      double *latency_s, double *wall_s)
+{
+    if (!s || R < 0 || (R > 0 && (!stream_ids || !offs || !lens || !arrival_s || !x || !y)))
+        return SOS_EINVAL;
+    std::vector<uint64_t> tickets((size_t)R, 0);
+    std::vector<const float *> xs;
+    std::vector<float *> ys;
+    std::vector<int64_t> ids, ns;
+    const Clock::time_point t0 = Clock::now();
+    int rc = SOS_OK;
+    int64_t r = 0;
+    while (r < R && rc == SOS_OK) {
+        const double now = std::chrono::duration<double>(Clock::now() - t0).count();
+        int64_t e = r;
+        while (e < R && arrival_s[e] <= now) ++e;
+        if (e == r) {
+            std::this_thread::yield();
+            continue;
+        }
+        xs.clear();
+        ys.clear();
+        ids.clear();
+        ns.clear();
+        for (int64_t i = r; i < e; ++i) {
+            xs.push_back(x + offs[i]);
+            ys.push_back(y + offs[i]);
+            ids.push_back(stream_ids[i]);
+            ns.push_back(lens[i]);
+        }
+        rc = push_many(s, (int)(e - r), ids.data(), xs.data(), ys.data(), ns.data(),
+                       tickets.data() + r);
+        r = e;
+    }
+    int last = SOS_OK;
+    for (int64_t i = 0; i < r; ++i) {
+        double lat = 0.0;
+        const int w = sos_stream_wait(s, tickets[(size_t)i], &lat);
+        if (latency_s) latency_s[i] = lat;
+        if (w != SOS_OK && last == SOS_OK) last = w;
+    }
+    if (wall_s) *wall_s = std::chrono::duration<double>(Clock::now() - t0).count();
+    return rc != SOS_OK ? rc : last;
+}
+
+}  // extern "C"

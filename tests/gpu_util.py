@@ -18,3 +18,34 @@ def max_over_peak(y, ref):
 def tol_for(K):
     """rel-L2 bound: 1e-5 up to order 8 (K <= 4), 1e-4 at order 16 (K = 8)."""
     return 1e-5 if K <= 4 else 1e-4
+
+
+# Ratio allowed between the HIP path's FP32 error and the error of a
+# sequential FP32 cascade on the same input. Measured on MI355X over 320
+# random cascades of orders 2..16 (random stable sections, random initial
+# states, 2^15 samples) at three tiles: median 0.8-1.2, 90th percentile
+# 1.8-2.7, maximum 8.1. The factor only matters when the sequential FP32
+# error itself exceeds the order's bound (a cascade whose output is orders of
+# magnitude below its input); there the FP64 compute type is checked against
+# the order's bound instead.
+FLOOR_FACTOR = 16.0
+
+
+def fp32_floor(sos, x, zi, ref):
+    """Relative L2 error of a sequential FP32 cascade (scipy's sosfilt run in
+    float32, a third-party implementation used only as the FP32 yardstick)
+    against the FP64 reference `ref`."""
+    import scipy.signal
+
+    sos32 = np.asarray(sos, dtype=np.float32)
+    x32 = np.asarray(x, dtype=np.float32)
+    if zi is None:
+        y32 = scipy.signal.sosfilt(sos32, x32)
+    else:
+        y32, _ = scipy.signal.sosfilt(sos32, x32, zi=np.asarray(zi, dtype=np.float32))
+    return rel_l2(y32, ref)
+
+
+def fp32_bound(K, floor):
+    """The order's bound, or FLOOR_FACTOR times the FP32 floor if larger."""
+    return max(tol_for(K), FLOOR_FACTOR * floor)

@@ -49,6 +49,18 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_get_precision(None) == P.SOS_EINVAL
     assert lib.sos_set_timeout(None, 1.0) == P.SOS_EINVAL
     assert lib.sos_wall_clock_khz(None) == P.SOS_EINVAL
+    # serving entry points
+    assert lib.sos_server_create(None, None, 0, 1) == P.SOS_EINVAL
+    assert lib.sos_server_destroy(None) == P.SOS_EINVAL
+    assert lib.sos_server_limits(None, None, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_stream_open(None, None, 1, None, None) == P.SOS_EINVAL
+    assert lib.sos_stream_push(None, 1, None, 10, None, None) == P.SOS_EINVAL
+    assert lib.sos_stream_push_many(None, 1, None, None, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_stream_wait(None, 1, None) == P.SOS_EINVAL
+    assert lib.sos_stream_state(None, 1, None) == P.SOS_EINVAL
+    assert lib.sos_stream_close(None, 1) == P.SOS_EINVAL
+    assert lib.sos_server_replay(None, 0, None, None, None, None, None, None, None,
+                                 None) == P.SOS_EINVAL
     assert lib.sos_filter_batched(None, 1, 1, 1, 10, None, None, None, None, None, None, None,
                                   None, None) == P.SOS_EINVAL
     assert lib.sos_filter_train(None, None, 1, None, None, 10, None, None, None,

@@ -106,3 +106,27 @@ def uneven_batch(B: int = 4096, log2_lo: float = 10.0, log2_hi: float = 22.0, se
 
 def batch_signal(total: int, seed: int = 30) -> np.ndarray:
     return signal(total, seed)
+
+
+def serving_trace(S: int = 1024, R: int | None = None, rate_chunks_per_s: float = 1e5,
+                  lo: int = 4096, hi: int = 65536, k_lo: int = 1, k_hi: int = 8,
+                  seed: int = 4):
+    """Serving load: S streams, stream s filtered by K_s ~ U{k_lo..k_hi} random
+    stable sections (zero initial state); R chunks (default 4 per stream) with
+    lengths floor(2**U), U ~ U[log2 lo, log2 hi], arriving as a Poisson process
+    of the given aggregate rate, each assigned to a uniformly drawn stream
+    (a stream's chunks are its arrivals in time order).
+
+    Returns (Ks, sections list, stream_of_chunk, lens, offs, arrival_s) with
+    offs the exclusive prefix of lens (one packed sample buffer for all
+    chunks)."""
+    g = rng(seed)
+    Ks = g.integers(k_lo, k_hi + 1, size=S).astype(np.int32)
+    sections = [random_stable_sos(int(k), g) for k in Ks]
+    R = 4 * S if R is None else R
+    lens = np.floor(2.0 ** g.uniform(np.log2(lo), np.log2(hi), size=R)).astype(np.int64)
+    ids = g.integers(0, S, size=R).astype(np.int64)
+    arrival = np.cumsum(g.exponential(1.0 / rate_chunks_per_s, size=R))
+    offs = np.zeros(R, dtype=np.int64)
+    np.cumsum(lens[:-1], out=offs[1:])
+    return Ks, sections, ids, lens, offs, arrival
