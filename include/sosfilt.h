@@ -216,6 +216,44 @@ int sos_bench_copy(const float *x, float *y, int64_t n, hipStream_t stream);
 int sos_debug_carries(sos_handle_t h, float *out, int64_t capacity_floats, int64_t *groups,
                       int *K);
 
+/* ------------------------------------------------------- graph and tuning
+ * An uneven batch (sos_filter_batched's arguments) captured once into a HIP
+ * graph: coefficient preparation, the device-built work table, the arm step
+ * and the persistent filter launch, with no memset nodes. Creation allocates
+ * a private workspace (the graph pins it) at the tile, compute type and
+ * lookback bound of `h`, and captures on a private stream. A launch replays
+ * the same four kernels on `stream` with the same pointers: the contents of
+ * every input array (samples, sections, K, sec_off, sig_off, zi) may change
+ * between launches as long as B, kmax, total_rows and total_samples stay the
+ * bounds they were at creation (the work table is rebuilt on the device each
+ * launch). Device errors of the last finished launch: sos_graph_last_error. */
+typedef struct sos_graph *sos_graph_t;
+int sos_graph_create_batched(sos_graph_t *g, sos_handle_t h, int B, int kmax,
+                             int64_t total_rows, int64_t total_samples, const int32_t *K,
+                             const int32_t *sec_off, const float *sections,
+                             const int64_t *sig_off, const float *x, float *y, const float *zi,
+                             float *zf);
+int sos_graph_launch(sos_graph_t g, hipStream_t stream);
+int sos_graph_last_error(sos_graph_t g);
+int sos_graph_destroy(sos_graph_t g);
+
+/* Autotuner for the two parameters of the multi-block layout (Sec. IV-A/C):
+ * lanes per group L and samples per lane N (group size C = N L). Runs the
+ * batch on its own buffers: the compiled (L, N) shapes are first pruned by a
+ * padding model (a signal of n samples costs ceil(n / C) groups of C, so
+ * tiles whose padded work exceeds 1.5x the best tile's are dropped), then
+ * each survivor is timed (one warm-up, `reps` timed runs, median, HIP events
+ * on `stream`). The fastest tile becomes h's tile and is cached per (compute
+ * type, kmax, B, floor(log2 total_samples)) for sos_tune_lookup; y and zf
+ * end up holding the winning tile's result. zi must not equal zf (the batch
+ * runs several times). Synchronises `stream`. */
+int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_t total_samples,
+                     const int32_t *K, const int32_t *sec_off, const float *sections,
+                     const int64_t *sig_off, const float *x, float *y, const float *zi,
+                     float *zf, hipStream_t stream, int reps, int *L, int *N, float *ms);
+/* A cached tuning result for the key above, or SOS_EINVAL if none. */
+int sos_tune_lookup(sos_handle_t h, int B, int kmax, int64_t total_samples, int *L, int *N);
+
 /* ------------------------------------------------------------------ serving
  * Many long signals ("streams") that arrive in chunks, each filtered by its
  * own cascade as one continuous signal (the problem of Sec. II per stream;

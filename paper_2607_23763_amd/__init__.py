@@ -82,6 +82,19 @@ def lib():
             L.sos_stream_state.argtypes = [vp, i64, vp]
             L.sos_stream_close.argtypes = [vp, i64]
             L.sos_server_replay.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, dp]
+            L.sos_graph_create_batched.argtypes = [ctypes.POINTER(vp), vp, i32, i32, i64, i64, vp,
+                                                   vp, vp, vp, vp, vp, vp, vp]
+            L.sos_graph_launch.argtypes = [vp, vp]
+            L.sos_graph_last_error.argtypes = [vp]
+            L.sos_graph_destroy.argtypes = [vp]
+            L.sos_tune_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                           vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                           ctypes.POINTER(ctypes.c_float)]
+            L.sos_tune_lookup.argtypes = [vp, i32, i32, i64, ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32)]
+            for name in ("sos_graph_create_batched", "sos_graph_launch", "sos_graph_last_error",
+                         "sos_graph_destroy", "sos_tune_batched", "sos_tune_lookup"):
+                getattr(L, name).restype = i32
             for name in ("sos_server_create", "sos_server_destroy", "sos_server_limits",
                          "sos_stream_open", "sos_stream_push", "sos_stream_push_many",
                          "sos_stream_wait", "sos_stream_state", "sos_stream_close",
@@ -271,13 +284,7 @@ def sosfilt(x, sos, zi=None, handle: Handle | None = None):
     return y, zf
 
 
-def sosfilt_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None, kmax=None,
-                    handle: Handle | None = None):
-    """Uneven batch: signal i is x[sig_off[i]:sig_off[i+1]] filtered by the K[i]
-    rows of `sections` starting at row sec_off[i] (default: prefix of K).
-    x, sections, zi: float32 GPU tensors; K (int32), sig_off (int64, B+1),
-    sec_off (int32, B+1): GPU tensors. Returns (y, zf) with zf shaped like zi
-    (sec_off[B] x 2). One persistent launch on the current stream."""
+def _batch_args(x, sections, K, sig_off, zi, y, zf, sec_off, kmax):
     import torch
 
     x = _as_dev_f32(x, "x").reshape(-1)
@@ -299,12 +306,89 @@ def sosfilt_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=N
         y = torch.empty_like(x)
     if zf is None:
         zf = torch.empty((nsec, 2), dtype=torch.float32, device=x.device)
-    h = handle or default_handle(x.device.index or 0)
-    _check(lib().sos_filter_batched(h.ptr, B, int(kmax), nsec, x.numel(), _p(K.contiguous()),
-                                    _p(sec_off.contiguous()), _p(sections), _p(sig_off.contiguous()),
-                                    _p(x), _p(y), _p(zi), _p(zf), _stream_ptr(x.device)),
+    return dict(x=x, sections=sections, K=K.contiguous(), sig_off=sig_off.contiguous(),
+                sec_off=sec_off.contiguous(), zi=zi, y=y, zf=zf, B=B, kmax=int(kmax), nsec=nsec)
+
+
+def sosfilt_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None, kmax=None,
+                    handle: Handle | None = None):
+    """Uneven batch: signal i is x[sig_off[i]:sig_off[i+1]] filtered by the K[i]
+    rows of `sections` starting at row sec_off[i] (default: prefix of K).
+    x, sections, zi: float32 GPU tensors; K (int32), sig_off (int64, B+1),
+    sec_off (int32, B+1): GPU tensors. Returns (y, zf) with zf shaped like zi
+    (sec_off[B] x 2). One persistent launch on the current stream."""
+    a = _batch_args(x, sections, K, sig_off, zi, y, zf, sec_off, kmax)
+    h = handle or default_handle(a["x"].device.index or 0)
+    _check(lib().sos_filter_batched(h.ptr, a["B"], a["kmax"], a["nsec"], a["x"].numel(),
+                                    _p(a["K"]), _p(a["sec_off"]), _p(a["sections"]),
+                                    _p(a["sig_off"]), _p(a["x"]), _p(a["y"]), _p(a["zi"]),
+                                    _p(a["zf"]), _stream_ptr(a["x"].device)),
            "sos_filter_batched")
-    return y, zf
+    return a["y"], a["zf"]
+
+
+def tune_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None, kmax=None,
+                 handle: Handle | None = None, reps: int = 3):
+    """Autotune (L, N) for this batch (sos_tune_batched); the handle keeps the
+    winner. Returns ((L, N), ms, y, zf) with y, zf the winner's result."""
+    a = _batch_args(x, sections, K, sig_off, zi, y, zf, sec_off, kmax)
+    h = handle or default_handle(a["x"].device.index or 0)
+    L, N, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check(lib().sos_tune_batched(h.ptr, a["B"], a["kmax"], a["nsec"], a["x"].numel(),
+                                  _p(a["K"]), _p(a["sec_off"]), _p(a["sections"]),
+                                  _p(a["sig_off"]), _p(a["x"]), _p(a["y"]), _p(a["zi"]),
+                                  _p(a["zf"]), _stream_ptr(a["x"].device), int(reps),
+                                  ctypes.byref(L), ctypes.byref(N), ctypes.byref(ms)),
+           "sos_tune_batched")
+    return (L.value, N.value), ms.value, a["y"], a["zf"]
+
+
+class BatchGraph:
+    """An uneven batch captured into a HIP graph (sos_graph_create_batched).
+    The tensors passed here are the graph's buffers: refill them in place and
+    call launch() to filter new data with the same shapes and bounds."""
+
+    def __init__(self, x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None,
+                 kmax=None, handle: Handle | None = None):
+        a = _batch_args(x, sections, K, sig_off, zi, y, zf, sec_off, kmax)
+        self.args = a
+        h = handle or default_handle(a["x"].device.index or 0)
+        self._g = ctypes.c_void_p()
+        import torch
+
+        torch.cuda.current_stream(a["x"].device).synchronize()
+        _check(lib().sos_graph_create_batched(ctypes.byref(self._g), h.ptr, a["B"], a["kmax"],
+                                              a["nsec"], a["x"].numel(), _p(a["K"]),
+                                              _p(a["sec_off"]), _p(a["sections"]),
+                                              _p(a["sig_off"]), _p(a["x"]), _p(a["y"]),
+                                              _p(a["zi"]), _p(a["zf"])),
+               "sos_graph_create_batched")
+
+    @property
+    def y(self):
+        return self.args["y"]
+
+    @property
+    def zf(self):
+        return self.args["zf"]
+
+    def launch(self):
+        _check(lib().sos_graph_launch(self._g, _stream_ptr(self.args["x"].device)),
+               "sos_graph_launch")
+
+    def last_error(self) -> int:
+        return int(lib().sos_graph_last_error(self._g))
+
+    def close(self):
+        if self._g:
+            lib().sos_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sosfilt_train(x, sos, zi=None, handle: Handle | None = None):

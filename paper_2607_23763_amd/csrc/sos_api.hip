@@ -125,6 +125,69 @@ void mark_degenerate(sos_ctx *h, int K)
 
 }  // namespace
 
+namespace sosint {
+
+int batch_check(const BatchArgs &ba)
+{
+    if (ba.B < 0 || ba.kmax < 0 || ba.kmax > SOS_MAX_SECTIONS || ba.total_samples < 0 ||
+        ba.total_rows < 0)
+        return SOS_EINVAL;
+    if (ba.B == 0) return SOS_OK;
+    if (!ba.K || !ba.sec_off || !ba.sig_off) return SOS_EINVAL;
+    if (ba.total_rows > 0 && !ba.sections) return SOS_EINVAL;
+    return check_signal(ba.x, ba.y, ba.total_samples);
+}
+
+int batch_reserve(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream)
+{
+    const int64_t C = (int64_t)t.L * t.N;
+    const int64_t max_groups = ba.total_samples / C + ba.B;
+    if (max_groups >= (int64_t)1 << 31 || ba.total_rows >= (int64_t)1 << 31) return SOS_EINVAL;
+    const int kd = ba.kmax > 0 ? ba.kmax : 1;   // descriptor stride
+    int rc = ensure_buf(h->tabs, h->tabs_cap,
+                        tab_bytes((int)(ba.total_rows > 8 ? ba.total_rows : 8), bits), stream);
+    if (rc) return rc;
+    rc = ensure_desc(h, (size_t)max_groups * (size_t)kd * 4u, stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->gpre, h->gpre_cap, (size_t)ba.B + 1, stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->sigmap, h->sigmap_cap, (size_t)max_groups, stream);
+    if (rc) return rc;
+    if (!h->total_dev && hipMalloc(&h->total_dev, sizeof(int64_t)) != hipSuccess)
+        return SOS_ENOMEM;
+    return SOS_OK;
+}
+
+int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream)
+{
+    const int64_t C = (int64_t)t.L * t.N;
+    const int64_t max_groups = ba.total_samples / C + ba.B;
+    const int kd = ba.kmax > 0 ? ba.kmax : 1;
+    const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
+    if (ba.total_rows > 0 &&
+        sos_launch_prep_batched(bits, ba.sections, ba.B, ba.kmax, ba.total_rows, ba.K,
+                                ba.sec_off, log2n, log2w, h->tabs, h->ctrl, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_worktable(ba.B, ba.kmax, ba.total_rows, C, ba.total_samples, max_groups, ba.K,
+                             ba.sec_off, ba.sig_off, h->gpre, h->sigmap, h->total_dev, ba.zi,
+                             ba.zf, h->ctrl, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    int64_t grid = grid_of(bits, t.L, t.N);
+    if (grid <= 0 || grid > max_groups) grid = max_groups;
+    if (sos_launch_fwd_batched(bits, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
+                               h->sigmap, h->total_dev, ba.x, ba.y, h->tabs, ba.zi, ba.zf,
+                               h->desc, h->ctrl, h->timeout_ticks, grid, nullptr, nullptr,
+                               stream) != hipSuccess)
+        return SOS_EHIP;
+    h->prep_K = -1;        // the batch overwrote the plain tables
+    h->last_groups = 0;
+    h->last_K = 0;
+    return SOS_OK;
+}
+
+}  // namespace sosint
+
 extern "C" {
 
 const char *sos_strerror(int code)
@@ -308,54 +371,18 @@ int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
                        const float *sections, const int64_t *sig_off, const float *x, float *y,
                        const float *zi, float *zf, hipStream_t stream)
 {
-    if (!h || B < 0 || kmax < 0 || kmax > SOS_MAX_SECTIONS || total_samples < 0 ||
-        total_rows < 0)
-        return SOS_EINVAL;
-    if (B == 0) return SOS_OK;
-    if (!K || !sec_off || !sig_off) return SOS_EINVAL;
-    if (total_rows > 0 && !sections) return SOS_EINVAL;
-    int rc = check_signal(x, y, total_samples);
-    if (rc) return rc;
+    if (!h) return SOS_EINVAL;
+    BatchArgs ba{B, kmax, total_rows, total_samples, K, sec_off, sections, sig_off, x, y, zi, zf};
+    int rc = batch_check(ba);
+    if (rc || B == 0) return rc;
     std::lock_guard<std::mutex> lk(h->mu);
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     const Tile t = tile_of(h);
     const int bits = bits_of(h);
-    const int64_t C = (int64_t)t.L * t.N;
-    const int64_t max_groups = total_samples / C + B;
-    if (max_groups >= (int64_t)1 << 31 || total_rows >= (int64_t)1 << 31) return SOS_EINVAL;
-    const int kd = kmax > 0 ? kmax : 1;   // descriptor stride
-    rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes((int)(total_rows > 8 ? total_rows : 8), bits),
-                    stream);
+    rc = batch_reserve(h, t, bits, ba, stream);
     if (rc) return rc;
-    rc = ensure_desc(h, (size_t)max_groups * (size_t)kd * 4u, stream);
-    if (rc) return rc;
-    rc = ensure_buf(h->gpre, h->gpre_cap, (size_t)B + 1, stream);
-    if (rc) return rc;
-    rc = ensure_buf(h->sigmap, h->sigmap_cap, (size_t)max_groups, stream);
-    if (rc) return rc;
-    if (!h->total_dev && hipMalloc(&h->total_dev, sizeof(int64_t)) != hipSuccess)
-        return SOS_ENOMEM;
-    const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
-    if (total_rows > 0 &&
-        sos_launch_prep_batched(bits, sections, B, kmax, total_rows, K, sec_off, log2n, log2w,
-                                h->tabs, h->ctrl, stream) != hipSuccess)
-        return SOS_EHIP;
-    if (sos_launch_worktable(B, kmax, total_rows, C, total_samples, max_groups, K, sec_off,
-                             sig_off, h->gpre, h->sigmap, h->total_dev, zi, zf, h->ctrl,
-                             stream) != hipSuccess)
-        return SOS_EHIP;
-    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    int64_t grid = grid_of(bits, t.L, t.N);
-    if (grid <= 0 || grid > max_groups) grid = max_groups;
-    if (sos_launch_fwd_batched(bits, t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre, h->sigmap,
-                               h->total_dev, x, y, h->tabs, zi, zf, h->desc, h->ctrl,
-                               h->timeout_ticks, grid, nullptr, nullptr, stream) != hipSuccess)
-        return SOS_EHIP;
-    h->prep_K = -1;        // the batch overwrote the plain tables
-    h->last_groups = 0;
-    h->last_K = 0;
-    return SOS_OK;
+    return batch_enqueue(h, t, bits, ba, stream);
 }
 
 int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *x, float *y,

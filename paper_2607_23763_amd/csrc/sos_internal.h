@@ -144,4 +144,24 @@ inline int64_t grid_of(int bits, int L, int N)
     return grid;
 }
 
+// Arguments of one uneven batch (see sos_filter_batched).
+struct BatchArgs {
+    int B, kmax;
+    int64_t total_rows, total_samples;
+    const int32_t *K, *sec_off;
+    const float *sections;
+    const int64_t *sig_off;
+    const float *x;
+    float *y;
+    const float *zi;
+    float *zf;
+};
+// Argument checks (no device work).
+int batch_check(const BatchArgs &ba);
+// Grow the handle's workspace for the batch at tile t (may allocate and
+// synchronise `stream`; never called under graph capture).
+int batch_reserve(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream);
+// Enqueue prep, work table, arm and filter launches only (graph-capturable).
+int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream);
+
 }  // namespace sosint

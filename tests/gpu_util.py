@@ -49,3 +49,30 @@ def fp32_floor(sos, x, zi, ref):
 def fp32_bound(K, floor):
     """The order's bound, or FLOOR_FACTOR times the FP32 floor if larger."""
     return max(tol_for(K), FLOOR_FACTOR * floor)
+
+
+def fp32_bounds(K, sos, x, zi, ref, zf_ref):
+    """Bounds for the output and the final state of one FP32 run: each is the
+    order's bound or FLOOR_FACTOR times the sequential FP32 error of that
+    quantity (scipy's float32 sosfilt against the FP64 reference)."""
+    import scipy.signal
+
+    sos32 = np.asarray(sos, dtype=np.float32)
+    x32 = np.asarray(x, dtype=np.float32)
+    z32 = np.zeros((sos32.shape[0], 2), np.float32) if zi is None else \
+        np.asarray(zi, dtype=np.float32)
+    y32, zf32 = scipy.signal.sosfilt(sos32, x32, zi=z32)
+    return fp32_bound(K, rel_l2(y32, ref)), fp32_bound(K, rel_l2(zf32, zf_ref))
+
+
+def zf_bound(K, by, bz, y_ref, zf_ref):
+    """Bound for the relative error of a final state. The state after the last
+    sample is a combination of the last outputs and inputs with coefficients
+    of magnitude up to about 2, whose terms can cancel; its absolute error
+    is that of the last outputs. So besides its own FP32 bound it may carry
+    the output's relative bound measured on the output's scale (4 x the RMS
+    output per state entry)."""
+    y_ref = np.asarray(y_ref, dtype=np.float64)
+    zn = max(float(np.linalg.norm(zf_ref)), 1e-300)
+    scale = 4.0 * float(np.sqrt(np.mean(y_ref ** 2))) * np.sqrt(2 * K) if y_ref.size else 0.0
+    return max(bz, by * max(1.0, scale / zn))

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_util import fp32_bound, fp32_floor, rel_l2, tol_for
+from tests.gpu_util import fp32_bounds, rel_l2, tol_for, zf_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -50,13 +50,15 @@ def test_uneven_batch_matches_oracle(env, tile, precision):
         a, b = sig_off[i], sig_off[i + 1]
         rows_i = rows[so[i]:so[i + 1]]
         zi_i = zi[so[i]:so[i + 1]]
-        bound = tol_for(int(Ks[i]))
+        by = bz = tol_for(int(Ks[i]))
         if precision != 64 and b > a:
-            bound = fp32_bound(int(Ks[i]), fp32_floor(rows_i, x[a:b], zi_i, yr[a:b]))
+            by, bz = fp32_bounds(int(Ks[i]), rows_i, x[a:b], zi_i, yr[a:b],
+                                 zfr[so[i]:so[i + 1]])
         e = rel_l2(y[a:b], yr[a:b])
-        assert e <= bound, (i, Ks[i], b - a, e)
+        assert e <= by, (i, Ks[i], b - a, e)
         ez = rel_l2(zf[so[i]:so[i + 1]], zfr[so[i]:so[i + 1]])
-        assert ez <= max(bound, tol_for(int(Ks[i]))), (i, Ks[i], b - a, ez)
+        bz = zf_bound(int(Ks[i]), by, bz, yr[a:b], zfr[so[i]:so[i + 1]])
+        assert ez <= bz, (i, Ks[i], b - a, ez)
 
 
 def test_alone_equals_in_the_mix(env):

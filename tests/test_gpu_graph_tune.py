@@ -1,0 +1,96 @@
+"""GPU checks of the captured uneven batch (sos_graph_*) and of the
+autotuner (sos_tune_batched): every graph replay, with new data written into
+the captured buffers and eager work in between, equals the eager batched
+call on the same data and the FP64 oracle; the tuner returns a compiled tile
+whose result equals the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import fp32_bounds, rel_l2, zf_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_23763_amd as P
+
+    P.lib()
+    return torch, P
+
+
+def check_vs_oracle(Ks, rows, sig_off, x, zi, y, zf):
+    yr, zfr = oracle.sosfilt_batched(Ks, rows, sig_off, x, zi, nthreads=8)
+    so = np.r_[0, np.cumsum(Ks)]
+    for i in range(len(Ks)):
+        a, b = sig_off[i], sig_off[i + 1]
+        if b == a:
+            continue
+        by, bz = fp32_bounds(int(Ks[i]), rows[so[i]:so[i + 1]], x[a:b], zi[so[i]:so[i + 1]],
+                             yr[a:b], zfr[so[i]:so[i + 1]])
+        assert rel_l2(y[a:b], yr[a:b]) <= by, (i, Ks[i], b - a)
+        bz = zf_bound(int(Ks[i]), by, bz, yr[a:b], zfr[so[i]:so[i + 1]])
+        assert rel_l2(zf[so[i]:so[i + 1]], zfr[so[i]:so[i + 1]]) <= bz, i
+
+
+@pytest.mark.parametrize("tile", [(256, 16), (512, 64)])
+def test_graph_replays_match_eager_and_oracle(env, tile):
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=64, log2_lo=2, log2_hi=16, seed=61)
+    total = int(sig_off[-1])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xg = dev(workloads.batch_signal(total, seed=62))
+    zig, rowsg = dev(zi), dev(rows)
+    Kg, sg = dev(Ks.astype(np.int32)), dev(sig_off.astype(np.int64))
+    h = P.Handle(0, tile=tile)
+    gr = P.BatchGraph(xg, rowsg, Kg, sg, zi=zig, handle=h)
+    he = P.Handle(0, tile=tile)
+    for rep in range(3):
+        x = workloads.batch_signal(total, seed=63 + rep)
+        zi_r = workloads.initial_state(int(Ks.sum()), workloads.rng(70 + rep))
+        so_r = sig_off.copy()
+        if rep == 2:
+            # new lengths, same bounds: the work table is rebuilt on the device
+            lens = np.diff(sig_off)[::-1].copy()
+            so_r[1:] = np.cumsum(lens)
+            sg.copy_(dev(so_r))
+        xg.copy_(dev(x))
+        zig.copy_(dev(zi_r))
+        gr.launch()
+        torch.cuda.synchronize()
+        assert gr.last_error() == P.SOS_OK
+        y_graph, zf_graph = gr.y.cpu().numpy(), gr.zf.cpu().numpy()
+        # eager work between replays, then the eager call on the same data
+        ye, zfe = P.sosfilt_batched(dev(x), rowsg, Kg, dev(so_r), zi=dev(zi_r), handle=he)
+        torch.cuda.synchronize()
+        assert he.last_error() == P.SOS_OK
+        ye, zfe = ye.cpu().numpy(), zfe.cpu().numpy()
+        scale = max(np.abs(ye).max(), 1.0)
+        print("replay", rep, "max |graph - eager| / scale", np.abs(y_graph - ye).max() / scale)
+        assert np.abs(y_graph - ye).max() <= 1e-5 * scale
+        check_vs_oracle(Ks, rows, so_r, x, zi_r, y_graph, zf_graph)
+    gr.close()
+
+
+def test_tuner_returns_a_compiled_tile_with_exact_output(env):
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=128, log2_lo=8, log2_hi=18, seed=64)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=65)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h = P.Handle(0)
+    (L, N), ms, y, zf = P.tune_batched(dev(x), dev(rows), dev(Ks.astype(np.int32)),
+                                       dev(sig_off.astype(np.int64)), zi=dev(zi), handle=h,
+                                       reps=2)
+    torch.cuda.synchronize()
+    print("tuned tile", (L, N), "%.4f ms" % ms)
+    assert h.last_error() == P.SOS_OK
+    assert h.tile() == (L, N) and ms > 0
+    assert (L, N) in {(64, 16), (64, 32), (64, 64), (256, 16), (256, 32), (256, 64),
+                      (512, 16), (512, 32), (512, 64), (1024, 16), (1024, 32)}
+    check_vs_oracle(Ks, rows, sig_off, x, zi, y.cpu().numpy(), zf.cpu().numpy())
