@@ -33,7 +33,7 @@ enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u, ERR
 // C = L*N samples per group. Uniform entries are read with scalar loads; the
 // two per-lane arrays with one 128-bit load per lane.
 enum : int {
-    OFF_STATUS = 0,         // 0 = usable, else ERRBIT_* (stored as int bits)
+    OFF_STATUS = 0,         // 0 = usable, else ERRBIT_* (stored as a number)
     OFF_FIR = 1,            // [3] adjoint tables only: b0, b1, b2 of the section
     OFF_TAPS = 4,           // [5] taps of B(z) A(-z): the level-1 right-hand side
     OFF_B1 = 9, OFF_B2 = 10, OFF_A1 = 11, OFF_A2 = 12,
