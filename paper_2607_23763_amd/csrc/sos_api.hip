@@ -62,7 +62,7 @@ int check_signal(const float *x, const float *y, int64_t n)
 // Tables for `sections` at the handle's shape and type (caller holds the lock).
 int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream)
 {
-    const Tile t = tile_of(h);
+    const Tile t = tile_of(h, K);
     const int bits = bits_of(h);
     int rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes(K > 8 ? K : 8, bits), stream);
     if (rc) return rc;
@@ -116,7 +116,7 @@ void set_timeout_ms(sos_ctx *h, double ms)
 
 void mark_degenerate(sos_ctx *h, int K)
 {
-    const Tile t = tile_of(h);   // degenerate calls need no tables
+    const Tile t = tile_of(h, K);   // degenerate calls need no tables
     h->prep_K = K;
     h->prep_L = t.L;
     h->prep_N = t.N;
@@ -339,7 +339,7 @@ int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, con
     int rc = check_signal(x, y, n);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(h->mu);
-    const Tile t = tile_of(h);
+    const Tile t = tile_of(h, h->prep_K);
     if (h->prep_K < 0 || h->prep_N != t.N || h->prep_L != t.L || h->prep_bits != bits_of(h))
         return SOS_EINVAL;
     DeviceGuard g(h->device);
@@ -378,7 +378,7 @@ int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
     std::lock_guard<std::mutex> lk(h->mu);
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
-    const Tile t = tile_of(h);
+    const Tile t = tile_of(h, kmax);
     const int bits = bits_of(h);
     rc = batch_reserve(h, t, bits, ba, stream);
     if (rc) return rc;

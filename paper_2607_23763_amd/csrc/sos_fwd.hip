@@ -213,6 +213,17 @@ __device__ __forceinline__ T wave_sum(T v)
     return readlane(v, 63);
 }
 
+// Workgroup barrier that orders LDS only. __syncthreads() also waits for all
+// of the wave's outstanding global memory operations (vmcnt 0), which would
+// make every barrier wait for the next group's prefetch and the previous
+// group's stores; no barrier here protects global memory.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------- descriptors
 
 __device__ __forceinline__ unsigned long long pack(float v, unsigned tag)
@@ -252,86 +263,106 @@ __device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, i
 // Resolve the incoming state of group it.g (> 0) of a signal for section s by
 // decoupled lookback; executed by one whole wave. Returns wave-uniform values.
 //
-// Each round the wave reads up to 64 of the newest predecessors not yet
-// consumed, one per lane. It consumes the longest prefix that is ready: if a
-// resolved carry (inclusive) lies in that prefix at lane j*, the result is
-// inc[j*] propagated over j* groups plus the local carries (aggregates) of
-// the j* groups in front of it, and the walk ends; otherwise the prefix's
-// aggregates are added and the walk slides past them. When the newest
-// unconsumed predecessor is not ready yet, the wave waits on that single
-// descriptor with exponential backoff, so waiting waves issue one request per
-// poll. On timeout it returns NaNs and sets the error bit (the caller still
-// publishes, so successors terminate).
+// Each round the wave reads the kWin x 64 newest predecessors not yet
+// consumed (lane l reads predecessors l, l + 64, ...) and consumes, window by
+// window, the longest prefix that is ready (kWin = 1 here): if a resolved carry (inclusive)
+// lies in that prefix at lane j*, the result is inc[j*] propagated over j*
+// groups plus the local carries (aggregates) of the j* groups in front of it,
+// and the walk ends; otherwise the prefix's aggregates are added and the walk
+// slides past them, into the next window of the same round when the whole
+// window was consumed. When the newest unconsumed predecessor is not ready,
+// the wave waits on that single descriptor with exponential backoff, so
+// waiting waves issue one request per poll. On timeout it returns NaNs and
+// sets the error bit (the caller still publishes, so successors terminate).
 template <typename T>
 __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int s,
                          unsigned epoch, int lane, T &r1, T &r2)
 {
+    // one window per round: reading two per round (fewer rounds, twice the
+    // agent-scope loads each) measured slower, most at small groups
+    constexpr int kWin = 1;
     const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);   // T^(C lane)
     T acc1 = 0, acc2 = 0;
     T m00 = 1, m01 = 0, m10 = 0, m11 = 1;   // transform from the newest unconsumed group
     const int64_t first = it.t - it.g;      // ticket of the signal's first group
     int64_t base = it.t - 1;                // newest unconsumed predecessor
-    int span = 64;                          // lanes reading this round
+    bool single = false;                    // waiting on the newest one only
     int nap = 0;
     const unsigned long long t0 = wall_clock64();
     while (true) {
-        const int64_t h = base - lane;
-        unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
-        if (lane < span && h >= first) {
-            const unsigned long long *d = a.desc + ((size_t)h * a.K + s) * 4;
+        unsigned long long w[kWin][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) w[i] = load_word(d + i);
-        }
-        const bool inc_ok = (unsigned)(w[2] >> 32) == epoch && (unsigned)(w[3] >> 32) == epoch;
-        const bool agg_ok = (unsigned)(w[0] >> 32) == epoch && (unsigned)(w[1] >> 32) == epoch;
-        const unsigned long long incm = __ballot(inc_ok);
-        const unsigned long long rdym = __ballot(inc_ok || agg_ok);
-        const unsigned long long spanm = span == 64 ? ~0ull : ((1ull << span) - 1ull);
-        const unsigned long long notr = ~rdym & spanm;
-        const int nr = notr ? __builtin_ctzll(notr) : span;   // ready prefix
-        const int jstar = incm ? __builtin_ctzll(incm) : 64;
-        const bool done = jstar < nr;
-        const int c = done ? jstar : nr;                       // aggregates consumed
-        if (c == 0 && !done) {
-            if (wall_clock64() - t0 > a.timeout_ticks) {
-                if (lane == 0) atomicOr(&a.ctrl[CTRL_ERR], ERRBIT_TIMEOUT);
-                r1 = r2 = T(__builtin_nanf(""));
-                return;
+        for (int r = 0; r < kWin; ++r) {
+            const int64_t h = base - lane - kLanes * r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[r][i] = 0ull;
+            if (h >= first && (!single || (r == 0 && lane == 0))) {
+                const unsigned long long *d = a.desc + ((size_t)h * a.K + s) * 4;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[r][i] = load_word(d + i);
             }
-            for (int i = 0; i < (1 << nap); ++i) __builtin_amdgcn_s_sleep(2);
-            if (nap < 4) ++nap;
-            span = 1;
+        }
+        bool done = false, progressed = false;
+#pragma unroll
+        for (int r = 0; r < kWin; ++r) {
+            if (single && r > 0) break;
+            const bool inc_ok =
+                (unsigned)(w[r][2] >> 32) == epoch && (unsigned)(w[r][3] >> 32) == epoch;
+            const bool agg_ok =
+                (unsigned)(w[r][0] >> 32) == epoch && (unsigned)(w[r][1] >> 32) == epoch;
+            const unsigned long long incm = __ballot(inc_ok);
+            const unsigned long long rdym = __ballot(inc_ok || agg_ok);
+            const unsigned long long spanm = single ? 1ull : ~0ull;
+            const unsigned long long notr = ~rdym & spanm;
+            const int nr = notr ? __builtin_ctzll(notr) : (single ? 1 : 64);   // ready prefix
+            const int jstar = incm ? __builtin_ctzll(incm) : 64;
+            done = jstar < nr;
+            const int c = done ? jstar : nr;                                 // aggregates consumed
+            if (c == 0 && !done) break;
+            progressed = true;
+            T v1 = 0, v2 = 0;
+            if (lane < c) {
+                v1 = __uint_as_float((unsigned)w[r][0]);
+                v2 = __uint_as_float((unsigned)w[r][1]);
+            } else if (done && lane == jstar) {
+                v1 = __uint_as_float((unsigned)w[r][2]);
+                v2 = __uint_as_float((unsigned)w[r][3]);
+            }
+            const T s1 = wave_sum<T>(gp.a * v1 + gp.b * v2);
+            const T s2 = wave_sum<T>(gp.c * v1 + gp.d * v2);
+            acc1 += m00 * s1 + m01 * s2;
+            acc2 += m10 * s1 + m11 * s2;
+            if (done) break;
+            // slide past the c consumed groups: m <- m T^(C c)
+            T p00, p01, p10, p11;
+            if (c == 64) {
+                ctabT<T> *tab = ctabp(tabv);
+                p00 = tab[OFF_TW + 0]; p01 = tab[OFF_TW + 1];
+                p10 = tab[OFF_TW + 2]; p11 = tab[OFF_TW + 3];
+            } else {
+                p00 = readlane(gp.a, c); p01 = readlane(gp.b, c);
+                p10 = readlane(gp.c, c); p11 = readlane(gp.d, c);
+            }
+            const T n00 = m00 * p00 + m01 * p10, n01 = m00 * p01 + m01 * p11;
+            const T n10 = m10 * p00 + m11 * p10, n11 = m10 * p01 + m11 * p11;
+            m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+            base -= c;
+            if (c < 64) break;   // the next window was read from the old base
+        }
+        if (done) break;
+        if (progressed) {
+            nap = 0;
+            single = false;
             continue;
         }
-        nap = 0;
-        T v1 = 0, v2 = 0;
-        if (lane < c) {
-            v1 = __uint_as_float((unsigned)w[0]);
-            v2 = __uint_as_float((unsigned)w[1]);
-        } else if (done && lane == jstar) {
-            v1 = __uint_as_float((unsigned)w[2]);
-            v2 = __uint_as_float((unsigned)w[3]);
+        if (wall_clock64() - t0 > a.timeout_ticks) {
+            if (lane == 0) atomicOr(&a.ctrl[CTRL_ERR], ERRBIT_TIMEOUT);
+            r1 = r2 = T(__builtin_nanf(""));
+            return;
         }
-        const T s1 = wave_sum<T>(gp.a * v1 + gp.b * v2);
-        const T s2 = wave_sum<T>(gp.c * v1 + gp.d * v2);
-        acc1 += m00 * s1 + m01 * s2;
-        acc2 += m10 * s1 + m11 * s2;
-        if (done) break;
-        // slide past the c consumed groups: m <- m T^(C c)
-        T p00, p01, p10, p11;
-        if (c == 64) {
-            ctabT<T> *tab = ctabp(tabv);
-            p00 = tab[OFF_TW + 0]; p01 = tab[OFF_TW + 1];
-            p10 = tab[OFF_TW + 2]; p11 = tab[OFF_TW + 3];
-        } else {
-            p00 = readlane(gp.a, c); p01 = readlane(gp.b, c);
-            p10 = readlane(gp.c, c); p11 = readlane(gp.d, c);
-        }
-        const T n00 = m00 * p00 + m01 * p10, n01 = m00 * p01 + m01 * p11;
-        const T n10 = m10 * p00 + m11 * p10, n11 = m10 * p01 + m11 * p11;
-        m00 = n00; m01 = n01; m10 = n10; m11 = n11;
-        base -= c;
-        span = 64;
+        for (int i = 0; i < (1 << nap); ++i) __builtin_amdgcn_s_sleep(2);
+        if (nap < 4) ++nap;
+        single = true;
     }
     r1 = acc1;
     r2 = acc2;
@@ -413,7 +444,7 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             xch.wave_tot[wv][0] = p1;
             xch.wave_tot[wv][1] = p2;
         }
-        __syncthreads();
+        lds_barrier();
         for (int v = 0; v < wv; ++v) {
             T o1 = xch.wave_tot[v][0], o2 = xch.wave_tot[v][1];
             mv_add<T>(tab + OFF_TWAVE, e1w, e2w, o1, o2);
@@ -449,7 +480,7 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             xch.grp[1] = sg2;
         }
     }
-    __syncthreads();
+    lds_barrier();
     const T sg1 = xch.grp[0], sg2 = xch.grp[1];
 
     // --- 5. incoming state of every lane, then back substitution
@@ -624,25 +655,53 @@ __device__ __forceinline__ void store_rows(const T (&u)[N], float *tl, int lane,
 
 // --------------------------------------------------------- forward kernel
 
+// The work item of ticket t (plain signal or one signal of a batch).
+template <typename T>
+__device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, int64_t t)
+{
+    Item<T> it;
+    it.t = t;
+    if (a.B == 0) {
+        it.x = a.x;
+        it.y = a.y;
+        it.n = a.n;
+        it.g = t;
+        it.tabs = tabs;
+        it.zi = a.zi;
+        it.zf = a.zf;
+        it.K = a.K;
+    } else {
+        const int i = a.sigmap[t];
+        const int64_t so = a.sig_off[i];
+        const int32_t sc = a.sec_off[i];
+        it.x = a.xp ? a.xp[i] : a.x + so;
+        it.y = a.yp ? a.yp[i] : a.y + so;
+        it.n = a.sig_off[i + 1] - so;
+        it.g = t - a.gpre[i];
+        it.tabs = tabs + (size_t)sc * TAB_FLOATS;
+        it.zi = a.zi ? a.zi + 2 * (int64_t)sc : nullptr;
+        it.zf = a.zf ? a.zf + 2 * (int64_t)sc : nullptr;
+        it.K = a.Ks[i];
+    }
+    return it;
+}
+
+__device__ __forceinline__ bool aligned16(const void *p)
+{
+    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// Everything after the wave's samples are in registers: the K sections, then
+// registers -> the wave's LDS rows -> coalesced 128-bit global stores.
 template <typename T, int N, int W>
-__device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &it, float *tl,
-                                              Xch<T, W> &xch, unsigned epoch, int wv, int lane)
+__device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it, T (&u)[N],
+                                             float *tl, Xch<T, W> &xch, unsigned epoch, int wv,
+                                             int lane)
 {
     constexpr int CW = kLanes * N;   // samples per wave
     constexpr int C = CW * W;        // samples per group
-
     const int64_t g0 = it.g * C + (int64_t)wv * CW;   // first sample of this wave
     const int64_t rem = it.n - g0;                    // may be <= 0 in the last group
-    const bool vec = ((reinterpret_cast<uintptr_t>(it.x) | reinterpret_cast<uintptr_t>(it.y)) &
-                      15u) == 0;
-
-    // --- load: coalesced 128-bit global loads -> the wave's LDS rows -> registers.
-    //     The tile is the wave's own, so wave-scope ordering suffices.
-    tile_load<N>(it.x + g0, rem, vec, tl, lane);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    T u[N];
-    regs_from_rows<T, N>(u, tl, lane);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
     // --- sections (an unusable section poisons its signal)
     bool bad = false;
@@ -667,11 +726,25 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &i
             for (int s = 0; s < it.K; ++s) it.zf[2 * s] = it.zf[2 * s + 1] = __builtin_nanf("");
     }
 
-    // --- store: registers -> the wave's LDS rows -> coalesced 128-bit global stores
+    // --- store: the tile is the wave's own, so wave-scope ordering suffices
     rows_from_regs<T, N>(u, tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    tile_store<N, true>(it.y + g0, rem, vec, tl, lane);
+    tile_store<N, true>(it.y + g0, rem, aligned16(it.y), tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Minimum waves per SIMD the register allocation must allow, chosen so that
+// two workgroups fit on a CU where LDS allows it (W = 4: 2 waves of <= 256
+// registers; W = 8: 4 waves of <= 128); otherwise the compiler's choice.
+// With one workgroup per CU, its load, lookback and store phases leave the
+// CU idle; a second resident group fills them.
+template <typename T, int N, int W>
+constexpr int min_waves_per_simd()
+{
+    if (sizeof(T) != 4) return 1;
+    if (W == 4) return 2;
+    if (W == 8 && N <= 32) return 4;
+    return 1;
 }
 
 // The filter kernel: every workgroup draws tickets until the work runs out.
@@ -680,9 +753,13 @@ __device__ __forceinline__ void process_group(const FwdArgs &a, const Item<T> &i
 // on) before it, which guarantees forward progress of the lookback whatever
 // the grid size (Sec. IV-A).
 template <typename T, int N, int W>
-__global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<T, N, W>())))
+    sos_fwd_kernel(FwdArgs a)
 {
     constexpr int RS = N + 4;
+    constexpr int CW = kLanes * N;
+    constexpr int C = CW * W;
     __shared__ float tile[W][kLanes * RS];
     __shared__ Xch<T, W> xch;
     __shared__ int64_t ticket;
@@ -696,35 +773,19 @@ __global__ void __launch_bounds__(64 * W) sos_fwd_kernel(FwdArgs a)
 
     for (;;) {
         if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
-        __syncthreads();
+        lds_barrier();
         const int64_t t = ticket;
-        __syncthreads();
+        lds_barrier();
         if (t >= total) break;
-        Item<T> it;
-        it.t = t;
-        if (a.B == 0) {
-            it.x = a.x;
-            it.y = a.y;
-            it.n = a.n;
-            it.g = t;
-            it.tabs = tabs;
-            it.zi = a.zi;
-            it.zf = a.zf;
-            it.K = a.K;
-        } else {
-            const int i = a.sigmap[t];
-            const int64_t so = a.sig_off[i];
-            const int32_t sc = a.sec_off[i];
-            it.x = a.xp ? a.xp[i] : a.x + so;
-            it.y = a.yp ? a.yp[i] : a.y + so;
-            it.n = a.sig_off[i + 1] - so;
-            it.g = t - a.gpre[i];
-            it.tabs = tabs + (size_t)sc * TAB_FLOATS;
-            it.zi = a.zi ? a.zi + 2 * (int64_t)sc : nullptr;
-            it.zf = a.zf ? a.zf + 2 * (int64_t)sc : nullptr;
-            it.K = a.Ks[i];
-        }
-        process_group<T, N, W>(a, it, tl, xch, epoch, wv, lane);
+        const Item<T> it = make_item<T>(a, tabs, t);
+        const int64_t g0 = it.g * C + (int64_t)wv * CW;
+        // load: coalesced 128-bit global loads -> the wave's LDS rows -> registers
+        tile_load<N>(it.x + g0, it.n - g0, aligned16(it.x), tl, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        T u[N];
+        regs_from_rows<T, N>(u, tl, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        finish_group<T, N, W>(a, it, u, tl, xch, epoch, wv, lane);
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
     }
 }

@@ -107,9 +107,14 @@ struct Tile {
     int L, N;
 };
 
-inline Tile tile_of(const sos_ctx *h)
+// The handle's tile, else SOS_TILE_L / SOS_TILE_N, else the default for a
+// cascade of K sections: with one section the group is cheap enough that two
+// resident groups per CU (L = 512, N = 32) beat one larger group; from two
+// sections on, the larger group (N = 64) halves the lookbacks per sample and
+// wins (measured on MI355X, 2^28 samples, orders 2-16).
+inline Tile tile_of(const sos_ctx *h, int K = 1)
 {
-    Tile t{kDefaultL, kDefaultN};
+    Tile t{kDefaultL, K <= 1 ? 32 : kDefaultN};
     if (const char *e = std::getenv("SOS_TILE_L")) {
         const int v = std::atoi(e);
         if (sos_fwd_shape_supported(v, t.N)) t.L = v;

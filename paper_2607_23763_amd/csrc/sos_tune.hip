@@ -92,7 +92,7 @@ int sos_graph_create_batched(sos_graph_t *out, sos_handle_t hu, int B, int kmax,
         delete g;
         return rc;
     }
-    const Tile t = tile_of(hu);
+    const Tile t = tile_of(hu, kmax);
     const int bits = bits_of(hu);
     g->h->tile_L = t.L;
     g->h->tile_N = t.N;
