@@ -820,23 +820,89 @@ struct BwdArgs {
     unsigned long long timeout_ticks;
 };
 
-// Stage the wave's part of a signal in reversed time into its LDS rows:
-// element e of the wave (reversed index r0 + e) is src[n-1-r0-e], 0 past the end.
+// Reversed time without reversed memory traffic. The wave's part in reversed
+// time, reversed indices [r0, r0 + 64N), is the forward window
+// [n - r0 - 64N, n - r0); lane l's reversed samples l N .. l N + N - 1 are
+// forward row 63 - l of that window read backwards. So the window moves with
+// the same coalesced 128-bit accesses and padded LDS rows as the forward
+// filter, and only the row read is mirrored. Samples before forward index 0
+// (the padding of the last reversed group) read as 0 and are not written.
+
+// src[start .. start + 64N) -> tile, zero outside [0, n).
 template <int N>
-__device__ __forceinline__ void stage_reversed(const float *src, int64_t n, int64_t r0, float *tl,
-                                               int lane)
+__device__ __forceinline__ void window_load(const float *src, int64_t start, int64_t n, float *tl,
+                                            int lane)
 {
-    constexpr int RS = N + 4;
-#pragma unroll 4
-    for (int j = 0; j < N; ++j) {
-        const int e = kLanes * j + lane;
-        const int64_t r = r0 + e;
-        tl[(e / N) * RS + (e % N)] = r < n ? src[n - 1 - r] : 0.0f;
+    if (start >= 0) {
+        tile_load<N>(src + start, n - start, aligned16(src + start), tl, lane);
+        return;
+    }
+    using TT = WaveTile<N>;
+    float *p = tl + TT::slot_base(lane);
+#pragma unroll
+    for (int j = 0; j < TT::Q; ++j) {
+        const int64_t q = start + 4 * (int64_t)(kLanes * j + lane);
+        f4 t;
+        t.x = q + 0 >= 0 && q + 0 < n ? src[q + 0] : 0.0f;
+        t.y = q + 1 >= 0 && q + 1 < n ? src[q + 1] : 0.0f;
+        t.z = q + 2 >= 0 && q + 2 < n ? src[q + 2] : 0.0f;
+        t.w = q + 3 >= 0 && q + 3 < n ? src[q + 3] : 0.0f;
+        *reinterpret_cast<f4 *>(p + j * TT::STEP) = t;
+    }
+}
+
+// tile -> dst[start .. start + 64N) restricted to [0, n).
+template <int N>
+__device__ __forceinline__ void window_store(float *dst, int64_t start, int64_t n,
+                                             const float *tl, int lane)
+{
+    if (start >= 0) {
+        tile_store<N, true>(dst + start, n - start, aligned16(dst + start), tl, lane);
+        return;
+    }
+    using TT = WaveTile<N>;
+    const float *p = tl + TT::slot_base(lane);
+#pragma unroll
+    for (int j = 0; j < TT::Q; ++j) {
+        const int64_t q = start + 4 * (int64_t)(kLanes * j + lane);
+        const f4 t = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
+        if (q + 0 >= 0 && q + 0 < n) dst[q + 0] = t.x;
+        if (q + 1 >= 0 && q + 1 < n) dst[q + 1] = t.y;
+        if (q + 2 >= 0 && q + 2 < n) dst[q + 2] = t.z;
+        if (q + 3 >= 0 && q + 3 < n) dst[q + 3] = t.w;
+    }
+}
+
+// Lane l's N registers <-> forward row 63 - l of the tile, mirrored.
+template <typename T, int N>
+__device__ __forceinline__ void regs_from_rows_rev(T (&u)[N], const float *tl, int lane)
+{
+    const float *row = tl + (kLanes - 1 - lane) * WaveTile<N>::RS;
+#pragma unroll
+    for (int k = 0; k < N / 4; ++k) {
+        const f4 v = *reinterpret_cast<const f4 *>(row + 4 * k);
+        u[N - 1 - 4 * k] = v.x;
+        u[N - 2 - 4 * k] = v.y;
+        u[N - 3 - 4 * k] = v.z;
+        u[N - 4 - 4 * k] = v.w;
+    }
+}
+template <typename T, int N>
+__device__ __forceinline__ void rows_from_regs_rev(const T (&u)[N], float *tl, int lane)
+{
+    float *row = tl + (kLanes - 1 - lane) * WaveTile<N>::RS;
+#pragma unroll
+    for (int k = 0; k < N / 4; ++k) {
+        const f4 v = {(float)u[N - 1 - 4 * k], (float)u[N - 2 - 4 * k], (float)u[N - 3 - 4 * k],
+                      (float)u[N - 4 - 4 * k]};
+        *reinterpret_cast<f4 *>(row + 4 * k) = v;
     }
 }
 
 template <typename T, int N, int W>
-__global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && W >= 4 ? 2 : 1)))
+    sos_bwd_kernel(BwdArgs b)
 {
     constexpr int RS = N + 4;
     constexpr int CW = kLanes * N;
@@ -865,9 +931,9 @@ __global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
 
     for (;;) {
         if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&b.ctrl[CTRL_TICKET], 1u);
-        __syncthreads();
+        lds_barrier();
         const int64_t t = ticket;
-        __syncthreads();
+        lds_barrier();
         if (t >= b.total) break;
         Item<T> it{};
         it.n = b.n;
@@ -876,18 +942,13 @@ __global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
         it.zi = b.gzf;
         it.K = b.K;
         const int64_t r0 = t * C + (int64_t)wv * CW;   // reversed index of the wave's start
+        const int64_t f0 = b.n - r0 - CW;              // forward index of the window's start
 
-        stage_reversed<N>(b.gy, b.n, r0, tl, lane);
-        __syncthreads();
+        window_load<N>(b.gy, f0, b.n, tl, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         T u[N];
-#pragma unroll
-        for (int k = 0; k < N / 4; ++k) {
-            const float4 v = *reinterpret_cast<const float4 *>(&tl[lane * RS + 4 * k]);
-            u[4 * k + 0] = v.x;
-            u[4 * k + 1] = v.y;
-            u[4 * k + 2] = v.z;
-            u[4 * k + 3] = v.w;
-        }
+        regs_from_rows_rev<T, N>(u, tl, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // lane / position of reversed index n-1 (forward sample 0) if this wave holds it
         const int64_t pz = (b.n - 1) - r0;
         const bool has_first = pz >= 0 && pz < CW;
@@ -896,26 +957,36 @@ __global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
         for (int k = b.K - 1; k >= 0 && !bad; --k) {
             const T *tabv = tabs + (size_t)k * TAB_FLOATS;
             ctabT<T> *tab = ctabp(tabv);
-            __syncthreads();
-            stage_reversed<N>(k == 0 ? b.x : b.saved + (size_t)(k - 1) * b.n, b.n, r0, tl, lane);
-            stage_reversed<N>(k == b.K - 1 ? b.y : b.saved + (size_t)k * b.n, b.n, r0, tl2, lane);
-            __syncthreads();
+            // the section's forward input and output over the window (own tiles)
+            window_load<N>(k == 0 ? b.x : b.saved + (size_t)(k - 1) * b.n, f0, b.n, tl, lane);
+            window_load<N>(k == b.K - 1 ? b.y : b.saved + (size_t)k * b.n, f0, b.n, tl2, lane);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             T q1, q2;   // lam'[-2], lam'[-1] of this lane
             run_section<T, N, W, true>(u, xch, tl, a, it, tabv, k, epoch, wv, lane, false, 0, 0,
                                        q1, q2);
-            // coefficient sums over the lane
+            // coefficient sums over the lane (reversed position m = forward column N-1-m)
             T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+            const float *ru = tl + (kLanes - 1 - lane) * RS;
+            const float *rv = tl2 + (kLanes - 1 - lane) * RS;
 #pragma unroll
-            for (int m = 0; m < N; ++m) {
-                const T L0 = u[m];
-                const T L1 = m >= 1 ? u[m - 1] : q2;
-                const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
-                const T uu = tl[lane * RS + m], vv = tl2[lane * RS + m];
-                s0 = fmaT(L0, uu, s0);
-                s1 = fmaT(L1, uu, s1);
-                s2 = fmaT(L2, uu, s2);
-                s3 = fmaT(-L1, vv, s3);
-                s4 = fmaT(-L2, vv, s4);
+            for (int k4 = 0; k4 < N / 4; ++k4) {
+                const f4 U = *reinterpret_cast<const f4 *>(ru + 4 * k4);
+                const f4 V = *reinterpret_cast<const f4 *>(rv + 4 * k4);
+                const float uq[4] = {U.w, U.z, U.y, U.x};
+                const float vq[4] = {V.w, V.z, V.y, V.x};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = N - 4 - 4 * k4 + i;
+                    const T L0 = u[m];
+                    const T L1 = m >= 1 ? u[m - 1] : q2;
+                    const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
+                    const T uu = uq[i], vv = vq[i];
+                    s0 = fmaT(L0, uu, s0);
+                    s1 = fmaT(L1, uu, s1);
+                    s2 = fmaT(L2, uu, s2);
+                    s3 = fmaT(-L1, vv, s3);
+                    s4 = fmaT(-L2, vv, s4);
+                }
             }
             // d/dzi = (lam'[n-1], lam'[n-2])
             if (has_first && b.gzi) {
@@ -928,12 +999,12 @@ __global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
                 }
             }
             // gradient for the section below: 3-tap FIR of lam' (descending, in place)
-            const T f0 = tab[OFF_FIR + 0], f1 = tab[OFF_FIR + 1], f2 = tab[OFF_FIR + 2];
+            const T f0c = tab[OFF_FIR + 0], f1c = tab[OFF_FIR + 1], f2c = tab[OFF_FIR + 2];
 #pragma unroll
             for (int m = N - 1; m >= 0; --m) {
                 const T L1 = m >= 1 ? u[m - 1] : q2;
                 const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
-                u[m] = fmaT(f0, u[m], fmaT(f1, L1, f2 * L2));
+                u[m] = fmaT(f0c, u[m], fmaT(f1c, L1, f2c * L2));
             }
             // group partial sums (waves combined in FP64)
             const T w0 = wave_sum<T>(s0), w1 = wave_sum<T>(s1), w2 = wave_sum<T>(s2);
@@ -945,12 +1016,14 @@ __global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
                 red[wv][3] = w3;
                 red[wv][4] = w4;
             }
-            __syncthreads();
+            lds_barrier();
             if (threadIdx.x < 5) {
                 double acc = 0.0;
                 for (int v = 0; v < W; ++v) acc += red[v][threadIdx.x];
                 b.partials[((size_t)t * b.K + k) * 5 + threadIdx.x] = acc;
             }
+            // the tiles are re-staged for the next section: wave-local, ordered
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
         if (bad) {
 #pragma unroll
@@ -958,20 +1031,12 @@ __global__ void __launch_bounds__(64 * W) sos_bwd_kernel(BwdArgs b)
             for (int i = threadIdx.x; i < 5 * b.K; i += blockDim.x)
                 b.partials[(size_t)t * b.K * 5 + i] = __builtin_nan("");
         }
-        // store dL/dx in forward order
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < N / 4; ++k)
-            *reinterpret_cast<float4 *>(&tl[lane * RS + 4 * k]) =
-                make_float4((float)u[4 * k + 0], (float)u[4 * k + 1], (float)u[4 * k + 2],
-                            (float)u[4 * k + 3]);
-        __syncthreads();
-#pragma unroll 4
-        for (int j = 0; j < N; ++j) {
-            const int e = kLanes * j + lane;
-            const int64_t r = r0 + e;
-            if (r < b.n) b.gx[b.n - 1 - r] = tl[(e / N) * RS + (e % N)];
-        }
+        // store dL/dx in forward order through the wave's rows
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        rows_from_regs_rev<T, N>(u, tl, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        window_store<N>(b.gx, f0, b.n, tl, lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if ((int64_t)gridDim.x >= b.total) break;
     }
 }
@@ -1136,7 +1201,7 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
     return dispatch_fwd(bits, L, N, a, grid, stream);
 }
 
-// Adjoint of the plain filter: grid <= 0 means one workgroup per group.
+// Adjoint of the plain filter: grid <= 0 means a persistent grid.
 extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx,
                                      int64_t n, int64_t groups, const void *tabs, int K,
                                      const float *x, const float *y, const float *saved,
@@ -1147,16 +1212,32 @@ extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, fl
 {
     BwdArgs b{gy, gx, n, tabs, x, y, saved, gzf, gzi, partials, desc, ctrl, K, groups,
               timeout_ticks};
-    if (grid <= 0 || grid > groups) grid = groups;
     const int W = L / 64;
+    // grid <= 0: persistent, as many workgroups as can be resident
+    auto resident = [&](const void *kern, int threads) -> int64_t {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        return (int64_t)per_cu * cus;
+    };
 #define SOS_BWD_CASE(NN, WW)                                                                   \
     if (N == NN && W == WW) {                                                                  \
-        if (bits == 64)                                                                        \
+        if (bits == 64) {                                                                      \
+            if (grid <= 0) grid = resident((const void *)sos_bwd_kernel<double, NN, WW>, 64 * WW); \
+            if (grid > groups) grid = groups;                                                  \
             hipLaunchKernelGGL((sos_bwd_kernel<double, NN, WW>), dim3((unsigned)grid),        \
                                dim3(64 * WW), 0, stream, b);                                   \
-        else                                                                                   \
+        } else {                                                                               \
+            if (grid <= 0) grid = resident((const void *)sos_bwd_kernel<float, NN, WW>, 64 * WW); \
+            if (grid > groups) grid = groups;                                                  \
             hipLaunchKernelGGL((sos_bwd_kernel<float, NN, WW>), dim3((unsigned)grid),         \
                                dim3(64 * WW), 0, stream, b);                                   \
+        }                                                                                      \
         return hipGetLastError();                                                              \
     }
     SOS_BWD_CASE(16, 1)
