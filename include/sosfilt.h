@@ -199,6 +199,29 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
                    const float *saved, int64_t n, const float *gy, const float *gzf, float *gx,
                    float *gzi, float *gsections, hipStream_t stream);
 
+/* Batched training pair: sos_filter_batched's arguments (same layouts and
+ * rules) plus, for the forward, `saved`: DEVICE (kmax-1) x total_samples
+ * floats receiving the outputs of sections 0..K[i]-2 of signal i at
+ * saved + s * total_samples + sig_off[i] (NULL allowed when kmax <= 1;
+ * x != y). The adjoint takes the same batch description, the forward's x, y
+ * and saved, the cotangents gy (like y) and gzf (like zf, nullable), and
+ * writes gx (like x), gzi (like zi, nullable) and gsections (like sections,
+ * nullable: the rows of the batch's signals). Empty signals get gzi = gzf and
+ * zero coefficient gradients. One persistent launch of the adjoint over the
+ * reversed groups of every signal, then a per-(signal, section) FP64
+ * reduction of the coefficient partials. */
+int sos_filter_train_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                             int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                             const float *sections, const int64_t *sig_off, const float *x,
+                             float *y, const float *zi, float *zf, float *saved,
+                             hipStream_t stream);
+int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                           int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                           const float *sections, const int64_t *sig_off, const float *x,
+                           const float *y, const float *saved, const float *gy,
+                           const float *gzf, float *gx, float *gzi, float *gsections,
+                           hipStream_t stream);
+
 /* Memory-floor reference (the t_mem = b_s / BW term of the cost model,
  * Eq. (28), with b_s = 8 bytes per sample): a plain streaming copy y = x of n
  * FP32 samples with the same 128-bit nontemporal accesses as the filter.

@@ -92,6 +92,12 @@ def lib():
                                            ctypes.POINTER(ctypes.c_float)]
             L.sos_tune_lookup.argtypes = [vp, i32, i32, i64, ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+            L.sos_filter_train_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp,
+                                                   vp, vp, vp, vp, vp]
+            L.sos_filter_vjp_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp,
+                                                 vp, vp, vp, vp, vp, vp, vp]
+            L.sos_filter_train_batched.restype = i32
+            L.sos_filter_vjp_batched.restype = i32
             for name in ("sos_graph_create_batched", "sos_graph_launch", "sos_graph_last_error",
                          "sos_graph_destroy", "sos_tune_batched", "sos_tune_lookup"):
                 getattr(L, name).restype = i32
@@ -327,6 +333,49 @@ def sosfilt_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=N
     return a["y"], a["zf"]
 
 
+def sosfilt_train_batched(x, sections, K, sig_off, zi=None, sec_off=None, kmax=None,
+                          handle: Handle | None = None):
+    """Batched forward keeping the section outputs for the adjoint
+    (sos_filter_train_batched). Returns (y, zf, saved)."""
+    import torch
+
+    a = _batch_args(x, sections, K, sig_off, zi, None, None, sec_off, kmax)
+    saved = torch.empty((max(a["kmax"] - 1, 1), a["x"].numel()), dtype=torch.float32,
+                        device=a["x"].device)
+    h = handle or default_handle(a["x"].device.index or 0)
+    _check(lib().sos_filter_train_batched(h.ptr, a["B"], a["kmax"], a["nsec"], a["x"].numel(),
+                                          _p(a["K"]), _p(a["sec_off"]), _p(a["sections"]),
+                                          _p(a["sig_off"]), _p(a["x"]), _p(a["y"]), _p(a["zi"]),
+                                          _p(a["zf"]), _p(saved), _stream_ptr(a["x"].device)),
+           "sos_filter_train_batched")
+    return a["y"], a["zf"], saved
+
+
+def sosfilt_vjp_batched(sections, K, sig_off, x, y, saved, gy, gzf=None, sec_off=None,
+                        kmax=None, handle: Handle | None = None):
+    """Vector-Jacobian product of a batched forward (sos_filter_vjp_batched).
+    Returns (gx, gzi, gsections), gzi and gsections shaped like zi and
+    sections (rows of the batch's signals)."""
+    import torch
+
+    a = _batch_args(x, sections, K, sig_off, None, None, None, sec_off, kmax)
+    y = _as_dev_f32(y, "y").reshape(-1)
+    gy = _as_dev_f32(gy, "gy").reshape(-1)
+    if gzf is not None:
+        gzf = _as_dev_f32(gzf, "gzf").reshape(-1, 2)
+    gx = torch.empty_like(a["x"])
+    gzi = torch.zeros((a["nsec"], 2), dtype=torch.float32, device=a["x"].device)
+    gs = torch.zeros((a["nsec"], 6), dtype=torch.float32, device=a["x"].device)
+    h = handle or default_handle(a["x"].device.index or 0)
+    _check(lib().sos_filter_vjp_batched(h.ptr, a["B"], a["kmax"], a["nsec"], a["x"].numel(),
+                                        _p(a["K"]), _p(a["sec_off"]), _p(a["sections"]),
+                                        _p(a["sig_off"]), _p(a["x"]), _p(y), _p(saved), _p(gy),
+                                        _p(gzf), _p(gx), _p(gzi), _p(gs),
+                                        _stream_ptr(a["x"].device)),
+           "sos_filter_vjp_batched")
+    return gx, gzi, gs
+
+
 def tune_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None, kmax=None,
                  handle: Handle | None = None, reps: int = 3):
     """Autotune (L, N) for this batch (sos_tune_batched); the handle keeps the
@@ -453,22 +502,63 @@ def _autograd_fn():
                                         None if gzf is None else gzf.contiguous())
             return gx, gsos, gzi
 
-    return SosFilterFn
+    class SosFilterBatchFn(torch.autograd.Function):
+        """A batch of equal-length signals x (B x n): forward =
+        sos_filter_train_batched, backward = sos_filter_vjp_batched (one
+        persistent adjoint launch for the whole batch). sos is K x 6 (shared
+        by the batch: its gradient is summed over the signals) or B x K x 6;
+        zi is B x K x 2."""
+
+        @staticmethod
+        def forward(ctx, x, sos, zi):
+            B, n = x.shape
+            K = sos.shape[-2]
+            rows = (sos.expand(B, K, 6) if sos.dim() == 2 else sos).reshape(B * K, 6).contiguous()
+            dev = x.device
+            Ks = torch.full((B,), K, dtype=torch.int32, device=dev)
+            sig_off = torch.arange(B + 1, dtype=torch.int64, device=dev) * n
+            sec_off = torch.arange(B + 1, dtype=torch.int32, device=dev) * K
+            xf = x.reshape(-1).contiguous()
+            y, zf, saved = sosfilt_train_batched(xf, rows, Ks, sig_off, zi.reshape(-1, 2),
+                                                 sec_off=sec_off, kmax=K)
+            ctx.save_for_backward(xf, rows, Ks, sig_off, sec_off, y, saved)
+            ctx.shape = (B, n, K, sos.dim())
+            return y.reshape(B, n), zf.reshape(B, K, 2)
+
+        @staticmethod
+        def backward(ctx, gy, gzf):
+            xf, rows, Ks, sig_off, sec_off, y, saved = ctx.saved_tensors
+            B, n, K, sdim = ctx.shape
+            gy = torch.zeros_like(y) if gy is None else gy.reshape(-1).contiguous()
+            gzf = None if gzf is None else gzf.reshape(-1, 2).contiguous()
+            gx, gzi, gs = sosfilt_vjp_batched(rows, Ks, sig_off, xf, y, saved, gy, gzf,
+                                              sec_off=sec_off, kmax=K)
+            gs = gs.reshape(B, K, 6)
+            return gx.reshape(B, n), (gs.sum(0) if sdim == 2 else gs), gzi.reshape(B, K, 2)
+
+    return SosFilterFn, SosFilterBatchFn
 
 
 _fn = None
 
 
 def sosfilt_autograd(x, sos, zi=None):
-    """y, zf with gradients flowing to x, sos and zi through the adjoint kernel."""
+    """y, zf with gradients flowing to x, sos and zi through the adjoint kernel.
+    x of shape (n,) with sos K x 6 and zi K x 2, or a batch x of shape (B, n)
+    with sos K x 6 (shared) or B x K x 6 and zi B x K x 2."""
     import torch
 
     global _fn
     if _fn is None:
         _fn = _autograd_fn()
+    K = sos.shape[-2]
+    if x.dim() == 2:
+        if zi is None:
+            zi = torch.zeros((x.shape[0], K, 2), dtype=torch.float32, device=x.device)
+        return _fn[1].apply(x, sos, zi)
     if zi is None:
-        zi = torch.zeros((sos.shape[0], 2), dtype=torch.float32, device=x.device)
-    return _fn.apply(x, sos, zi)
+        zi = torch.zeros((K, 2), dtype=torch.float32, device=x.device)
+    return _fn[0].apply(x, sos, zi)
 
 
 class Server:

@@ -166,7 +166,8 @@ int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
     const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
     if (ba.total_rows > 0 &&
         sos_launch_prep_batched(bits, ba.sections, ba.B, ba.kmax, ba.total_rows, ba.K,
-                                ba.sec_off, log2n, log2w, h->tabs, h->ctrl, stream) != hipSuccess)
+                                ba.sec_off, log2n, log2w, h->tabs, h->ctrl, 0, stream) !=
+            hipSuccess)
         return SOS_EHIP;
     if (sos_launch_worktable(ba.B, ba.kmax, ba.total_rows, C, ba.total_samples, max_groups, ba.K,
                              ba.sec_off, ba.sig_off, h->gpre, h->sigmap, h->total_dev, ba.zi,
@@ -178,7 +179,7 @@ int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
     if (sos_launch_fwd_batched(bits, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
                                h->sigmap, h->total_dev, ba.x, ba.y, h->tabs, ba.zi, ba.zf,
                                h->desc, h->ctrl, h->timeout_ticks, grid, nullptr, nullptr,
-                               stream) != hipSuccess)
+                               ba.saved, ba.total_samples, stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = -1;        // the batch overwrote the plain tables
     h->last_groups = 0;
@@ -452,6 +453,91 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
     if (gsections &&
         sos_launch_bwd_reduce(h->partials, groups, K, sections, gsections, stream) != hipSuccess)
         return SOS_EHIP;
+    h->last_groups = 0;
+    h->last_K = 0;
+    return SOS_OK;
+}
+
+int sos_filter_train_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                             int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                             const float *sections, const int64_t *sig_off, const float *x,
+                             float *y, const float *zi, float *zf, float *saved,
+                             hipStream_t stream)
+{
+    if (!h) return SOS_EINVAL;
+    BatchArgs ba{B, kmax, total_rows, total_samples, K, sec_off, sections, sig_off, x, y, zi, zf};
+    int rc = batch_check(ba);
+    if (rc || B == 0) return rc;
+    if (total_samples > 0 && x == y) return SOS_EINVAL;   // the adjoint needs the input
+    if (kmax > 1 && total_samples > 0 && !saved) return SOS_EINVAL;
+    ba.saved = kmax > 1 ? saved : nullptr;
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    const Tile t = tile_of(h, kmax);
+    const int bits = bits_of(h);
+    rc = batch_reserve(h, t, bits, ba, stream);
+    if (rc) return rc;
+    return batch_enqueue(h, t, bits, ba, stream);
+}
+
+int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                           int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                           const float *sections, const int64_t *sig_off, const float *x,
+                           const float *y, const float *saved, const float *gy,
+                           const float *gzf, float *gx, float *gzi, float *gsections,
+                           hipStream_t stream)
+{
+    if (!h || B < 0 || kmax < 0 || kmax > SOS_MAX_SECTIONS || total_samples < 0 ||
+        total_rows < 0)
+        return SOS_EINVAL;
+    if (B == 0) return SOS_OK;
+    if (!K || !sec_off || !sig_off || (total_rows > 0 && !sections)) return SOS_EINVAL;
+    if (total_samples > 0 && (!x || !y || !gy || !gx)) return SOS_EINVAL;
+    if (kmax > 1 && total_samples > 0 && !saved) return SOS_EINVAL;
+    std::lock_guard<std::mutex> lk(h->mu);
+    DeviceGuard g(h->device);
+    if (!g.ok) return SOS_EHIP;
+    Tile t = tile_of(h, kmax);
+    if (!sos_bwd_shape_supported(t.L, t.N)) t = Tile{256, 32};
+    const int bits = bits_of(h);
+    const int64_t C = (int64_t)t.L * t.N;
+    const int64_t max_groups = total_samples / C + B;
+    if (max_groups >= (int64_t)1 << 31 || total_rows >= (int64_t)1 << 31) return SOS_EINVAL;
+    const int kd = kmax > 0 ? kmax : 1;
+    int rc = ensure_buf(h->tabs_bwd, h->tabs_bwd_cap,
+                        tab_bytes((int)(total_rows > 1 ? total_rows : 1), bits), stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->partials, h->partials_cap, (size_t)max_groups * kd * 5, stream);
+    if (rc) return rc;
+    rc = ensure_desc(h, (size_t)max_groups * (size_t)kd * 4u, stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->gpre, h->gpre_cap, (size_t)B + 1, stream);
+    if (rc) return rc;
+    rc = ensure_buf(h->sigmap, h->sigmap_cap, (size_t)max_groups, stream);
+    if (rc) return rc;
+    if (!h->total_dev && hipMalloc(&h->total_dev, sizeof(int64_t)) != hipSuccess)
+        return SOS_ENOMEM;
+    const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
+    if (total_rows > 0 &&
+        sos_launch_prep_batched(bits, sections, B, kmax, total_rows, K, sec_off, log2n, log2w,
+                                h->tabs_bwd, h->ctrl, 1, stream) != hipSuccess)
+        return SOS_EHIP;
+    // work table over the adjoint's groups; an empty signal gets gzi = gzf
+    if (sos_launch_worktable(B, kmax, total_rows, C, total_samples, max_groups, K, sec_off,
+                             sig_off, h->gpre, h->sigmap, h->total_dev, gzf, gzi, h->ctrl,
+                             stream) != hipSuccess)
+        return SOS_EHIP;
+    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    if (sos_launch_bwd_batched(bits, t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre, h->sigmap,
+                               h->total_dev, max_groups, gy, gx, h->tabs_bwd, x, y, saved,
+                               total_samples, gzf, gzi, h->partials, h->desc, h->ctrl,
+                               h->timeout_ticks, stream) != hipSuccess)
+        return SOS_EHIP;
+    if (gsections && sos_launch_bwd_reduce_batched(h->partials, B, kd, K, sec_off, h->gpre,
+                                                   sections, gsections, stream) != hipSuccess)
+        return SOS_EHIP;
+    h->prep_K = -1;
     h->last_groups = 0;
     h->last_K = 0;
     return SOS_OK;

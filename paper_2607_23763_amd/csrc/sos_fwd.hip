@@ -66,7 +66,9 @@ struct FwdArgs {
     const float *const *xp; // batched, optional: per-signal input pointers (else x + sig_off)
     float *const *yp;       //   and output pointers (else y + sig_off)
     // both modes
-    float *saved;           // plain mode, optional: outputs of sections 0..K-2 ((K-1) x n)
+    float *saved;           // optional: outputs of sections 0..K-2, section s of a signal at
+                            // saved + s * saved_stride (+ its sample offset when batched)
+    int64_t saved_stride;
     int64_t total;          // number of work items (plain)
     unsigned long long *desc;
     unsigned *ctrl;
@@ -84,6 +86,7 @@ struct Item {
     const T *tabs;          // tables of the signal's sections
     const float *zi;
     float *zf;
+    float *saved;           // the signal's intermediate outputs (or null)
     int K;
 };
 
@@ -669,6 +672,7 @@ __device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, in
         it.tabs = tabs;
         it.zi = a.zi;
         it.zf = a.zf;
+        it.saved = a.saved;
         it.K = a.K;
     } else {
         const int i = a.sigmap[t];
@@ -681,6 +685,7 @@ __device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, in
         it.tabs = tabs + (size_t)sc * TAB_FLOATS;
         it.zi = a.zi ? a.zi + 2 * (int64_t)sc : nullptr;
         it.zf = a.zf ? a.zf + 2 * (int64_t)sc : nullptr;
+        it.saved = a.saved ? a.saved + so : nullptr;
         it.K = a.Ks[i];
     }
     return it;
@@ -716,8 +721,8 @@ __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it
             T q1, q2;
             run_section<T, N, W, false>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s,
                                         epoch, wv, lane, has_last, zl, zp, q1, q2);
-            if (a.saved && s + 1 < it.K)
-                store_rows<T, N>(u, tl, lane, it.n, g0, a.saved + (size_t)s * it.n);
+            if (it.saved && s + 1 < it.K)
+                store_rows<T, N>(u, tl, lane, it.n, g0, it.saved + (size_t)s * a.saved_stride);
         }
     } else {
 #pragma unroll
@@ -815,10 +820,63 @@ struct BwdArgs {
     double *partials;        // total x K x 5 per-group coefficient sums
     unsigned long long *desc;
     unsigned *ctrl;
-    int K;
+    int K;                   // plain: sections; batched: stride (max sections)
     int64_t total;
     unsigned long long timeout_ticks;
+    // batched mode (B > 0): per-signal arrays and the work table (reversed groups)
+    int B;
+    const int32_t *Ks;
+    const int32_t *sec_off;
+    const int64_t *sig_off;
+    const int64_t *gpre;
+    const int32_t *sigmap;
+    const int64_t *total_dev;
+    int64_t saved_stride;    // distance between the saved outputs of two sections
 };
+
+// One reversed-time group of one signal.
+template <typename T>
+struct BItem {
+    Item<T> it;              // t, g, n, K, tabs, zi = the final-state cotangent
+    const float *gy, *x, *y, *saved;
+    float *gx, *gzi;
+};
+
+template <typename T>
+__device__ __forceinline__ BItem<T> make_bwd_item(const BwdArgs &b, const T *tabs, int64_t t)
+{
+    BItem<T> r{};
+    r.it.t = t;
+    if (b.B == 0) {
+        r.it.n = b.n;
+        r.it.g = t;
+        r.it.K = b.K;
+        r.it.tabs = tabs;
+        r.it.zi = b.gzf;
+        r.gy = b.gy;
+        r.gx = b.gx;
+        r.x = b.x;
+        r.y = b.y;
+        r.saved = b.saved;
+        r.gzi = b.gzi;
+    } else {
+        const int i = b.sigmap[t];
+        const int64_t so = b.sig_off[i];
+        const int32_t sc = b.sec_off[i];
+        r.it.n = b.sig_off[i + 1] - so;
+        r.it.g = t - b.gpre[i];
+        r.it.K = b.Ks[i];
+        r.it.tabs = tabs + (size_t)sc * TAB_FLOATS;
+        r.it.zi = b.gzf ? b.gzf + 2 * (int64_t)sc : nullptr;
+        r.gy = b.gy + so;
+        r.gx = b.gx + so;
+        r.x = b.x + so;
+        r.y = b.y + so;
+        r.saved = b.saved ? b.saved + so : nullptr;
+        r.gzi = b.gzi ? b.gzi + 2 * (int64_t)sc : nullptr;
+    }
+    return r;
+}
 
 // Reversed time without reversed memory traffic. The wave's part in reversed
 // time, reversed indices [r0, r0 + 64N), is the forward window
@@ -916,6 +974,7 @@ __global__ void __launch_bounds__(64 * W)
     const int wv = threadIdx.x >> 6;
     const unsigned epoch = __hip_atomic_load(&b.ctrl[CTRL_EPOCH], __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t total = b.B > 0 ? *b.total_dev : b.total;
     float *tl = tile[wv];
     float *tl2 = tile2[wv];
     const T *tabs = reinterpret_cast<const T *>(b.tabs);
@@ -925,41 +984,39 @@ __global__ void __launch_bounds__(64 * W)
     a.ctrl = b.ctrl;
     a.timeout_ticks = b.timeout_ticks;
 
-    bool bad = false;
-    for (int k = 0; k < b.K; ++k)
-        bad |= __float_as_uint((float)ctabp(tabs)[(size_t)k * TAB_FLOATS + OFF_STATUS]) != 0u;
-
     for (;;) {
         if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&b.ctrl[CTRL_TICKET], 1u);
         lds_barrier();
         const int64_t t = ticket;
         lds_barrier();
-        if (t >= b.total) break;
-        Item<T> it{};
-        it.n = b.n;
-        it.g = t;
-        it.t = t;
-        it.zi = b.gzf;
-        it.K = b.K;
-        const int64_t r0 = t * C + (int64_t)wv * CW;   // reversed index of the wave's start
-        const int64_t f0 = b.n - r0 - CW;              // forward index of the window's start
+        if (t >= total) break;
+        const BItem<T> bi = make_bwd_item<T>(b, tabs, t);
+        const Item<T> &it = bi.it;
+        const int64_t n = it.n;
+        bool bad = false;
+        for (int k = 0; k < it.K; ++k)
+            bad |= __float_as_uint((float)ctabp(it.tabs)[(size_t)k * TAB_FLOATS + OFF_STATUS]) !=
+                   0u;
+        const int64_t r0 = it.g * C + (int64_t)wv * CW;   // reversed index of the wave's start
+        const int64_t f0 = n - r0 - CW;                   // forward index of the window's start
 
-        window_load<N>(b.gy, f0, b.n, tl, lane);
+        window_load<N>(bi.gy, f0, n, tl, lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         T u[N];
         regs_from_rows_rev<T, N>(u, tl, lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // lane / position of reversed index n-1 (forward sample 0) if this wave holds it
-        const int64_t pz = (b.n - 1) - r0;
+        const int64_t pz = (n - 1) - r0;
         const bool has_first = pz >= 0 && pz < CW;
         const int zl = has_first ? (int)(pz / N) : 0, zp = has_first ? (int)(pz % N) : 0;
+        const int64_t sst = b.B > 0 ? b.saved_stride : n;
 
-        for (int k = b.K - 1; k >= 0 && !bad; --k) {
-            const T *tabv = tabs + (size_t)k * TAB_FLOATS;
+        for (int k = it.K - 1; k >= 0 && !bad; --k) {
+            const T *tabv = it.tabs + (size_t)k * TAB_FLOATS;
             ctabT<T> *tab = ctabp(tabv);
             // the section's forward input and output over the window (own tiles)
-            window_load<N>(k == 0 ? b.x : b.saved + (size_t)(k - 1) * b.n, f0, b.n, tl, lane);
-            window_load<N>(k == b.K - 1 ? b.y : b.saved + (size_t)k * b.n, f0, b.n, tl2, lane);
+            window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tl, lane);
+            window_load<N>(k == it.K - 1 ? bi.y : bi.saved + (size_t)k * sst, f0, n, tl2, lane);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             T q1, q2;   // lam'[-2], lam'[-1] of this lane
             run_section<T, N, W, true>(u, xch, tl, a, it, tabv, k, epoch, wv, lane, false, 0, 0,
@@ -989,13 +1046,13 @@ __global__ void __launch_bounds__(64 * W)
                 }
             }
             // d/dzi = (lam'[n-1], lam'[n-2])
-            if (has_first && b.gzi) {
+            if (has_first && bi.gzi) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 T l1 = 0, l2 = 0;
                 pick_two<T, N>(u, tl, lane, zl, zp, l1, l2);
                 if (lane == zl) {
-                    b.gzi[2 * k] = (float)l1;
-                    b.gzi[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
+                    bi.gzi[2 * k] = (float)l1;
+                    bi.gzi[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
                 }
             }
             // gradient for the section below: 3-tap FIR of lam' (descending, in place)
@@ -1028,16 +1085,16 @@ __global__ void __launch_bounds__(64 * W)
         if (bad) {
 #pragma unroll
             for (int m = 0; m < N; ++m) u[m] = T(__builtin_nanf(""));
-            for (int i = threadIdx.x; i < 5 * b.K; i += blockDim.x)
+            for (int i = threadIdx.x; i < 5 * it.K; i += blockDim.x)
                 b.partials[(size_t)t * b.K * 5 + i] = __builtin_nan("");
         }
         // store dL/dx in forward order through the wave's rows
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         rows_from_regs_rev<T, N>(u, tl, lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        window_store<N>(b.gx, f0, b.n, tl, lane);
+        window_store<N>(bi.gx, f0, n, tl, lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if ((int64_t)gridDim.x >= b.total) break;
+        if ((int64_t)gridDim.x >= total) break;
     }
 }
 
@@ -1066,6 +1123,44 @@ sos_bwd_reduce_kernel(const double *partials, int64_t total, int K, const float 
         const double an1 = row[4] / a0, an2 = row[5] / a0;
         const double *g = sh[0];
         float *o = gsections + 6 * k;
+        o[0] = (float)(g[0] / a0);
+        o[1] = (float)(g[1] / a0);
+        o[2] = (float)(g[2] / a0);
+        o[4] = (float)(g[3] / a0);
+        o[5] = (float)(g[4] / a0);
+        o[3] = (float)(-(g[0] * bn0 + g[1] * bn1 + g[2] * bn2 + g[3] * an1 + g[4] * an2) / a0);
+    }
+}
+
+// Batched form: block (i, k) sums section k of signal i over the signal's
+// tickets gpre[i] .. gpre[i+1]-1 (fixed order) and applies the a0 chain rule.
+__global__ void __launch_bounds__(256)
+sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, const int32_t *Ks,
+                              const int32_t *sec_off, const int64_t *gpre,
+                              const float *sections, float *gsections)
+{
+    __shared__ double sh[256][5];
+    const int i = blockIdx.x, k = blockIdx.y;
+    if (i >= B || k >= Ks[i]) return;     // uniform per block
+    const int64_t t0 = gpre[i], t1 = gpre[i + 1];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256)
+        for (int c = 0; c < 5; ++c) acc[c] += partials[((size_t)t * kmax + k) * 5 + c];
+    for (int c = 0; c < 5; ++c) sh[threadIdx.x][c] = acc[c];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d)
+            for (int c = 0; c < 5; ++c) sh[threadIdx.x][c] += sh[threadIdx.x + d][c];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t row_i = (int64_t)sec_off[i] + k;
+        const float *row = sections + 6 * row_i;
+        const double a0 = row[3];
+        const double bn0 = row[0] / a0, bn1 = row[1] / a0, bn2 = row[2] / a0;
+        const double an1 = row[4] / a0, an2 = row[5] / a0;
+        const double *g = sh[0];
+        float *o = gsections + 6 * row_i;
         o[0] = (float)(g[0] / a0);
         o[1] = (float)(g[1] / a0);
         o[2] = (float)(g[2] / a0);
@@ -1150,6 +1245,7 @@ extern "C" hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, flo
 {
     FwdArgs a{};
     a.saved = saved;
+    a.saved_stride = n;
     a.x = x;
     a.y = y;
     a.n = n;
@@ -1177,6 +1273,7 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
                                              unsigned long long *desc, unsigned *ctrl,
                                              unsigned long long timeout_ticks, int64_t grid,
                                              const float *const *xp, float *const *yp,
+                                             float *saved, int64_t saved_stride,
                                              hipStream_t stream)
 {
     FwdArgs a{};
@@ -1184,6 +1281,8 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
     a.y = y;
     a.xp = xp;
     a.yp = yp;
+    a.saved = saved;
+    a.saved_stride = saved_stride;
     a.tabs = tabs;
     a.zi = zi;
     a.zf = zf;
@@ -1201,17 +1300,11 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
     return dispatch_fwd(bits, L, N, a, grid, stream);
 }
 
-// Adjoint of the plain filter: grid <= 0 means a persistent grid.
-extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx,
-                                     int64_t n, int64_t groups, const void *tabs, int K,
-                                     const float *x, const float *y, const float *saved,
-                                     const float *gzf, float *gzi, double *partials,
-                                     unsigned long long *desc, unsigned *ctrl,
-                                     unsigned long long timeout_ticks, int64_t grid,
-                                     hipStream_t stream)
+// Launch the adjoint kernel of shape (L, N) in the compute type; grid <= 0:
+// persistent (as many workgroups as can be resident), at most `groups`.
+static hipError_t launch_bwd_args(int bits, int L, int N, const BwdArgs &b, int64_t groups,
+                           int64_t grid, hipStream_t stream)
 {
-    BwdArgs b{gy, gx, n, tabs, x, y, saved, gzf, gzi, partials, desc, ctrl, K, groups,
-              timeout_ticks};
     const int W = L / 64;
     // grid <= 0: persistent, as many workgroups as can be resident
     auto resident = [&](const void *kern, int threads) -> int64_t {
@@ -1248,6 +1341,85 @@ extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, fl
     SOS_BWD_CASE(32, 8)
 #undef SOS_BWD_CASE
     return hipErrorInvalidValue;
+}
+
+// Adjoint of the plain filter: grid <= 0 means a persistent grid.
+extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx,
+                                     int64_t n, int64_t groups, const void *tabs, int K,
+                                     const float *x, const float *y, const float *saved,
+                                     const float *gzf, float *gzi, double *partials,
+                                     unsigned long long *desc, unsigned *ctrl,
+                                     unsigned long long timeout_ticks, int64_t grid,
+                                     hipStream_t stream)
+{
+    BwdArgs b{};
+    b.gy = gy;
+    b.gx = gx;
+    b.n = n;
+    b.tabs = tabs;
+    b.x = x;
+    b.y = y;
+    b.saved = saved;
+    b.gzf = gzf;
+    b.gzi = gzi;
+    b.partials = partials;
+    b.desc = desc;
+    b.ctrl = ctrl;
+    b.K = K;
+    b.total = groups;
+    b.timeout_ticks = timeout_ticks;
+    return launch_bwd_args(bits, L, N, b, groups, grid, stream);
+}
+
+// Batched adjoint: one persistent launch over the reversed groups of every
+// signal (work table built by sos_launch_worktable with the adjoint's C).
+extern "C" hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int kmax,
+                                             const int32_t *Ks, const int32_t *sec_off,
+                                             const int64_t *sig_off, const int64_t *gpre,
+                                             const int32_t *sigmap, const int64_t *total_dev,
+                                             int64_t max_groups, const float *gy, float *gx,
+                                             const void *tabs, const float *x, const float *y,
+                                             const float *saved, int64_t saved_stride,
+                                             const float *gzf, float *gzi, double *partials,
+                                             unsigned long long *desc, unsigned *ctrl,
+                                             unsigned long long timeout_ticks,
+                                             hipStream_t stream)
+{
+    BwdArgs b{};
+    b.gy = gy;
+    b.gx = gx;
+    b.tabs = tabs;
+    b.x = x;
+    b.y = y;
+    b.saved = saved;
+    b.gzf = gzf;
+    b.gzi = gzi;
+    b.partials = partials;
+    b.desc = desc;
+    b.ctrl = ctrl;
+    b.K = kmax;
+    b.timeout_ticks = timeout_ticks;
+    b.B = B;
+    b.Ks = Ks;
+    b.sec_off = sec_off;
+    b.sig_off = sig_off;
+    b.gpre = gpre;
+    b.sigmap = sigmap;
+    b.total_dev = total_dev;
+    b.saved_stride = saved_stride;
+    return launch_bwd_args(bits, L, N, b, max_groups, 0, stream);
+}
+
+extern "C" hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax,
+                                                    const int32_t *Ks, const int32_t *sec_off,
+                                                    const int64_t *gpre, const float *sections,
+                                                    float *gsections, hipStream_t stream)
+{
+    if (B <= 0 || kmax <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sos_bwd_reduce_batched_kernel, dim3((unsigned)B, (unsigned)kmax),
+                       dim3(256), 0, stream, partials, B, kmax, Ks, sec_off, gpre, sections,
+                       gsections);
+    return hipGetLastError();
 }
 
 extern "C" int sos_bwd_shape_supported(int L, int N)

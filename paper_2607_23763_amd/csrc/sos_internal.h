@@ -17,7 +17,8 @@ hipError_t sos_launch_prep(int bits, const float *sections, int K, int log2n, in
                            void *tabs, unsigned *ctrl, int pair, hipStream_t stream);
 hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int kmax, int64_t rows,
                                    const int32_t *Ks, const int32_t *sec_off, int log2n,
-                                   int log2w, void *tabs, unsigned *ctrl, hipStream_t stream);
+                                   int log2w, void *tabs, unsigned *ctrl, int pair,
+                                   hipStream_t stream);
 hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
 hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, float *y, int64_t n,
                           int64_t groups, const void *tabs, int K, const float *zi, float *zf,
@@ -31,7 +32,21 @@ hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax, const
                                   const void *tabs, const float *zi, float *zf,
                                   unsigned long long *desc, unsigned *ctrl,
                                   unsigned long long timeout_ticks, int64_t grid,
-                                  const float *const *xp, float *const *yp, hipStream_t stream);
+                                  const float *const *xp, float *const *yp, float *saved,
+                                  int64_t saved_stride, hipStream_t stream);
+hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int kmax, const int32_t *Ks,
+                                  const int32_t *sec_off, const int64_t *sig_off,
+                                  const int64_t *gpre, const int32_t *sigmap,
+                                  const int64_t *total_dev, int64_t max_groups, const float *gy,
+                                  float *gx, const void *tabs, const float *x, const float *y,
+                                  const float *saved, int64_t saved_stride, const float *gzf,
+                                  float *gzi, double *partials, unsigned long long *desc,
+                                  unsigned *ctrl, unsigned long long timeout_ticks,
+                                  hipStream_t stream);
+hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax,
+                                         const int32_t *Ks, const int32_t *sec_off,
+                                         const int64_t *gpre, const float *sections,
+                                         float *gsections, hipStream_t stream);
 hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
                                 int64_t max_groups, const int32_t *Ks, const int32_t *sec_off,
                                 const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
@@ -160,6 +175,7 @@ struct BatchArgs {
     float *y;
     const float *zi;
     float *zf;
+    float *saved = nullptr;   // training: outputs of sections 0..kmax-2, stride total_samples
 };
 // Argument checks (no device work).
 int batch_check(const BatchArgs &ba);

@@ -149,7 +149,8 @@ template <typename T>
 __global__ void __launch_bounds__(64)
 sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax, int64_t rows,
                         const int32_t *__restrict__ Ks, const int32_t *__restrict__ sec_off,
-                        int log2n, int log2w, T *__restrict__ tabs, unsigned *__restrict__ ctrl)
+                        int log2n, int log2w, T *__restrict__ tabs, unsigned *__restrict__ ctrl,
+                        int pair)
 {
     const int i = blockIdx.x;
     if (i >= B) return;
@@ -158,7 +159,7 @@ sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax, int
     if (K < 0 || K > kmax || so < 0 || so + K > rows) return;
     for (int k = 0; k < K; ++k)
         prep_section<T>(sections + 6 * (so + k), tabs + (size_t)(so + k) * TAB_FLOATS, log2n,
-                        log2w, ctrl, threadIdx.x, false);
+                        log2w, ctrl, threadIdx.x, pair != 0);
 }
 
 // K sections -> tables of the compute type `bits` (32 or 64). pair != 0: the
@@ -180,17 +181,18 @@ extern "C" hipError_t sos_launch_prep(int bits, const float *sections, int K, in
 extern "C" hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int kmax,
                                               int64_t rows, const int32_t *Ks,
                                               const int32_t *sec_off, int log2n, int log2w,
-                                              void *tabs, unsigned *ctrl, hipStream_t stream)
+                                              void *tabs, unsigned *ctrl, int pair,
+                                              hipStream_t stream)
 {
     if (B <= 0) return hipSuccess;
     if (bits == 64)
         hipLaunchKernelGGL(sos_prep_batched_kernel<double>, dim3(B), dim3(64), 0, stream,
                            sections, B, kmax, rows, Ks, sec_off, log2n, log2w, (double *)tabs,
-                           ctrl);
+                           ctrl, pair);
     else
         hipLaunchKernelGGL(sos_prep_batched_kernel<float>, dim3(B), dim3(64), 0, stream,
                            sections, B, kmax, rows, Ks, sec_off, log2n, log2w, (float *)tabs,
-                           ctrl);
+                           ctrl, pair);
     return hipGetLastError();
 }
 

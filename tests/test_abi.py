@@ -49,6 +49,10 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_get_precision(None) == P.SOS_EINVAL
     assert lib.sos_set_timeout(None, 1.0) == P.SOS_EINVAL
     assert lib.sos_wall_clock_khz(None) == P.SOS_EINVAL
+    assert lib.sos_filter_train_batched(None, 1, 1, 1, 10, None, None, None, None, None, None,
+                                        None, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_filter_vjp_batched(None, 1, 1, 1, 10, None, None, None, None, None, None, None,
+                                      None, None, None, None, None, None) == P.SOS_EINVAL
     # graph and tuning entry points
     assert lib.sos_graph_create_batched(None, None, 1, 1, 1, 10, None, None, None, None, None,
                                         None, None, None) == P.SOS_EINVAL
