@@ -179,7 +179,7 @@ int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
     if (sos_launch_fwd_batched(bits, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
                                h->sigmap, h->total_dev, ba.x, ba.y, h->tabs, ba.zi, ba.zf,
                                h->desc, h->ctrl, h->timeout_ticks, grid, nullptr, nullptr,
-                               ba.saved, ba.total_samples, stream) != hipSuccess)
+                               ba.saved, ba.total_samples, max_groups, stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = -1;        // the batch overwrote the plain tables
     h->last_groups = 0;
@@ -566,12 +566,16 @@ int sos_debug_carries(sos_handle_t h, float *out, int64_t capacity_floats, int64
     if (hipMemcpy(w.data(), h->desc, w.size() * sizeof(unsigned long long),
                   hipMemcpyDeviceToHost) != hipSuccess)
         return SOS_EHIP;
-    for (int64_t i = 0; i < need / 2; ++i) {
-        const uint32_t v1 = (uint32_t)(w[4 * i + 2] & 0xffffffffu);
-        const uint32_t v2 = (uint32_t)(w[4 * i + 3] & 0xffffffffu);
-        std::memcpy(out + 2 * i, &v1, 4);
-        std::memcpy(out + 2 * i + 1, &v2, 4);
-    }
+    // descriptors are section-major: section s of group g at (s * groups + g) * 4
+    const int64_t G = h->last_groups;
+    for (int64_t g = 0; g < G; ++g)
+        for (int s = 0; s < h->last_K; ++s) {
+            const size_t wi = ((size_t)s * G + g) * 4;
+            const uint32_t v1 = (uint32_t)(w[wi + 2] & 0xffffffffu);
+            const uint32_t v2 = (uint32_t)(w[wi + 3] & 0xffffffffu);
+            std::memcpy(out + 2 * (g * h->last_K + s), &v1, 4);
+            std::memcpy(out + 2 * (g * h->last_K + s) + 1, &v2, 4);
+        }
     return SOS_OK;
 }
 

@@ -35,7 +35,9 @@
 // is registers). Data in HBM, LDS staging and descriptor values are FP32.
 //
 // Descriptors: per (group, section) four 64-bit words {agg.z1, agg.z2,
-// inc.z1, inc.z2}, each {float value | 32-bit epoch tag}. A word is valid when
+// inc.z1, inc.z2}, each {float value | 32-bit epoch tag}, stored
+// section-major (section s, group h at s * dstride + h), so the window of
+// consecutive predecessors a lookback reads spans few cache lines. A word is valid when
 // its tag equals the launch epoch, so words are self-validating: no fences, no
 // clearing between launches, and the agent-scope relaxed atomics keep them
 // coherent across the XCDs' separate L2 caches. A one-thread kernel before
@@ -71,6 +73,7 @@ struct FwdArgs {
     int64_t saved_stride;
     int64_t total;          // number of work items (plain)
     unsigned long long *desc;
+    int64_t dstride;        // descriptor slots per section (>= the number of work items)
     unsigned *ctrl;
     unsigned long long timeout_ticks;
 };
@@ -266,9 +269,9 @@ __device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, i
 // Resolve the incoming state of group it.g (> 0) of a signal for section s by
 // decoupled lookback; executed by one whole wave. Returns wave-uniform values.
 //
-// Each round the wave reads the kWin x 64 newest predecessors not yet
-// consumed (lane l reads predecessors l, l + 64, ...) and consumes, window by
-// window, the longest prefix that is ready (kWin = 1 here): if a resolved carry (inclusive)
+// Each round the wave reads the kSpan newest predecessors not yet consumed
+// (lane l < kSpan reads predecessor l; kWin windows of them, one here) and
+// consumes the longest prefix that is ready: if a resolved carry (inclusive)
 // lies in that prefix at lane j*, the result is inc[j*] propagated over j*
 // groups plus the local carries (aggregates) of the j* groups in front of it,
 // and the walk ends; otherwise the prefix's aggregates are added and the walk
@@ -277,12 +280,16 @@ __device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, i
 // the wave waits on that single descriptor with exponential backoff, so
 // waiting waves issue one request per poll. On timeout it returns NaNs and
 // sets the error bit (the caller still publishes, so successors terminate).
-template <typename T>
+template <typename T, int kSpan>
 __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int s,
                          unsigned epoch, int lane, T &r1, T &r2)
 {
-    // one window per round: reading two per round (fewer rounds, twice the
-    // agent-scope loads each) measured slower, most at small groups
+    // One window of kSpan predecessors per round. Every descriptor read is an
+    // agent-scope load served beyond the XCD's L2, competing with the sample
+    // stream, so reading few per round wins over fewer rounds: measured on
+    // MI355X, 16 for groups of up to 16 K samples and 8 for 32 K beat 64
+    // (order 2: +8-11 %; order 16 at 4 K-sample groups: +35 %), and two or
+    // four windows per round lose.
     constexpr int kWin = 1;
     const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);   // T^(C lane)
     T acc1 = 0, acc2 = 0;
@@ -299,8 +306,8 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
             const int64_t h = base - lane - kLanes * r;
 #pragma unroll
             for (int i = 0; i < 4; ++i) w[r][i] = 0ull;
-            if (h >= first && (!single || (r == 0 && lane == 0))) {
-                const unsigned long long *d = a.desc + ((size_t)h * a.K + s) * 4;
+            if (h >= first && (single ? (r == 0 && lane == 0) : lane < kSpan)) {
+                const unsigned long long *d = a.desc + ((size_t)s * a.dstride + h) * 4;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) w[r][i] = load_word(d + i);
             }
@@ -315,9 +322,10 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
                 (unsigned)(w[r][0] >> 32) == epoch && (unsigned)(w[r][1] >> 32) == epoch;
             const unsigned long long incm = __ballot(inc_ok);
             const unsigned long long rdym = __ballot(inc_ok || agg_ok);
-            const unsigned long long spanm = single ? 1ull : ~0ull;
+            const int span = single ? 1 : kSpan;
+            const unsigned long long spanm = span == 64 ? ~0ull : ((1ull << span) - 1ull);
             const unsigned long long notr = ~rdym & spanm;
-            const int nr = notr ? __builtin_ctzll(notr) : (single ? 1 : 64);   // ready prefix
+            const int nr = notr ? __builtin_ctzll(notr) : span;               // ready prefix
             const int jstar = incm ? __builtin_ctzll(incm) : 64;
             done = jstar < nr;
             const int c = done ? jstar : nr;                                 // aggregates consumed
@@ -350,7 +358,7 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
             const T n10 = m10 * p00 + m11 * p10, n11 = m10 * p01 + m11 * p11;
             m00 = n00; m01 = n01; m10 = n10; m11 = n11;
             base -= c;
-            if (c < 64) break;   // the next window was read from the old base
+            if (c < kSpan || kSpan < 64) break;   // the next window was read from the old base
         }
         if (done) break;
         if (progressed) {
@@ -461,7 +469,7 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
         if (W > 1) mv_add<T>(tab + OFF_TWAVE, e1w, e2w, g1, g2);
 
         // --- 4. decoupled lookback for the group's incoming state
-        unsigned long long *dsc = a.desc + ((size_t)it.t * a.K + s) * 4;
+        unsigned long long *dsc = a.desc + ((size_t)s * a.dstride + it.t) * 4;
         T sg1, sg2;
         if (it.g == 0) {
             // PAIR: the initial carry arrives as (y[-1], y[-2]) (the adjoint of zf)
@@ -472,7 +480,8 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
                 store_word(dsc + 0, pack((float)g1, epoch));
                 store_word(dsc + 1, pack((float)g2, epoch));
             }
-            lookback<T>(a, it, tabv, s, epoch, lane, sg1, sg2);
+            lookback<T, (kLanes * N * W >= 32768 ? 8 : 16)>(a, it, tabv, s, epoch, lane, sg1,
+                                                              sg2);
         }
         T i1 = g1, i2 = g2;
         mv_add<T>(tab + OFF_TC, sg1, sg2, i1, i2);
@@ -819,6 +828,7 @@ struct BwdArgs {
     float *gzi;              // K x 2 or null
     double *partials;        // total x K x 5 per-group coefficient sums
     unsigned long long *desc;
+    int64_t dstride;         // descriptor slots per section
     unsigned *ctrl;
     int K;                   // plain: sections; batched: stride (max sections)
     int64_t total;
@@ -981,6 +991,7 @@ __global__ void __launch_bounds__(64 * W)
     FwdArgs a{};                 // the fields the section step and lookback use
     a.K = b.K;
     a.desc = b.desc;
+    a.dstride = b.dstride;
     a.ctrl = b.ctrl;
     a.timeout_ticks = b.timeout_ticks;
 
@@ -1256,6 +1267,7 @@ extern "C" hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, flo
     a.B = 0;
     a.total = groups;
     a.desc = desc;
+    a.dstride = groups;
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
     if (grid <= 0 || grid > groups) grid = groups;
@@ -1274,7 +1286,7 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
                                              unsigned long long timeout_ticks, int64_t grid,
                                              const float *const *xp, float *const *yp,
                                              float *saved, int64_t saved_stride,
-                                             hipStream_t stream)
+                                             int64_t max_groups, hipStream_t stream)
 {
     FwdArgs a{};
     a.x = x;
@@ -1295,6 +1307,7 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
     a.sigmap = sigmap;
     a.total_dev = total_dev;
     a.desc = desc;
+    a.dstride = max_groups;
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
     return dispatch_fwd(bits, L, N, a, grid, stream);
@@ -1364,6 +1377,7 @@ extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, fl
     b.gzi = gzi;
     b.partials = partials;
     b.desc = desc;
+    b.dstride = groups;
     b.ctrl = ctrl;
     b.K = K;
     b.total = groups;
@@ -1396,6 +1410,7 @@ extern "C" hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int 
     b.gzi = gzi;
     b.partials = partials;
     b.desc = desc;
+    b.dstride = max_groups;
     b.ctrl = ctrl;
     b.K = kmax;
     b.timeout_ticks = timeout_ticks;

@@ -33,7 +33,7 @@ hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax, const
                                   unsigned long long *desc, unsigned *ctrl,
                                   unsigned long long timeout_ticks, int64_t grid,
                                   const float *const *xp, float *const *yp, float *saved,
-                                  int64_t saved_stride, hipStream_t stream);
+                                  int64_t saved_stride, int64_t max_groups, hipStream_t stream);
 hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int kmax, const int32_t *Ks,
                                   const int32_t *sec_off, const int64_t *sig_off,
                                   const int64_t *gpre, const int32_t *sigmap,

@@ -247,7 +247,7 @@ void launch_step(sos_srv *s, Step &st)
         sos_launch_fwd_batched(s->bits, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
                                h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
                                s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
-                               nullptr, 0, s->stream) == hipSuccess &&
+                               nullptr, 0, s->max_groups, s->stream) == hipSuccess &&
         hipMemcpyAsync(err, h->ctrl + CTRL_ERR, sizeof(unsigned), hipMemcpyDeviceToHost,
                        s->stream) == hipSuccess &&
         sos_launch_fill(reinterpret_cast<float *>(h->ctrl + CTRL_ERR), nullptr, 1, s->stream) ==
