@@ -219,6 +219,17 @@ __device__ __forceinline__ T wave_sum(T v)
     return readlane(v, 63);
 }
 
+// Sample memory is global memory; saying so makes its loads and stores
+// global rather than flat instructions, which count only against the vector
+// memory counter, so waits for LDS and scalar loads do not also wait for them
+// (the signal pointers of a batch are loaded from memory, which hides their
+// address space from the compiler).
+template <typename P>
+__device__ __forceinline__ __attribute__((address_space(1))) P *gptr(P *p)
+{
+    return (__attribute__((address_space(1))) P *)p;
+}
+
 // Workgroup barrier that orders LDS only. __syncthreads() also waits for all
 // of the wave's outstanding global memory operations (vmcnt 0), which would
 // make every barrier wait for the next group's prefetch and the previous
@@ -384,6 +395,13 @@ template <typename T, int W>
 struct Xch {
     T wave_tot[W][2];   // zero-state totals of the waves
     T grp[2];           // resolved incoming state of the group
+    int64_t nxt;        // ticket drawn once the last section's state is resolved
+};
+
+// Hook run by every wave right after the group state is broadcast, given the
+// ticket drawn at that point (see run_section).
+struct NoNext {
+    __device__ void operator()(int64_t) const {}
 };
 
 // ------------------------------------------------------------- one section
@@ -393,11 +411,17 @@ struct Xch {
 // PAIR = true: a pure recursive section 1/A(z) (the adjoint's reversed-time
 //   pass); carries are the last two outputs (y[-2], y[-1]), and the tables hold
 //   the matching state map. On return (q1, q2) is the lane's incoming carry.
-template <typename T, int N, int W, bool PAIR>
+// draw: the lookback wave draws the workgroup's next ticket as soon as the
+//   group state is resolved (not earlier: a ticket drawn before the wait would
+//   carry the wait's jitter into the next group's aggregate), and every wave
+//   passes it to on_next right after the broadcast, so that the next group's
+//   loads overlap this group's correction and store.
+template <typename T, int N, int W, bool PAIR, typename OnNext = NoNext>
 __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl,
                                             const FwdArgs &a, const Item<T> &it, const T *tabv,
                                             int s, unsigned epoch, int wv, int lane, bool has_last,
-                                            int zl, int zp, T &q1, T &q2)
+                                            int zl, int zp, T &q1, T &q2, bool draw = false,
+                                            const OnNext &on_next = OnNext())
 {
     constexpr int LOG = __builtin_ctz(N);
     ctabT<T> *tab = ctabp(tabv);
@@ -447,6 +471,12 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
         p2 = b2 * xl1 - a2 * u[N - 1];
     }
     wave_scan<T>(p1, p2, tabv, lane);
+    // The lane power of step 5 is read here, not at its use: a vector load
+    // issued after on_next's loads would wait for all of them. The empty asm
+    // (which the compiler must assume rewrites the values) keeps it from
+    // sinking or re-issuing the load at the use.
+    M2<T> lp = load_m2(tabv + OFF_LANEPOW + 4 * lane);
+    asm volatile("" : "+v"(lp.a), "+v"(lp.b), "+v"(lp.c), "+v"(lp.d));
 
     //     ... and over the W waves of the group (zero group state)
     T e1w = 0, e2w = 0;      // zero-state incoming state of this wave
@@ -483,6 +513,8 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             lookback<T, (kLanes * N * W >= 32768 ? 8 : 16)>(a, it, tabv, s, epoch, lane, sg1,
                                                               sg2);
         }
+        unsigned tk = 0;
+        if (draw && lane == 0) tk = atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
         T i1 = g1, i2 = g2;
         mv_add<T>(tab + OFF_TC, sg1, sg2, i1, i2);
         if (lane == 0) {
@@ -490,15 +522,16 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             store_word(dsc + 3, pack((float)i2, epoch));
             xch.grp[0] = sg1;
             xch.grp[1] = sg2;
+            if (draw) xch.nxt = (int64_t)tk;
         }
     }
     lds_barrier();
     const T sg1 = xch.grp[0], sg2 = xch.grp[1];
+    if (draw) on_next(xch.nxt);
 
     // --- 5. incoming state of every lane, then back substitution
     T sw1 = e1w, sw2 = e2w;
     mv_add<T>(tab + OFF_WPOW + 4 * wv, sg1, sg2, sw1, sw2);
-    const M2<T> lp = load_m2(tabv + OFF_LANEPOW + 4 * lane);
     const T e1 = dpp0<DPP_WAVE_SHR1, 0xF>(p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(p2);
     q1 = fmaT(lp.a, sw1, fmaT(lp.b, sw2, e1));
     q2 = fmaT(lp.c, sw1, fmaT(lp.d, sw2, e2));
@@ -533,8 +566,8 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
                 z1 = b1 * zx1 + b2 * zx2 - a1 * yo1 - a2 * yo2;
             else
                 z1 = b1 * zx1 - a1 * yo1 + s2;   // s2: this lane's incoming state
-            it.zf[2 * s] = (float)z1;
-            it.zf[2 * s + 1] = (float)(b2 * zx1 - a2 * yo1);
+            gptr(it.zf)[2 * s] = (float)z1;
+            gptr(it.zf)[2 * s + 1] = (float)(b2 * zx1 - a2 * yo1);
         }
     }
 }
@@ -558,35 +591,49 @@ struct WaveTile {
     }
 };
 
-// src[0 .. 64N) -> tile; `rem` samples are valid (zeros past them); `vec`
-// says src is 16-byte aligned. All loads of a lane are issued before the
-// first LDS write.
+// src[0 .. 64N) -> the lane's coalesced slots t[0 .. N/4); `rem` samples are
+// valid (zeros past them); `vec` says src is 16-byte aligned.
+template <int N>
+__device__ __forceinline__ void tile_fetch(f4 (&t)[N / 4], const float *src, int64_t rem,
+                                           bool vec, int lane)
+{
+    if (vec && rem >= kLanes * N) {
+        const auto s4 = gptr(reinterpret_cast<const f4 *>(src) + lane);
+#pragma unroll
+        for (int j = 0; j < N / 4; ++j) t[j] = __builtin_nontemporal_load(s4 + kLanes * j);
+    } else {
+        const auto g = gptr(src);
+        const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+#pragma unroll
+        for (int j = 0; j < N / 4; ++j) {
+            const int q = 4 * (kLanes * j + lane);
+            t[j].x = q + 0 < r ? g[q + 0] : 0.0f;
+            t[j].y = q + 1 < r ? g[q + 1] : 0.0f;
+            t[j].z = q + 2 < r ? g[q + 2] : 0.0f;
+            t[j].w = q + 3 < r ? g[q + 3] : 0.0f;
+        }
+    }
+}
+
+// the lane's coalesced slots -> the wave's LDS rows
+template <int N>
+__device__ __forceinline__ void tile_put(const f4 (&t)[N / 4], float *tl, int lane)
+{
+    using TT = WaveTile<N>;
+    float *p = tl + TT::slot_base(lane);
+#pragma unroll
+    for (int j = 0; j < TT::Q; ++j) *reinterpret_cast<f4 *>(p + j * TT::STEP) = t[j];
+}
+
+// src[0 .. 64N) -> tile; all loads of a lane are issued before the first LDS
+// write.
 template <int N>
 __device__ __forceinline__ void tile_load(const float *src, int64_t rem, bool vec, float *tl,
                                           int lane)
 {
-    using TT = WaveTile<N>;
-    float *p = tl + TT::slot_base(lane);
-    if (vec && rem >= kLanes * N) {
-        const f4 *s4 = reinterpret_cast<const f4 *>(src) + lane;
-        f4 t[TT::Q];
-#pragma unroll
-        for (int j = 0; j < TT::Q; ++j) t[j] = __builtin_nontemporal_load(s4 + kLanes * j);
-#pragma unroll
-        for (int j = 0; j < TT::Q; ++j) *reinterpret_cast<f4 *>(p + j * TT::STEP) = t[j];
-    } else {
-        const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
-#pragma unroll
-        for (int j = 0; j < TT::Q; ++j) {
-            const int q = 4 * (kLanes * j + lane);
-            f4 t;
-            t.x = q + 0 < r ? src[q + 0] : 0.0f;
-            t.y = q + 1 < r ? src[q + 1] : 0.0f;
-            t.z = q + 2 < r ? src[q + 2] : 0.0f;
-            t.w = q + 3 < r ? src[q + 3] : 0.0f;
-            *reinterpret_cast<f4 *>(p + j * TT::STEP) = t;
-        }
-    }
+    f4 t[N / 4];
+    tile_fetch<N>(t, src, rem, vec, lane);
+    tile_put<N>(t, tl, lane);
 }
 
 // tile -> dst[0 .. min(rem, 64N)). NT: nontemporal stores, all LDS reads
@@ -601,7 +648,7 @@ __device__ __forceinline__ void tile_store(float *dst, int64_t rem, bool vec, co
     using TT = WaveTile<N>;
     const float *p = tl + TT::slot_base(lane);
     if (vec && rem >= kLanes * N) {
-        f4 *d4 = reinterpret_cast<f4 *>(dst) + lane;
+        const auto d4 = gptr(reinterpret_cast<f4 *>(dst) + lane);
         if (NT) {
             f4 t[TT::Q];
 #pragma unroll
@@ -613,15 +660,16 @@ __device__ __forceinline__ void tile_store(float *dst, int64_t rem, bool vec, co
             for (int j = 0; j < TT::Q; ++j) d4[kLanes * j] = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
         }
     } else {
+        const auto g = gptr(dst);
         const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
 #pragma unroll
         for (int j = 0; j < TT::Q; ++j) {
             const int q = 4 * (kLanes * j + lane);
             const f4 t = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
-            if (q + 0 < r) dst[q + 0] = t.x;
-            if (q + 1 < r) dst[q + 1] = t.y;
-            if (q + 2 < r) dst[q + 2] = t.z;
-            if (q + 3 < r) dst[q + 3] = t.w;
+            if (q + 0 < r) g[q + 0] = t.x;
+            if (q + 1 < r) g[q + 1] = t.y;
+            if (q + 2 < r) g[q + 2] = t.z;
+            if (q + 3 < r) g[q + 3] = t.w;
         }
     }
 }
@@ -706,11 +754,12 @@ __device__ __forceinline__ bool aligned16(const void *p)
 }
 
 // Everything after the wave's samples are in registers: the K sections, then
-// registers -> the wave's LDS rows -> coalesced 128-bit global stores.
-template <typename T, int N, int W>
+// registers -> the wave's LDS rows -> coalesced 128-bit global stores. With
+// draw set, the last section draws the next ticket and calls on_next with it.
+template <typename T, int N, int W, typename OnNext>
 __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it, T (&u)[N],
                                              float *tl, Xch<T, W> &xch, unsigned epoch, int wv,
-                                             int lane)
+                                             int lane, bool draw, const OnNext &on_next)
 {
     constexpr int CW = kLanes * N;   // samples per wave
     constexpr int C = CW * W;        // samples per group
@@ -726,12 +775,21 @@ __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it
     const bool has_last = lp >= 0 && lp < CW;
     const int zl = has_last ? (int)(lp / N) : 0, zp = has_last ? (int)(lp % N) : 0;
     if (!bad) {
-        for (int s = 0; s < it.K; ++s) {
+        // with draw, the last section is peeled off the loop so that the
+        // next group's registers are live only from its draw on
+        const int kl = draw ? it.K - 1 : it.K;
+        for (int s = 0; s < kl; ++s) {
             T q1, q2;
             run_section<T, N, W, false>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s,
                                         epoch, wv, lane, has_last, zl, zp, q1, q2);
             if (it.saved && s + 1 < it.K)
                 store_rows<T, N>(u, tl, lane, it.n, g0, it.saved + (size_t)s * a.saved_stride);
+        }
+        if (draw && it.K > 0) {
+            const int s = it.K - 1;
+            T q1, q2;
+            run_section<T, N, W, false>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s,
+                                        epoch, wv, lane, has_last, zl, zp, q1, q2, true, on_next);
         }
     } else {
 #pragma unroll
@@ -778,28 +836,56 @@ __global__ void __launch_bounds__(64 * W)
     __shared__ Xch<T, W> xch;
     __shared__ int64_t ticket;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar addressing
     const unsigned epoch = __hip_atomic_load(&a.ctrl[CTRL_EPOCH], __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
     const int64_t total = a.B > 0 ? *a.total_dev : a.total;
     float *tl = tile[wv];
     const T *tabs = reinterpret_cast<const T *>(a.tabs);
+    // Software pipeline over groups (FP32 compute): the next ticket is drawn
+    // when the current group's last state is resolved, and its samples are
+    // loaded into registers while this group is corrected and stored.
+    constexpr bool kPrefetch = sizeof(T) == 4;
+    const bool draw = kPrefetch && (int64_t)gridDim.x < total;
+    f4 pf[N / 4];     // coalesced slots of ticket tn
+    int64_t tn = -1;  // ticket drawn by the previous group, or -1
 
     for (;;) {
-        if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
-        lds_barrier();
-        const int64_t t = ticket;
-        lds_barrier();
+        int64_t t = tn;
+        if (t < 0) {
+            if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
+            lds_barrier();
+            t = ticket;
+            lds_barrier();
+        }
         if (t >= total) break;
         const Item<T> it = make_item<T>(a, tabs, t);
         const int64_t g0 = it.g * C + (int64_t)wv * CW;
         // load: coalesced 128-bit global loads -> the wave's LDS rows -> registers
-        tile_load<N>(it.x + g0, it.n - g0, aligned16(it.x), tl, lane);
+        if (tn < 0) tile_fetch<N>(pf, it.x + g0, it.n - g0, aligned16(it.x), lane);
+        tile_put<N>(pf, tl, lane);
+        tn = -1;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         T u[N];
         regs_from_rows<T, N>(u, tl, lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        finish_group<T, N, W>(a, it, u, tl, xch, epoch, wv, lane);
+        // The next group's slots live in a buffer of this iteration that starts
+        // unspecified and is copied to pf unconditionally at the end, so that
+        // pf holds no registers while the group is filtered.
+        f4 nf[N / 4];
+#pragma unroll
+        for (int j = 0; j < N / 4; ++j) nf[j] = __builtin_nondeterministic_value(f4{});
+        auto on_next = [&](int64_t nx) {
+            tn = nx;
+            if (nx < total) {
+                const Item<T> ni = make_item<T>(a, tabs, nx);
+                const int64_t h0 = ni.g * C + (int64_t)wv * CW;
+                tile_fetch<N>(nf, ni.x + h0, ni.n - h0, aligned16(ni.x), lane);
+            }
+        };
+        finish_group<T, N, W>(a, it, u, tl, xch, epoch, wv, lane, draw, on_next);
+#pragma unroll
+        for (int j = 0; j < N / 4; ++j) pf[j] = nf[j];
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
     }
 }
@@ -911,10 +997,10 @@ __device__ __forceinline__ void window_load(const float *src, int64_t start, int
     for (int j = 0; j < TT::Q; ++j) {
         const int64_t q = start + 4 * (int64_t)(kLanes * j + lane);
         f4 t;
-        t.x = q + 0 >= 0 && q + 0 < n ? src[q + 0] : 0.0f;
-        t.y = q + 1 >= 0 && q + 1 < n ? src[q + 1] : 0.0f;
-        t.z = q + 2 >= 0 && q + 2 < n ? src[q + 2] : 0.0f;
-        t.w = q + 3 >= 0 && q + 3 < n ? src[q + 3] : 0.0f;
+        t.x = q + 0 >= 0 && q + 0 < n ? gptr(src)[q + 0] : 0.0f;
+        t.y = q + 1 >= 0 && q + 1 < n ? gptr(src)[q + 1] : 0.0f;
+        t.z = q + 2 >= 0 && q + 2 < n ? gptr(src)[q + 2] : 0.0f;
+        t.w = q + 3 >= 0 && q + 3 < n ? gptr(src)[q + 3] : 0.0f;
         *reinterpret_cast<f4 *>(p + j * TT::STEP) = t;
     }
 }
@@ -934,10 +1020,10 @@ __device__ __forceinline__ void window_store(float *dst, int64_t start, int64_t 
     for (int j = 0; j < TT::Q; ++j) {
         const int64_t q = start + 4 * (int64_t)(kLanes * j + lane);
         const f4 t = *reinterpret_cast<const f4 *>(p + j * TT::STEP);
-        if (q + 0 >= 0 && q + 0 < n) dst[q + 0] = t.x;
-        if (q + 1 >= 0 && q + 1 < n) dst[q + 1] = t.y;
-        if (q + 2 >= 0 && q + 2 < n) dst[q + 2] = t.z;
-        if (q + 3 >= 0 && q + 3 < n) dst[q + 3] = t.w;
+        if (q + 0 >= 0 && q + 0 < n) gptr(dst)[q + 0] = t.x;
+        if (q + 1 >= 0 && q + 1 < n) gptr(dst)[q + 1] = t.y;
+        if (q + 2 >= 0 && q + 2 < n) gptr(dst)[q + 2] = t.z;
+        if (q + 3 >= 0 && q + 3 < n) gptr(dst)[q + 3] = t.w;
     }
 }
 
@@ -981,7 +1067,7 @@ __global__ void __launch_bounds__(64 * W)
     __shared__ int64_t ticket;
     __shared__ double red[W][5];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar addressing
     const unsigned epoch = __hip_atomic_load(&b.ctrl[CTRL_EPOCH], __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
     const int64_t total = b.B > 0 ? *b.total_dev : b.total;
@@ -1062,8 +1148,8 @@ __global__ void __launch_bounds__(64 * W)
                 T l1 = 0, l2 = 0;
                 pick_two<T, N>(u, tl, lane, zl, zp, l1, l2);
                 if (lane == zl) {
-                    bi.gzi[2 * k] = (float)l1;
-                    bi.gzi[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
+                    gptr(bi.gzi)[2 * k] = (float)l1;
+                    gptr(bi.gzi)[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
                 }
             }
             // gradient for the section below: 3-tap FIR of lam' (descending, in place)

@@ -100,7 +100,7 @@ struct sos_ctx {
 
 namespace sosint {
 
-constexpr int kDefaultL = 512;   // measured best at order 2 with a persistent grid
+constexpr int kDefaultL = 512;   // measured best at orders 2-16 with a persistent grid
 constexpr int kDefaultN = 64;
 constexpr int kDefaultBits = 32;
 
@@ -122,14 +122,15 @@ struct Tile {
     int L, N;
 };
 
-// The handle's tile, else SOS_TILE_L / SOS_TILE_N, else the default for a
-// cascade of K sections: with one section the group is cheap enough that two
-// resident groups per CU (L = 512, N = 32) beat one larger group; from two
-// sections on, the larger group (N = 64) halves the lookbacks per sample and
-// wins (measured on MI355X, 2^28 samples, orders 2-16).
+// The handle's tile, else SOS_TILE_L / SOS_TILE_N, else the default
+// (L = 512, N = 64): one resident group of 32 K samples per CU, whose next
+// group's samples are loaded while it is corrected and stored, beat two
+// resident groups of 16 K at every order measured on MI355X (2^28 samples,
+// orders 2-16). K is kept for shape choices that depend on the cascade.
 inline Tile tile_of(const sos_ctx *h, int K = 1)
 {
-    Tile t{kDefaultL, K <= 1 ? 32 : kDefaultN};
+    (void)K;
+    Tile t{kDefaultL, kDefaultN};
     if (const char *e = std::getenv("SOS_TILE_L")) {
         const int v = std::atoi(e);
         if (sos_fwd_shape_supported(v, t.N)) t.L = v;
