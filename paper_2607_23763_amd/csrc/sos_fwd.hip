@@ -298,9 +298,9 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
     // One window of kSpan predecessors per round. Every descriptor read is an
     // agent-scope load served beyond the XCD's L2, competing with the sample
     // stream, so reading few per round wins over fewer rounds: measured on
-    // MI355X, 16 for groups of up to 16 K samples and 8 for 32 K beat 64
-    // (order 2: +8-11 %; order 16 at 4 K-sample groups: +35 %), and two or
-    // four windows per round lose.
+    // MI355X, 16 beats 64 (order 2: +8-11 %; order 16 at 4 K-sample groups:
+    // +35 %) and, with the next group prefetched, also 8 and 32 at 32 K-sample
+    // groups (+2-4 %); two or four windows per round lose.
     constexpr int kWin = 1;
     const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);   // T^(C lane)
     T acc1 = 0, acc2 = 0;
@@ -510,8 +510,7 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
                 store_word(dsc + 0, pack((float)g1, epoch));
                 store_word(dsc + 1, pack((float)g2, epoch));
             }
-            lookback<T, (kLanes * N * W >= 32768 ? 8 : 16)>(a, it, tabv, s, epoch, lane, sg1,
-                                                              sg2);
+            lookback<T, 16>(a, it, tabv, s, epoch, lane, sg1, sg2);
         }
         unsigned tk = 0;
         if (draw && lane == 0) tk = atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
