@@ -590,14 +590,30 @@ struct WaveTile {
     }
 };
 
+// Four samples in global memory, which need only be 4-byte aligned: a signal
+// of a batch starts at any sample. gfx950 serves a dword-aligned 128-bit
+// global access in one instruction (at worst one extra cache line), so the
+// whole-tile path never falls back to single-sample accesses.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef __attribute__((address_space(1))) f4u gf4u;
+
+__device__ __forceinline__ const gf4u *gptr4(const float *p)
+{
+    return (const gf4u *)p;
+}
+__device__ __forceinline__ gf4u *gptr4(float *p)
+{
+    return (gf4u *)p;
+}
+
 // src[0 .. 64N) -> the lane's coalesced slots t[0 .. N/4); `rem` samples are
-// valid (zeros past them); `vec` says src is 16-byte aligned.
+// valid (zeros past them).
 template <int N>
 __device__ __forceinline__ void tile_fetch(f4 (&t)[N / 4], const float *src, int64_t rem,
-                                           bool vec, int lane)
+                                           int lane)
 {
-    if (vec && rem >= kLanes * N) {
-        const auto s4 = gptr(reinterpret_cast<const f4 *>(src) + lane);
+    if (rem >= kLanes * N) {
+        const gf4u *s4 = gptr4(src) + lane;
 #pragma unroll
         for (int j = 0; j < N / 4; ++j) t[j] = __builtin_nontemporal_load(s4 + kLanes * j);
     } else {
@@ -627,11 +643,10 @@ __device__ __forceinline__ void tile_put(const f4 (&t)[N / 4], float *tl, int la
 // src[0 .. 64N) -> tile; all loads of a lane are issued before the first LDS
 // write.
 template <int N>
-__device__ __forceinline__ void tile_load(const float *src, int64_t rem, bool vec, float *tl,
-                                          int lane)
+__device__ __forceinline__ void tile_load(const float *src, int64_t rem, float *tl, int lane)
 {
     f4 t[N / 4];
-    tile_fetch<N>(t, src, rem, vec, lane);
+    tile_fetch<N>(t, src, rem, lane);
     tile_put<N>(t, tl, lane);
 }
 
@@ -641,13 +656,12 @@ __device__ __forceinline__ void tile_load(const float *src, int64_t rem, bool ve
 // the intermediate outputs kept for the adjoint, while the lane's N
 // registers are live).
 template <int N, bool NT>
-__device__ __forceinline__ void tile_store(float *dst, int64_t rem, bool vec, const float *tl,
-                                           int lane)
+__device__ __forceinline__ void tile_store(float *dst, int64_t rem, const float *tl, int lane)
 {
     using TT = WaveTile<N>;
     const float *p = tl + TT::slot_base(lane);
-    if (vec && rem >= kLanes * N) {
-        const auto d4 = gptr(reinterpret_cast<f4 *>(dst) + lane);
+    if (rem >= kLanes * N) {
+        gf4u *d4 = gptr4(dst) + lane;
         if (NT) {
             f4 t[TT::Q];
 #pragma unroll
@@ -707,8 +721,7 @@ __device__ __forceinline__ void store_rows(const T (&u)[N], float *tl, int lane,
 {
     rows_from_regs<T, N>(u, tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    tile_store<N, false>(dst + g0, n - g0, (reinterpret_cast<uintptr_t>(dst + g0) & 15u) == 0, tl,
-                         lane);
+    tile_store<N, false>(dst + g0, n - g0, tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
@@ -747,10 +760,6 @@ __device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, in
     return it;
 }
 
-__device__ __forceinline__ bool aligned16(const void *p)
-{
-    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
-}
 
 // Everything after the wave's samples are in registers: the K sections, then
 // registers -> the wave's LDS rows -> coalesced 128-bit global stores. With
@@ -800,7 +809,7 @@ __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it
     // --- store: the tile is the wave's own, so wave-scope ordering suffices
     rows_from_regs<T, N>(u, tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    tile_store<N, true>(it.y + g0, rem, aligned16(it.y), tl, lane);
+    tile_store<N, true>(it.y + g0, rem, tl, lane);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
@@ -861,7 +870,7 @@ __global__ void __launch_bounds__(64 * W)
         const Item<T> it = make_item<T>(a, tabs, t);
         const int64_t g0 = it.g * C + (int64_t)wv * CW;
         // load: coalesced 128-bit global loads -> the wave's LDS rows -> registers
-        if (tn < 0) tile_fetch<N>(pf, it.x + g0, it.n - g0, aligned16(it.x), lane);
+        if (tn < 0) tile_fetch<N>(pf, it.x + g0, it.n - g0, lane);
         tile_put<N>(pf, tl, lane);
         tn = -1;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -879,7 +888,7 @@ __global__ void __launch_bounds__(64 * W)
             if (nx < total) {
                 const Item<T> ni = make_item<T>(a, tabs, nx);
                 const int64_t h0 = ni.g * C + (int64_t)wv * CW;
-                tile_fetch<N>(nf, ni.x + h0, ni.n - h0, aligned16(ni.x), lane);
+                tile_fetch<N>(nf, ni.x + h0, ni.n - h0, lane);
             }
         };
         finish_group<T, N, W>(a, it, u, tl, xch, epoch, wv, lane, draw, on_next);
@@ -987,7 +996,7 @@ __device__ __forceinline__ void window_load(const float *src, int64_t start, int
                                             int lane)
 {
     if (start >= 0) {
-        tile_load<N>(src + start, n - start, aligned16(src + start), tl, lane);
+        tile_load<N>(src + start, n - start, tl, lane);
         return;
     }
     using TT = WaveTile<N>;
@@ -1010,7 +1019,7 @@ __device__ __forceinline__ void window_store(float *dst, int64_t start, int64_t 
                                              const float *tl, int lane)
 {
     if (start >= 0) {
-        tile_store<N, true>(dst + start, n - start, aligned16(dst + start), tl, lane);
+        tile_store<N, true>(dst + start, n - start, tl, lane);
         return;
     }
     using TT = WaveTile<N>;

@@ -106,15 +106,18 @@ def test_in_place_and_misaligned(torch_cuda, P):
     P.sosfilt_(xd, sd, y=xd, zf=zf)
     torch.cuda.synchronize()
     assert rel_l2(xd.cpu().numpy(), yr) <= 1e-5
-    # 4-byte-misaligned input and output (scalar load/store path)
-    buf = torch.zeros(n + 2, device="cuda")
-    buf[1:n + 1] = torch.from_numpy(x).cuda()
-    out = torch.zeros(n + 2, device="cuda")
-    P.sosfilt_(buf[1:n + 1], sd, y=out[1:n + 1], zf=zf)
-    torch.cuda.synchronize()
-    assert rel_l2(out[1:n + 1].cpu().numpy(), yr) <= 1e-5
-    assert out[0].item() == 0.0 and out[n + 1].item() == 0.0
-    assert rel_l2(zf.cpu().numpy(), zfr) <= 1e-5
+    # input and output at every 4-byte offset from a 16-byte boundary (128-bit
+    # accesses at dword alignment), the two offsets differing
+    for oi, oo in ((1, 1), (2, 3), (3, 2), (0, 1), (1, 0)):
+        buf = torch.zeros(n + 4, device="cuda")
+        buf[oi:oi + n] = torch.from_numpy(x).cuda()
+        out = torch.zeros(n + 4, device="cuda")
+        P.sosfilt_(buf[oi:oi + n], sd, y=out[oo:oo + n], zf=zf)
+        torch.cuda.synchronize()
+        assert rel_l2(out[oo:oo + n].cpu().numpy(), yr) <= 1e-5, (oi, oo)
+        o = out.cpu().numpy()
+        assert not o[:oo].any() and not o[oo + n:].any(), (oi, oo)   # nothing written outside
+        assert rel_l2(zf.cpu().numpy(), zfr) <= 1e-5
 
 
 def test_degenerate_k0_n0(torch_cuda, P):
