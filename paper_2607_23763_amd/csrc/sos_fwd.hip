@@ -396,7 +396,22 @@ struct Xch {
     T wave_tot[W][2];   // zero-state totals of the waves
     T grp[2];           // resolved incoming state of the group
     int64_t nxt;        // ticket drawn once the last section's state is resolved
+    T zx[2];            // a section's inputs at samples n-1, n-2 (lane that holds n-1)
 };
+
+// A value all lanes of a wave hold alike, made visibly uniform (a scalar
+// register instead of a vector one).
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Hook run by every wave right after the group state is broadcast, given the
 // ticket drawn at that point (see run_section).
@@ -406,30 +421,43 @@ struct NoNext {
 
 // ------------------------------------------------------------- one section
 
-// One section of the cascade on the group held by the workgroup.
+// One section of the cascade on the group held by the workgroup, in two
+// halves: section_zs solves the section at zero group state (steps 1-3) and
+// publishes the group's local carry; section_corr resolves the group's
+// incoming state (step 4) and corrects the samples (step 5). What the first
+// half leaves for the second is small and mostly wave-uniform.
 // PAIR = false: the forward filter; carries are TDF-II states.
 // PAIR = true: a pure recursive section 1/A(z) (the adjoint's reversed-time
 //   pass); carries are the last two outputs (y[-2], y[-1]), and the tables hold
-//   the matching state map. On return (q1, q2) is the lane's incoming carry.
-// draw: the lookback wave draws the workgroup's next ticket as soon as the
-//   group state is resolved (not earlier: a ticket drawn before the wait would
-//   carry the wait's jitter into the next group's aggregate), and every wave
-//   passes it to on_next right after the broadcast, so that the next group's
-//   loads overlap this group's correction and store.
-template <typename T, int N, int W, bool PAIR, typename OnNext = NoNext>
-__device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl,
-                                            const FwdArgs &a, const Item<T> &it, const T *tabv,
-                                            int s, unsigned epoch, int wv, int lane, bool has_last,
-                                            int zl, int zp, T &q1, T &q2, bool draw = false,
-                                            const OnNext &on_next = OnNext())
+//   the matching state map.
+
+// What the zero-state half leaves for the correction half of one section.
+template <typename T>
+struct SecState {
+    T p1, p2;     // the lane's zero-state terminal pair, scanned over the wave
+    T e1w, e2w;   // the wave's incoming state at zero group state (wave-uniform)
+    T g1, g2;     // the group's local carry (lookback wave, wave-uniform)
+};
+
+template <typename T, int N, int W, bool PAIR>
+__device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
+                                           const FwdArgs &a, const Item<T> &it, const T *tabv,
+                                           int s, unsigned epoch, int wv, int lane, bool has_last,
+                                           int zl, int zp, SecState<T> &st)
 {
     constexpr int LOG = __builtin_ctz(N);
     ctabT<T> *tab = ctabp(tabv);
 
-    // --- inputs kept for the terminal state (and for zf at sample n-1)
+    // --- inputs kept for the terminal state (and, in LDS, for zf at sample n-1)
     const T xl1 = u[N - 1], xl2 = u[N - 2];
-    T zx1 = 0, zx2 = 0;
-    if (!PAIR && has_last) pick_two<T, N>(u, tl, lane, zl, zp, zx1, zx2);
+    if (!PAIR && has_last) {
+        T zx1 = 0, zx2 = 0;
+        pick_two<T, N>(u, tl, lane, zl, zp, zx1, zx2);
+        if (lane == zl) {
+            xch.zx[0] = zx1;
+            xch.zx[1] = zx2;
+        }
+    }
 
     // --- 1. level-1 right-hand side, in place from the end
     const T c0 = tab[OFF_TAPS + 0], c1 = tab[OFF_TAPS + 1], c2 = tab[OFF_TAPS + 2];
@@ -447,14 +475,14 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
     // --- 2. reduction of both parity chains (positions that stay, descending)
 #pragma unroll
     for (int i = 1; i < LOG; ++i) {
-        const int st = 1 << i;
+        const int st2 = 1 << i;
         const T e = tab[OFF_E + i], f = tab[OFF_F + i];
 #pragma unroll
         for (int m = N - 1; m >= 0; --m) {
-            if (((m + 1) % (2 * st)) == 0 || ((m + 2) % (2 * st)) == 0) {
+            if (((m + 1) % (2 * st2)) == 0 || ((m + 2) % (2 * st2)) == 0) {
                 T r = u[m];
-                if (m - st >= 0) r = fmaT(-e, u[m - st], r);
-                if (m - 2 * st >= 0) r = fmaT(f, u[m - 2 * st], r);
+                if (m - st2 >= 0) r = fmaT(-e, u[m - st2], r);
+                if (m - 2 * st2 >= 0) r = fmaT(f, u[m - 2 * st2], r);
                 u[m] = r;
             }
         }
@@ -471,12 +499,6 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
         p2 = b2 * xl1 - a2 * u[N - 1];
     }
     wave_scan<T>(p1, p2, tabv, lane);
-    // The lane power of step 5 is read here, not at its use: a vector load
-    // issued after on_next's loads would wait for all of them. The empty asm
-    // (which the compiler must assume rewrites the values) keeps it from
-    // sinking or re-issuing the load at the use.
-    M2<T> lp = load_m2(tabv + OFF_LANEPOW + 4 * lane);
-    asm volatile("" : "+v"(lp.a), "+v"(lp.b), "+v"(lp.c), "+v"(lp.d));
 
     //     ... and over the W waves of the group (zero group state)
     T e1w = 0, e2w = 0;      // zero-state incoming state of this wave
@@ -493,12 +515,49 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             e2w = o2;
         }
     }
+    st.p1 = p1;
+    st.p2 = p2;
+    st.e1w = wave_uniform(e1w);
+    st.e2w = wave_uniform(e2w);
+    st.g1 = st.g2 = 0;
     if (wv == W - 1) {
         // group local carry = state after the last wave at zero group state
         T g1 = readlane(p1, 63), g2 = readlane(p2, 63);
-        if (W > 1) mv_add<T>(tab + OFF_TWAVE, e1w, e2w, g1, g2);
+        if (W > 1) mv_add<T>(tab + OFF_TWAVE, st.e1w, st.e2w, g1, g2);
+        st.g1 = wave_uniform(g1);
+        st.g2 = wave_uniform(g2);
+        // --- 4a. publish the local carry (the first group of a signal has none)
+        if (it.g != 0 && lane == 0) {
+            unsigned long long *dsc = a.desc + ((size_t)s * a.dstride + it.t) * 4;
+            store_word(dsc + 0, pack((float)g1, epoch));
+            store_word(dsc + 1, pack((float)g2, epoch));
+        }
+    }
+}
 
-        // --- 4. decoupled lookback for the group's incoming state
+// draw: the lookback wave draws the workgroup's next ticket as soon as the
+//   group state is resolved (not earlier: a ticket drawn before the wait would
+//   carry the wait's jitter into the next group's aggregate), and every wave
+//   passes it to on_next right after the broadcast, so that the next group's
+//   loads overlap this group's correction and store.
+template <typename T, int N, int W, bool PAIR, typename OnNext = NoNext>
+__device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *tl,
+                                             const FwdArgs &a, const Item<T> &it, const T *tabv,
+                                             int s, unsigned epoch, int wv, int lane,
+                                             bool has_last, int zl, int zp, const SecState<T> &st,
+                                             T &q1, T &q2, bool draw = false,
+                                             const OnNext &on_next = OnNext())
+{
+    constexpr int LOG = __builtin_ctz(N);
+    ctabT<T> *tab = ctabp(tabv);
+    // The lane power of step 5 is read before the lookback, not at its use: a
+    // vector load issued after on_next's loads would wait for all of them. The
+    // empty asm (which the compiler must assume rewrites the values) keeps it
+    // from sinking or re-issuing the load at the use.
+    M2<T> lp = load_m2(tabv + OFF_LANEPOW + 4 * lane);
+    asm volatile("" : "+v"(lp.a), "+v"(lp.b), "+v"(lp.c), "+v"(lp.d));
+    if (wv == W - 1) {
+        // --- 4b. decoupled lookback for the group's incoming state
         unsigned long long *dsc = a.desc + ((size_t)s * a.dstride + it.t) * 4;
         T sg1, sg2;
         if (it.g == 0) {
@@ -506,15 +565,11 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             sg1 = it.zi ? T(ctab(it.zi)[2 * s + (PAIR ? 1 : 0)]) : T(0);
             sg2 = it.zi ? T(ctab(it.zi)[2 * s + (PAIR ? 0 : 1)]) : T(0);
         } else {
-            if (lane == 0) {
-                store_word(dsc + 0, pack((float)g1, epoch));
-                store_word(dsc + 1, pack((float)g2, epoch));
-            }
             lookback<T, 16>(a, it, tabv, s, epoch, lane, sg1, sg2);
         }
         unsigned tk = 0;
         if (draw && lane == 0) tk = atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
-        T i1 = g1, i2 = g2;
+        T i1 = st.g1, i2 = st.g2;
         mv_add<T>(tab + OFF_TC, sg1, sg2, i1, i2);
         if (lane == 0) {
             store_word(dsc + 2, pack((float)i1, epoch));
@@ -529,9 +584,10 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
     if (draw) on_next(xch.nxt);
 
     // --- 5. incoming state of every lane, then back substitution
-    T sw1 = e1w, sw2 = e2w;
+    const T b1 = tab[OFF_B1], b2 = tab[OFF_B2], a1 = tab[OFF_A1], a2 = tab[OFF_A2];
+    T sw1 = st.e1w, sw2 = st.e2w;
     mv_add<T>(tab + OFF_WPOW + 4 * wv, sg1, sg2, sw1, sw2);
-    const T e1 = dpp0<DPP_WAVE_SHR1, 0xF>(p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(p2);
+    const T e1 = dpp0<DPP_WAVE_SHR1, 0xF>(st.p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(st.p2);
     q1 = fmaT(lp.a, sw1, fmaT(lp.b, sw2, e1));
     q2 = fmaT(lp.c, sw1, fmaT(lp.d, sw2, e2));
     // TDF-II injection (s1, s2) of the lane's incoming carry
@@ -543,15 +599,15 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
     u[N - 2] = fmaT(g[N - 2], s1, fmaT(g[N - 3], s2, u[N - 2]));
 #pragma unroll
     for (int i = LOG - 1; i >= 1; --i) {
-        const int st = 1 << i;
+        const int st2 = 1 << i;
         const T e = tab[OFF_E + i], f = tab[OFF_F + i];
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
-            const int m0 = st - 1 - par;                 // odd chain, then even chain
+            const int m0 = st2 - 1 - par;                 // odd chain, then even chain
             u[m0] = fmaT(g[m0], s1, fmaT(g[m0 - 1], s2, u[m0]));
 #pragma unroll
-            for (int m = m0 + 2 * st; m < N; m += 2 * st)
-                u[m] = fmaT(-e, u[m - st], fmaT(-f, u[m - 2 * st], u[m]));
+            for (int m = m0 + 2 * st2; m < N; m += 2 * st2)
+                u[m] = fmaT(-e, u[m - st2], fmaT(-f, u[m - 2 * st2], u[m]));
         }
     }
 
@@ -560,6 +616,7 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
         T yo1 = 0, yo2 = 0;
         pick_two<T, N>(u, tl, lane, zl, zp, yo1, yo2);
         if (lane == zl) {
+            const T zx1 = xch.zx[0], zx2 = xch.zx[1];
             T z1;
             if (zp >= 1)
                 z1 = b1 * zx1 + b2 * zx2 - a1 * yo1 - a2 * yo2;
@@ -569,6 +626,20 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
             gptr(it.zf)[2 * s + 1] = (float)(b2 * zx1 - a2 * yo1);
         }
     }
+}
+
+// Both halves back to back. On return (q1, q2) is the lane's incoming carry.
+template <typename T, int N, int W, bool PAIR, typename OnNext = NoNext>
+__device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl,
+                                            const FwdArgs &a, const Item<T> &it, const T *tabv,
+                                            int s, unsigned epoch, int wv, int lane, bool has_last,
+                                            int zl, int zp, T &q1, T &q2, bool draw = false,
+                                            const OnNext &on_next = OnNext())
+{
+    SecState<T> st;
+    section_zs<T, N, W, PAIR>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl, zp, st);
+    section_corr<T, N, W, PAIR>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl, zp,
+                                st, q1, q2, draw, on_next);
 }
 
 // ---------------------------------------------------------------- wave tile
