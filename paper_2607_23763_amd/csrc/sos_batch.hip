@@ -26,15 +26,28 @@ __device__ inline bool signal_ok(int i, int kmax, int64_t rows, int64_t total_sa
 }
 
 // One block of kScanThreads threads: group counts and their exclusive prefix.
+// Optionally it first copies `stage_bytes` of arguments from host memory
+// (pinned, coherent) to device memory and arms the filter launch (ticket 0, a
+// fresh epoch), which saves a step of the server a copy and a launch.
 __global__ void __launch_bounds__(kScanThreads)
 worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
                       int64_t max_groups,
                       const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
-                      int64_t *gpre, int64_t *total_dev, unsigned *ctrl)
+                      int64_t *gpre, int64_t *total_dev, unsigned *ctrl,
+                      const unsigned *stage_src, unsigned *stage_dst, int64_t stage_words)
 {
     __shared__ int64_t part[kScanThreads];
     __shared__ int64_t carry;
     const int tid = threadIdx.x;
+    if (stage_src) {
+        for (int64_t w = tid; w < stage_words; w += kScanThreads) stage_dst[w] = stage_src[w];
+        if (tid == 0) {
+            ctrl[CTRL_TICKET] = 0u;
+            const unsigned e = ctrl[CTRL_EPOCH] + 1u;
+            ctrl[CTRL_EPOCH] = (e == 0u) ? 1u : e;
+        }
+        __threadfence_block();
+    }
     if (tid == 0) carry = 0;
     __syncthreads();
     for (int base = 0; base < B; base += kScanThreads) {
@@ -94,6 +107,25 @@ worktable_fill_kernel(int B, const int64_t *gpre, const int64_t *total_dev, int3
 
 }  // namespace
 
+static hipError_t launch_worktable(int B, int kmax, int64_t rows, int64_t C,
+                                   int64_t total_samples, int64_t max_groups, const int32_t *Ks,
+                                   const int32_t *sec_off, const int64_t *sig_off, int64_t *gpre,
+                                   int32_t *sigmap, int64_t *total_dev, const float *zi,
+                                   float *zf, unsigned *ctrl, const void *stage_src,
+                                   void *stage_dst, int64_t stage_bytes, hipStream_t stream)
+{
+    hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax,
+                       rows, C, total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev,
+                       ctrl, static_cast<const unsigned *>(stage_src),
+                       static_cast<unsigned *>(stage_dst), stage_bytes / 4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (B > 0)
+        hipLaunchKernelGGL(worktable_fill_kernel, dim3(B), dim3(256), 0, stream, B, gpre,
+                           total_dev, sigmap, Ks, sec_off, sig_off, zi, zf);
+    return hipGetLastError();
+}
+
 extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C,
                                            int64_t total_samples,
                                            int64_t max_groups, const int32_t *Ks,
@@ -102,13 +134,24 @@ extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_
                                            const float *zi, float *zf, unsigned *ctrl,
                                            hipStream_t stream)
 {
-    hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax,
-                       rows, C, total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev,
-                       ctrl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (B > 0)
-        hipLaunchKernelGGL(worktable_fill_kernel, dim3(B), dim3(256), 0, stream, B, gpre,
-                           total_dev, sigmap, Ks, sec_off, sig_off, zi, zf);
-    return hipGetLastError();
+    return launch_worktable(B, kmax, rows, C, total_samples, max_groups, Ks, sec_off, sig_off,
+                            gpre, sigmap, total_dev, zi, zf, ctrl, nullptr, nullptr, 0, stream);
+}
+
+// The same, first copying stage_bytes (a multiple of 4) from pinned coherent
+// host memory to device memory (where Ks, sec_off and sig_off point) and
+// arming the launch that follows.
+extern "C" hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows, int64_t C,
+                                                  int64_t total_samples, int64_t max_groups,
+                                                  const int32_t *Ks, const int32_t *sec_off,
+                                                  const int64_t *sig_off, int64_t *gpre,
+                                                  int32_t *sigmap, int64_t *total_dev,
+                                                  const float *zi, float *zf, unsigned *ctrl,
+                                                  const void *stage_src, void *stage_dst,
+                                                  int64_t stage_bytes, hipStream_t stream)
+{
+    if (!stage_src || !stage_dst || stage_bytes < 0 || (stage_bytes & 3)) return hipErrorInvalidValue;
+    return launch_worktable(B, kmax, rows, C, total_samples, max_groups, Ks, sec_off, sig_off,
+                            gpre, sigmap, total_dev, zi, zf, ctrl, stage_src, stage_dst,
+                            stage_bytes, stream);
 }

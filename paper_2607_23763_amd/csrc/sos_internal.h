@@ -52,6 +52,14 @@ hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C, int64_
                                 const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
                                 int64_t *total_dev, const float *zi, float *zf, unsigned *ctrl,
                                 hipStream_t stream);
+hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows, int64_t C,
+                                       int64_t total_samples, int64_t max_groups,
+                                       const int32_t *Ks, const int32_t *sec_off,
+                                       const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
+                                       int64_t *total_dev, const float *zi, float *zf,
+                                       unsigned *ctrl, const void *stage_src, void *stage_dst,
+                                       int64_t stage_bytes, hipStream_t stream);
+hipError_t sos_launch_report_err(unsigned *ctrl_err, unsigned *host_err, hipStream_t stream);
 hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx, int64_t n,
                           int64_t groups, const void *tabs, int K, const float *x,
                           const float *y, const float *saved, const float *gzf, float *gzi,

@@ -28,6 +28,7 @@
 #include <unordered_map>
 #include <utility>
 #include <vector>
+#include <vector>
 
 #include "sos_internal.h"
 
@@ -99,7 +100,9 @@ struct Stream {
 };
 
 // Per-step argument arrays, laid out identically in pinned host memory and
-// in the device copy: K | sec_off | sig_off | xp | yp (| err word, host only).
+// in the device copy: K | sec_off | sig_off | xp | yp. A step packs its B
+// chunks with ArgLayout(B); the buffers are sized for ArgLayout(max_slots),
+// whose end holds the host-only error word.
 struct ArgLayout {
     size_t k, sec, sig, xp, yp, bytes, err;
     explicit ArgLayout(int slots = 0)
@@ -184,12 +187,14 @@ void retire(sos_srv *s, Step &st, int status)
 void launch_step(sos_srv *s, Step &st)
 {
     unsigned char *hb = st.host;
-    int32_t *K = reinterpret_cast<int32_t *>(hb + s->lay.k);
-    int32_t *sec = reinterpret_cast<int32_t *>(hb + s->lay.sec);
-    int64_t *sig = reinterpret_cast<int64_t *>(hb + s->lay.sig);
-    const float **xp = reinterpret_cast<const float **>(hb + s->lay.xp);
-    float **yp = reinterpret_cast<float **>(hb + s->lay.yp);
     unsigned *err = reinterpret_cast<unsigned *>(hb + s->lay.err);
+    struct Pick {
+        int32_t K, row;
+        const float *x;
+        float *y;
+        int64_t n;
+    };
+    std::vector<Pick> pick;
     int B = 0, kmax = 0;
     int64_t total = 0;
     std::deque<int64_t> deferred;
@@ -206,11 +211,7 @@ void launch_step(sos_srv *s, Step &st)
             continue;
         }
         str.pending.pop_front();
-        K[B] = str.K;
-        sec[B] = (int32_t)str.row;
-        sig[B] = total;
-        xp[B] = rq.x;
-        yp[B] = rq.y;
+        pick.push_back(Pick{str.K, (int32_t)str.row, rq.x, rq.y, rq.n});
         total += rq.n;
         kmax = std::max(kmax, str.K);
         st.tickets.push_back(tk);
@@ -225,33 +226,52 @@ void launch_step(sos_srv *s, Step &st)
         }
     }
     if (B == 0) return;
+    // this step's arrays, packed for its B chunks, so that the device copy
+    // (made by the work-table kernel) moves only what is used
+    const ArgLayout lb(B);
+    int32_t *K = reinterpret_cast<int32_t *>(hb + lb.k);
+    int32_t *sec = reinterpret_cast<int32_t *>(hb + lb.sec);
+    int64_t *sig = reinterpret_cast<int64_t *>(hb + lb.sig);
+    const float **xp = reinterpret_cast<const float **>(hb + lb.xp);
+    float **yp = reinterpret_cast<float **>(hb + lb.yp);
+    int64_t off = 0;
+    for (int i = 0; i < B; ++i) {
+        K[i] = pick[i].K;
+        sec[i] = pick[i].row;
+        sig[i] = off;
+        xp[i] = pick[i].x;
+        yp[i] = pick[i].y;
+        off += pick[i].n;
+    }
     sig[B] = total;
     *err = 0;
     st.busy = true;
     sos_ctx *h = s->h;
-    const unsigned char *d = s->dargs;
-    const int32_t *dK = reinterpret_cast<const int32_t *>(d + s->lay.k);
-    const int32_t *dsec = reinterpret_cast<const int32_t *>(d + s->lay.sec);
-    const int64_t *dsig = reinterpret_cast<const int64_t *>(d + s->lay.sig);
-    const float *const *dxp = reinterpret_cast<const float *const *>(d + s->lay.xp);
-    float *const *dyp = reinterpret_cast<float *const *>(d + s->lay.yp);
+    unsigned char *d = s->dargs;
+    const int32_t *dK = reinterpret_cast<const int32_t *>(d + lb.k);
+    const int32_t *dsec = reinterpret_cast<const int32_t *>(d + lb.sec);
+    const int64_t *dsig = reinterpret_cast<const int64_t *>(d + lb.sig);
+    const float *const *dxp = reinterpret_cast<const float *const *>(d + lb.xp);
+    float *const *dyp = reinterpret_cast<float *const *>(d + lb.yp);
+    // persistent grid, but no more workgroups than the step has groups (each
+    // chunk adds at most one partial group): a step of a few chunks launches
+    // a few workgroups, not a device-filling grid that mostly exits at once
+    const int64_t step_groups = total / s->C + B;
     int64_t grid = grid_of(s->bits, s->L, s->N);
     if (grid <= 0 || grid > s->max_groups) grid = s->max_groups;
+    if (grid > step_groups) grid = step_groups;
+    // Four launches, no copy operations: the work-table kernel copies the
+    // arguments from the step's pinned host buffer and arms the filter, and the
+    // last kernel reports the error bits into that buffer and clears them.
     bool ok =
-        hipMemcpyAsync(s->dargs, hb, s->lay.bytes, hipMemcpyHostToDevice, s->stream) ==
-            hipSuccess &&
-        sos_launch_worktable(B, kmax, s->max_rows, s->C, total, s->max_groups, dK, dsec, dsig,
-                             h->gpre, h->sigmap, h->total_dev, s->state, s->state, h->ctrl,
-                             s->stream) == hipSuccess &&
-        sos_launch_arm(h->ctrl, s->stream) == hipSuccess &&
+        sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total, s->max_groups, dK, dsec,
+                                    dsig, h->gpre, h->sigmap, h->total_dev, s->state, s->state,
+                                    h->ctrl, hb, d, (int64_t)lb.bytes, s->stream) == hipSuccess &&
         sos_launch_fwd_batched(s->bits, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
                                h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
                                s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
                                nullptr, 0, s->max_groups, s->stream) == hipSuccess &&
-        hipMemcpyAsync(err, h->ctrl + CTRL_ERR, sizeof(unsigned), hipMemcpyDeviceToHost,
-                       s->stream) == hipSuccess &&
-        sos_launch_fill(reinterpret_cast<float *>(h->ctrl + CTRL_ERR), nullptr, 1, s->stream) ==
-            hipSuccess &&
+        sos_launch_report_err(h->ctrl + CTRL_ERR, err, s->stream) == hipSuccess &&
         hipEventRecord(st.done, s->stream) == hipSuccess;
     if (!ok) retire(s, st, SOS_EHIP);
 }
@@ -402,7 +422,9 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
             hipSuccess;
     for (Step &st : s->steps) {
         ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
-             hipHostMalloc(&st.host, s->lay.bytes + 8, hipHostMallocDefault) == hipSuccess;
+             // coherent: kernels read the step's arguments from it and write the
+             // step's error word into it
+             hipHostMalloc(&st.host, s->lay.bytes + 8, hipHostMallocCoherent) == hipSuccess;
     }
     if (!ok) {
         free_server(s);

@@ -26,7 +26,22 @@ __global__ void __launch_bounds__(256) copy_kernel(const f4 *x, f4 *y, int64_t n
     if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
 }
 
+// End of a server step: the launch's error bits to the step's host result
+// word (pinned, coherent host memory), then cleared for the next launch.
+__global__ void report_err_kernel(unsigned *ctrl_err, unsigned *host_err)
+{
+    *host_err = *ctrl_err;
+    *ctrl_err = 0u;
+}
+
 }  // namespace
+
+extern "C" hipError_t sos_launch_report_err(unsigned *ctrl_err, unsigned *host_err,
+                                            hipStream_t stream)
+{
+    hipLaunchKernelGGL(report_err_kernel, dim3(1), dim3(1), 0, stream, ctrl_err, host_err);
+    return hipGetLastError();
+}
 
 extern "C" hipError_t sos_launch_fill(float *dst, const float *src, int64_t count,
                                       hipStream_t stream)
