@@ -92,10 +92,9 @@ int sos_last_error(sos_handle_t h);
  * and N samples per lane; a group holds C = L*N samples and one workgroup of
  * L/64 wavefronts processes it. Compiled shapes: L in {64, 256, 512} with
  * N in {16, 32, 64}, and L = 1024 with N in {16, 32}. sos_set_tile(h, 0, 0)
- * restores the default, which depends on the cascade: (1024, 32) for one
- * section, (512, 64) for more (sos_get_tile reports the one-section default
- * when no tile is set). Applies to later calls (tables prepared for another
- * shape must be prepared again). Unsupported shapes return SOS_EINVAL. */
+ * restores the default, (512, 64). Applies to later calls (tables prepared
+ * for another shape must be prepared again). Unsupported shapes return
+ * SOS_EINVAL. */
 int sos_set_tile(sos_handle_t h, int L, int N);
 int sos_get_tile(sos_handle_t h, int *L, int *N);
 

@@ -108,7 +108,7 @@ struct sos_ctx {
 
 namespace sosint {
 
-constexpr int kDefaultL = 512;   // default group shape from two sections on
+constexpr int kDefaultL = 512;   // default group shape
 constexpr int kDefaultN = 64;
 constexpr int kDefaultBits = 32;
 
@@ -130,16 +130,17 @@ struct Tile {
     int L, N;
 };
 
-// The handle's tile, else SOS_TILE_L / SOS_TILE_N, else the default for a
-// cascade of K sections: one resident group of 32 K samples per CU, whose
-// next group's samples are loaded while it is corrected and stored, beat two
+// The handle's tile, else SOS_TILE_L / SOS_TILE_N, else the default
+// (L = 512, N = 64): one resident group of 32 K samples per CU, whose next
+// group's samples are loaded while it is corrected and stored, beat two
 // resident groups of 16 K at every order measured on MI355X (2^28 samples,
-// orders 2-16); one section runs best as 16 waves of N = 32 (L = 1024), more
-// sections as 8 waves of N = 64 (L = 512), whose fewer, longer lanes spend
-// less per sample on the per-section scans.
+// orders 2-16), and 8 waves of N = 64 beat 16 waves of N = 32 (L = 1024) by
+// 7-8 % at order 2 and more at higher orders. K is kept for shape choices
+// that depend on the cascade.
 inline Tile tile_of(const sos_ctx *h, int K = 1)
 {
-    Tile t = K <= 1 ? Tile{1024, 32} : Tile{kDefaultL, kDefaultN};
+    (void)K;
+    Tile t{kDefaultL, kDefaultN};
     if (const char *e = std::getenv("SOS_TILE_L")) {
         const int v = std::atoi(e);
         if (sos_fwd_shape_supported(v, t.N)) t.L = v;
