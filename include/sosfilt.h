@@ -190,7 +190,9 @@ int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, con
  * output gives the gradient of the section input, and per-group correlations
  * of that output with the section's input and output give the coefficient
  * gradients, reduced over groups in FP64 in a fixed order. The paper does not
- * treat gradients; this is the adjoint of its Eq. (1) cascade.
+ * treat gradients; this is the adjoint of its Eq. (1) cascade. The adjoint
+ * uses the handle's tile when it is one of its shapes (L in {64, 256, 512},
+ * N in {16, 32}), else (512, 32).
  */
 int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *x, float *y,
                      int64_t n, const float *zi, float *zf, float *saved, hipStream_t stream);

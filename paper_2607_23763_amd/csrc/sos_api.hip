@@ -431,7 +431,7 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
         return SOS_OK;
     }
     Tile t = tile_of(h);
-    if (!sos_bwd_shape_supported(t.L, t.N)) t = Tile{256, 32};
+    if (!sos_bwd_shape_supported(t.L, t.N)) t = Tile{512, 32};   // fastest adjoint shape measured
     const int bits = bits_of(h);
     const int64_t C = (int64_t)t.L * t.N;
     const int64_t groups = (n + C - 1) / C;
@@ -499,7 +499,7 @@ int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     Tile t = tile_of(h, kmax);
-    if (!sos_bwd_shape_supported(t.L, t.N)) t = Tile{256, 32};
+    if (!sos_bwd_shape_supported(t.L, t.N)) t = Tile{512, 32};   // fastest adjoint shape measured
     const int bits = bits_of(h);
     const int64_t C = (int64_t)t.L * t.N;
     const int64_t max_groups = total_samples / C + B;
