@@ -159,3 +159,45 @@ def test_full_size_uneven_batch_graph_tuned(env):
         assert e <= by, (i, e, by)
         assert rel_l2(zfh[sec[i]:sec[i + 1]], zfr) <= zf_bound(int(Ks[i]), by, bz, yr, zfr)
     g.close()
+
+
+@pytest.mark.parametrize("tile", [(512, 64), (256, 32), (64, 16)])
+def test_small_grid_many_groups_per_workgroup(env, tile, monkeypatch):
+    """Three workgroups for the whole batch: each draws many tickets, so the
+    next group is loaded while the current one is corrected and stored across
+    signal boundaries, partial last groups, a signal with no sections and a
+    signal with an unusable section (which poisons only that signal)."""
+    torch, P = env
+    monkeypatch.setenv("SOS_GRID", "3")
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=40, log2_lo=2, log2_hi=17, seed=41)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=42)
+    so = np.r_[0, np.cumsum(Ks)]
+    bad = 11                                         # a2 > 1 in its last section
+    rows = rows.copy()
+    rows[so[bad + 1] - 1, 5] = 1.5 * rows[so[bad + 1] - 1, 3]
+    h = P.Handle(0, tile=tile)
+    Kd = Ks.copy()
+    Kd[23] = 0                                       # no sections: a copy
+    y, zf = P.sosfilt_batched(dev(torch, x), dev(torch, rows), dev(torch, Kd),
+                              dev(torch, sig_off), zi=dev(torch, zi),
+                              sec_off=dev(torch, so.astype(np.int32)), kmax=int(Ks.max()),
+                              handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_EUNSTABLE
+    y, zf = y.cpu().numpy(), zf.cpu().numpy()
+    yr, zfr = oracle.sosfilt_batched(Ks, rows, sig_off, x, zi, nthreads=8)
+    for i in range(len(Ks)):
+        a, b = sig_off[i], sig_off[i + 1]
+        if i == bad:
+            assert b == a or np.all(np.isnan(y[a:b]))
+            continue
+        if i == 23:
+            assert np.array_equal(y[a:b], x[a:b])
+            continue
+        rows_i, zi_i = rows[so[i]:so[i + 1]], zi[so[i]:so[i + 1]]
+        by = bz = tol_for(int(Ks[i]))
+        if b > a:
+            by, bz = fp32_bounds(int(Ks[i]), rows_i, x[a:b], zi_i, yr[a:b], zfr[so[i]:so[i + 1]])
+        assert rel_l2(y[a:b], yr[a:b]) <= by, (i, Ks[i], b - a)
+        bz = zf_bound(int(Ks[i]), by, bz, yr[a:b], zfr[so[i]:so[i + 1]])
+        assert rel_l2(zf[so[i]:so[i + 1]], zfr[so[i]:so[i + 1]]) <= bz, (i, Ks[i], b - a)

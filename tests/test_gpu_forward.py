@@ -92,6 +92,36 @@ def test_edge_lengths(torch_cuda, P, tile):
             assert rel_l2(zf, zfr) <= 1e-5, (K, n, tile, zf, zfr)
 
 
+@pytest.mark.parametrize("tile", TILES)
+def test_small_grid_many_groups_per_workgroup(torch_cuda, P, tile, monkeypatch):
+    """One, two or five workgroups for the whole signal: each draws many
+    tickets and loads the next group while the current one is corrected and
+    stored, up to the partial last group; also in place."""
+    L, N = tile
+    C = L * N
+    g = workloads.rng(88)
+    for grid in (1, 2, 5):
+        monkeypatch.setenv("SOS_GRID", str(grid))
+        for K in (1, 4):
+            sos = workloads.random_stable_sos(K, g)
+            zi = workloads.initial_state(K, g)
+            n = 7 * C + 123
+            x = workloads.signal(n, seed=grid * 10 + K)
+            y, zf, _ = run(torch_cuda, P, sos, x, zi, tile=tile)
+            yr, zfr = oracle.sosfilt(sos, x, zi)
+            assert rel_l2(y, yr) <= 1e-5, (grid, K, tile)
+            assert rel_l2(zf, zfr) <= 1e-5, (grid, K, tile)
+    monkeypatch.setenv("SOS_GRID", "2")
+    torch = torch_cuda
+    xd = torch.from_numpy(x).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(sos, dtype=np.float32)).cuda()
+    h = P.Handle(0, tile=tile)
+    P.sosfilt_(xd, sd, zi=torch.from_numpy(zi).cuda(), y=xd, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    assert rel_l2(xd.cpu().numpy(), yr) <= 1e-5
+
+
 def test_in_place_and_misaligned(torch_cuda, P):
     torch = torch_cuda
     K = 4
