@@ -448,7 +448,7 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
     if (sos_launch_bwd(bits, t.L, t.N, gy, gx, n, groups, h->tabs_bwd, K, x, y, saved, gzf, gzi,
-                       h->partials, h->desc, h->ctrl, h->timeout_ticks, 0, stream) != hipSuccess)
+                       h->partials, h->desc, h->ctrl, h->timeout_ticks, grid_override(), stream) != hipSuccess)
         return SOS_EHIP;
     if (gsections &&
         sos_launch_bwd_reduce(h->partials, groups, K, sections, gsections, stream) != hipSuccess)

@@ -163,15 +163,22 @@ inline int bits_of(const sos_ctx *h)
     return kDefaultBits;
 }
 
+// SOS_GRID: exactly this many workgroups for every persistent launch, or 0
+// (tests: many groups per workgroup).
+inline int64_t grid_override()
+{
+    if (const char *e = std::getenv("SOS_GRID")) {
+        const long long g = std::atoll(e);
+        if (g > 0) return (int64_t)g;
+    }
+    return 0;
+}
+
 inline int64_t grid_of(int bits, int L, int N)
 {
     // persistent grid: as many workgroups as can be resident, drawing tickets
     // until the groups run out (measured faster than one workgroup per group)
-    if (const char *e = std::getenv("SOS_GRID")) {
-        // exactly this many workgroups (tests: many groups per workgroup)
-        const long long g = std::atoll(e);
-        if (g > 0) return (int64_t)g;
-    }
+    if (const int64_t g = grid_override()) return g;
     int64_t grid = sos_fwd_capacity(bits, L, N);
     if (const char *e = std::getenv("SOS_PERSISTENT")) {
         const int f = std::atoi(e);

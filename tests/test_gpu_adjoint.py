@@ -52,6 +52,27 @@ def test_vjp_matches_oracle(env, K, n, tile):
     assert rel_l2(gs, rs) <= 1e-4
 
 
+@pytest.mark.parametrize("tile", [(512, 32), (64, 16)])
+def test_vjp_small_grid(env, tile, monkeypatch):
+    """Two workgroups for the whole reversed-time pass: each draws many
+    tickets, including the first group of the signal last."""
+    torch, P = env
+    monkeypatch.setenv("SOS_GRID", "2")
+    L, N = tile
+    K, n = 4, 5 * L * N + 77
+    g = workloads.rng(130)
+    sos = workloads.random_stable_sos(K, g)
+    x = workloads.signal(n, seed=17)
+    zi = workloads.initial_state(K, g)
+    gy = workloads.signal(n, seed=18)
+    gzf = workloads.initial_state(K, g, var=1.0)
+    gx, gzi, gs = gpu_vjp(torch, P, sos, x, zi, gy, gzf, tile)
+    rx, rzi, rs = oracle.sosfilt_vjp(sos, x, zi, gy, gzf)
+    assert rel_l2(gx, rx) <= 1e-5
+    assert rel_l2(gzi, rzi) <= 1e-5
+    assert rel_l2(gs, rs) <= 1e-4
+
+
 @pytest.mark.parametrize("precision", [64, 32])
 def test_vjp_order16_lightly_damped(env, precision):
     """8 sections, poles at radius 0.995, section 0 scaled to unit white-noise
