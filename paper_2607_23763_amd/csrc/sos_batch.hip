@@ -40,7 +40,25 @@ worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_sa
     __shared__ int64_t carry;
     const int tid = threadIdx.x;
     if (stage_src) {
-        for (int64_t w = tid; w < stage_words; w += kScanThreads) stage_dst[w] = stage_src[w];
+        // 8-byte words, four per thread in flight: a full step's arguments
+        // (32 KB at 1024 chunks) cost one round trip to host memory, not eight
+        const uint2 *src8 = reinterpret_cast<const uint2 *>(stage_src);
+        uint2 *dst8 = reinterpret_cast<uint2 *>(stage_dst);
+        const int64_t n8 = stage_words / 2;
+        for (int64_t base = 0; base < n8; base += 4 * kScanThreads) {
+            uint2 v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t w = base + r * kScanThreads + tid;
+                if (w < n8) v[r] = src8[w];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t w = base + r * kScanThreads + tid;
+                if (w < n8) dst8[w] = v[r];
+            }
+        }
+        if ((stage_words & 1) && tid == 0) stage_dst[stage_words - 1] = stage_src[stage_words - 1];
         if (tid == 0) {
             ctrl[CTRL_TICKET] = 0u;
             const unsigned e = ctrl[CTRL_EPOCH] + 1u;
@@ -138,9 +156,9 @@ extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_
                             gpre, sigmap, total_dev, zi, zf, ctrl, nullptr, nullptr, 0, stream);
 }
 
-// The same, first copying stage_bytes (a multiple of 4) from pinned coherent
-// host memory to device memory (where Ks, sec_off and sig_off point) and
-// arming the launch that follows.
+// The same, first copying stage_bytes (a multiple of 4; both buffers 8-byte
+// aligned) from pinned coherent host memory to device memory (where Ks,
+// sec_off and sig_off point) and arming the launch that follows.
 extern "C" hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows, int64_t C,
                                                   int64_t total_samples, int64_t max_groups,
                                                   const int32_t *Ks, const int32_t *sec_off,
@@ -150,7 +168,9 @@ extern "C" hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows,
                                                   const void *stage_src, void *stage_dst,
                                                   int64_t stage_bytes, hipStream_t stream)
 {
-    if (!stage_src || !stage_dst || stage_bytes < 0 || (stage_bytes & 3)) return hipErrorInvalidValue;
+    if (!stage_src || !stage_dst || stage_bytes < 0 || (stage_bytes & 3) ||
+        ((reinterpret_cast<uintptr_t>(stage_src) | reinterpret_cast<uintptr_t>(stage_dst)) & 7))
+        return hipErrorInvalidValue;
     return launch_worktable(B, kmax, rows, C, total_samples, max_groups, Ks, sec_off, sig_off,
                             gpre, sigmap, total_dev, zi, zf, ctrl, stage_src, stage_dst,
                             stage_bytes, stream);
