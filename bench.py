@@ -6,7 +6,9 @@ samples, zero initial state, cascades of K = 1, 2, 4, 8 sections (orders 2-16),
 Butterworth low-pass at 0.2*Nyquist and random stable sections. The JSON
 `value` is the order-2 (K = 1) Butterworth case: samples per second of one
 whole step (coefficient preparation + filter kernel) with input and output
-resident in HBM, in GS/s. The other orders are reported under "sweep".
+resident in HBM, in GS/s, with the divide-and-conquer cyclic-reduction
+section solver (--alg ph: the PH solver). The other orders are reported under
+"sweep", each timed with both solvers.
 
 Timing: W untimed warm-up steps, then exactly K timed steps between
 torch.cuda.synchronize() calls; two rotating input/output buffer pairs of
@@ -43,6 +45,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
 METRIC = "GS/s & % HBM roof, orders 2-16; p50/p99 stream-chunk latency; fwd+bwd GS/s"
 BYTES_PER_SAMPLE = 8            # 4 B FP32 in + 4 B FP32 out (Eq. (28))
+# Algorithmic multiply/FMA operations per sample and section of each solver
+# (2 flop each): DC-CR fold 5 + reduction 2 + back substitution 2; PH
+# feed-forward 3 + recursion 2 + homogeneous correction 2 (Table III).
+OPS_PER_SAMPLE_SECTION = {"dccr": 9, "ph": 7}
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, packed FP32
+FP32_UNPACKED_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 KERNEL_SOURCES = ("paper_2607_23763_amd/csrc/sos_fwd.hip", "paper_2607_23763_amd/csrc/sos_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sos_fwd_kernel_k1_2p28.json")
 
@@ -277,6 +285,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-k", type=int, default=0, help="profile helper: only this K, Butterworth")
     ap.add_argument("--quick", action="store_true", help="headline and sweep only")
+    ap.add_argument("--alg", default="dccr", choices=("dccr", "ph"),
+                    help="section solver of the headline (the sweep times both)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -293,7 +303,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.lib()
     dev = torch.device("cuda", 0)
-    h = P.Handle(0, tile=tuple(int(v) for v in args.tile.split(",")) if args.tile else None)
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    h = P.Handle(0, tile=tile, algorithm=args.alg)
     L, N = h.tile()
     n = 1 << args.log2n
     log("generating %d samples" % n)
@@ -316,17 +327,30 @@ def main():
 
     result_sweep = {}
     if not args.no_sweep and not args.only_k:
+        other = "ph" if args.alg == "dccr" else "dccr"
+        h2 = P.Handle(0, tile=tile, algorithm=other)
         for kind in ("butter", "random"):
             result_sweep[kind] = {}
             for K in (1, 2, 4, 8):
                 sos_d = torch.from_numpy(workloads.sweep_sections(K, kind)).to(dev)
                 ms, mk = time_steps(torch, P, h, sos_d, xs, ys, max(10, args.steps // 2), 3)
                 assert h.last_error() == P.SOS_OK
+                ms2, mk2 = time_steps(torch, P, h2, sos_d, xs, ys, max(10, args.steps // 2), 3)
+                assert h2.last_error() == P.SOS_OK
+                tf = gss(mk) * 2 * OPS_PER_SAMPLE_SECTION[args.alg] * K / 1e3
+                tf2 = gss(mk2) * 2 * OPS_PER_SAMPLE_SECTION[other] * K / 1e3
                 result_sweep[kind][str(K)] = {
                     "order": 2 * K, "GS_per_s": round(gss(ms), 2),
                     "kernel_GS_per_s": round(gss(mk), 2),
-                    "hbm_roof_frac": round(gss(mk) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4)}
+                    "hbm_roof_frac": round(gss(mk) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
+                    "alu_TFLOPs": round(tf, 2),
+                    "alu_roof_frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    "alu_unpacked_roof_frac": round(tf / FP32_UNPACKED_PEAK_TFLOPS, 4),
+                    other + "_GS_per_s": round(gss(ms2), 2),
+                    other + "_kernel_GS_per_s": round(gss(mk2), 2),
+                    other + "_alu_roof_frac": round(tf2 / FP32_VECTOR_PEAK_TFLOPS, 4)}
                 log(kind, K, result_sweep[kind][str(K)])
+        h2.close()
 
     copy_ms = time_copy(torch, P, xs, ys, 20, 3)
     copy_gbs = n * BYTES_PER_SAMPLE / (copy_ms * 1e-3) / 1e9
@@ -374,7 +398,7 @@ def main():
         "config": {"workload": "one FP32 signal of 2^%d N(0,1) samples, order-%d Butterworth "
                                "low-pass at 0.2*Nyquist (K=%d SOS), zi=0" % (args.log2n, 2 * K1, K1),
                    "n": n, "K": K1, "lanes_per_group_L": L, "samples_per_lane_N": N,
-                   "group_C": L * N},
+                   "group_C": L * N, "section_solver": args.alg},
         "hbm_roof_frac_step": round(gss(ms_step) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,

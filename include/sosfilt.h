@@ -110,7 +110,28 @@ int sos_get_tile(sos_handle_t h, int *L, int *N);
 int sos_set_precision(sos_handle_t h, int bits);
 int sos_get_precision(sos_handle_t h);
 
-/* Bound on each lookback wait (Sec. IV-A's decoupled lookback spins on its
+/* Section solver of the filter kernels (Sec. IV-E compares the candidates):
+ *   SOS_ALG_DCCR  divide-and-conquer cyclic reduction (Sec. II-E, the
+ *                 default): both terminal blocks of every lane from a
+ *                 log-depth reduction of each parity chain, then back
+ *                 substitution; about 9 FMAs per sample and section.
+ *   SOS_ALG_PH    PH factorization (Sec. II-C): the lane's particular
+ *                 solution (its samples through the section from rest,
+ *                 Eq. (9)), then the homogeneous correction of every sample
+ *                 from the lane's incoming state (Eq. (11)); about 7 FMAs per
+ *                 sample and section and a lane-sequential chain of N FMAs.
+ * Both share the cross-lane scan, the decoupled lookback, the tables and the
+ * state conventions, and accept every tile and compute type. SOS_ALG_DEFAULT
+ * (0) restores the default: SOS_ALG in the environment ("ph" or "dccr"),
+ * else DC-CR. Applies to later launches of the handle (plain, batched,
+ * captured batches and servers created afterwards); the adjoint kernel's
+ * recursive pass always uses DC-CR. sos_get_algorithm returns the solver in
+ * effect (SOS_ALG_DCCR or SOS_ALG_PH), or SOS_EINVAL for a null handle. */
+enum { SOS_ALG_DEFAULT = 0, SOS_ALG_DCCR = 1, SOS_ALG_PH = 2 };
+int sos_set_algorithm(sos_handle_t h, int alg);
+int sos_get_algorithm(sos_handle_t h);
+
+/* Bound on each lookback wait (Sec. IV-B's decoupled lookback spins on its
  * predecessors' descriptors): `ms` milliseconds of the device wall clock
  * (0 restores the default, 2000 ms, or SOS_TIMEOUT_MS at sos_create). A wait
  * that exceeds it poisons the group's outputs with NaN, still publishes so

@@ -27,6 +27,12 @@ SOS_ETIMEOUT = -6
 SOS_ECLOSED = -7
 SOS_EBUSY = -8
 SOS_MAX_SECTIONS = 64
+SOS_ALG_DEFAULT = 0
+SOS_ALG_DCCR = 1
+SOS_ALG_PH = 2
+_ALGS = {None: SOS_ALG_DEFAULT, "default": SOS_ALG_DEFAULT, "dccr": SOS_ALG_DCCR,
+         "ph": SOS_ALG_PH, SOS_ALG_DEFAULT: SOS_ALG_DEFAULT, SOS_ALG_DCCR: SOS_ALG_DCCR,
+         SOS_ALG_PH: SOS_ALG_PH}
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -67,6 +73,8 @@ def lib():
             L.sos_set_timeout.argtypes = [vp, ctypes.c_double]
             L.sos_wall_clock_khz.argtypes = [vp]
             L.sos_get_precision.argtypes = [vp]
+            L.sos_set_algorithm.argtypes = [vp, i32]
+            L.sos_get_algorithm.argtypes = [vp]
             L.sos_filter_train.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp, vp]
             L.sos_filter_vjp.argtypes = [vp, vp, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
             u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -110,7 +118,8 @@ def lib():
                          "sos_get_tile", "sos_filter", "sos_debug_carries", "sos_prepare",
                          "sos_filter_prepared", "sos_bench_copy", "sos_filter_batched",
                          "sos_filter_train", "sos_filter_vjp", "sos_set_precision",
-                         "sos_get_precision", "sos_set_timeout", "sos_wall_clock_khz"):
+                         "sos_get_precision", "sos_set_timeout", "sos_wall_clock_khz",
+                         "sos_set_algorithm", "sos_get_algorithm"):
                 getattr(L, name).restype = i32
             _lib = L
     return _lib
@@ -137,7 +146,7 @@ def _stream_ptr(device=None):
 class Handle:
     """Owns a libsosfilt handle (workspace: tables, lookback descriptors)."""
 
-    def __init__(self, device: int = 0, tile=None, precision: int = 0):
+    def __init__(self, device: int = 0, tile=None, precision: int = 0, algorithm=None):
         self._h = ctypes.c_void_p()
         self.device = int(device)
         _check(lib().sos_create(ctypes.byref(self._h), self.device), "sos_create")
@@ -145,6 +154,20 @@ class Handle:
             self.set_tile(*tile)
         if precision:
             self.set_precision(precision)
+        if algorithm:
+            self.set_algorithm(algorithm)
+
+    def set_algorithm(self, alg):
+        """Section solver: "dccr" (cyclic reduction), "ph" (particular +
+        homogeneous), or None / "default"."""
+        code = _ALGS.get(alg if not isinstance(alg, str) else alg.lower())
+        if code is None:
+            raise ValueError("unknown algorithm %r" % (alg,))
+        _check(lib().sos_set_algorithm(self._h, code), "sos_set_algorithm")
+
+    def algorithm(self) -> str:
+        code = int(lib().sos_get_algorithm(self._h))
+        return {SOS_ALG_DCCR: "dccr", SOS_ALG_PH: "ph"}[code]
 
     def set_precision(self, bits: int):
         """Compute type of the kernels: 32 or 64 (0 = default)."""

@@ -2,10 +2,12 @@
 libsosfilt.so next to this file (in-tree, so it travels with the sources)."""
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -29,13 +31,28 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel (one hipcc each), then
+    link the shared library; the library is replaced only on success."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    srcs = sources()
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    subprocess.check_call(cmd)
+    with tempfile.TemporaryDirectory(prefix="sosfilt_build_") as d:
+        objs = [os.path.join(d, os.path.basename(src) + ".o") for src in srcs]
+        cmds = [[hipcc, *flags, *inc, "-c", "-o", o, src] for src, o in zip(srcs, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), file=sys.stderr)
+        jobs = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            for c, rc in zip(cmds, ex.map(subprocess.call, cmds)):
+                if rc != 0:
+                    raise subprocess.CalledProcessError(rc, c)
+        link = [hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(link), file=sys.stderr)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

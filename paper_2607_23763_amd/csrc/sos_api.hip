@@ -98,8 +98,9 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
     if (rc) return rc;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_fwd(bits, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
-                       h->timeout_ticks, grid_of(bits, L, N), saved, stream) != hipSuccess)
+    const int alg = alg_of(h);
+    if (sos_launch_fwd(bits, alg, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
+                       h->timeout_ticks, grid_of(bits, alg, L, N), saved, stream) != hipSuccess)
         return SOS_EHIP;
     h->last_groups = groups;
     h->last_K = K;
@@ -174,9 +175,10 @@ int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
                              ba.zf, h->ctrl, stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    int64_t grid = grid_of(bits, t.L, t.N);
+    const int alg = alg_of(h);
+    int64_t grid = grid_of(bits, alg, t.L, t.N);
     if (grid <= 0 || grid > max_groups) grid = max_groups;
-    if (sos_launch_fwd_batched(bits, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
+    if (sos_launch_fwd_batched(bits, alg, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
                                h->sigmap, h->total_dev, ba.x, ba.y, h->tabs, ba.zi, ba.zf,
                                h->desc, h->ctrl, h->timeout_ticks, grid, nullptr, nullptr,
                                ba.saved, ba.total_samples, max_groups, stream) != hipSuccess)
@@ -321,6 +323,20 @@ int sos_get_precision(sos_handle_t h)
 {
     if (!h) return SOS_EINVAL;
     return bits_of(h);
+}
+
+int sos_set_algorithm(sos_handle_t h, int alg)
+{
+    if (!h || (alg != SOS_ALG_DEFAULT && alg != SOS_ALG_DCCR && alg != SOS_ALG_PH))
+        return SOS_EINVAL;
+    h->alg = alg;
+    return SOS_OK;
+}
+
+int sos_get_algorithm(sos_handle_t h)
+{
+    if (!h) return SOS_EINVAL;
+    return alg_of(h) == ALG_PH ? SOS_ALG_PH : SOS_ALG_DCCR;
 }
 
 int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream)

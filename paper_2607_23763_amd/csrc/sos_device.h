@@ -28,6 +28,10 @@ enum : int {
 };
 enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u, ERRBIT_BADARG = 8u };
 
+// Per-section solver of the filter kernel: divide-and-conquer cyclic
+// reduction, or PH (particular solution + homogeneous correction).
+enum : int { ALG_DCCR = 0, ALG_PH = 1 };
+
 // Per-section coefficient table (FP32 values computed in FP64 on the device)
 // for one group shape: L = 64*W lanes in W waves, N samples per lane,
 // C = L*N samples per group. Uniform entries are read with scalar loads; the

@@ -30,6 +30,14 @@
 //      g[n-1] s2 (no divisions).
 // The section output stays in registers as the next section's input.
 //
+// The PH variant (Sec. II-C, Sec. IV-E) replaces steps 1-2 by the lane's
+// particular solution (the section run over the lane's samples from rest,
+// whose end state is directly the lane's zero-state terminal state) and the
+// back substitution of step 5 by the homogeneous correction y[m] += g[m] s1 +
+// g[m-1] s2 on every sample; steps 3-4 are shared. About 7 operations per
+// sample and section instead of about 9, and one lane-sequential chain of N
+// dependent FMAs instead of the reduction's log-depth levels.
+//
 // Compute type T: float, or double for lightly damped / high-order cascades
 // (MI355X issues FP64 FMAs at the same rate as unpacked FP32 FMAs; the cost
 // is registers). Data in HBM, LDS staging and descriptor values are FP32.
@@ -439,7 +447,7 @@ struct SecState {
     T g1, g2;     // the group's local carry (lookback wave, wave-uniform)
 };
 
-template <typename T, int N, int W, bool PAIR>
+template <typename T, int N, int W, bool PAIR, int ALG>
 __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
                                            const FwdArgs &a, const Item<T> &it, const T *tabv,
                                            int s, unsigned epoch, int wv, int lane, bool has_last,
@@ -459,31 +467,53 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
         }
     }
 
-    // --- 1. level-1 right-hand side, in place from the end
-    const T c0 = tab[OFF_TAPS + 0], c1 = tab[OFF_TAPS + 1], c2 = tab[OFF_TAPS + 2];
-    const T c3 = tab[OFF_TAPS + 3], c4 = tab[OFF_TAPS + 4];
+    if (ALG == ALG_PH) {
+        // --- 1-2 (PH). Particular solution (Sec. II-C, Eq. (9)): the lane's
+        // own samples through the section from rest, feedforward B(z) (in
+        // place from the end), then the recursion 1/A(z) (in place from the
+        // start; one FMA of dependency per sample). Nothing crosses lanes;
+        // the lane's incoming state enters only in the correction.
+        const T a1 = tab[OFF_A1], a2 = tab[OFF_A2];
+        if (!PAIR) {
+            const T b0 = tab[OFF_TAPS + 0], b1 = tab[OFF_B1], b2 = tab[OFF_B2];
 #pragma unroll
-    for (int m = N - 1; m >= 0; --m) {
-        T r = c0 * u[m];
-        if (m >= 1) r = fmaT(c1, u[m - 1], r);
-        if (m >= 2) r = fmaT(c2, u[m - 2], r);
-        if (m >= 3) r = fmaT(c3, u[m - 3], r);
-        if (m >= 4) r = fmaT(c4, u[m - 4], r);
-        u[m] = r;
-    }
-
-    // --- 2. reduction of both parity chains (positions that stay, descending)
+            for (int m = N - 1; m >= 0; --m) {
+                T r = b0 * u[m];
+                if (m >= 1) r = fmaT(b1, u[m - 1], r);
+                if (m >= 2) r = fmaT(b2, u[m - 2], r);
+                u[m] = r;
+            }
+        }
+        u[1] = fmaT(-a1, u[0], u[1]);
 #pragma unroll
-    for (int i = 1; i < LOG; ++i) {
-        const int st2 = 1 << i;
-        const T e = tab[OFF_E + i], f = tab[OFF_F + i];
+        for (int m = 2; m < N; ++m) u[m] = fmaT(-a1, u[m - 1], fmaT(-a2, u[m - 2], u[m]));
+    } else {
+        // --- 1. level-1 right-hand side, in place from the end
+        const T c0 = tab[OFF_TAPS + 0], c1 = tab[OFF_TAPS + 1], c2 = tab[OFF_TAPS + 2];
+        const T c3 = tab[OFF_TAPS + 3], c4 = tab[OFF_TAPS + 4];
 #pragma unroll
         for (int m = N - 1; m >= 0; --m) {
-            if (((m + 1) % (2 * st2)) == 0 || ((m + 2) % (2 * st2)) == 0) {
-                T r = u[m];
-                if (m - st2 >= 0) r = fmaT(-e, u[m - st2], r);
-                if (m - 2 * st2 >= 0) r = fmaT(f, u[m - 2 * st2], r);
-                u[m] = r;
+            T r = c0 * u[m];
+            if (m >= 1) r = fmaT(c1, u[m - 1], r);
+            if (m >= 2) r = fmaT(c2, u[m - 2], r);
+            if (m >= 3) r = fmaT(c3, u[m - 3], r);
+            if (m >= 4) r = fmaT(c4, u[m - 4], r);
+            u[m] = r;
+        }
+
+        // --- 2. reduction of both parity chains (positions that stay, descending)
+#pragma unroll
+        for (int i = 1; i < LOG; ++i) {
+            const int st2 = 1 << i;
+            const T e = tab[OFF_E + i], f = tab[OFF_F + i];
+#pragma unroll
+            for (int m = N - 1; m >= 0; --m) {
+                if (((m + 1) % (2 * st2)) == 0 || ((m + 2) % (2 * st2)) == 0) {
+                    T r = u[m];
+                    if (m - st2 >= 0) r = fmaT(-e, u[m - st2], r);
+                    if (m - 2 * st2 >= 0) r = fmaT(f, u[m - 2 * st2], r);
+                    u[m] = r;
+                }
             }
         }
     }
@@ -540,7 +570,7 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
 //   carry the wait's jitter into the next group's aggregate), and every wave
 //   passes it to on_next right after the broadcast, so that the next group's
 //   loads overlap this group's correction and store.
-template <typename T, int N, int W, bool PAIR, typename OnNext = NoNext>
+template <typename T, int N, int W, bool PAIR, int ALG, typename OnNext = NoNext>
 __device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *tl,
                                              const FwdArgs &a, const Item<T> &it, const T *tabv,
                                              int s, unsigned epoch, int wv, int lane,
@@ -595,19 +625,26 @@ __device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *t
     const T s2 = PAIR ? -a2 * q2 : q2;
     ctabT<T> *g = tab + OFF_G + 1;   // g[-1] is readable and 0
 
-    u[N - 1] = fmaT(g[N - 1], s1, fmaT(g[N - 2], s2, u[N - 1]));
-    u[N - 2] = fmaT(g[N - 2], s1, fmaT(g[N - 3], s2, u[N - 2]));
+    if (ALG == ALG_PH) {
+        // homogeneous correction (Eq. (11)): the incoming state's free
+        // response, added to every sample independently
 #pragma unroll
-    for (int i = LOG - 1; i >= 1; --i) {
-        const int st2 = 1 << i;
-        const T e = tab[OFF_E + i], f = tab[OFF_F + i];
+        for (int m = 0; m < N; ++m) u[m] = fmaT(g[m], s1, fmaT(g[m - 1], s2, u[m]));
+    } else {
+        u[N - 1] = fmaT(g[N - 1], s1, fmaT(g[N - 2], s2, u[N - 1]));
+        u[N - 2] = fmaT(g[N - 2], s1, fmaT(g[N - 3], s2, u[N - 2]));
 #pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            const int m0 = st2 - 1 - par;                 // odd chain, then even chain
-            u[m0] = fmaT(g[m0], s1, fmaT(g[m0 - 1], s2, u[m0]));
+        for (int i = LOG - 1; i >= 1; --i) {
+            const int st2 = 1 << i;
+            const T e = tab[OFF_E + i], f = tab[OFF_F + i];
 #pragma unroll
-            for (int m = m0 + 2 * st2; m < N; m += 2 * st2)
-                u[m] = fmaT(-e, u[m - st2], fmaT(-f, u[m - 2 * st2], u[m]));
+            for (int par = 0; par < 2; ++par) {
+                const int m0 = st2 - 1 - par;                 // odd chain, then even chain
+                u[m0] = fmaT(g[m0], s1, fmaT(g[m0 - 1], s2, u[m0]));
+#pragma unroll
+                for (int m = m0 + 2 * st2; m < N; m += 2 * st2)
+                    u[m] = fmaT(-e, u[m - st2], fmaT(-f, u[m - 2 * st2], u[m]));
+            }
         }
     }
 
@@ -629,7 +666,7 @@ __device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *t
 }
 
 // Both halves back to back. On return (q1, q2) is the lane's incoming carry.
-template <typename T, int N, int W, bool PAIR, typename OnNext = NoNext>
+template <typename T, int N, int W, bool PAIR, int ALG = ALG_DCCR, typename OnNext = NoNext>
 __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl,
                                             const FwdArgs &a, const Item<T> &it, const T *tabv,
                                             int s, unsigned epoch, int wv, int lane, bool has_last,
@@ -637,9 +674,10 @@ __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl
                                             const OnNext &on_next = OnNext())
 {
     SecState<T> st;
-    section_zs<T, N, W, PAIR>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl, zp, st);
-    section_corr<T, N, W, PAIR>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl, zp,
-                                st, q1, q2, draw, on_next);
+    section_zs<T, N, W, PAIR, ALG>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl, zp,
+                                   st);
+    section_corr<T, N, W, PAIR, ALG>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl,
+                                     zp, st, q1, q2, draw, on_next);
 }
 
 // ---------------------------------------------------------------- wave tile
@@ -835,7 +873,7 @@ __device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, in
 // Everything after the wave's samples are in registers: the K sections, then
 // registers -> the wave's LDS rows -> coalesced 128-bit global stores. With
 // draw set, the last section draws the next ticket and calls on_next with it.
-template <typename T, int N, int W, typename OnNext>
+template <typename T, int N, int W, int ALG, typename OnNext>
 __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it, T (&u)[N],
                                              float *tl, Xch<T, W> &xch, unsigned epoch, int wv,
                                              int lane, bool draw, const OnNext &on_next)
@@ -859,16 +897,17 @@ __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it
         const int kl = draw ? it.K - 1 : it.K;
         for (int s = 0; s < kl; ++s) {
             T q1, q2;
-            run_section<T, N, W, false>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s,
-                                        epoch, wv, lane, has_last, zl, zp, q1, q2);
+            run_section<T, N, W, false, ALG>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS,
+                                             s, epoch, wv, lane, has_last, zl, zp, q1, q2);
             if (it.saved && s + 1 < it.K)
                 store_rows<T, N>(u, tl, lane, it.n, g0, it.saved + (size_t)s * a.saved_stride);
         }
         if (draw && it.K > 0) {
             const int s = it.K - 1;
             T q1, q2;
-            run_section<T, N, W, false>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS, s,
-                                        epoch, wv, lane, has_last, zl, zp, q1, q2, true, on_next);
+            run_section<T, N, W, false, ALG>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS,
+                                             s, epoch, wv, lane, has_last, zl, zp, q1, q2, true,
+                                             on_next);
         }
     } else {
 #pragma unroll
@@ -903,7 +942,7 @@ constexpr int min_waves_per_simd()
 // the group index, so a group's predecessors were drawn (and are being worked
 // on) before it, which guarantees forward progress of the lookback whatever
 // the grid size (Sec. IV-A).
-template <typename T, int N, int W>
+template <typename T, int N, int W, int ALG>
 __global__ void __launch_bounds__(64 * W)
     __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<T, N, W>())))
     sos_fwd_kernel(FwdArgs a)
@@ -962,7 +1001,7 @@ __global__ void __launch_bounds__(64 * W)
                 tile_fetch<N>(nf, ni.x + h0, ni.n - h0, lane);
             }
         };
-        finish_group<T, N, W>(a, it, u, tl, xch, epoch, wv, lane, draw, on_next);
+        finish_group<T, N, W, ALG>(a, it, u, tl, xch, epoch, wv, lane, draw, on_next);
 #pragma unroll
         for (int j = 0; j < N / 4; ++j) pf[j] = nf[j];
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
@@ -1349,19 +1388,24 @@ sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, const int
 // ------------------------------------------------------------------ launch
 
 template <typename T, int N, int W>
-hipError_t launch_fwd(const FwdArgs &a, int64_t grid, hipStream_t stream)
+hipError_t launch_fwd(int alg, const FwdArgs &a, int64_t grid, hipStream_t stream)
 {
-    hipLaunchKernelGGL((sos_fwd_kernel<T, N, W>), dim3((unsigned)grid), dim3(64 * W), 0, stream,
-                       a);
+    if (alg == ALG_PH)
+        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_PH>), dim3((unsigned)grid), dim3(64 * W),
+                           0, stream, a);
+    else
+        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_DCCR>), dim3((unsigned)grid),
+                           dim3(64 * W), 0, stream, a);
     return hipGetLastError();
 }
 
 template <typename T, int N, int W>
-int capacity_of()
+int capacity_of(int alg)
 {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sos_fwd_kernel<T, N, W>, 64 * W,
-                                                     0) != hipSuccess)
+    const void *kern = alg == ALG_PH ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH>
+                                     : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, 0) != hipSuccess)
         per_cu = 1;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1374,14 +1418,14 @@ int capacity_of()
     X(16, 1) X(32, 1) X(64, 1) X(16, 4) X(32, 4) X(64, 4) X(16, 8) X(32, 8) X(64, 8)    \
         X(16, 16) X(32, 16)
 
-hipError_t dispatch_fwd(int bits, int L, int N, const FwdArgs &a, int64_t grid,
+hipError_t dispatch_fwd(int bits, int alg, int L, int N, const FwdArgs &a, int64_t grid,
                         hipStream_t stream)
 {
     const int W = L / 64;
 #define SOS_CASE(NN, WW)                                                                  \
     if (N == NN && W == WW)                                                               \
-        return bits == 64 ? launch_fwd<double, NN, WW>(a, grid, stream)                   \
-                          : launch_fwd<float, NN, WW>(a, grid, stream);
+        return bits == 64 ? launch_fwd<double, NN, WW>(alg, a, grid, stream)              \
+                          : launch_fwd<float, NN, WW>(alg, a, grid, stream);
     SOS_SHAPES(SOS_CASE)
 #undef SOS_CASE
     return hipErrorInvalidValue;
@@ -1401,21 +1445,22 @@ extern "C" int sos_fwd_shape_supported(int L, int N)
 }
 
 // Workgroups of shape (L, N) that can be resident on the whole device at once.
-extern "C" int sos_fwd_capacity(int bits, int L, int N)
+extern "C" int sos_fwd_capacity(int bits, int alg, int L, int N)
 {
     const int W = L / 64;
 #define SOS_CASE(NN, WW)                                                                  \
-    if (N == NN && W == WW) return bits == 64 ? capacity_of<double, NN, WW>()              \
-                                              : capacity_of<float, NN, WW>();
+    if (N == NN && W == WW) return bits == 64 ? capacity_of<double, NN, WW>(alg)           \
+                                              : capacity_of<float, NN, WW>(alg);
     SOS_SHAPES(SOS_CASE)
 #undef SOS_CASE
     return 0;
 }
 
 // Plain filter of one signal; grid <= 0 means one workgroup per group.
-extern "C" hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, float *y, int64_t n,
-                                     int64_t groups, const void *tabs, int K, const float *zi,
-                                     float *zf, unsigned long long *desc, unsigned *ctrl,
+extern "C" hipError_t sos_launch_fwd(int bits, int alg, int L, int N, const float *x, float *y,
+                                     int64_t n, int64_t groups, const void *tabs, int K,
+                                     const float *zi, float *zf, unsigned long long *desc,
+                                     unsigned *ctrl,
                                      unsigned long long timeout_ticks, int64_t grid, float *saved,
                                      hipStream_t stream)
 {
@@ -1436,12 +1481,12 @@ extern "C" hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, flo
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
     if (grid <= 0 || grid > groups) grid = groups;
-    return dispatch_fwd(bits, L, N, a, grid, stream);
+    return dispatch_fwd(bits, alg, L, N, a, grid, stream);
 }
 
 // Uneven batch in one persistent launch. The work table (gpre, sigmap,
 // *total_dev) is produced on the device by sos_launch_worktable.
-extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax,
+extern "C" hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, int B, int kmax,
                                              const int32_t *Ks, const int32_t *sec_off,
                                              const int64_t *sig_off, const int64_t *gpre,
                                              const int32_t *sigmap, const int64_t *total_dev,
@@ -1475,7 +1520,7 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int 
     a.dstride = max_groups;
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
-    return dispatch_fwd(bits, L, N, a, grid, stream);
+    return dispatch_fwd(bits, alg, L, N, a, grid, stream);
 }
 
 // Launch the adjoint kernel of shape (L, N) in the compute type; grid <= 0:

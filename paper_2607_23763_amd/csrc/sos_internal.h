@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <cstring>
 #include <mutex>
 
 #include "sosfilt.h"
@@ -20,13 +21,13 @@ hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int k
                                    int log2w, void *tabs, unsigned *ctrl, int pair,
                                    hipStream_t stream);
 hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
-hipError_t sos_launch_fwd(int bits, int L, int N, const float *x, float *y, int64_t n,
+hipError_t sos_launch_fwd(int bits, int alg, int L, int N, const float *x, float *y, int64_t n,
                           int64_t groups, const void *tabs, int K, const float *zi, float *zf,
                           unsigned long long *desc, unsigned *ctrl,
                           unsigned long long timeout_ticks, int64_t grid, float *saved,
                           hipStream_t stream);
-hipError_t sos_launch_fwd_batched(int bits, int L, int N, int B, int kmax, const int32_t *Ks,
-                                  const int32_t *sec_off, const int64_t *sig_off,
+hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, int B, int kmax,
+                                  const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                                   const int64_t *gpre, const int32_t *sigmap,
                                   const int64_t *total_dev, const float *x, float *y,
                                   const void *tabs, const float *zi, float *zf,
@@ -70,7 +71,7 @@ hipError_t sos_launch_bwd_reduce(const double *partials, int64_t groups, int K,
 hipError_t sos_launch_fill(float *dst, const float *src, int64_t count, hipStream_t stream);
 hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
 int sos_fwd_shape_supported(int L, int N);
-int sos_fwd_capacity(int bits, int L, int N);
+int sos_fwd_capacity(int bits, int alg, int L, int N);
 int sos_bwd_shape_supported(int L, int N);
 }
 
@@ -79,6 +80,7 @@ struct sos_ctx {
     int tile_L = 0;                       // lanes per group L = 64 W; 0 = default
     int tile_N = 0;                       // samples per lane N; 0 = default
     int bits = 0;                         // compute type: 32, 64; 0 = default
+    int alg = 0;                          // section solver: SOS_ALG_*; 0 = default
     unsigned *ctrl = nullptr;             // CTRL_WORDS
     unsigned char *tabs = nullptr;        // coefficient tables (bytes)
     size_t tabs_cap = 0;
@@ -163,6 +165,18 @@ inline int bits_of(const sos_ctx *h)
     return kDefaultBits;
 }
 
+// Section solver of the filter kernels (ALG_DCCR or ALG_PH): the handle's
+// choice, else SOS_ALG in the environment ("ph" or "dccr"), else DC-CR.
+inline int alg_of(const sos_ctx *h)
+{
+    if (h->alg == SOS_ALG_PH) return sosdev::ALG_PH;
+    if (h->alg == SOS_ALG_DCCR) return sosdev::ALG_DCCR;
+    if (const char *e = std::getenv("SOS_ALG")) {
+        if (!std::strcmp(e, "ph") || !std::strcmp(e, "PH")) return sosdev::ALG_PH;
+    }
+    return sosdev::ALG_DCCR;
+}
+
 // SOS_GRID: exactly this many workgroups for every persistent launch, or 0
 // (tests: many groups per workgroup).
 inline int64_t grid_override()
@@ -174,12 +188,12 @@ inline int64_t grid_override()
     return 0;
 }
 
-inline int64_t grid_of(int bits, int L, int N)
+inline int64_t grid_of(int bits, int alg, int L, int N)
 {
     // persistent grid: as many workgroups as can be resident, drawing tickets
     // until the groups run out (measured faster than one workgroup per group)
     if (const int64_t g = grid_override()) return g;
-    int64_t grid = sos_fwd_capacity(bits, L, N);
+    int64_t grid = sos_fwd_capacity(bits, alg, L, N);
     if (const char *e = std::getenv("SOS_PERSISTENT")) {
         const int f = std::atoi(e);
         grid = f > 0 ? (int64_t)f * grid : 0;   // 0: one workgroup per group

@@ -132,7 +132,7 @@ struct sos_srv {
     hipStream_t stream = nullptr;     // steps
     hipStream_t ostream = nullptr;    // stream opening (table preparation)
     unsigned *octrl = nullptr;        // error word of the preparation launches
-    int device = 0, L = 0, N = 0, bits = 32;
+    int device = 0, L = 0, N = 0, bits = 32, alg = 0;
     int64_t C = 0;
     int max_slots = 0;
     int64_t max_rows = 0, max_groups = 0, max_step_samples = 0;
@@ -257,7 +257,7 @@ void launch_step(sos_srv *s, Step &st)
     // chunk adds at most one partial group): a step of a few chunks launches
     // a few workgroups, not a device-filling grid that mostly exits at once
     const int64_t step_groups = total / s->C + B;
-    int64_t grid = grid_of(s->bits, s->L, s->N);
+    int64_t grid = grid_of(s->bits, s->alg, s->L, s->N);
     if (grid <= 0 || grid > s->max_groups) grid = s->max_groups;
     if (grid > step_groups) grid = step_groups;
     // Four launches, no copy operations: the work-table kernel copies the
@@ -267,7 +267,7 @@ void launch_step(sos_srv *s, Step &st)
         sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total, s->max_groups, dK, dsec,
                                     dsig, h->gpre, h->sigmap, h->total_dev, s->state, s->state,
                                     h->ctrl, hb, d, (int64_t)lb.bytes, s->stream) == hipSuccess &&
-        sos_launch_fwd_batched(s->bits, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
+        sos_launch_fwd_batched(s->bits, s->alg, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
                                h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
                                s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
                                nullptr, 0, s->max_groups, s->stream) == hipSuccess &&
@@ -386,6 +386,7 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
     s->L = t.L;
     s->N = t.N;
     s->bits = bits_of(hu);
+    s->alg = alg_of(hu);
     s->h->timeout_ticks = hu->timeout_ticks;
     s->C = (int64_t)t.L * t.N;
     s->max_slots = max_slots;

@@ -28,16 +28,17 @@ struct sos_graph {
 
 namespace {
 
-// Tuner cache: (compute type, kmax, batch size, log2 of total samples) -> tile.
+// Tuner cache: (compute type and section solver, kmax, batch size, log2 of
+// total samples) -> tile.
 using TuneKey = std::tuple<int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tile> g_tune_cache;
 
-TuneKey key_of(int bits, const BatchArgs &ba)
+TuneKey key_of(const sos_ctx *h, const BatchArgs &ba)
 {
     int lg = 0;
     while (lg < 62 && ((int64_t)1 << (lg + 1)) <= ba.total_samples) ++lg;
-    return TuneKey{bits, ba.kmax, ba.B, lg};
+    return TuneKey{bits_of(h) * 2 + alg_of(h), ba.kmax, ba.B, lg};
 }
 
 void destroy_graph(sos_graph *g)
@@ -97,6 +98,7 @@ int sos_graph_create_batched(sos_graph_t *out, sos_handle_t hu, int B, int kmax,
     g->h->tile_L = t.L;
     g->h->tile_N = t.N;
     g->h->bits = bits;
+    g->h->alg = hu->alg;
     g->h->timeout_ticks = hu->timeout_ticks;
     if (hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking) != hipSuccess) {
         destroy_graph(g);
@@ -237,7 +239,7 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
     h->tile_N = best.N;
     {
         std::lock_guard<std::mutex> tl(g_tune_mu);
-        g_tune_cache[key_of(bits, ba)] = best;
+        g_tune_cache[key_of(h, ba)] = best;
     }
     if (L_out) *L_out = best.L;
     if (N_out) *N_out = best.N;
@@ -252,7 +254,7 @@ int sos_tune_lookup(sos_handle_t h, int B, int kmax, int64_t total_samples, int 
     BatchArgs ba{B, kmax, 0, total_samples, nullptr, nullptr, nullptr, nullptr,
                  nullptr, nullptr, nullptr, nullptr};
     std::lock_guard<std::mutex> tl(g_tune_mu);
-    auto it = g_tune_cache.find(key_of(bits_of(h), ba));
+    auto it = g_tune_cache.find(key_of(h, ba));
     if (it == g_tune_cache.end()) return SOS_EINVAL;
     if (L_out) *L_out = it->second.L;
     if (N_out) *N_out = it->second.N;

@@ -124,10 +124,46 @@ def back_substitute(r, s_lane, c):
     return y
 
 
-def filter_model(sos, x, zi=None, N=8, L=4, window=3, seed=0):
+def lane_particular(u, c):
+    """PH (Sec. II-C): every lane's samples through the section from rest,
+    the feed-forward B(z) and then the recursion 1/A(z) of Eq. (9) with zero
+    history. Returns the particular solution w (L x N) and the lanes'
+    zero-state terminal TDF-II states t (L x 2)."""
+    b0, b1, b2, a1, a2 = c
+    L, N = u.shape
+    v = b0 * u
+    v[:, 1:] += b1 * u[:, :-1]
+    v[:, 2:] += b2 * u[:, :-2]
+    w = np.zeros_like(u)
+    for n in range(N):
+        w[:, n] = v[:, n]
+        if n >= 1:
+            w[:, n] -= a1 * w[:, n - 1]
+        if n >= 2:
+            w[:, n] -= a2 * w[:, n - 2]
+    t = np.stack([b1 * u[:, N - 1] + b2 * u[:, N - 2] - a1 * w[:, N - 1] - a2 * w[:, N - 2],
+                  b2 * u[:, N - 1] - a2 * w[:, N - 1]], axis=1)
+    return w, t
+
+
+def homogeneous_correct(w, s_lane, c):
+    """PH: add the free response of each lane's incoming TDF-II state (s1, s2)
+    to every sample, y[m] = w[m] + g[m] s1 + g[m-1] s2 (the role of Eq. (11))."""
+    a1, a2 = c[3], c[4]
+    N = w.shape[1]
+    g = np.r_[impulse_1_over_A(a1, a2, N), 0.0]      # g[-1] reads the trailing 0
+    m = np.arange(N)
+    return w + s_lane[:, 0:1] * g[m] + s_lane[:, 1:2] * g[m - 1]
+
+
+def filter_model(sos, x, zi=None, N=8, L=4, window=3, seed=0, solver="dccr"):
     """Whole cascade over a signal of any length with the kernel's algorithm.
     Groups resolve their incoming states by decoupled lookback under a random
-    interleaving of group progress. Returns (y, zf)."""
+    interleaving of group progress. solver: "dccr" (fold, two-chain reduction,
+    back substitution) or "ph" (particular solution, homogeneous correction);
+    the scan and the lookback are the same. Returns (y, zf)."""
+    zero_state, correct = ((lane_particular, homogeneous_correct) if solver == "ph"
+                           else (lane_zero_state, back_substitute))
     sos = np.asarray(sos, dtype=np.float64).reshape(-1, 6)
     K = sos.shape[0]
     x = np.asarray(x, dtype=np.float64)
@@ -159,7 +195,7 @@ def filter_model(sos, x, zi=None, N=8, L=4, window=3, seed=0):
         TC = np.linalg.matrix_power(TN, L)
         if ph == 0:
             u = data[g]
-            r, t = lane_zero_state(u, c)
+            r, t = zero_state(u, c)
             P = lane_scan(t, TN)
             local[g] = (u, r, P)
             if g == 0:
@@ -208,7 +244,7 @@ def filter_model(sos, x, zi=None, N=8, L=4, window=3, seed=0):
         Pexc = np.vstack([np.zeros(2), P[:-1]])
         pw = [np.linalg.matrix_power(TN, l) for l in range(L)]
         s_lane = np.stack([pw[l] @ s_in + Pexc[l] for l in range(L)])
-        y = back_substitute(r, s_lane, c)
+        y = correct(r, s_lane, c)
         if g == last:
             # state after sample n-1 of this section (not at the padded group end)
             l1, p1 = divmod(pos_last, N)

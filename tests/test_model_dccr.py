@@ -30,6 +30,40 @@ def test_model_matches_oracle(N, L, K):
         assert np.max(np.abs(zf - zfr)) < 1e-10 * max(1, np.max(np.abs(zfr))), (N, L, K, n)
 
 
+@pytest.mark.parametrize("N,L", [(2, 4), (4, 4), (8, 4), (16, 8), (32, 2), (8, 16)])
+@pytest.mark.parametrize("K", [1, 3])
+def test_ph_model_matches_oracle(N, L, K):
+    """The PH solver (particular solution from rest, then the homogeneous
+    correction from the scanned TDF-II carries) reproduces the oracle."""
+    rows = _rows(K, 200 + N + L + K)
+    g = np.random.default_rng(N * L + K + 7)
+    zi = g.normal(size=(K, 2))
+    for n in (1, 2, 3, N * L - 1, N * L, N * L + 1, 5 * N * L + 3):
+        x = g.normal(size=n)
+        y, zf = M.filter_model(rows, x, zi, N=N, L=L, window=3, seed=n, solver="ph")
+        yr, zfr = oracle.sosfilt(rows, x, zi)
+        assert np.max(np.abs(y - yr)) < 1e-10 * max(1, np.max(np.abs(yr))), (N, L, K, n)
+        assert np.max(np.abs(zf - zfr)) < 1e-10 * max(1, np.max(np.abs(zfr))), (N, L, K, n)
+
+
+def test_ph_correction_is_eq11_in_state_coordinates():
+    """Eq. (11) corrects the particular solution with u_{2,m} y[-2] + u_{1,m}
+    y[-1] (DF-I output history, u from powers of Phi); the kernel uses
+    g[m] s1 + g[m-1] s2 on the TDF-II state. With the input history folded
+    into the particular solution the two agree: for zero lane input, the
+    correction alone must equal the free response from (y[-2], y[-1])."""
+    b0, b1, b2, a1, a2 = 1.0, 0.0, 0.0, -1.2, 0.6
+    Phi = np.array([[0.0, 1.0], [-a2, -a1]])
+    ym2, ym1 = 0.7, -0.3
+    N = 12
+    # TDF-II state of a pure recursive section whose last outputs are (y[-2], y[-1])
+    s = np.array([[-(a1 * ym1 + a2 * ym2), -a2 * ym1]])
+    corr = M.homogeneous_correct(np.zeros((1, N)), s, (b0, b1, b2, a1, a2))[0]
+    u2 = np.array([-np.linalg.matrix_power(Phi, m + 1)[1, 0] for m in range(N)])
+    u1 = np.array([-np.linalg.matrix_power(Phi, m + 1)[1, 1] for m in range(N)])
+    assert np.allclose(corr, -(u2 * ym2 + u1 * ym1), atol=1e-14)
+
+
 def test_model_random_completion_orders():
     rows = _rows(4, 7)
     x = np.random.default_rng(8).normal(size=40 * 32 + 5)
