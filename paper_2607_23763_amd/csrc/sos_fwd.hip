@@ -727,7 +727,12 @@ __device__ __forceinline__ void tile_fetch(f4 (&t)[N / 4], const float *src, int
         for (int j = 0; j < N / 4; ++j) t[j] = __builtin_nontemporal_load(s4 + kLanes * j);
     } else {
         const auto g = gptr(src);
-        const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+        int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+        // The per-element bounds of a partial tile depend only on r; the
+        // empty asm keeps them in this (rare) branch. Otherwise the compiler
+        // merges them with tile_store's identical bounds and computes all of
+        // them for every group, parking the masks in spilled registers.
+        asm volatile("" : "+v"(r));
 #pragma unroll
         for (int j = 0; j < N / 4; ++j) {
             const int q = 4 * (kLanes * j + lane);
@@ -783,7 +788,8 @@ __device__ __forceinline__ void tile_store(float *dst, int64_t rem, const float 
         }
     } else {
         const auto g = gptr(dst);
-        const int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+        int r = rem <= 0 ? 0 : (rem >= kLanes * N ? kLanes * N : (int)rem);
+        asm volatile("" : "+v"(r));   // bounds stay in this branch (see tile_fetch)
 #pragma unroll
         for (int j = 0; j < TT::Q; ++j) {
             const int q = 4 * (kLanes * j + lane);
