@@ -123,10 +123,12 @@ int sos_get_precision(sos_handle_t h);
  * Both share the cross-lane scan, the decoupled lookback, the tables and the
  * state conventions, and accept every tile and compute type. SOS_ALG_DEFAULT
  * (0) restores the default: SOS_ALG in the environment ("ph" or "dccr"),
- * else DC-CR. Applies to later launches of the handle (plain, batched,
- * captured batches and servers created afterwards); the adjoint kernel's
- * recursive pass always uses DC-CR. sos_get_algorithm returns the solver in
- * effect (SOS_ALG_DCCR or SOS_ALG_PH), or SOS_EINVAL for a null handle. */
+ * else DC-CR. Applies to later launches of the handle: plain, batched,
+ * captured batches, servers created afterwards, and both passes of the
+ * adjoint (the training forward and the reversed-time recursion of the VJP).
+ * sos_set_algorithm returns SOS_EINVAL for an unknown value or a null
+ * handle; sos_get_algorithm returns the solver in effect (SOS_ALG_DCCR or
+ * SOS_ALG_PH), or SOS_EINVAL for a null handle. */
 enum { SOS_ALG_DEFAULT = 0, SOS_ALG_DCCR = 1, SOS_ALG_PH = 2 };
 int sos_set_algorithm(sos_handle_t h, int alg);
 int sos_get_algorithm(sos_handle_t h);

@@ -463,8 +463,9 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
                         stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_bwd(bits, t.L, t.N, gy, gx, n, groups, h->tabs_bwd, K, x, y, saved, gzf, gzi,
-                       h->partials, h->desc, h->ctrl, h->timeout_ticks, grid_override(), stream) != hipSuccess)
+    if (sos_launch_bwd(bits, alg_of(h), t.L, t.N, gy, gx, n, groups, h->tabs_bwd, K, x, y, saved,
+                       gzf, gzi, h->partials, h->desc, h->ctrl, h->timeout_ticks, grid_override(),
+                       stream) != hipSuccess)
         return SOS_EHIP;
     if (gsections &&
         sos_launch_bwd_reduce(h->partials, groups, K, sections, gsections, stream) != hipSuccess)
@@ -545,8 +546,8 @@ int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
                              stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_bwd_batched(bits, t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre, h->sigmap,
-                               h->total_dev, max_groups, gy, gx, h->tabs_bwd, x, y, saved,
+    if (sos_launch_bwd_batched(bits, alg_of(h), t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre,
+                               h->sigmap, h->total_dev, max_groups, gy, gx, h->tabs_bwd, x, y, saved,
                                total_samples, gzf, gzi, h->partials, h->desc, h->ctrl,
                                h->timeout_ticks, stream) != hipSuccess)
         return SOS_EHIP;

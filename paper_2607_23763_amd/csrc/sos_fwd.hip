@@ -1177,7 +1177,7 @@ __device__ __forceinline__ void rows_from_regs_rev(const T (&u)[N], float *tl, i
     }
 }
 
-template <typename T, int N, int W>
+template <typename T, int N, int W, int ALG>
 __global__ void __launch_bounds__(64 * W)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && W >= 4 ? 2 : 1)))
     sos_bwd_kernel(BwdArgs b)
@@ -1240,7 +1240,8 @@ __global__ void __launch_bounds__(64 * W)
             window_load<N>(k == it.K - 1 ? bi.y : bi.saved + (size_t)k * sst, f0, n, tl2, lane);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             T q1, q2;   // lam'[-2], lam'[-1] of this lane
-            run_section<T, N, W, true>(u, xch, tl, a, it, tabv, k, epoch, wv, lane, false, 0, 0,
+            run_section<T, N, W, true, ALG>(u, xch, tl, a, it, tabv, k, epoch, wv, lane, false, 0,
+                                            0,
                                        q1, q2);
             // coefficient sums over the lane (reversed position m = forward column N-1-m)
             T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
@@ -1531,8 +1532,8 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, in
 
 // Launch the adjoint kernel of shape (L, N) in the compute type; grid <= 0:
 // persistent (as many workgroups as can be resident), at most `groups`.
-static hipError_t launch_bwd_args(int bits, int L, int N, const BwdArgs &b, int64_t groups,
-                           int64_t grid, hipStream_t stream)
+static hipError_t launch_bwd_args(int bits, int alg, int L, int N, const BwdArgs &b,
+                                  int64_t groups, int64_t grid, hipStream_t stream)
 {
     const int W = L / 64;
     // grid <= 0: persistent, as many workgroups as can be resident
@@ -1547,20 +1548,19 @@ static hipError_t launch_bwd_args(int bits, int L, int N, const BwdArgs &b, int6
             cus = 256;
         return (int64_t)per_cu * cus;
     };
+    auto launch = [&](auto kern, int threads) {
+        if (grid <= 0) grid = resident((const void *)kern, threads);
+        if (grid > groups) grid = groups;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), 0, stream, b);
+        return hipGetLastError();
+    };
 #define SOS_BWD_CASE(NN, WW)                                                                   \
     if (N == NN && W == WW) {                                                                  \
-        if (bits == 64) {                                                                      \
-            if (grid <= 0) grid = resident((const void *)sos_bwd_kernel<double, NN, WW>, 64 * WW); \
-            if (grid > groups) grid = groups;                                                  \
-            hipLaunchKernelGGL((sos_bwd_kernel<double, NN, WW>), dim3((unsigned)grid),        \
-                               dim3(64 * WW), 0, stream, b);                                   \
-        } else {                                                                               \
-            if (grid <= 0) grid = resident((const void *)sos_bwd_kernel<float, NN, WW>, 64 * WW); \
-            if (grid > groups) grid = groups;                                                  \
-            hipLaunchKernelGGL((sos_bwd_kernel<float, NN, WW>), dim3((unsigned)grid),         \
-                               dim3(64 * WW), 0, stream, b);                                   \
-        }                                                                                      \
-        return hipGetLastError();                                                              \
+        if (bits == 64)                                                                        \
+            return alg == ALG_PH ? launch(sos_bwd_kernel<double, NN, WW, ALG_PH>, 64 * WW)     \
+                                 : launch(sos_bwd_kernel<double, NN, WW, ALG_DCCR>, 64 * WW);  \
+        return alg == ALG_PH ? launch(sos_bwd_kernel<float, NN, WW, ALG_PH>, 64 * WW)          \
+                             : launch(sos_bwd_kernel<float, NN, WW, ALG_DCCR>, 64 * WW);       \
     }
     SOS_BWD_CASE(16, 1)
     SOS_BWD_CASE(32, 1)
@@ -1573,7 +1573,7 @@ static hipError_t launch_bwd_args(int bits, int L, int N, const BwdArgs &b, int6
 }
 
 // Adjoint of the plain filter: grid <= 0 means a persistent grid.
-extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx,
+extern "C" hipError_t sos_launch_bwd(int bits, int alg, int L, int N, const float *gy, float *gx,
                                      int64_t n, int64_t groups, const void *tabs, int K,
                                      const float *x, const float *y, const float *saved,
                                      const float *gzf, float *gzi, double *partials,
@@ -1598,12 +1598,12 @@ extern "C" hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, fl
     b.K = K;
     b.total = groups;
     b.timeout_ticks = timeout_ticks;
-    return launch_bwd_args(bits, L, N, b, groups, grid, stream);
+    return launch_bwd_args(bits, alg, L, N, b, groups, grid, stream);
 }
 
 // Batched adjoint: one persistent launch over the reversed groups of every
 // signal (work table built by sos_launch_worktable with the adjoint's C).
-extern "C" hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int kmax,
+extern "C" hipError_t sos_launch_bwd_batched(int bits, int alg, int L, int N, int B, int kmax,
                                              const int32_t *Ks, const int32_t *sec_off,
                                              const int64_t *sig_off, const int64_t *gpre,
                                              const int32_t *sigmap, const int64_t *total_dev,
@@ -1638,7 +1638,7 @@ extern "C" hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int 
     b.sigmap = sigmap;
     b.total_dev = total_dev;
     b.saved_stride = saved_stride;
-    return launch_bwd_args(bits, L, N, b, max_groups, 0, stream);
+    return launch_bwd_args(bits, alg, L, N, b, max_groups, 0, stream);
 }
 
 extern "C" hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax,

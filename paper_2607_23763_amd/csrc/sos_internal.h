@@ -35,8 +35,8 @@ hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, int B, int km
                                   unsigned long long timeout_ticks, int64_t grid,
                                   const float *const *xp, float *const *yp, float *saved,
                                   int64_t saved_stride, int64_t max_groups, hipStream_t stream);
-hipError_t sos_launch_bwd_batched(int bits, int L, int N, int B, int kmax, const int32_t *Ks,
-                                  const int32_t *sec_off, const int64_t *sig_off,
+hipError_t sos_launch_bwd_batched(int bits, int alg, int L, int N, int B, int kmax,
+                                  const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                                   const int64_t *gpre, const int32_t *sigmap,
                                   const int64_t *total_dev, int64_t max_groups, const float *gy,
                                   float *gx, const void *tabs, const float *x, const float *y,
@@ -61,7 +61,7 @@ hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows, int64_t C,
                                        unsigned *ctrl, const void *stage_src, void *stage_dst,
                                        int64_t stage_bytes, hipStream_t stream);
 hipError_t sos_launch_report_err(unsigned *ctrl_err, unsigned *host_err, hipStream_t stream);
-hipError_t sos_launch_bwd(int bits, int L, int N, const float *gy, float *gx, int64_t n,
+hipError_t sos_launch_bwd(int bits, int alg, int L, int N, const float *gy, float *gx, int64_t n,
                           int64_t groups, const void *tabs, int K, const float *x,
                           const float *y, const float *saved, const float *gzf, float *gzi,
                           double *partials, unsigned long long *desc, unsigned *ctrl,

@@ -300,6 +300,69 @@ def test_server_streams(env):
         assert rel_l2(states[s], zfr) <= zf_bound(int(Ks[s]), by, bz, yr, zfr), s
 
 
+@pytest.mark.parametrize("tile", [(64, 16), (256, 32), (512, 16)])
+@pytest.mark.parametrize("K,n", [(1, 5000), (4, 70001), (8, 1 << 16), (3, 1)])
+def test_vjp_with_ph(env, K, n, tile):
+    """Both passes with the PH solver (the training forward, then the
+    reversed-time recursion of the adjoint) against the oracle's VJP."""
+    torch, P = env
+    g = workloads.rng(300 + K + n % 97)
+    sos = workloads.random_stable_sos(K, g)
+    sos[0] *= 1.25                                       # a0 != 1
+    x = workloads.signal(n, seed=17)
+    zi = workloads.initial_state(K, g)
+    gy = workloads.signal(n, seed=18)
+    gzf = workloads.initial_state(K, g, var=1.0)
+    h = ph_handle(P, tile)
+    d = lambda a: dev(torch, np.asarray(a, np.float32))
+    y, zf, saved = P.sosfilt_train(d(x), d(sos), d(zi), handle=h)
+    gx, gzi, gs = P.sosfilt_vjp(d(sos), d(x), y, saved, d(gy), d(gzf), handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    rx, rzi, rs = oracle.sosfilt_vjp(sos, x, zi, gy, gzf)
+    print("ph vjp K", K, "n", n, "tile", tile, rel_l2(gx.cpu().numpy(), rx),
+          rel_l2(gzi.cpu().numpy(), rzi), rel_l2(gs.cpu().numpy(), rs))
+    assert rel_l2(gx.cpu().numpy(), rx) <= tol_for(K)
+    assert rel_l2(gzi.cpu().numpy(), rzi) <= tol_for(K)
+    assert rel_l2(gs.cpu().numpy(), rs) <= 1e-4
+
+
+def test_batched_vjp_with_ph(env):
+    """Uneven batch (empty and one-sample signals included), training forward
+    and VJP in one launch each with the PH solver, against the oracle."""
+    torch, P = env
+    g = workloads.rng(310)
+    B = 24
+    Ks = g.integers(1, 5, size=B).astype(np.int32)
+    Ks[3] = 2
+    lens = np.floor(2.0 ** g.uniform(0, 15, size=B)).astype(np.int64)
+    lens[5], lens[9] = 0, 1
+    sig_off = np.r_[0, np.cumsum(lens)].astype(np.int64)
+    rows = np.concatenate([workloads.random_stable_sos(int(k), g) for k in Ks]).astype(np.float32)
+    zi = workloads.initial_state(int(Ks.sum()), g)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=311)
+    gy = workloads.batch_signal(int(sig_off[-1]), seed=312)
+    gzf = workloads.initial_state(int(Ks.sum()), g, var=1.0)
+    h = ph_handle(P, (256, 32))
+    y, zf, saved = P.sosfilt_train_batched(dev(torch, x), dev(torch, rows), dev(torch, Ks),
+                                           dev(torch, sig_off), zi=dev(torch, zi), handle=h)
+    gx, gzi, gs = P.sosfilt_vjp_batched(dev(torch, rows), dev(torch, Ks), dev(torch, sig_off),
+                                        dev(torch, x), y, saved, dev(torch, gy),
+                                        gzf=dev(torch, gzf), handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    gx, gzi, gs = gx.cpu().numpy(), gzi.cpu().numpy(), gs.cpu().numpy()
+    so = np.r_[0, np.cumsum(Ks)]
+    for i in range(B):
+        a, b = sig_off[i], sig_off[i + 1]
+        r = slice(so[i], so[i + 1])
+        rx, rzi, rs = oracle.sosfilt_vjp(rows[r], x[a:b], zi[r], gy[a:b], gzf[r])
+        e = (rel_l2(gx[a:b], rx) if b > a else 0.0, rel_l2(gzi[r], rzi), rel_l2(gs[r], rs))
+        print("signal", i, "K", Ks[i], "n", b - a, e)
+        assert e[0] <= tol_for(int(Ks[i])), (i, e)
+        assert e[1] <= 1e-4 and e[2] <= 1e-4, (i, e)
+
+
 def test_training_forward_then_vjp(env):
     """The training forward (which also keeps every section's output) with the
     PH solver, then the adjoint: gradients equal the oracle's VJP."""
