@@ -151,7 +151,7 @@ def bench_batched(torch, P, workloads, np, log):
     h = P.Handle(0)
     (L, N), tune_ms, _, _ = P.tune_batched(x, rows_d, Kd, so, zi=zi_d, y=y, zf=zf, handle=h,
                                            reps=2)
-    log("batched: tuned tile", (L, N), "%.3f ms" % tune_ms)
+    log("batched: tuned tile", (L, N), h.algorithm(), "%.3f ms" % tune_ms)
     g = P.BatchGraph(x, rows_d, Kd, so, zi=zi_d, y=y, zf=zf, handle=h)
     for _ in range(2):
         g.launch()
@@ -168,7 +168,8 @@ def bench_batched(torch, P, workloads, np, log):
     gs = total / (ms * 1e-3) / 1e9
     out = {"workload": "4096 signals, lengths floor(2^U) U~U[10,22], K~U{1..8} random stable "
                        "SOS, zi~N(0,0.1)", "B": 4096, "samples": total,
-           "tile_L_N": [L, N], "ms": round(ms, 4), "GS_per_s": round(gs, 2),
+           "tile_L_N": [L, N], "section_solver": h.algorithm(), "ms": round(ms, 4),
+           "GS_per_s": round(gs, 2),
            "hbm_roof_frac": round(gs * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
            "graph": True}
     log("batched", out)

@@ -292,10 +292,13 @@ int sos_graph_destroy(sos_graph_t g);
  * padding model (a signal of n samples costs ceil(n / C) groups of C, so
  * tiles whose padded work exceeds 1.5x the best tile's are dropped), then
  * each survivor is timed (one warm-up, `reps` timed runs, median, HIP events
- * on `stream`). The fastest tile becomes h's tile and is cached per (compute
- * type, kmax, B, floor(log2 total_samples)) for sos_tune_lookup; y and zf
- * end up holding the winning tile's result. zi must not equal zf (the batch
- * runs several times). Synchronises `stream`. */
+ * on `stream`). When h has no section solver set (SOS_ALG_DEFAULT), every
+ * tile is timed with both solvers and the winning solver becomes h's too;
+ * otherwise only h's solver is timed. The fastest tile becomes h's tile and
+ * is cached per (compute type, requested solver, kmax, B, floor(log2
+ * total_samples)) for sos_tune_lookup (a default request is also cached under
+ * the winning solver); y and zf end up holding the winner's result. zi must
+ * not equal zf (the batch runs several times). Synchronises `stream`. */
 int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_t total_samples,
                      const int32_t *K, const int32_t *sec_off, const float *sections,
                      const int64_t *sig_off, const float *x, float *y, const float *zi,

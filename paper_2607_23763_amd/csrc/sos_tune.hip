@@ -28,8 +28,8 @@ struct sos_graph {
 
 namespace {
 
-// Tuner cache: (compute type and section solver, kmax, batch size, log2 of
-// total samples) -> tile.
+// Tuner cache: (compute type and requested section solver, kmax, batch size,
+// log2 of total samples) -> tile.
 using TuneKey = std::tuple<int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tile> g_tune_cache;
@@ -38,7 +38,7 @@ TuneKey key_of(const sos_ctx *h, const BatchArgs &ba)
 {
     int lg = 0;
     while (lg < 62 && ((int64_t)1 << (lg + 1)) <= ba.total_samples) ++lg;
-    return TuneKey{bits_of(h) * 2 + alg_of(h), ba.kmax, ba.B, lg};
+    return TuneKey{bits_of(h) * 4 + h->alg, ba.kmax, ba.B, lg};   // the solver as requested
 }
 
 void destroy_graph(sos_graph *g)
@@ -196,11 +196,24 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
         (void)hipEventDestroy(e0);
         return SOS_EHIP;
     }
+    // the section solvers to try: the handle's, or both when it has none set
+    const int requested = h->alg;
+    const TuneKey key_req = key_of(h, ba);
+    std::vector<int> algs;
+    if (requested == SOS_ALG_DEFAULT) {
+        algs.push_back(SOS_ALG_DCCR);
+        algs.push_back(SOS_ALG_PH);
+    } else {
+        algs.push_back(requested);
+    }
     Tile best{0, 0};
+    int best_alg = requested;
     float best_ms = 1e30f;
-    for (size_t c = 0; c < cand.size() && rc == SOS_OK; ++c) {
+    for (size_t k = 0; k < cand.size() * algs.size() && rc == SOS_OK; ++k) {
+        const size_t c = k / algs.size();
         if (padded[c] > 1.5 * best_pad) continue;
         const Tile t = cand[c];
+        h->alg = algs[k % algs.size()];
         rc = batch_reserve(h, t, bits, ba, stream);
         if (rc) break;
         rc = batch_enqueue(h, t, bits, ba, stream);   // warm-up
@@ -222,23 +235,31 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
         if (med < best_ms) {
             best_ms = med;
             best = t;
+            best_alg = h->alg;
         }
         if (std::getenv("SOS_TUNE_VERBOSE"))
-            std::fprintf(stderr, "sos_tune: L=%d N=%d padded=%.3f %.4f ms\n", t.L, t.N,
+            std::fprintf(stderr, "sos_tune: L=%d N=%d %s padded=%.3f %.4f ms\n", t.L, t.N,
+                         h->alg == SOS_ALG_PH ? "ph" : "dccr",
                          padded[c] / std::max(1.0, (double)total_samples), med);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    h->alg = requested;
     if (rc) return rc;
     if (best.L == 0) return SOS_EINVAL;
-    // the caller's outputs: the winning tile's result
+    // the caller's outputs: the winning tile's (and solver's) result
+    h->alg = best_alg;
     rc = batch_reserve(h, best, bits, ba, stream);
     if (!rc) rc = batch_enqueue(h, best, bits, ba, stream);
-    if (rc) return rc;
+    if (rc) {
+        h->alg = requested;
+        return rc;
+    }
     h->tile_L = best.L;
     h->tile_N = best.N;
     {
         std::lock_guard<std::mutex> tl(g_tune_mu);
+        g_tune_cache[key_req] = best;
         g_tune_cache[key_of(h, ba)] = best;
     }
     if (L_out) *L_out = best.L;

@@ -88,9 +88,32 @@ def test_tuner_returns_a_compiled_tile_with_exact_output(env):
                                        dev(sig_off.astype(np.int64)), zi=dev(zi), handle=h,
                                        reps=2)
     torch.cuda.synchronize()
-    print("tuned tile", (L, N), "%.4f ms" % ms)
+    print("tuned tile", (L, N), h.algorithm(), "%.4f ms" % ms)
     assert h.last_error() == P.SOS_OK
     assert h.tile() == (L, N) and ms > 0
+    assert h.algorithm() in ("dccr", "ph")          # no solver set: both were timed
     assert (L, N) in {(64, 16), (64, 32), (64, 64), (256, 16), (256, 32), (256, 64),
                       (512, 16), (512, 32), (512, 64), (1024, 16), (1024, 32)}
     check_vs_oracle(Ks, rows, sig_off, x, zi, y.cpu().numpy(), zf.cpu().numpy())
+
+
+def test_tuner_keeps_an_explicit_solver(env):
+    """A handle with a solver set is tuned over tiles only, keeps its solver,
+    and the cached tile is found again for the same request."""
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=32, log2_lo=8, log2_hi=14, seed=66)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=67)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for alg in ("dccr", "ph"):
+        h = P.Handle(0, algorithm=alg)
+        (L, N), ms, y, zf = P.tune_batched(dev(x), dev(rows), dev(Ks.astype(np.int32)),
+                                           dev(sig_off.astype(np.int64)), zi=dev(zi), handle=h,
+                                           reps=1)
+        torch.cuda.synchronize()
+        assert h.last_error() == P.SOS_OK
+        assert h.algorithm() == alg and h.tile() == (L, N)
+        Lc, Nc = P.ctypes.c_int(), P.ctypes.c_int()
+        assert P.lib().sos_tune_lookup(h.ptr, len(Ks), int(Ks.max()), int(sig_off[-1]),
+                                       P.ctypes.byref(Lc), P.ctypes.byref(Nc)) == P.SOS_OK
+        assert (Lc.value, Nc.value) == (L, N)
+        check_vs_oracle(Ks, rows, sig_off, x, zi, y.cpu().numpy(), zf.cpu().numpy())
