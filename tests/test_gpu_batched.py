@@ -161,8 +161,9 @@ def test_full_size_uneven_batch_graph_tuned(env):
     g.close()
 
 
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
 @pytest.mark.parametrize("tile", [(512, 64), (256, 32), (64, 16)])
-def test_small_grid_many_groups_per_workgroup(env, tile, monkeypatch):
+def test_small_grid_many_groups_per_workgroup(env, tile, alg, monkeypatch):
     """Three workgroups for the whole batch: each draws many tickets, so the
     next group is loaded while the current one is corrected and stored across
     signal boundaries, partial last groups, a signal with no sections and a
@@ -175,7 +176,7 @@ def test_small_grid_many_groups_per_workgroup(env, tile, monkeypatch):
     bad = 11                                         # a2 > 1 in its last section
     rows = rows.copy()
     rows[so[bad + 1] - 1, 5] = 1.5 * rows[so[bad + 1] - 1, 3]
-    h = P.Handle(0, tile=tile)
+    h = P.Handle(0, tile=tile, algorithm=alg)
     Kd = Ks.copy()
     Kd[23] = 0                                       # no sections: a copy
     y, zf = P.sosfilt_batched(dev(torch, x), dev(torch, rows), dev(torch, Kd),

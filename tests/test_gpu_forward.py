@@ -35,8 +35,8 @@ def P():
     return P
 
 
-def run(torch, P, sos, x, zi=None, tile=None, handle=None):
-    h = handle or P.Handle(0, tile=tile)
+def run(torch, P, sos, x, zi=None, tile=None, handle=None, alg=None):
+    h = handle or P.Handle(0, tile=tile, algorithm=alg)
     xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     sd = torch.from_numpy(np.ascontiguousarray(sos, dtype=np.float32)).cuda()
     zd = None if zi is None else torch.from_numpy(np.ascontiguousarray(zi, np.float32)).cuda()
@@ -150,23 +150,26 @@ def test_in_place_and_misaligned(torch_cuda, P):
         assert rel_l2(zf.cpu().numpy(), zfr) <= 1e-5
 
 
-def test_degenerate_k0_n0(torch_cuda, P):
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
+def test_degenerate_k0_n0(torch_cuda, P, alg):
     torch = torch_cuda
+    h = P.Handle(0, algorithm=alg)
     x = torch.from_numpy(workloads.signal(1000, 3)).cuda()
-    y, zf = P.sosfilt(x, torch.zeros((0, 6), device="cuda"))
+    y, zf = P.sosfilt(x, torch.zeros((0, 6), device="cuda"), handle=h)
     torch.cuda.synchronize()
     assert torch.equal(y, x) and zf.numel() == 0
     sos = torch.from_numpy(workloads.butterworth_sos(2)).cuda()
     zi = torch.from_numpy(workloads.initial_state(2, workloads.rng(1))).cuda()
-    y, zf = P.sosfilt(torch.zeros(0, device="cuda"), sos, zi)
+    y, zf = P.sosfilt(torch.zeros(0, device="cuda"), sos, zi, handle=h)
     torch.cuda.synchronize()
     assert y.numel() == 0 and torch.equal(zf, zi)
-    y, zf = P.sosfilt(torch.zeros(0, device="cuda"), sos, None)
+    y, zf = P.sosfilt(torch.zeros(0, device="cuda"), sos, None, handle=h)
     torch.cuda.synchronize()
     assert torch.count_nonzero(zf).item() == 0
 
 
-def test_lookback_carries_are_oracle_states(torch_cuda, P):
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
+def test_lookback_carries_are_oracle_states(torch_cuda, P, alg):
     """The resolved carry each group publishes equals the oracle's state after
     the group's last sample."""
     K = 3
@@ -176,7 +179,7 @@ def test_lookback_carries_are_oracle_states(torch_cuda, P):
     C = tile[0] * tile[1]
     G = 37
     x = workloads.signal(G * C, seed=4)
-    _, _, h = run(torch_cuda, P, sos, x, zi, tile=tile)
+    _, _, h = run(torch_cuda, P, sos, x, zi, tile=tile, alg=alg)
     car = h.carries()
     assert car.shape == (G, K, 2)
     for g in range(G):
@@ -185,9 +188,10 @@ def test_lookback_carries_are_oracle_states(torch_cuda, P):
         assert np.max(np.abs(car[g] - st)) <= 2e-5 * scale, (g, car[g], st)
 
 
-def test_bad_sections_report_and_poison(torch_cuda, P):
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
+def test_bad_sections_report_and_poison(torch_cuda, P, alg):
     torch = torch_cuda
-    h = P.Handle(0)
+    h = P.Handle(0, algorithm=alg)
     x = torch.from_numpy(workloads.signal(5000, 2)).cuda()
     sos = workloads.butterworth_sos(2).copy()
     sos[1, 3] = 0.0                                   # a0 == 0
@@ -286,7 +290,8 @@ def test_lightly_damped_order16(torch_cuda, P, tile):
     assert np.isfinite(y32).all()
 
 
-def test_lookback_timeout_is_bounded_and_reported(torch_cuda, P):
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
+def test_lookback_timeout_is_bounded_and_reported(torch_cuda, P, alg):
     """A one-tick bound on each lookback wait, forced from the host: the launch
     still ends, any group whose wait ran out is NaN and the handle reports
     SOS_ETIMEOUT; with the default bound restored the same handle is exact."""
@@ -295,7 +300,7 @@ def test_lookback_timeout_is_bounded_and_reported(torch_cuda, P):
     sos = workloads.sweep_sections(K, "random")
     n = 1 << 22
     x = workloads.signal(n, seed=31)
-    h = P.Handle(0, tile=(256, 16))
+    h = P.Handle(0, tile=(256, 16), algorithm=alg)
     print("device wall clock kHz", h.wall_clock_khz())
     xd = torch.from_numpy(x).cuda()
     sd = torch.from_numpy(sos).cuda()
