@@ -10,13 +10,14 @@
  *   - every lane is solved at zero incoming state by one divide-and-conquer
  *     level followed by one-sided cyclic reduction per parity (Sec. II-D/E,
  *     Eqs. (14)-(23)), which exposes both terminal samples of the lane before
- *     any back substitution;
+ *     any back substitution (or, selected per handle, by the PH
+ *     factorization's particular solution, Sec. II-C; sos_set_algorithm);
  *   - the lanes' zero-state terminal states are combined by a cross-lane scan
  *     (the role of Eq. (13)), the group's incoming state arrives over a
  *     decoupled lookback between groups (Sec. IV-B, Eq. (25)), and the
- *     homogeneous correction is folded into the back substitution
- *     (Sec. II-F, Eq. (24)); all K sections run in registers inside one kernel
- *     launch per call (Sec. IV-A).
+ *     homogeneous correction is folded into the back substitution (Sec.
+ *     II-F, Eq. (24); for PH it is added to every sample, Eq. (11)); all K
+ *     sections run in registers inside one kernel launch per call (Sec. IV-A).
  *
  * Conventions shared by every entry point
  *   sections : K x 6 FP32 rows [b0 b1 b2 a0 a1 a2] (scipy "sos" layout),
