@@ -119,6 +119,26 @@ def cpu_baseline(sos, x_host, n_sample, reps=3):
     return n_sample / ts[len(ts) // 2] / 1e9, ts[len(ts) // 2]
 
 
+def cpu_wavefront_rate(sos, x_host, n_sample, reps=3):
+    """The paper's multi-core CPU method (wavefront over groups and sections,
+    Sec. III-A) on the first n_sample samples: GS/s, seconds, threads."""
+    import numpy as np
+
+    import cpu_wavefront
+
+    xs = np.ascontiguousarray(x_host[:n_sample], dtype=np.float32)
+    ys = np.empty_like(xs)
+    threads = cpu_wavefront.default_threads()
+    cpu_wavefront.sosfilt(sos, xs[:4096], threads=threads)     # load outside the timing
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        cpu_wavefront.sosfilt(sos, xs, threads=threads, out=ys)
+        ts.append(time.perf_counter() - t)
+    ts.sort()
+    return n_sample / ts[len(ts) // 2] / 1e9, ts[len(ts) // 2], threads
+
+
 def traffic_bytes(n):
     """HBM bytes per filter launch from the committed rocprofv3 counter runs,
     scaled by the same counters on the copy kernel; None if the counters were
@@ -374,6 +394,7 @@ def main():
         extra["fwd_bwd"] = bench_fwd_bwd(torch, P, workloads, np, log)
 
     cpu = None
+    cpu_extra = None
     if not args.no_cpu:
         n_cpu = min(n, 1 << 27)
         v, secs = cpu_baseline(sos1, x_host, n_cpu)
@@ -382,6 +403,17 @@ def main():
                          "K=%d Butterworth signal, median of 3 runs (%.2f s each)"
                          % (n_cpu.bit_length() - 1, K1, secs)}
         log("cpu", cpu)
+        # the paper's multi-core CPU method, beside the oracle (not the baseline)
+        wf = {}
+        for K in (K1, 8):
+            v, secs, thr = cpu_wavefront_rate(workloads.sweep_sections(K, "butter"), x_host,
+                                              min(n, 1 << 26))
+            wf["order_%d" % (2 * K)] = {"value": round(v, 4), "unit": "GS/s", "threads": thr,
+                                        "seconds": round(secs, 3)}
+        cpu_extra = {"kind": "wavefront over groups of 2^16 samples and sections, FP32, "
+                             "pthreads (Sec. III-A); first 2^26 samples, median of 3 runs",
+                     **wf}
+        log("cpu wavefront", cpu_extra)
 
     out = {
         "metric": METRIC,
@@ -403,6 +435,7 @@ def main():
         "hbm_roof_frac_step": round(gss(ms_step) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_wavefront": cpu_extra,
         "sweep": result_sweep,
     }
     out.update(extra)
