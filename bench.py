@@ -26,7 +26,7 @@ Beside the headline, on the same GPU (skipped with --quick):
   library's native replay driver; achieved GS/s and p50/p99 chunk latency
   (tile (256, 16), PH solver: 10-13 % lower latency than DC-CR there).
 * "fwd_bwd": forward (keeping the section outputs) plus the adjoint, on one
-  2^24-sample signal and on 256 signals of 2^16 samples, order 8.
+  2^24-sample signal and on 256 signals of 2^16 samples, order 8, PH solver.
 
 Prints one JSON line on stdout. `python bench.py --gpus N` with N > 1 exits:
 this build runs on one GPU.
@@ -243,7 +243,7 @@ def bench_fwd_bwd(torch, P, workloads, np, log):
     n = 1 << 24
     x = torch.randn(n, generator=gen, device=dev)
     gy = torch.randn(n, generator=gen, device=dev)
-    h = P.Handle(0)
+    h = P.Handle(0, algorithm="ph")
     for _ in range(2):
         yv, zf, saved = P.sosfilt_train(x, sos, None, handle=h)
         P.sosfilt_vjp(sos, x, yv, saved, gy, None, handle=h)
@@ -262,6 +262,7 @@ def bench_fwd_bwd(torch, P, workloads, np, log):
         tb += ev[1].elapsed_time(ev[2])
     assert h.last_error() == P.SOS_OK
     tf, tb = tf / reps, tb / reps
+    out["section_solver"] = "ph"
     out["one_signal_2p24"] = {"fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
                               "fwd_bwd_GS_per_s": round(n / ((tf + tb) * 1e-3) / 1e9, 2),
                               "fwd_GS_per_s": round(n / (tf * 1e-3) / 1e9, 2)}
