@@ -47,6 +47,11 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_get_tile(None, None, None) == P.SOS_EINVAL
     assert lib.sos_set_precision(None, 64) == P.SOS_EINVAL
     assert lib.sos_get_precision(None) == P.SOS_EINVAL
+    assert lib.sos_set_algorithm(None, P.SOS_ALG_PH) == P.SOS_EINVAL
+    assert lib.sos_get_algorithm(None) == P.SOS_EINVAL
+    hdr = open(os.path.join(ROOT, "include", "sosfilt.h")).read()
+    for name, val in re.findall(r"(SOS_ALG_[A-Z]+) = (\d+)", hdr):
+        assert getattr(P, name) == int(val), name      # binding constants follow the header
     assert lib.sos_set_timeout(None, 1.0) == P.SOS_EINVAL
     assert lib.sos_wall_clock_khz(None) == P.SOS_EINVAL
     assert lib.sos_filter_train_batched(None, 1, 1, 1, 10, None, None, None, None, None, None,
