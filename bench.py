@@ -8,7 +8,8 @@ Butterworth low-pass at 0.2*Nyquist and random stable sections. The JSON
 whole step (coefficient preparation + filter kernel) with input and output
 resident in HBM, in GS/s, with the divide-and-conquer cyclic-reduction
 section solver (--alg ph: the PH solver). The other orders are reported under
-"sweep", each timed with both solvers.
+"sweep", each timed with both solvers; "plateau" gives the kernel rate against
+the signal length, 2^24..2^28 samples, at orders 2 and 16.
 
 Timing: W untimed warm-up steps, then exactly K timed steps between
 torch.cuda.synchronize() calls; two rotating input/output buffer pairs of
@@ -71,9 +72,10 @@ def log(*a):
 def time_steps(torch, P, h, sos_d, xs, ys, steps, warmup):
     """Run warmup + steps whole steps (prepare + filter) rotating buffers.
     Returns (ms per step, mean filter-kernel ms from HIP events)."""
+    nb = len(xs)
     for i in range(warmup):
         P.prepare(sos_d, handle=h)
-        P.filter_prepared(xs[i % 2], ys[i % 2], handle=h)
+        P.filter_prepared(xs[i % nb], ys[i % nb], handle=h)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
@@ -81,7 +83,7 @@ def time_steps(torch, P, h, sos_d, xs, ys, steps, warmup):
     for i in range(steps):
         P.prepare(sos_d, handle=h)
         ev[i][0].record()
-        P.filter_prepared(xs[i % 2], ys[i % 2], handle=h)
+        P.filter_prepared(xs[i % nb], ys[i % nb], handle=h)
         ev[i][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -376,6 +378,25 @@ def main():
                 log(kind, K, result_sweep[kind][str(K)])
         h2.close()
 
+    # plateau: kernel GS/s against the signal length (disjoint slices of the
+    # two 1 GiB buffer pairs, rotated so that >= 512 MiB is touched per cycle,
+    # beyond the 256 MB Infinity Cache)
+    plateau = {}
+    if not args.no_sweep and not args.only_k and args.log2n == 28:
+        for K in (1, 8):
+            sos_d = torch.from_numpy(workloads.sweep_sections(K, "butter")).to(dev)
+            pts = []
+            for lg in (24, 25, 26, 27, 28):
+                m = 1 << lg
+                k = min(8, n // m)
+                sx = [xs[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
+                sy = [ys[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
+                _, mk = time_steps(torch, P, h, sos_d, sx, sy, 20, 4)
+                assert h.last_error() == P.SOS_OK
+                pts.append({"log2n": lg, "kernel_GS_per_s": round(m / (mk * 1e-3) / 1e9, 2)})
+            plateau["order_%d" % (2 * K)] = pts
+            log("plateau", K, pts)
+
     copy_ms = time_copy(torch, P, xs, ys, 20, 3)
     copy_gbs = n * BYTES_PER_SAMPLE / (copy_ms * 1e-3) / 1e9
     log("copy %.4f ms = %.0f GB/s" % (copy_ms, copy_gbs))
@@ -440,6 +461,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_wavefront": cpu_extra,
         "sweep": result_sweep,
+        "plateau": plateau,
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
