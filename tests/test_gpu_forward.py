@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_util import max_over_peak, rel_l2, tol_for
+from tests.gpu_util import fp32_bounds, max_over_peak, rel_l2, tol_for, zf_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -318,3 +318,46 @@ def test_lookback_timeout_is_bounded_and_reported(torch_cuda, P, alg):
     assert h.last_error() == P.SOS_OK
     yr, _ = oracle.sosfilt(sos, x)
     assert rel_l2(y.cpu().numpy(), yr) <= 1e-5
+
+
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
+@pytest.mark.parametrize("K", [12, 32, 64])
+def test_long_cascades(torch_cuda, P, K, alg):
+    """Cascades beyond order 16, up to the 64 sections the ABI allows: random
+    stable sections of unit gain at their pole angle and random zi. FP32 is
+    held to the order's bound or 16x the sequential FP32 error, FP64 compute
+    to 1e-5; also as one signal of an uneven batch beside short ones."""
+    torch = torch_cuda
+    g = workloads.rng(600 + K)
+    sos = workloads.random_stable_sos(K, g, r_lo=0.5, r_hi=0.95)
+    zi = workloads.initial_state(K, g)
+    n = (1 << 17) + 4321
+    x = workloads.signal(n, seed=K)
+    yr, zfr = oracle.sosfilt(sos, x, zi)
+    y, zf, _ = run(torch, P, sos, x, zi, alg=alg)
+    by, bz = fp32_bounds(K, sos, x, zi, yr, zfr)
+    bz = zf_bound(K, by, bz, yr, zfr)
+    print("K", K, alg, "fp32 rel_l2", rel_l2(y, yr), "bound", by, "zf", rel_l2(zf, zfr), bz)
+    assert rel_l2(y, yr) <= by
+    assert rel_l2(zf, zfr) <= bz
+    y64, zf64, _ = run(torch, P, sos, x, zi, handle=P.Handle(0, precision=64, algorithm=alg))
+    print("K", K, alg, "fp64 rel_l2", rel_l2(y64, yr), "zf", rel_l2(zf64, zfr))
+    assert rel_l2(y64, yr) <= 1e-5 and rel_l2(zf64, zfr) <= 1e-5
+    # the same cascade as one signal of a batch, between two short order-2 ones
+    rows = np.concatenate([workloads.butterworth_sos(1), sos, workloads.butterworth_sos(1)])
+    Ks = np.array([1, K, 1], dtype=np.int32)
+    zib = np.concatenate([np.zeros((1, 2), np.float32), zi, np.zeros((1, 2), np.float32)])
+    xb = np.concatenate([workloads.signal(999, seed=1), x, workloads.signal(5000, seed=5)])
+    sig_off = np.array([0, 999, 999 + n, 999 + n + 5000], dtype=np.int64)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h = P.Handle(0, algorithm=alg)
+    yb, zfb = P.sosfilt_batched(d(xb), d(rows.astype(np.float32)), d(Ks), d(sig_off),
+                                zi=d(zib), handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    yb = yb.cpu().numpy()
+    assert rel_l2(yb[999:999 + n], yr) <= by
+    assert rel_l2(zfb.cpu().numpy()[1:1 + K], zfr) <= bz
+    for (a, b), r in (((0, 999), rows[:1]), ((999 + n, 999 + n + 5000), rows[-1:])):
+        ys, _ = oracle.sosfilt(r, xb[a:b])
+        assert rel_l2(yb[a:b], ys) <= 1e-5
