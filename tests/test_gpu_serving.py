@@ -247,3 +247,46 @@ def test_replay_poisson_load(env):
     yr, _, bnd = oracle_per_stream(Ks, secs, ids, lens, offs, x)
     for s in yr:
         assert rel_l2(gathered(y, ids, lens, offs, s), yr[s]) <= bnd[s][0], s
+
+
+def test_device_errors_reach_their_chunks(env):
+    """Device-side error bits travel from the filter kernel (its last
+    workgroup writes them into the step's host result word) to the step's
+    chunks, and are cleared for the next step. A one-tick lookback bound,
+    forced from the host, on long chunks yields SOS_ETIMEOUT (with NaN
+    outputs) or SOS_OK; a later one-group chunk, which never waits, is OK and
+    exact."""
+    torch, P = env
+    h = P.Handle(0, tile=(64, 16))
+    h.set_timeout(1e-6)
+    srv = P.Server(handle=h, max_slots=8)
+    sos = workloads.sweep_sections(4, "random")
+    a = srv.open(sos)
+    b = srv.open(sos)
+    x = torch.from_numpy(workloads.signal(1 << 18, seed=9)).cuda()
+    codes = []
+    timed_out = False
+    for _ in range(4):
+        y = torch.empty_like(x)
+        tk, _ = srv.push(a, x, y)
+        try:
+            srv.wait(tk)
+            code = P.SOS_OK
+        except P.SosError as e:
+            code = e.code
+        assert code in (P.SOS_OK, P.SOS_ETIMEOUT)
+        has_nan = bool(torch.isnan(y).any().item())
+        if code == P.SOS_ETIMEOUT:
+            assert has_nan
+        elif not timed_out:
+            assert not has_nan
+        timed_out |= code == P.SOS_ETIMEOUT
+        codes.append(code)
+    print("one-tick bound, chunk codes", codes)
+    xs = workloads.signal(500, seed=10)
+    ys = torch.empty(500, device="cuda")
+    tk, _ = srv.push(b, torch.from_numpy(xs).cuda(), ys)
+    srv.wait(tk)                                    # raises if the bits were left set
+    yr, _ = oracle.sosfilt(sos, xs)
+    assert rel_l2(ys.cpu().numpy(), yr) <= 1e-5
+    srv.close()
