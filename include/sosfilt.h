@@ -93,9 +93,10 @@ int sos_last_error(sos_handle_t h);
  * and N samples per lane; a group holds C = L*N samples and one workgroup of
  * L/64 wavefronts processes it. Compiled shapes: L in {64, 256, 512} with
  * N in {16, 32, 64}, and L = 1024 with N in {16, 32}. sos_set_tile(h, 0, 0)
- * restores the default, (512, 64). Applies to later calls (tables prepared
- * for another shape must be prepared again). Unsupported shapes return
- * SOS_EINVAL. */
+ * restores the default, (512, 64), which sos_get_tile reports (with no tile
+ * set, sos_filter and sos_filter_train may pick a smaller shape for short
+ * FP32 signals). Applies to later calls (tables prepared for another shape
+ * must be prepared again). Unsupported shapes return SOS_EINVAL. */
 int sos_set_tile(sos_handle_t h, int L, int N);
 int sos_get_tile(sos_handle_t h, int *L, int *N);
 
@@ -153,7 +154,11 @@ int sos_wall_clock_khz(sos_handle_t h);
  * Enqueues: the coefficient-preparation kernel (FP64 tables), a one-thread
  * kernel that re-arms the ticket counter and the descriptor epoch, and the
  * filter kernel (ticketed groups, register-resident cascade, decoupled
- * lookback).
+ * lookback). In FP32 with no tile set (sos_set_tile, SOS_TILE_L/N), the group
+ * shape follows n: (512, 16) up to 2^20 samples, (512, 32) up to 2^22, else
+ * the default (512, 64); shorter signals leave the device partly idle, and
+ * fewer samples per lane shorten each group's chain. sos_filter_train does
+ * the same.
  */
 int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, float *y,
                int64_t n, const float *zi, float *zf, hipStream_t stream);
@@ -191,8 +196,10 @@ int sos_filter_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
  * sos_prepare enqueues the coefficient-preparation kernel for `sections`
  * (K x 6, device) at the handle's current tile; sos_filter_prepared then
  * enqueues only the filter kernel, with the same conventions as sos_filter.
- * sos_filter_prepared returns SOS_EINVAL if nothing was prepared or the tile
- * changed since. The sections buffer is read by the preparation kernel only. */
+ * sos_filter_prepared returns SOS_EINVAL if nothing was prepared, the
+ * precision changed since, or a tile set on the handle differs from the one
+ * prepared at (with no tile set, the shape the tables were prepared at is
+ * used, including one that sos_filter picked from the signal length). The sections buffer is read by the preparation kernel only. */
 int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream);
 int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, const float *zi,
                         float *zf, hipStream_t stream);

@@ -59,10 +59,11 @@ int check_signal(const float *x, const float *y, int64_t n)
     return SOS_OK;
 }
 
-// Tables for `sections` at the handle's shape and type (caller holds the lock).
-int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream)
+// Tables for `sections` at the handle's shape (or, without one, the shape for
+// a signal of n samples; n < 0: unknown) and type (caller holds the lock).
+int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream, int64_t n = -1)
 {
-    const Tile t = tile_of(h, K);
+    const Tile t = tile_for_length(h, K, n);
     const int bits = bits_of(h);
     int rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes(K > 8 ? K : 8, bits), stream);
     if (rc) return rc;
@@ -356,8 +357,11 @@ int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, con
     int rc = check_signal(x, y, n);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(h->mu);
+    // Without a tile set, whatever shape the tables were prepared at is valid
+    // (sos_filter picks it from the signal length).
     const Tile t = tile_of(h, h->prep_K);
-    if (h->prep_K < 0 || h->prep_N != t.N || h->prep_L != t.L || h->prep_bits != bits_of(h))
+    if (h->prep_K < 0 || h->prep_bits != bits_of(h) ||
+        (tile_is_set(h) && (h->prep_N != t.N || h->prep_L != t.L)))
         return SOS_EINVAL;
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
@@ -375,7 +379,7 @@ int sos_filter(sos_handle_t h, const float *sections, int K, const float *x, flo
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     if (n > 0 && K > 0) {
-        rc = prepare_locked(h, sections, K, stream);
+        rc = prepare_locked(h, sections, K, stream, n);
         if (rc) return rc;
     } else {
         mark_degenerate(h, K);
@@ -415,7 +419,7 @@ int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     if (n > 0 && K > 0) {
-        rc = prepare_locked(h, sections, K, stream);
+        rc = prepare_locked(h, sections, K, stream, n);
         if (rc) return rc;
     } else {
         mark_degenerate(h, K);

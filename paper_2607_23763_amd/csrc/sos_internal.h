@@ -165,6 +165,29 @@ inline int bits_of(const sos_ctx *h)
     return kDefaultBits;
 }
 
+// True when the group shape comes from the handle or the environment rather
+// than from the defaults.
+inline bool tile_is_set(const sos_ctx *h)
+{
+    return h->tile_L || std::getenv("SOS_TILE_L") || std::getenv("SOS_TILE_N");
+}
+
+// Group shape for one FP32 signal of n samples when no tile is set: fewer
+// samples per lane for shorter signals, which shortens every group's
+// per-section chain while there are too few groups to fill the device
+// (measured on MI355X, one call including table preparation: 15-26 % less
+// time at orders 8-16 up to 2^20 samples with (512, 16), 8-10 % at 2^21-2^22
+// with (512, 32), which at 2^23 is already 8 % slower than the default).
+// n < 0: unknown, the default tile.
+inline Tile tile_for_length(const sos_ctx *h, int K, int64_t n)
+{
+    const Tile t = tile_of(h, K);
+    if (n < 0 || tile_is_set(h) || bits_of(h) != 32) return t;
+    if (n <= ((int64_t)1 << 20)) return Tile{512, 16};
+    if (n <= ((int64_t)1 << 22)) return Tile{512, 32};
+    return t;
+}
+
 // Section solver of the filter kernels (ALG_DCCR or ALG_PH): the handle's
 // choice, else SOS_ALG in the environment ("ph" or "dccr"), else DC-CR.
 inline int alg_of(const sos_ctx *h)

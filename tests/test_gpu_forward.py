@@ -361,3 +361,38 @@ def test_long_cascades(torch_cuda, P, K, alg):
     for (a, b), r in (((0, 999), rows[:1]), ((999 + n, 999 + n + 5000), rows[-1:])):
         ys, _ = oracle.sosfilt(r, xb[a:b])
         assert rel_l2(yb[a:b], ys) <= 1e-5
+
+
+@pytest.mark.parametrize("alg", ["dccr", "ph"])
+def test_length_chosen_tile(torch_cuda, P, alg):
+    """With no tile set, sos_filter picks the group shape from the signal
+    length; lengths on both sides of each switch (2^20 and 2^22 samples) stay
+    within the bounds, and the tables it prepared serve sos_filter_prepared
+    until a tile is set on the handle."""
+    torch = torch_cuda
+    K = 8
+    sos = workloads.sweep_sections(K, "butter")
+    zi = workloads.initial_state(K, workloads.rng(61))
+    h = P.Handle(0, algorithm=alg)
+    for n in (1000, (1 << 20) - 3, (1 << 20) + 1, (1 << 22) + 7):
+        x = workloads.signal(n, seed=62)
+        y, zf, _ = run(torch, P, sos, x, zi, handle=h)
+        yr, zfr = oracle.sosfilt(sos, x, zi)
+        print(alg, "n", n, "rel_l2", rel_l2(y, yr), "zf", rel_l2(zf, zfr))
+        assert rel_l2(y, yr) <= tol_for(K), n
+        assert rel_l2(zf, zfr) <= tol_for(K), n
+    # tables sos_filter prepared for a short signal, reused at another length
+    x = workloads.signal(5000, seed=63)
+    run(torch, P, sos, x, zi, handle=h)
+    x2 = workloads.signal((1 << 21) + 11, seed=64)
+    xd = torch.from_numpy(x2).cuda()
+    yd = torch.empty_like(xd)
+    P.filter_prepared(xd, yd, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    yr, _ = oracle.sosfilt(sos, x2)
+    assert rel_l2(yd.cpu().numpy(), yr) <= tol_for(K)
+    # a tile set afterwards invalidates them
+    h.set_tile(512, 64)
+    with pytest.raises(P.SosError):
+        P.filter_prepared(xd, yd, handle=h)
