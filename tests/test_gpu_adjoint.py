@@ -167,7 +167,9 @@ def test_batched_vjp_matches_oracle(env, tile, precision):
             continue
         assert max(e) <= 1e-3, (i, Ks[i], b - a, e)
         if b > a:
-            hp = P.Handle(0, tile=tile)
+            # the batch's own tile: with none set, the one-signal forward
+            # picks a smaller tile for short signals and rounds differently
+            hp = P.Handle(0, tile=tile or h.tile())
             yp, _, sp = P.sosfilt_train(dev(x[a:b]), dev(r), dev(zi_i), handle=hp)
             gxp, gzip, gsp = P.sosfilt_vjp(dev(r), dev(x[a:b]), yp, sp, dev(gy[a:b]), dev(gzf_i),
                                            handle=hp)
