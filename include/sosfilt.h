@@ -151,10 +151,10 @@ int sos_wall_clock_khz(sos_handle_t h);
  *   the final states. 0 <= K <= SOS_MAX_SECTIONS, n >= 0.
  *   n == 0: y is not touched and zf := zi (zeros if zi == NULL).
  *   K == 0: y := x.
- * Enqueues: the coefficient-preparation kernel (FP64 tables), a one-thread
- * kernel that re-arms the ticket counter and the descriptor epoch, and the
- * filter kernel (ticketed groups, register-resident cascade, decoupled
- * lookback). In FP32 with no tile set (sos_set_tile, SOS_TILE_L/N), the group
+ * Enqueues: the coefficient-preparation kernel (FP64 tables) and the filter
+ * kernel (ticketed groups, register-resident cascade, decoupled lookback),
+ * whose last workgroup to finish re-arms the ticket counter and the
+ * descriptor epoch for the next launch on the handle. In FP32 with no tile set (sos_set_tile, SOS_TILE_L/N), the group
  * shape follows n: (512, 16) up to 2^20 samples, (512, 32) up to 2^22, else
  * the default (512, 64); shorter signals leave the device partly idle, and
  * fewer samples per lane shorten each group's chain. sos_filter_train does

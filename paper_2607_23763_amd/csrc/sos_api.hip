@@ -98,7 +98,8 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
     const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
     if (rc) return rc;
-    if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
+    // no arm launch: the previous filter launch on this workspace (or its
+    // creation) left the ticket at 0 and a fresh epoch
     const int alg = alg_of(h);
     if (sos_launch_fwd(bits, alg, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
                        h->timeout_ticks, grid_of(bits, alg, L, N), saved, stream) != hipSuccess)

@@ -61,6 +61,7 @@ worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_sa
         if ((stage_words & 1) && tid == 0) stage_dst[stage_words - 1] = stage_src[stage_words - 1];
         if (tid == 0) {
             ctrl[CTRL_TICKET] = 0u;
+            ctrl[CTRL_DONE] = 0u;
             const unsigned e = ctrl[CTRL_EPOCH] + 1u;
             ctrl[CTRL_EPOCH] = (e == 0u) ? 1u : e;
         }

@@ -24,6 +24,7 @@ enum : int {
     CTRL_TICKET = 0,   // next group ticket of the running launch
     CTRL_EPOCH = 1,    // launch counter: tag of valid lookback descriptors
     CTRL_ERR = 2,      // sticky device-side error bits (ERRBIT_*)
+    CTRL_DONE = 3,     // workgroups of the running launch that have left it
     CTRL_WORDS = 16
 };
 enum : unsigned { ERRBIT_A0 = 1u, ERRBIT_UNSTABLE = 2u, ERRBIT_TIMEOUT = 4u, ERRBIT_BADARG = 8u };

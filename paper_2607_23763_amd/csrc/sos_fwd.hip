@@ -48,8 +48,10 @@
 // consecutive predecessors a lookback reads spans few cache lines. A word is valid when
 // its tag equals the launch epoch, so words are self-validating: no fences, no
 // clearing between launches, and the agent-scope relaxed atomics keep them
-// coherent across the XCDs' separate L2 caches. A one-thread kernel before
-// each launch zeroes the ticket and advances the epoch.
+// coherent across the XCDs' separate L2 caches. The last workgroup to leave a
+// launch zeroes the ticket and advances the epoch for the next launch on the
+// same control block (a fresh block starts in that state), so consecutive
+// launches need no kernel in between.
 #include "sos_device.h"
 
 using namespace sosdev;
@@ -426,6 +428,26 @@ __device__ __forceinline__ double wave_uniform(double v)
 struct NoNext {
     __device__ void operator()(int64_t) const {}
 };
+
+// Exit of a ticketed launch (thread 0 of every workgroup, after its last draw):
+// the workgroup that leaves last re-arms the control block for the next
+// launch. Every ticket of this launch has been drawn by then: each workgroup's
+// final draw is a returning device-scope atomic whose value decided the exit,
+// so it had been performed before that workgroup counted itself out, and the
+// count is one atomic order. The epoch was read by every workgroup at its
+// start. No release is needed (one would write back the L2 at every exit).
+__device__ __forceinline__ void rearm_on_exit(unsigned *ctrl, unsigned epoch)
+{
+    const unsigned d = __hip_atomic_fetch_add(&ctrl[CTRL_DONE], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    if (d + 1u == gridDim.x) {
+        const unsigned e = epoch + 1u;
+        __hip_atomic_store(&ctrl[CTRL_TICKET], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctrl[CTRL_EPOCH], e == 0u ? 1u : e, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctrl[CTRL_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
 
 // ------------------------------------------------------------- one section
 
@@ -1012,6 +1034,7 @@ __global__ void __launch_bounds__(64 * W)
         for (int j = 0; j < N / 4; ++j) pf[j] = nf[j];
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
     }
+    if (threadIdx.x == 0) rearm_on_exit(a.ctrl, epoch);
 }
 
 // ---------------------------------------------------------------------------
@@ -1318,6 +1341,7 @@ __global__ void __launch_bounds__(64 * W)
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if ((int64_t)gridDim.x >= total) break;
     }
+    if (threadIdx.x == 0) rearm_on_exit(b.ctrl, epoch);
 }
 
 // Sum the per-group coefficient partials of section k in FP64 (fixed order)

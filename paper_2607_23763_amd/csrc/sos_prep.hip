@@ -197,10 +197,12 @@ extern "C" hipError_t sos_launch_prep_batched(int bits, const float *sections, i
 }
 
 // Start of a filter launch: ticket counter to 0 and a fresh epoch tag for the
-// launch's lookback descriptors (tag 0 is never used). One thread.
+// launch's lookback descriptors (tag 0 is never used). One thread. The filter
+// kernels leave the block in this state themselves; this re-establishes it.
 extern "C" __global__ void sos_arm_kernel(unsigned *ctrl)
 {
     ctrl[CTRL_TICKET] = 0u;
+    ctrl[CTRL_DONE] = 0u;
     const unsigned e = ctrl[CTRL_EPOCH] + 1u;
     ctrl[CTRL_EPOCH] = (e == 0u) ? 1u : e;
 }

@@ -396,3 +396,55 @@ def test_length_chosen_tile(torch_cuda, P, alg):
     h.set_tile(512, 64)
     with pytest.raises(P.SosError):
         P.filter_prepared(xd, yd, handle=h)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_paths_interleaved_on_one_handle(torch_cuda, P, precision):
+    """Every ticketed launch leaves the handle's ticket counter and descriptor
+    epoch ready for the next one (the plain filter enqueues no arm step):
+    plain, prepared, batched, training forward and adjoint calls alternate on
+    one handle, with one-group-per-workgroup and multi-round grids, and each
+    result still matches the oracle."""
+    torch = torch_cuda
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h = P.Handle(0, tile=(256, 16), precision=precision)
+    K = 4
+    sos = workloads.sweep_sections(K, "random")
+    zi = workloads.initial_state(K, workloads.rng(71))
+    Ks, rows, sig_off, bzi = workloads.uneven_batch(B=24, log2_lo=2, log2_hi=16, seed=72)
+    bx = workloads.batch_signal(int(sig_off[-1]), seed=73)
+    so = np.r_[0, np.cumsum(Ks)]
+    tol = 1e-6 if precision == 64 else tol_for(K)
+    for rep in range(2):
+        for n in (3000, (1 << 20) + 5):          # one round of groups, then many
+            x = workloads.signal(n, seed=74 + rep)
+            y, zf, _ = run(torch, P, sos, x, zi, handle=h)
+            yr, zfr = oracle.sosfilt(sos, x, zi)
+            assert rel_l2(y, yr) <= tol and rel_l2(zf, zfr) <= tol, (rep, n)
+            xd = dev(x)
+            yd = torch.empty_like(xd)
+            P.prepare(dev(np.asarray(sos, np.float32)), handle=h)
+            for _ in range(2):
+                P.filter_prepared(xd, yd, handle=h)
+            torch.cuda.synchronize()
+            yr0, _ = oracle.sosfilt(sos, x)
+            assert rel_l2(yd.cpu().numpy(), yr0) <= tol, (rep, n, "prepared")
+        yb, zfb = P.sosfilt_batched(dev(bx), dev(rows), dev(Ks.astype(np.int32)),
+                                    dev(sig_off.astype(np.int64)), zi=dev(bzi), handle=h)
+        torch.cuda.synchronize()
+        yb = yb.cpu().numpy()
+        for i in (0, 7, 23):
+            a, b = sig_off[i], sig_off[i + 1]
+            yr, _ = oracle.sosfilt(rows[so[i]:so[i + 1]], bx[a:b], bzi[so[i]:so[i + 1]])
+            tb = 1e-6 if precision == 64 else tol_for(int(Ks[i]))
+            assert rel_l2(yb[a:b], yr) <= tb, i
+        x = workloads.signal(50000, seed=80 + rep)
+        gy = workloads.signal(50000, seed=90 + rep)
+        y, zf, saved = P.sosfilt_train(dev(x), dev(np.asarray(sos, np.float32)), dev(zi), handle=h)
+        gx, gzi, gs = P.sosfilt_vjp(dev(np.asarray(sos, np.float32)), dev(x), y, saved, dev(gy),
+                                    handle=h)
+        torch.cuda.synchronize()
+        rx, rzi, rs = oracle.sosfilt_vjp(sos, x, zi, gy, None)
+        assert rel_l2(gx.cpu().numpy(), rx) <= 1e-3, rep
+        assert rel_l2(gs.cpu().numpy(), rs) <= 1e-3, rep
+    assert h.last_error() == P.SOS_OK
