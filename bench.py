@@ -28,6 +28,12 @@ Beside the headline, on the same GPU (skipped with --quick):
   (tile (256, 16), PH solver: 10-13 % lower latency than DC-CR there).
 * "fwd_bwd": forward (keeping the section outputs) plus the adjoint, on one
   2^24-sample signal and on 256 signals of 2^16 samples, order 8, PH solver.
+* "toeplitz_mfma_bound": a lower bound for a block-Toeplitz (matrix-core)
+  form of the whole cascade, not part of the filter: the FP32 library GEMM
+  that maps every 64-sample chunk of a 2^28-sample signal through a 64 x 64
+  lower-triangular operator (the zero-state response), and through 80 x 64
+  (plus the 16 terminal states of an order-16 cascade), beside the order-16
+  filter kernel.
 
 Prints one JSON line on stdout. `python bench.py --gpus N` with N > 1 exits:
 this build runs on one GPU.
@@ -89,6 +95,42 @@ def time_steps(torch, P, h, sos_d, xs, ys, steps, warmup):
     t1 = time.perf_counter()
     kern = sum(a.elapsed_time(b) for a, b in ev) / steps
     return (t1 - t0) * 1e3 / steps, kern
+
+
+def bench_toeplitz_bound(torch, n, order16_kernel_gss, log):
+    """Chunk-by-operator products of a whole block-Toeplitz cascade form, as
+    FP32 library GEMMs (matrix cores), timed with HIP events: a lower bound
+    for that design's zero-state stage, with nothing fused."""
+    prev = torch.backends.cuda.matmul.allow_tf32
+    torch.backends.cuda.matmul.allow_tf32 = False
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = [torch.randn(n, device="cuda", generator=g) for _ in range(2)]
+    out = {"chunk": 64, "n": n, "order16_filter_kernel_GS_per_s": order16_kernel_gss}
+    for rows in (64, 80):
+        op = torch.randn(rows, 64, device="cuda", generator=g)
+        if rows == 64:
+            op = op.tril()
+        opt = op.t().contiguous()
+        ys = [torch.empty(n // 64, rows, device="cuda") for _ in range(2)]
+        xv = [v.view(-1, 64) for v in x]
+        for i in range(5):
+            torch.mm(xv[i % 2], opt, out=ys[i % 2])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(20):
+            torch.mm(xv[i % 2], opt, out=ys[i % 2])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        out["rows_%d" % rows] = {"ms": round(ms, 4), "GS_per_s": round(n / (ms * 1e-3) / 1e9, 1),
+                                 "TFLOP_per_s": round(2.0 * n * rows / (ms * 1e-3) / 1e12, 1)}
+        del ys
+    torch.backends.cuda.matmul.allow_tf32 = prev
+    del x
+    torch.cuda.empty_cache()
+    log("toeplitz_mfma_bound", out)
+    return out
 
 
 def time_copy(torch, P, xs, ys, steps, warmup):
@@ -416,6 +458,8 @@ def main():
         extra["batched"] = bench_batched(torch, P, workloads, np, log)
         extra["served"] = bench_served(torch, P, workloads, np, log)
         extra["fwd_bwd"] = bench_fwd_bwd(torch, P, workloads, np, log)
+        k16 = (result_sweep or {}).get("butter", {}).get("8", {}).get("kernel_GS_per_s")
+        extra["toeplitz_mfma_bound"] = bench_toeplitz_bound(torch, n, k16, log)
 
     cpu = None
     cpu_extra = None
