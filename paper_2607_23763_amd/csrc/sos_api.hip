@@ -78,6 +78,18 @@ int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream,
     return SOS_OK;
 }
 
+// Whether work enqueued on `stream` is being captured into a graph (a failed
+// query counts as capturing).
+bool capturing(hipStream_t stream)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return st != hipStreamCaptureStatusNone;
+}
+
 // Filter with the prepared tables (caller holds the lock).
 int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *zi, float *zf,
                   hipStream_t stream, float *saved)
@@ -98,14 +110,19 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
     const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
     if (rc) return rc;
-    // no arm launch: the previous filter launch on this workspace (or its
-    // creation) left the ticket at 0 and a fresh epoch
+    // Ticket 0 and a fresh epoch: left by the previous plain or adjoint launch
+    // on this workspace (their last workgroup re-arms) or by its creation,
+    // else armed here. A launch being captured into a graph carries its own
+    // arm step, so that every replay is self-contained.
+    const bool cap = capturing(stream);
+    if ((!h->armed || cap) && sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
     const int alg = alg_of(h);
     if (sos_launch_fwd(bits, alg, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
                        h->timeout_ticks, grid_of(bits, alg, L, N), saved, stream) != hipSuccess)
         return SOS_EHIP;
     h->last_groups = groups;
     h->last_K = K;
+    if (!cap) h->armed = true;
     return SOS_OK;
 }
 
@@ -163,6 +180,7 @@ int batch_reserve(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
 
 int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream)
 {
+    h->armed = false;   // a batched launch leaves the ticket counter advanced
     const int64_t C = (int64_t)t.L * t.N;
     const int64_t max_groups = ba.total_samples / C + ba.B;
     const int kd = ba.kmax > 0 ? ba.kmax : 1;

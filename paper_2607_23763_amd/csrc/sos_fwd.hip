@@ -49,9 +49,11 @@
 // its tag equals the launch epoch, so words are self-validating: no fences, no
 // clearing between launches, and the agent-scope relaxed atomics keep them
 // coherent across the XCDs' separate L2 caches. The last workgroup to leave a
-// launch zeroes the ticket and advances the epoch for the next launch on the
-// same control block (a fresh block starts in that state), so consecutive
-// launches need no kernel in between.
+// plain or adjoint launch zeroes the ticket and advances the epoch for the
+// next launch on the same control block (a fresh block starts in that state),
+// so consecutive plain launches need no kernel in between. Batched launches
+// are armed by their work-table kernel and skip this (it would lengthen every
+// served step).
 #include "sos_device.h"
 
 using namespace sosdev;
@@ -1034,7 +1036,7 @@ __global__ void __launch_bounds__(64 * W)
         for (int j = 0; j < N / 4; ++j) pf[j] = nf[j];
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
     }
-    if (threadIdx.x == 0) rearm_on_exit(a.ctrl, epoch);
+    if (a.B == 0 && threadIdx.x == 0) rearm_on_exit(a.ctrl, epoch);
 }
 
 // ---------------------------------------------------------------------------

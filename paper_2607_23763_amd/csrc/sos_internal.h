@@ -90,6 +90,8 @@ struct sos_ctx {
     int wall_khz = 0;                     // device wall clock (s_memrealtime) rate
     int64_t last_groups = 0;
     int last_K = 0;
+    bool armed = true;   // ctrl holds ticket 0 and an unused epoch once the enqueued
+                         // work has run (fresh, or last launch plain or adjoint)
     int prep_K = -1;                      // tables currently prepared (K, shape, type)
     int prep_L = 0;
     int prep_N = 0;

@@ -448,3 +448,53 @@ def test_paths_interleaved_on_one_handle(torch_cuda, P, precision):
         assert rel_l2(gx.cpu().numpy(), rx) <= 1e-3, rep
         assert rel_l2(gs.cpu().numpy(), rs) <= 1e-3, rep
     assert h.last_error() == P.SOS_OK
+
+
+def test_plain_filter_captured_in_a_graph(torch_cuda, P):
+    """A plain filter captured into a graph carries its own arm step, so its
+    replays stay correct when eager batched launches, which leave the ticket
+    counter advanced, run on the same handle between them. Every call runs
+    once at its exact size before the capture, so no later call grows (and
+    frees) a buffer the graph holds."""
+    torch = torch_cuda
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h = P.Handle(0, tile=(256, 16))
+    K = 2
+    sos = workloads.sweep_sections(K, "random")
+    sosd = dev(np.asarray(sos, np.float32))
+    n = 200003
+    x = workloads.signal(n, seed=91)
+    xd = dev(x)
+    yd = torch.empty_like(xd)
+    yr, _ = oracle.sosfilt(sos, x)
+    Ks, rows, sig_off, bzi = workloads.uneven_batch(B=16, log2_lo=4, log2_hi=15, seed=92)
+    bx = workloads.batch_signal(int(sig_off[-1]), seed=93)
+    bargs = (dev(bx), dev(rows), dev(Ks.astype(np.int32)), dev(sig_off.astype(np.int64)))
+    so = np.r_[0, np.cumsum(Ks)]
+    i = 5
+    ybr, _ = oracle.sosfilt(rows[so[i]:so[i + 1]], bx[sig_off[i]:sig_off[i + 1]], bzi[so[i]:so[i + 1]])
+
+    def batched():
+        yb, _ = P.sosfilt_batched(*bargs, zi=dev(bzi), handle=h)
+        torch.cuda.synchronize()
+        e = rel_l2(yb.cpu().numpy()[sig_off[i]:sig_off[i + 1]], ybr)
+        assert e <= tol_for(int(Ks[i])), e
+
+    P.sosfilt_(xd, sosd, yd, handle=h)
+    batched()
+    P.sosfilt_(xd, sosd, yd, handle=h)
+    torch.cuda.synchronize()
+    assert rel_l2(yd.cpu().numpy(), yr) <= tol_for(K)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.sosfilt_(xd, sosd, yd, handle=h)
+    for rep in range(3):
+        batched()
+        yd.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert rel_l2(yd.cpu().numpy(), yr) <= tol_for(K), rep
+        P.sosfilt_(xd, sosd, yd, handle=h)          # eager, after the replay
+        torch.cuda.synchronize()
+        assert rel_l2(yd.cpu().numpy(), yr) <= tol_for(K), rep
+    assert h.last_error() == P.SOS_OK
