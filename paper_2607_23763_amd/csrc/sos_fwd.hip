@@ -1257,21 +1257,32 @@ __global__ void __launch_bounds__(64 * W)
         const int zl = has_first ? (int)(pz / N) : 0, zp = has_first ? (int)(pz % N) : 0;
         const int64_t sst = b.B > 0 ? b.saved_stride : n;
 
+        // The section's forward input and output over the window, in the
+        // wave's two tiles. The input of section k is the output of section
+        // k - 1, so it stays staged for the next (lower) section, whose
+        // output tile it becomes: each signal is read from HBM once.
+        // The last section's two windows are loaded back to back, so that
+        // their global loads are in flight together.
+        float *tin = tl, *tout = tl2;
+        if (!bad && it.K > 0) {
+            const int k = it.K - 1;
+            window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tin, lane);
+            window_load<N>(bi.y, f0, n, tout, lane);
+        }
         for (int k = it.K - 1; k >= 0 && !bad; --k) {
             const T *tabv = it.tabs + (size_t)k * TAB_FLOATS;
             ctabT<T> *tab = ctabp(tabv);
-            // the section's forward input and output over the window (own tiles)
-            window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tl, lane);
-            window_load<N>(k == it.K - 1 ? bi.y : bi.saved + (size_t)k * sst, f0, n, tl2, lane);
+            if (k < it.K - 1)
+                window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tin, lane);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             T q1, q2;   // lam'[-2], lam'[-1] of this lane
-            run_section<T, N, W, true, ALG>(u, xch, tl, a, it, tabv, k, epoch, wv, lane, false, 0,
-                                            0,
-                                       q1, q2);
+            // (the pair section reads and writes no tile)
+            run_section<T, N, W, true, ALG>(u, xch, tout, a, it, tabv, k, epoch, wv, lane, false,
+                                            0, 0, q1, q2);
             // coefficient sums over the lane (reversed position m = forward column N-1-m)
             T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-            const float *ru = tl + (kLanes - 1 - lane) * RS;
-            const float *rv = tl2 + (kLanes - 1 - lane) * RS;
+            const float *ru = tin + (kLanes - 1 - lane) * RS;
+            const float *rv = tout + (kLanes - 1 - lane) * RS;
 #pragma unroll
             for (int k4 = 0; k4 < N / 4; ++k4) {
                 const f4 U = *reinterpret_cast<const f4 *>(ru + 4 * k4);
@@ -1292,11 +1303,12 @@ __global__ void __launch_bounds__(64 * W)
                     s4 = fmaT(-L2, vv, s4);
                 }
             }
-            // d/dzi = (lam'[n-1], lam'[n-2])
+            // d/dzi = (lam'[n-1], lam'[n-2]); scratch: the output tile, already
+            // consumed (the input tile is kept for the next section)
             if (has_first && bi.gzi) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 T l1 = 0, l2 = 0;
-                pick_two<T, N>(u, tl, lane, zl, zp, l1, l2);
+                pick_two<T, N>(u, tout, lane, zl, zp, l1, l2);
                 if (lane == zl) {
                     gptr(bi.gzi)[2 * k] = (float)l1;
                     gptr(bi.gzi)[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
@@ -1326,7 +1338,11 @@ __global__ void __launch_bounds__(64 * W)
                 for (int v = 0; v < W; ++v) acc += red[v][threadIdx.x];
                 b.partials[((size_t)t * b.K + k) * 5 + threadIdx.x] = acc;
             }
-            // the tiles are re-staged for the next section: wave-local, ordered
+            // this section's input tile is the next section's output tile;
+            // the other one is re-staged with the next input (wave-local, ordered)
+            float *const tsw = tin;
+            tin = tout;
+            tout = tsw;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
         if (bad) {
