@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-k", type=int, default=0, help="profile helper: only this K, Butterworth")
     ap.add_argument("--quick", action="store_true", help="headline and sweep only")
+    ap.add_argument("--only-fwd-bwd", action="store_true",
+                    help="profile helper: only the forward + adjoint leg, printed as its own JSON")
     ap.add_argument("--alg", default="dccr", choices=("dccr", "ph"),
                     help="section solver of the headline (the sweep times both)")
     args = ap.parse_args()
@@ -370,6 +372,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.lib()
+    if args.only_fwd_bwd:
+        print(json.dumps({"fwd_bwd": bench_fwd_bwd(torch, P, workloads, np, log)}), flush=True)
+        return
     dev = torch.device("cuda", 0)
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     h = P.Handle(0, tile=tile, algorithm=args.alg)
