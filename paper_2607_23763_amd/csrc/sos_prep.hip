@@ -143,8 +143,10 @@ sos_prep_kernel(const float *__restrict__ sections, int K, int log2n, int log2w,
                     threadIdx.x, pair != 0);
 }
 
-// Uneven batch: block i prepares the K[i] sections of signal i (rows and
-// tables at sec_off[i]); signals with inconsistent entries are skipped.
+// Uneven batch: block (i, k) prepares section k of signal i (row and table at
+// sec_off[i] + k), so the kernel takes one section's time however long the
+// cascades are; signals with inconsistent entries are skipped. Grid =
+// (B, max(kmax, 1)), block = 64.
 template <typename T>
 __global__ void __launch_bounds__(64)
 sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax, int64_t rows,
@@ -153,13 +155,13 @@ sos_prep_batched_kernel(const float *__restrict__ sections, int B, int kmax, int
                         int pair)
 {
     const int i = blockIdx.x;
+    const int k = blockIdx.y;
     if (i >= B) return;
     const int K = Ks[i];
     const int64_t so = sec_off[i];
-    if (K < 0 || K > kmax || so < 0 || so + K > rows) return;
-    for (int k = 0; k < K; ++k)
-        prep_section<T>(sections + 6 * (so + k), tabs + (size_t)(so + k) * TAB_FLOATS, log2n,
-                        log2w, ctrl, threadIdx.x, pair != 0);
+    if (K < 0 || K > kmax || so < 0 || so + K > rows || k >= K) return;
+    prep_section<T>(sections + 6 * (so + k), tabs + (size_t)(so + k) * TAB_FLOATS, log2n, log2w,
+                    ctrl, threadIdx.x, pair != 0);
 }
 
 // K sections -> tables of the compute type `bits` (32 or 64). pair != 0: the
@@ -185,14 +187,14 @@ extern "C" hipError_t sos_launch_prep_batched(int bits, const float *sections, i
                                               hipStream_t stream)
 {
     if (B <= 0) return hipSuccess;
+    if (kmax > 65535) return hipErrorInvalidValue;   // grid y limit (callers cap kmax at 64)
+    const dim3 grid((unsigned)B, (unsigned)(kmax > 0 ? kmax : 1));
     if (bits == 64)
-        hipLaunchKernelGGL(sos_prep_batched_kernel<double>, dim3(B), dim3(64), 0, stream,
-                           sections, B, kmax, rows, Ks, sec_off, log2n, log2w, (double *)tabs,
-                           ctrl, pair);
+        hipLaunchKernelGGL(sos_prep_batched_kernel<double>, grid, dim3(64), 0, stream, sections,
+                           B, kmax, rows, Ks, sec_off, log2n, log2w, (double *)tabs, ctrl, pair);
     else
-        hipLaunchKernelGGL(sos_prep_batched_kernel<float>, dim3(B), dim3(64), 0, stream,
-                           sections, B, kmax, rows, Ks, sec_off, log2n, log2w, (float *)tabs,
-                           ctrl, pair);
+        hipLaunchKernelGGL(sos_prep_batched_kernel<float>, grid, dim3(64), 0, stream, sections,
+                           B, kmax, rows, Ks, sec_off, log2n, log2w, (float *)tabs, ctrl, pair);
     return hipGetLastError();
 }
 
