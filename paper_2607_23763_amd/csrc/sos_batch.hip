@@ -25,16 +25,29 @@ __device__ inline bool signal_ok(int i, int kmax, int64_t rows, int64_t total_sa
            b <= total_samples;
 }
 
+// zf := zi (zeros without zi) for a consistent signal with no samples.
+__device__ inline void empty_signal_state(int i, const int32_t *Ks, const int32_t *sec_off,
+                                          const float *zi, float *zf, int k0, int dk)
+{
+    const int64_t so = sec_off[i];
+    for (int k = k0; k < 2 * Ks[i]; k += dk) zf[2 * so + k] = zi ? zi[2 * so + k] : 0.0f;
+}
+
 // One block of kScanThreads threads: group counts and their exclusive prefix.
 // Optionally it first copies `stage_bytes` of arguments from host memory
 // (pinned, coherent) to device memory and arms the filter launch (ticket 0, a
 // fresh epoch), which saves a step of the server a copy and a launch.
+// fuse != 0 (B <= kScanThreads, few groups): it also fills the ticket map and
+// the empty signals' final states, which saves the fill kernel's launch; the
+// inclusive prefix is still in LDS, so each ticket finds its signal there by
+// binary search.
 __global__ void __launch_bounds__(kScanThreads)
 worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
                       int64_t max_groups,
                       const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                       int64_t *gpre, int64_t *total_dev, unsigned *ctrl,
-                      const unsigned *stage_src, unsigned *stage_dst, int64_t stage_words)
+                      const unsigned *stage_src, unsigned *stage_dst, int64_t stage_words,
+                      int fuse, int32_t *sigmap, const float *zi, float *zf)
 {
     __shared__ int64_t part[kScanThreads];
     __shared__ int64_t carry;
@@ -103,25 +116,37 @@ worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_sa
         gpre[B] = tot;
         *total_dev = tot;
     }
+    if (!fuse) return;
+    // single scan round: part[i] is the inclusive prefix of signal i's groups
+    const int64_t tot = carry > max_groups ? 0 : carry;   // 0: the table was rejected
+    for (int64_t t = tid; t < tot; t += kScanThreads) {
+        int lo = 0, hi = B - 1;                            // first i with part[i] > t
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (part[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        sigmap[t] = lo;
+    }
+    if (zf && tid < B && sig_off[tid + 1] == sig_off[tid] &&
+        signal_ok(tid, kmax, rows, total_samples, Ks, sec_off, sig_off))
+        empty_signal_state(tid, Ks, sec_off, zi, zf, 0, 1);
 }
 
-// Block i: sigmap for the tickets of signal i; zf := zi for empty signals.
+// Block i: sigmap for the tickets of signal i; zf := zi for empty signals
+// (consistent ones only: an inconsistent sec_off must not address zf).
 __global__ void __launch_bounds__(256)
-worktable_fill_kernel(int B, const int64_t *gpre, const int64_t *total_dev, int32_t *sigmap,
-                      const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
-                      const float *zi, float *zf)
+worktable_fill_kernel(int B, int kmax, int64_t rows, int64_t total_samples, const int64_t *gpre,
+                      const int64_t *total_dev, int32_t *sigmap, const int32_t *Ks,
+                      const int32_t *sec_off, const int64_t *sig_off, const float *zi, float *zf)
 {
     const int i = blockIdx.x;
     if (i >= B) return;
     const int64_t a = gpre[i], b = gpre[i + 1];
     if (*total_dev == 0 && b > a) return;   // the table was rejected as a whole
     for (int64_t t = a + threadIdx.x; t < b; t += blockDim.x) sigmap[t] = i;
-    if (zf && a == b && sig_off[i + 1] == sig_off[i] && Ks[i] >= 0) {
-        // no samples: the final state is the initial state (zeros without zi)
-        const int64_t so = sec_off[i];
-        for (int k = threadIdx.x; k < 2 * Ks[i]; k += blockDim.x)
-            zf[2 * so + k] = zi ? zi[2 * so + k] : 0.0f;
-    }
+    if (zf && a == b && sig_off[i + 1] == sig_off[i] &&
+        signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off))
+        empty_signal_state(i, Ks, sec_off, zi, zf, threadIdx.x, blockDim.x);
 }
 
 }  // namespace
@@ -133,15 +158,18 @@ static hipError_t launch_worktable(int B, int kmax, int64_t rows, int64_t C,
                                    float *zf, unsigned *ctrl, const void *stage_src,
                                    void *stage_dst, int64_t stage_bytes, hipStream_t stream)
 {
+    // one kernel when the scan takes one round and the ticket map is short
+    // (at most four binary searches per thread)
+    const int fuse = B <= kScanThreads && max_groups <= 4 * (int64_t)kScanThreads;
     hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax,
                        rows, C, total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev,
                        ctrl, static_cast<const unsigned *>(stage_src),
-                       static_cast<unsigned *>(stage_dst), stage_bytes / 4);
+                       static_cast<unsigned *>(stage_dst), stage_bytes / 4, fuse, sigmap, zi, zf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (B > 0)
-        hipLaunchKernelGGL(worktable_fill_kernel, dim3(B), dim3(256), 0, stream, B, gpre,
-                           total_dev, sigmap, Ks, sec_off, sig_off, zi, zf);
+    if (B > 0 && !fuse)
+        hipLaunchKernelGGL(worktable_fill_kernel, dim3(B), dim3(256), 0, stream, B, kmax, rows,
+                           total_samples, gpre, total_dev, sigmap, Ks, sec_off, sig_off, zi, zf);
     return hipGetLastError();
 }
 

@@ -260,11 +260,15 @@ void launch_step(sos_srv *s, Step &st)
     int64_t grid = grid_of(s->bits, s->alg, s->L, s->N);
     if (grid <= 0 || grid > s->max_groups) grid = s->max_groups;
     if (grid > step_groups) grid = step_groups;
-    // Four launches, no copy operations: the work-table kernel copies the
-    // arguments from the step's pinned host buffer and arms the filter, and the
-    // last kernel reports the error bits into that buffer and clears them.
+    // Three or four launches, no copy operations: the work-table kernel copies
+    // the arguments from the step's pinned host buffer and arms the filter
+    // (and, for a step of at most 1024 chunks and 4096 groups, also fills the
+    // ticket map), and the last kernel reports the error bits into that
+    // buffer and clears them. The step's own group bound (each chunk adds at
+    // most one partial group) sizes the work table.
     bool ok =
-        sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total, s->max_groups, dK, dsec,
+        sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total,
+                                    std::min(step_groups, s->max_groups), dK, dsec,
                                     dsig, h->gpre, h->sigmap, h->total_dev, s->state, s->state,
                                     h->ctrl, hb, d, (int64_t)lb.bytes, s->stream) == hipSuccess &&
         sos_launch_fwd_batched(s->bits, s->alg, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
