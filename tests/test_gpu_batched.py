@@ -118,6 +118,42 @@ def test_inconsistent_signal_is_skipped_and_reported(env):
             assert rel_l2(y[a:b], yr[a:b]) <= 1e-5
 
 
+@pytest.mark.parametrize("B", [3, 1500])     # one kernel for the work table, then two
+def test_inconsistent_empty_signal_leaves_zf_alone(env, B):
+    """An empty signal whose section offset runs past the section rows is
+    reported and skipped: its final state is not written, so nothing past
+    the end of zf changes (a guard region after zf keeps its sentinel)."""
+    torch, P = env
+    rng = workloads.rng(33)
+    rows = np.concatenate([workloads.random_stable_sos(2, rng) for _ in range(B)])
+    R = rows.shape[0]                                  # 2 rows per signal
+    Ks = np.full(B, 2, dtype=np.int32)
+    so = np.arange(B + 1, dtype=np.int32) * 2
+    lens = np.full(B, 300, dtype=np.int64)
+    bad = 1
+    lens[bad] = 0
+    Ks[bad] = 2
+    so_bad = so.copy()
+    so_bad[bad] = R - 1                                # so + K = R + 1 > R
+    sig_off = np.r_[0, np.cumsum(lens)].astype(np.int64)
+    x = workloads.batch_signal(int(sig_off[-1]), seed=34)
+    zi = workloads.initial_state(R, rng)
+    zf_full = torch.full((R + 4, 2), 7.0, device="cuda")
+    zf = zf_full[:R]
+    h = P.Handle(0)
+    y, _ = P.sosfilt_batched(dev(torch, x), dev(torch, rows), dev(torch, Ks), dev(torch, sig_off),
+                             zi=dev(torch, zi), zf=zf, sec_off=dev(torch, so_bad), kmax=2,
+                             handle=h)
+    assert h.last_error() == P.SOS_EINVAL
+    guard = zf_full[R:].cpu().numpy()
+    assert np.all(guard == 7.0), guard
+    y = y.cpu().numpy()
+    for i in (0, B - 1):                               # consistent neighbours still filtered
+        a, b = sig_off[i], sig_off[i + 1]
+        yr, zfr = oracle.sosfilt(rows[so[i]:so[i] + 2], x[a:b], zi[so[i]:so[i] + 2])
+        assert rel_l2(y[a:b], yr) <= 1e-5, i
+
+
 def test_full_size_uneven_batch_graph_tuned(env):
     """The benchmarked uneven batch at full size (4096 signals, ~2e9 samples,
     device-drawn samples) in the benchmarked launch configuration: autotuned
