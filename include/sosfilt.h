@@ -39,7 +39,12 @@
  * the first call of a larger shape and is reused afterwards. Calls that share
  * one handle must be ordered (same stream, or synchronised): the workspace is
  * not shared safely between concurrently running calls. Use one handle per
- * concurrently used stream.
+ * concurrently used stream. A HIP graph that captures calls of a handle
+ * holds pointers into its workspace: while such a graph may still be
+ * replayed, make no call of a larger shape on that handle (it would replace
+ * the workspace), or give the graph a handle of its own. A captured plain
+ * filter carries its own re-arm step, so eager calls of any kind between
+ * replays are otherwise fine.
  *
  * Errors: every function returns an int status and never aborts across the
  * ABI. Argument errors are detected synchronously. Problems found on the
