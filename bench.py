@@ -355,6 +355,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline and sweep only")
     ap.add_argument("--only-fwd-bwd", action="store_true",
                     help="profile helper: only the forward + adjoint leg, printed as its own JSON")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="profile helper: only the uneven-batch leg, printed as its own JSON")
     ap.add_argument("--alg", default="dccr", choices=("dccr", "ph"),
                     help="section solver of the headline (the sweep times both)")
     args = ap.parse_args()
@@ -374,6 +376,9 @@ def main():
     P.lib()
     if args.only_fwd_bwd:
         print(json.dumps({"fwd_bwd": bench_fwd_bwd(torch, P, workloads, np, log)}), flush=True)
+        return
+    if args.only_batched:
+        print(json.dumps({"batched": bench_batched(torch, P, workloads, np, log)}), flush=True)
         return
     dev = torch.device("cuda", 0)
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
