@@ -67,7 +67,8 @@ enum {
     SOS_OK = 0,
     SOS_EINVAL = -1,      /* bad argument (null pointer, negative size, K out of range ...) */
     SOS_EA0 = -2,         /* a section has a0 == 0                                          */
-    SOS_EUNSTABLE = -3,   /* |a2| > 1 or |a1| > 1 + a2 after normalisation                   */
+    SOS_EUNSTABLE = -3,   /* |a2| >= 1 or |a1| >= 1 + a2 after normalisation (a pole on or  */
+                          /* outside the unit circle)                                       */
     SOS_ENOMEM = -4,      /* device allocation failed                                        */
     SOS_EHIP = -5,        /* a HIP runtime call failed                                       */
     SOS_ETIMEOUT = -6,    /* a lookback wait exceeded its bound (outputs poisoned with NaN)  */
@@ -105,38 +106,50 @@ int sos_last_error(sos_handle_t h);
 int sos_set_tile(sos_handle_t h, int L, int N);
 int sos_get_tile(sos_handle_t h, int *L, int *N);
 
-/* Arithmetic type of the filter kernels: 32 (FP32, the default) or 64 (FP64;
- * 0 restores the default). Data in memory stay FP32 either way. The solver
- * applies derived coefficients (fold taps, level coefficients, state-map
- * powers) that are rounded to the compute type; for cascades of lightly
- * damped sections (poles within ~0.05 of the unit circle, high order) FP32
- * rounding of those coefficients can cost more accuracy than a sequential
- * FP32 filter loses, and FP64 removes it. MI355X issues FP64 FMAs at the
- * unpacked-FP32 rate, so the cost is register pressure. Applies to later
- * calls. */
+/* Arithmetic type of the per-sample work of the filter kernels: 32 (FP32,
+ * the default) or 64 (FP64; 0 restores the default). Data in memory stay FP32
+ * either way, and everything that acts on carried states (the lanes' and
+ * groups' terminal states, the scans over lanes, waves and groups through
+ * powers of the state map, the lanes' incoming states and zf) is computed in
+ * FP64 whatever the type: those powers are badly conditioned for lightly
+ * damped sections with poles near the real axis, and FP32 rounding of them
+ * would be amplified into every sample of a group. With FP32, a cascade is
+ * about as accurate as a sequential FP32 filter; FP64 goes further where a
+ * cascade's own FP32 error floor is too high. MI355X issues FP64 FMAs at the
+ * unpacked-FP32 rate, so the cost of FP64 is register pressure. Applies to
+ * later calls. */
 int sos_set_precision(sos_handle_t h, int bits);
 int sos_get_precision(sos_handle_t h);
 
 /* Section solver of the filter kernels (Sec. IV-E compares the candidates):
- *   SOS_ALG_DCCR  divide-and-conquer cyclic reduction (Sec. II-E, the
- *                 default): both terminal blocks of every lane from a
- *                 log-depth reduction of each parity chain, then back
- *                 substitution; about 9 FMAs per sample and section.
+ *   SOS_ALG_DCCR  divide-and-conquer cyclic reduction (Sec. II-E): both
+ *                 terminal blocks of every lane from a log-depth reduction of
+ *                 each parity chain, then back substitution; about 9 FMAs per
+ *                 sample and section.
  *   SOS_ALG_PH    PH factorization (Sec. II-C): the lane's particular
  *                 solution (its samples through the section from rest,
  *                 Eq. (9)), then the homogeneous correction of every sample
  *                 from the lane's incoming state (Eq. (11)); about 7 FMAs per
  *                 sample and section and a lane-sequential chain of N FMAs.
- * Both share the cross-lane scan, the decoupled lookback, the tables and the
+ *   SOS_ALG_AUTO  DC-CR for every section except those whose recursive part
+ *                 has a peak gain 1 / min |A(e^{jw})| above 32 (poles very
+ *                 close to the unit circle), which are solved by PH in the
+ *                 same launch. DC-CR's fold multiplies by A(-z), which
+ *                 amplifies rounding near the mirror frequency of such poles
+ *                 when an earlier section has put the signal's energy there;
+ *                 PH applies no such factor. Butterworth designs up to order
+ *                 16 stay on DC-CR entirely.
+ * All share the cross-lane scan, the decoupled lookback, the tables and the
  * state conventions, and accept every tile and compute type. SOS_ALG_DEFAULT
- * (0) restores the default: SOS_ALG in the environment ("ph" or "dccr"),
- * else DC-CR. Applies to later launches of the handle: plain, batched,
- * captured batches, servers created afterwards, and both passes of the
- * adjoint (the training forward and the reversed-time recursion of the VJP).
+ * (0) restores the default: SOS_ALG in the environment ("auto", "dccr" or
+ * "ph"), else SOS_ALG_AUTO. Applies to later launches of the handle: plain,
+ * batched, captured batches, servers created afterwards, and both passes of
+ * the adjoint (the training forward and the reversed-time recursion of the
+ * VJP). Tables prepared by sos_prepare belong to the solver in effect then.
  * sos_set_algorithm returns SOS_EINVAL for an unknown value or a null
- * handle; sos_get_algorithm returns the solver in effect (SOS_ALG_DCCR or
- * SOS_ALG_PH), or SOS_EINVAL for a null handle. */
-enum { SOS_ALG_DEFAULT = 0, SOS_ALG_DCCR = 1, SOS_ALG_PH = 2 };
+ * handle; sos_get_algorithm returns the solver in effect (SOS_ALG_AUTO,
+ * SOS_ALG_DCCR or SOS_ALG_PH), or SOS_EINVAL for a null handle. */
+enum { SOS_ALG_DEFAULT = 0, SOS_ALG_DCCR = 1, SOS_ALG_PH = 2, SOS_ALG_AUTO = 3 };
 int sos_set_algorithm(sos_handle_t h, int alg);
 int sos_get_algorithm(sos_handle_t h);
 
@@ -306,12 +319,14 @@ int sos_graph_destroy(sos_graph_t g);
  * tiles whose padded work exceeds 1.5x the best tile's are dropped), then
  * each survivor is timed (one warm-up, `reps` timed runs, median, HIP events
  * on `stream`). When h has no section solver set (SOS_ALG_DEFAULT), every
- * tile is timed with both solvers and the winning solver becomes h's too;
- * otherwise only h's solver is timed. The fastest tile becomes h's tile and
- * is cached per (compute type, requested solver, kmax, B, floor(log2
- * total_samples)) for sos_tune_lookup (a default request is also cached under
- * the winning solver); y and zf end up holding the winner's result. zi must
- * not equal zf (the batch runs several times). Synchronises `stream`. */
+ * tile is timed with SOS_ALG_AUTO and SOS_ALG_PH and the winning solver
+ * becomes h's too; otherwise only h's solver is timed. The fastest tile
+ * becomes h's tile and is cached per (compute type, requested solver, kmax,
+ * B, floor(log2 total_samples)) for sos_tune_lookup (a default request is
+ * also cached under the winning solver); y and zf end up holding the
+ * winner's result. The batch runs several times, so it cannot be filtered in
+ * place: x == y (with samples) and zi == zf return SOS_EINVAL. Synchronises
+ * `stream`. */
 int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_t total_samples,
                      const int32_t *K, const int32_t *sec_off, const float *sections,
                      const int64_t *sig_off, const float *x, float *y, const float *zi,
@@ -360,22 +375,32 @@ int sos_stream_open(sos_server_t s, const float *sections_host, int K, const flo
                     int64_t *stream_id);
 /* Enqueue the next chunk of a stream: n samples at `chunk`, output to `out`.
  * Returns at once with a ticket for sos_stream_wait. SOS_EINVAL for n < 0 or
- * n above the largest chunk, SOS_ECLOSED for an unknown or closing stream. */
+ * n above the largest chunk, SOS_ECLOSED for an unknown or closing stream,
+ * and the stream's failure status for a failed stream (below). */
 int sos_stream_push(sos_server_t s, int64_t stream_id, const float *chunk, int64_t n, float *out,
                     uint64_t *ticket);
 /* The same for `count` chunks at once (one lock; arrays of count entries). */
 int sos_stream_push_many(sos_server_t s, int count, const int64_t *stream_ids,
                          const float *const *chunks, const int64_t *n, float *const *outs,
                          uint64_t *tickets);
-/* Block until the chunk is filtered; returns its status (SOS_OK, or
- * SOS_ETIMEOUT / SOS_EINVAL / SOS_EHIP for its step, SOS_ECLOSED if the server
- * was destroyed first) and, if latency_s is not NULL, the time in seconds from
- * its push to the host's observation that its step completed. A ticket can be
- * waited on once. */
+/* Block until the chunk is filtered; returns its own status and, if
+ * latency_s is not NULL, the time in seconds from its push to the host's
+ * observation that its step completed. A ticket can be waited on once.
+ * Statuses are per chunk: SOS_ETIMEOUT when a lookback wait of this chunk's
+ * groups ran out (its outputs from there on are NaN), SOS_EINVAL when its
+ * step's work table rejected it, SOS_EHIP when its step could not be
+ * launched, SOS_ECLOSED when the server was destroyed first. The other
+ * chunks of the same step are not affected. A failed chunk leaves its
+ * stream's device state invalid (the state is updated in place), so the
+ * stream fails from then on: its chunks that finish later report the same
+ * status, later pushes return it at once, and sos_stream_state returns it
+ * instead of a state. Close the stream and open it again (from a
+ * checkpoint) to continue. */
 int sos_stream_wait(sos_server_t s, uint64_t ticket, double *latency_s);
 /* After all chunks pushed so far on the stream are finished, copy its K x 2
  * TDF-II state to HOST memory zf_host (a checkpoint: reopening a stream with
- * these states continues it exactly). */
+ * these states continues it exactly). Returns a failed stream's status
+ * without copying. */
 int sos_stream_state(sos_server_t s, int64_t stream_id, float *zf_host);
 /* Wait for the stream's outstanding chunks, then release its rows. */
 int sos_stream_close(sos_server_t s, int64_t stream_id);

@@ -30,9 +30,10 @@ SOS_MAX_SECTIONS = 64
 SOS_ALG_DEFAULT = 0
 SOS_ALG_DCCR = 1
 SOS_ALG_PH = 2
+SOS_ALG_AUTO = 3
 _ALGS = {None: SOS_ALG_DEFAULT, "default": SOS_ALG_DEFAULT, "dccr": SOS_ALG_DCCR,
-         "ph": SOS_ALG_PH, SOS_ALG_DEFAULT: SOS_ALG_DEFAULT, SOS_ALG_DCCR: SOS_ALG_DCCR,
-         SOS_ALG_PH: SOS_ALG_PH}
+         "ph": SOS_ALG_PH, "auto": SOS_ALG_AUTO, SOS_ALG_DEFAULT: SOS_ALG_DEFAULT,
+         SOS_ALG_DCCR: SOS_ALG_DCCR, SOS_ALG_PH: SOS_ALG_PH, SOS_ALG_AUTO: SOS_ALG_AUTO}
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -158,8 +159,10 @@ class Handle:
             self.set_algorithm(algorithm)
 
     def set_algorithm(self, alg):
-        """Section solver: "dccr" (cyclic reduction), "ph" (particular +
-        homogeneous), or None / "default"."""
+        """Section solver: "auto" (cyclic reduction, with PH for sections whose
+        poles lie very close to the unit circle), "dccr" (cyclic reduction
+        throughout), "ph" (particular + homogeneous), or None / "default"
+        (the environment's SOS_ALG, else "auto")."""
         code = _ALGS.get(alg if not isinstance(alg, str) else alg.lower())
         if code is None:
             raise ValueError("unknown algorithm %r" % (alg,))
@@ -167,7 +170,7 @@ class Handle:
 
     def algorithm(self) -> str:
         code = int(lib().sos_get_algorithm(self._h))
-        return {SOS_ALG_DCCR: "dccr", SOS_ALG_PH: "ph"}[code]
+        return {SOS_ALG_DCCR: "dccr", SOS_ALG_PH: "ph", SOS_ALG_AUTO: "auto"}[code]
 
     def set_precision(self, bits: int):
         """Compute type of the kernels: 32 or 64 (0 = default)."""

@@ -44,7 +44,8 @@ int ensure_desc(sos_ctx *h, size_t words, hipStream_t stream)
 
 size_t tab_bytes(int sections, int bits)
 {
-    return (size_t)sections * TAB_FLOATS * (bits == 64 ? 8 : 4);
+    (void)bits;   // one layout for both compute types
+    return (size_t)sections * TAB_BYTES;
 }
 
 int check_signal(const float *x, const float *y, int64_t n)
@@ -68,10 +69,11 @@ int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream,
     int rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes(K > 8 ? K : 8, bits), stream);
     if (rc) return rc;
     if (sos_launch_prep(bits, sections, K, __builtin_ctz((unsigned)t.N),
-                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl, 0,
+                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl, 0, rho_max_of(h),
                         stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = K;
+    h->prep_alg = solver_of(h);
     h->prep_L = t.L;
     h->prep_N = t.N;
     h->prep_bits = bits;
@@ -115,8 +117,9 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     // else armed here. A launch being captured into a graph carries its own
     // arm step, so that every replay is self-contained.
     const bool cap = capturing(stream);
-    if ((!h->armed || cap) && sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    const int alg = alg_of(h);
+    if ((!h->armed || cap || h->batch_captured) && sos_launch_arm(h->ctrl, stream) != hipSuccess)
+        return SOS_EHIP;
+    const int alg = launch_alg(bits, h->prep_alg);
     if (sos_launch_fwd(bits, alg, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
                        h->timeout_ticks, grid_of(bits, alg, L, N), saved, stream) != hipSuccess)
         return SOS_EHIP;
@@ -141,6 +144,7 @@ void mark_degenerate(sos_ctx *h, int K)
     h->prep_L = t.L;
     h->prep_N = t.N;
     h->prep_bits = bits_of(h);
+    h->prep_alg = solver_of(h);
 }
 
 }  // namespace
@@ -181,27 +185,29 @@ int batch_reserve(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
 int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream)
 {
     h->armed = false;   // a batched launch leaves the ticket counter advanced
+    if (capturing(stream)) h->batch_captured = true;
     const int64_t C = (int64_t)t.L * t.N;
     const int64_t max_groups = ba.total_samples / C + ba.B;
     const int kd = ba.kmax > 0 ? ba.kmax : 1;
     const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
     if (ba.total_rows > 0 &&
         sos_launch_prep_batched(bits, ba.sections, ba.B, ba.kmax, ba.total_rows, ba.K,
-                                ba.sec_off, log2n, log2w, h->tabs, h->ctrl, 0, stream) !=
-            hipSuccess)
+                                ba.sec_off, log2n, log2w, h->tabs, h->ctrl, 0, rho_max_of(h),
+                                stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_worktable(ba.B, ba.kmax, ba.total_rows, C, ba.total_samples, max_groups, ba.K,
                              ba.sec_off, ba.sig_off, h->gpre, h->sigmap, h->total_dev, ba.zi,
                              ba.zf, h->ctrl, stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    const int alg = alg_of(h);
+    const int alg = launch_alg(bits, solver_of(h));
     int64_t grid = grid_of(bits, alg, t.L, t.N);
     if (grid <= 0 || grid > max_groups) grid = max_groups;
     if (sos_launch_fwd_batched(bits, alg, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
                                h->sigmap, h->total_dev, ba.x, ba.y, h->tabs, ba.zi, ba.zf,
                                h->desc, h->ctrl, h->timeout_ticks, grid, nullptr, nullptr,
-                               ba.saved, ba.total_samples, max_groups, stream) != hipSuccess)
+                               ba.saved, ba.total_samples, max_groups, nullptr,
+                               stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = -1;        // the batch overwrote the plain tables
     h->last_groups = 0;
@@ -347,7 +353,8 @@ int sos_get_precision(sos_handle_t h)
 
 int sos_set_algorithm(sos_handle_t h, int alg)
 {
-    if (!h || (alg != SOS_ALG_DEFAULT && alg != SOS_ALG_DCCR && alg != SOS_ALG_PH))
+    if (!h || (alg != SOS_ALG_DEFAULT && alg != SOS_ALG_DCCR && alg != SOS_ALG_PH &&
+               alg != SOS_ALG_AUTO))
         return SOS_EINVAL;
     h->alg = alg;
     return SOS_OK;
@@ -356,7 +363,7 @@ int sos_set_algorithm(sos_handle_t h, int alg)
 int sos_get_algorithm(sos_handle_t h)
 {
     if (!h) return SOS_EINVAL;
-    return alg_of(h) == ALG_PH ? SOS_ALG_PH : SOS_ALG_DCCR;
+    return solver_of(h);
 }
 
 int sos_prepare(sos_handle_t h, const float *sections, int K, hipStream_t stream)
@@ -379,7 +386,7 @@ int sos_filter_prepared(sos_handle_t h, const float *x, float *y, int64_t n, con
     // Without a tile set, whatever shape the tables were prepared at is valid
     // (sos_filter picks it from the signal length).
     const Tile t = tile_of(h, h->prep_K);
-    if (h->prep_K < 0 || h->prep_bits != bits_of(h) ||
+    if (h->prep_K < 0 || h->prep_bits != bits_of(h) || h->prep_alg != solver_of(h) ||
         (tile_is_set(h) && (h->prep_N != t.N || h->prep_L != t.L)))
         return SOS_EINVAL;
     DeviceGuard g(h->device);
@@ -483,10 +490,11 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
     if (rc) return rc;
     if (sos_launch_prep(bits, sections, K, __builtin_ctz((unsigned)t.N),
                         __builtin_ctz((unsigned)(t.L / 64)), h->tabs_bwd, h->ctrl, 1,
-                        stream) != hipSuccess)
+                        rho_max_of(h), stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_bwd(bits, alg_of(h), t.L, t.N, gy, gx, n, groups, h->tabs_bwd, K, x, y, saved,
+    if (sos_launch_bwd(bits, launch_alg(bits, solver_of(h)), t.L, t.N, gy, gx, n, groups,
+                       h->tabs_bwd, K, x, y, saved,
                        gzf, gzi, h->partials, h->desc, h->ctrl, h->timeout_ticks, grid_override(),
                        stream) != hipSuccess)
         return SOS_EHIP;
@@ -561,7 +569,7 @@ int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
     const int log2n = __builtin_ctz((unsigned)t.N), log2w = __builtin_ctz((unsigned)(t.L / 64));
     if (total_rows > 0 &&
         sos_launch_prep_batched(bits, sections, B, kmax, total_rows, K, sec_off, log2n, log2w,
-                                h->tabs_bwd, h->ctrl, 1, stream) != hipSuccess)
+                                h->tabs_bwd, h->ctrl, 1, rho_max_of(h), stream) != hipSuccess)
         return SOS_EHIP;
     // work table over the adjoint's groups; an empty signal gets gzi = gzf
     if (sos_launch_worktable(B, kmax, total_rows, C, total_samples, max_groups, K, sec_off,
@@ -569,12 +577,14 @@ int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
                              stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_bwd_batched(bits, alg_of(h), t.L, t.N, B, kd, K, sec_off, sig_off, h->gpre,
+    if (sos_launch_bwd_batched(bits, launch_alg(bits, solver_of(h)), t.L, t.N, B, kd, K, sec_off,
+                               sig_off, h->gpre,
                                h->sigmap, h->total_dev, max_groups, gy, gx, h->tabs_bwd, x, y, saved,
                                total_samples, gzf, gzi, h->partials, h->desc, h->ctrl,
                                h->timeout_ticks, stream) != hipSuccess)
         return SOS_EHIP;
-    if (gsections && sos_launch_bwd_reduce_batched(h->partials, B, kd, K, sec_off, h->gpre,
+    if (gsections && sos_launch_bwd_reduce_batched(h->partials, B, kmax, total_rows,
+                                                   total_samples, K, sec_off, sig_off, h->gpre,
                                                    sections, gsections, stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = -1;

@@ -19,10 +19,7 @@ __device__ inline bool signal_ok(int i, int kmax, int64_t rows, int64_t total_sa
                                  const int32_t *Ks, const int32_t *sec_off,
                                  const int64_t *sig_off)
 {
-    const int K = Ks[i];
-    const int64_t so = sec_off[i], a = sig_off[i], b = sig_off[i + 1];
-    return K >= 0 && K <= kmax && so >= 0 && so + K <= rows && a >= 0 && b >= a &&
-           b <= total_samples;
+    return batch_signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off);
 }
 
 // zf := zi (zeros without zi) for a consistent signal with no samples.
@@ -47,7 +44,7 @@ worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_sa
                       const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                       int64_t *gpre, int64_t *total_dev, unsigned *ctrl,
                       const unsigned *stage_src, unsigned *stage_dst, int64_t stage_words,
-                      int fuse, int32_t *sigmap, const float *zi, float *zf)
+                      int fuse, int32_t *sigmap, const float *zi, float *zf, unsigned *sig_err)
 {
     __shared__ int64_t part[kScanThreads];
     __shared__ int64_t carry;
@@ -86,12 +83,16 @@ worktable_scan_kernel(int B, int kmax, int64_t rows, int64_t C, int64_t total_sa
         const int i = base + tid;
         int64_t gi = 0;
         if (i < B) {
-            if (signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off)) {
+            const bool ok = signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off);
+            if (ok) {
                 const int64_t n = sig_off[i + 1] - sig_off[i];
                 gi = (n + C - 1) / C;
             } else {
                 atomicOr(&ctrl[CTRL_ERR], ERRBIT_BADARG);
             }
+            // this launch's per-signal error words start here (the filter adds
+            // its lookback timeouts)
+            if (sig_err) sig_err[i] = ok ? 0u : ERRBIT_BADARG;
         }
         part[tid] = gi;
         __syncthreads();
@@ -156,7 +157,8 @@ static hipError_t launch_worktable(int B, int kmax, int64_t rows, int64_t C,
                                    const int32_t *sec_off, const int64_t *sig_off, int64_t *gpre,
                                    int32_t *sigmap, int64_t *total_dev, const float *zi,
                                    float *zf, unsigned *ctrl, const void *stage_src,
-                                   void *stage_dst, int64_t stage_bytes, hipStream_t stream)
+                                   void *stage_dst, int64_t stage_bytes, unsigned *sig_err,
+                                   hipStream_t stream)
 {
     // one kernel when the scan takes one round and the ticket map is short
     // (at most four binary searches per thread)
@@ -164,7 +166,8 @@ static hipError_t launch_worktable(int B, int kmax, int64_t rows, int64_t C,
     hipLaunchKernelGGL(worktable_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, B, kmax,
                        rows, C, total_samples, max_groups, Ks, sec_off, sig_off, gpre, total_dev,
                        ctrl, static_cast<const unsigned *>(stage_src),
-                       static_cast<unsigned *>(stage_dst), stage_bytes / 4, fuse, sigmap, zi, zf);
+                       static_cast<unsigned *>(stage_dst), stage_bytes / 4, fuse, sigmap, zi, zf,
+                       sig_err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (B > 0 && !fuse)
@@ -182,7 +185,8 @@ extern "C" hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_
                                            hipStream_t stream)
 {
     return launch_worktable(B, kmax, rows, C, total_samples, max_groups, Ks, sec_off, sig_off,
-                            gpre, sigmap, total_dev, zi, zf, ctrl, nullptr, nullptr, 0, stream);
+                            gpre, sigmap, total_dev, zi, zf, ctrl, nullptr, nullptr, 0, nullptr,
+                            stream);
 }
 
 // The same, first copying stage_bytes (a multiple of 4; both buffers 8-byte
@@ -195,12 +199,13 @@ extern "C" hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows,
                                                   int32_t *sigmap, int64_t *total_dev,
                                                   const float *zi, float *zf, unsigned *ctrl,
                                                   const void *stage_src, void *stage_dst,
-                                                  int64_t stage_bytes, hipStream_t stream)
+                                                  int64_t stage_bytes, unsigned *sig_err,
+                                                  hipStream_t stream)
 {
     if (!stage_src || !stage_dst || stage_bytes < 0 || (stage_bytes & 3) ||
         ((reinterpret_cast<uintptr_t>(stage_src) | reinterpret_cast<uintptr_t>(stage_dst)) & 7))
         return hipErrorInvalidValue;
     return launch_worktable(B, kmax, rows, C, total_samples, max_groups, Ks, sec_off, sig_off,
                             gpre, sigmap, total_dev, zi, zf, ctrl, stage_src, stage_dst,
-                            stage_bytes, stream);
+                            stage_bytes, sig_err, stream);
 }

@@ -38,9 +38,22 @@
 // sample and section instead of about 9, and one lane-sequential chain of N
 // dependent FMAs instead of the reduction's log-depth levels.
 //
-// Compute type T: float, or double for lightly damped / high-order cascades
-// (MI355X issues FP64 FMAs at the same rate as unpacked FP32 FMAs; the cost
-// is registers). Data in HBM, LDS staging and descriptor values are FP32.
+// Compute type T of the per-sample work: float, or double. Everything that
+// acts on carried states (the lanes' terminal states, the scans, the wave
+// combination, the lookback composition, the lanes' incoming states and zf)
+// is computed in FP64 with FP64 tables whatever T is: it is O(1) per lane and
+// section, and MI355X issues FP64 FMAs at the unpacked FP32 rate, while FP32
+// powers of the state map of a lightly damped section near the real axis
+// lose accuracy in proportion to 1/sin(theta). Each lane's incoming state is
+// applied to its samples through two orthonormal columns spanning the free
+// responses, after the FP64 change of basis R, so the two correction terms do
+// not cancel. Data in HBM, LDS staging and descriptor values are FP32.
+//
+// Inside a DC-CR launch, a section whose recursive part has a peak gain
+// above the handle's bound (marked in its table) is solved by PH: the fold
+// B(z)A(-z) amplifies rounding near the mirror frequency pi - theta of a
+// pole close to the unit circle, where an earlier section's resonance may
+// have put the signal's energy; PH applies no such factor.
 //
 // Descriptors: per (group, section) four 64-bit words {agg.z1, agg.z2,
 // inc.z1, inc.z2}, each {float value | 32-bit epoch tag}, stored
@@ -65,7 +78,7 @@ struct FwdArgs {
     const float *x;
     float *y;
     int64_t n;
-    const void *tabs;       // K x TAB_FLOATS entries of the compute type
+    const void *tabs;       // K tables of TAB_BYTES (sos_device.h)
     const float *zi;
     float *zf;
     int K;                  // plain: sections; batched: descriptor stride (max sections)
@@ -79,6 +92,7 @@ struct FwdArgs {
     const int64_t *total_dev;  // number of work items (batched)
     const float *const *xp; // batched, optional: per-signal input pointers (else x + sig_off)
     float *const *yp;       //   and output pointers (else y + sig_off)
+    unsigned *sig_err;      // batched, optional: per-signal error bits (ERRBIT_*)
     // both modes
     float *saved;           // optional: outputs of sections 0..K-2, section s of a signal at
                             // saved + s * saved_stride (+ its sample offset when batched)
@@ -98,11 +112,12 @@ struct Item {
     int64_t n;              // samples in the signal
     int64_t g;              // group index within the signal
     int64_t t;              // ticket (descriptor row)
-    const T *tabs;          // tables of the signal's sections
+    const unsigned char *tabs;   // tables of the signal's sections
     const float *zi;
     float *zf;
     float *saved;           // the signal's intermediate outputs (or null)
     int K;
+    int sig;                // signal of a batch (0 in plain mode)
 };
 
 // ----------------------------------------------------------------- lane ops
@@ -179,16 +194,64 @@ __device__ __forceinline__ void mv_add(ctabT<T> *p, T v1, T v2, T &o1, T &o2)
     o2 = n2;
 }
 
+// The two table layouts (sos_device.h) as seen by the kernels. S is the type
+// of the state arithmetic and of the state tables, X that of a lane's
+// zero-state incoming state kept across the lookback, and the *_ entries are
+// indexes into the state part (st) and the per-sample part (sp).
+template <typename T, bool ACC>
+struct Lay;
+template <typename T>
+struct Lay<T, false> {   // fast: one array of the compute type
+    using S = T;
+    using X = T;
+    enum : int {
+        KS = OFF_KS, TC = OFF_TC, TW = OFF_TW, TWAVE = OFF_TWAVE, WPOW = OFF_WPOW,
+        LANEPOW = OFF_LANEPOW, GRPPOW = OFF_GRPPOW, SCANPOW = OFF_SCANPOW, B1 = OFF_B1,
+        B2 = OFF_B2, A1 = OFF_A1, A2 = OFF_A2,
+        P_FIR = OFF_FIR, P_TAPS = OFF_TAPS, P_B1 = OFF_B1, P_B2 = OFF_B2, P_A1 = OFF_A1,
+        P_A2 = OFF_A2, P_E = OFF_E, P_F = OFF_F
+    };
+    static __device__ __forceinline__ const S *st(const unsigned char *tb)
+    {
+        return reinterpret_cast<const S *>(tb + TAB_HDR);
+    }
+    static __device__ __forceinline__ const T *sp(const unsigned char *tb)
+    {
+        return reinterpret_cast<const T *>(tb + TAB_HDR);
+    }
+};
+template <>
+struct Lay<float, true> {   // accurate: FP64 state part, FP32 per-sample part
+    using S = double;
+    using X = float;
+    enum : int {
+        KS = SD_KS, TC = SD_TC, TW = SD_TW, TWAVE = SD_TWAVE, WPOW = SD_WPOW,
+        LANEPOW = SD_LANEPOW, GRPPOW = SD_GRPPOW, SCANPOW = SD_SCANPOW, B1 = SD_B1,
+        B2 = SD_B2, A1 = SD_A1, A2 = SD_A2,
+        P_FIR = AP_FIR, P_TAPS = AP_TAPS, P_B1 = AP_B1, P_B2 = AP_B2, P_A1 = AP_A1,
+        P_A2 = AP_A2, P_E = AP_E, P_F = AP_F
+    };
+    static __device__ __forceinline__ const S *st(const unsigned char *tb)
+    {
+        return reinterpret_cast<const S *>(tb + TAB_HDR);
+    }
+    static __device__ __forceinline__ const float *sp(const unsigned char *tb)
+    {
+        return reinterpret_cast<const float *>(tb + kAccSampleOff);
+    }
+};
+
 // Inclusive affine scan over the 64 lanes of a wave:
 //   P[l] = t[l] + S P[l-1]   (P[-1] = 0),  S = the state map across one lane,
 // the cross-lane terminal-state recurrence (role of Eq. (13)). Within each
 // 16-lane row a Kogge-Stone ladder with the uniform powers S^(2^k), k < 4;
 // then rows 1 and 3 add lane 15 / 47 through S^((l%16)+1) and rows 2 and 3
 // add lane 31 through S^(l-31) (per-lane powers from the table).
-template <typename T>
-__device__ __forceinline__ void wave_scan(T &p1, T &p2, const T *tabv, int lane)
+template <typename LY, typename S>
+__device__ __forceinline__ void wave_scan(S &p1, S &p2, const S *stv, int lane)
 {
-    ctabT<T> *tab = ctabp(tabv);
+    using T = S;
+    ctabT<T> *tab = ctabp(stv);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         T q1, q2;
@@ -198,10 +261,10 @@ __device__ __forceinline__ void wave_scan(T &p1, T &p2, const T *tabv, int lane)
         case 2: q1 = dpp0<DPP_ROW_SHR + 4, 0xF>(p1); q2 = dpp0<DPP_ROW_SHR + 4, 0xF>(p2); break;
         default: q1 = dpp0<DPP_ROW_SHR + 8, 0xF>(p1); q2 = dpp0<DPP_ROW_SHR + 8, 0xF>(p2); break;
         }
-        mv_add<T>(tab + OFF_KS + 4 * k, q1, q2, p1, p2);
+        mv_add<T>(tab + LY::KS + 4 * k, q1, q2, p1, p2);
     }
-    const M2<T> pa = load_m2(tabv + OFF_SCANPOW + 8 * lane);
-    const M2<T> pb = load_m2(tabv + OFF_SCANPOW + 8 * lane + 4);
+    const M2<T> pa = load_m2(stv + LY::SCANPOW + 8 * lane);
+    const M2<T> pb = load_m2(stv + LY::SCANPOW + 8 * lane + 4);
     {
         const T q1 = dpp0<DPP_BCAST15, 0xA>(p1), q2 = dpp0<DPP_BCAST15, 0xA>(p2);
         const T n1 = fmaT(pa.a, q1, fmaT(pa.b, q2, p1));
@@ -303,8 +366,8 @@ __device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, i
 // the wave waits on that single descriptor with exponential backoff, so
 // waiting waves issue one request per poll. On timeout it returns NaNs and
 // sets the error bit (the caller still publishes, so successors terminate).
-template <typename T, int kSpan>
-__device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int s,
+template <int kSpan, typename LY, typename It, typename T>
+__device__ void lookback(const FwdArgs &a, const It &it, const T *stv, int s,
                          unsigned epoch, int lane, T &r1, T &r2)
 {
     // One window of kSpan predecessors per round. Every descriptor read is an
@@ -314,7 +377,7 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
     // +35 %) and, with the next group prefetched, also 8 and 32 at 32 K-sample
     // groups (+2-4 %); two or four windows per round lose.
     constexpr int kWin = 1;
-    const M2<T> gp = load_m2(tabv + OFF_GRPPOW + 4 * lane);   // T^(C lane)
+    const M2<T> gp = load_m2(stv + LY::GRPPOW + 4 * lane);   // T^(C lane)
     T acc1 = 0, acc2 = 0;
     T m00 = 1, m01 = 0, m10 = 0, m11 = 1;   // transform from the newest unconsumed group
     const int64_t first = it.t - it.g;      // ticket of the signal's first group
@@ -370,9 +433,9 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
             // slide past the c consumed groups: m <- m T^(C c)
             T p00, p01, p10, p11;
             if (c == 64) {
-                ctabT<T> *tab = ctabp(tabv);
-                p00 = tab[OFF_TW + 0]; p01 = tab[OFF_TW + 1];
-                p10 = tab[OFF_TW + 2]; p11 = tab[OFF_TW + 3];
+                ctabT<T> *tab = ctabp(stv);
+                p00 = tab[LY::TW + 0]; p01 = tab[LY::TW + 1];
+                p10 = tab[LY::TW + 2]; p11 = tab[LY::TW + 3];
             } else {
                 p00 = readlane(gp.a, c); p01 = readlane(gp.b, c);
                 p10 = readlane(gp.c, c); p11 = readlane(gp.d, c);
@@ -390,7 +453,10 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
             continue;
         }
         if (wall_clock64() - t0 > a.timeout_ticks) {
-            if (lane == 0) atomicOr(&a.ctrl[CTRL_ERR], ERRBIT_TIMEOUT);
+            if (lane == 0) {
+                atomicOr(&a.ctrl[CTRL_ERR], ERRBIT_TIMEOUT);
+                if (a.sig_err) atomicOr(&a.sig_err[it.sig], ERRBIT_TIMEOUT);
+            }
             r1 = r2 = T(__builtin_nanf(""));
             return;
         }
@@ -405,10 +471,24 @@ __device__ void lookback(const FwdArgs &a, const Item<T> &it, const T *tabv, int
 // Exchange area of one workgroup in LDS.
 template <typename T, int W>
 struct Xch {
-    T wave_tot[W][2];   // zero-state totals of the waves
-    T grp[2];           // resolved incoming state of the group
-    int64_t nxt;        // ticket drawn once the last section's state is resolved
-    T zx[2];            // a section's inputs at samples n-1, n-2 (lane that holds n-1)
+    T wave_tot[W][2];        // zero-state totals of the waves (fast layout)
+    T grp[2];                // resolved incoming state of the group (fast layout)
+    double wave_tot_d[W][2]; //   the same for the accurate layout's FP64 state work
+    double grp_d[2];
+    int64_t nxt;             // ticket drawn once the last section's state is resolved
+    T zx[2];                 // a section's inputs at samples n-1, n-2 (lane that holds n-1)
+    template <typename S>
+    __device__ __forceinline__ S (&tot())[W][2]
+    {
+        if constexpr (sizeof(S) == sizeof(T)) return wave_tot;
+        else return wave_tot_d;
+    }
+    template <typename S>
+    __device__ __forceinline__ S (&group())[2]
+    {
+        if constexpr (sizeof(S) == sizeof(T)) return grp;
+        else return grp_d;
+    }
 };
 
 // A value all lanes of a wave hold alike, made visibly uniform (a scalar
@@ -462,23 +542,46 @@ __device__ __forceinline__ void rearm_on_exit(unsigned *ctrl, unsigned epoch)
 // PAIR = true: a pure recursive section 1/A(z) (the adjoint's reversed-time
 //   pass); carries are the last two outputs (y[-2], y[-1]), and the tables hold
 //   the matching state map.
+// ACC: the table layout (sos_device.h). Fast: the state work in the compute
+//   type, the correction through g. Accurate (FP32 only): the state work in
+//   FP64, the correction through the orthonormal columns after R.
 
 // What the zero-state half leaves for the correction half of one section.
-template <typename T>
+template <typename S, typename X>
 struct SecState {
-    T p1, p2;     // the lane's zero-state terminal pair, scanned over the wave
-    T e1w, e2w;   // the wave's incoming state at zero group state (wave-uniform)
-    T g1, g2;     // the group's local carry (lookback wave, wave-uniform)
+    X x1, x2;     // the lane's zero-state incoming state (the scan's exclusive prefix);
+                  // FP32 in the accurate layout, rounded once like a sequential
+                  // filter's state, which keeps the FP64 values off the registers
+                  // that the lookback and the next group's prefetch need
+    S e1w, e2w;   // the wave's incoming state at zero group state (wave-uniform)
+    S g1, g2;     // the group's local carry (lookback wave, wave-uniform)
 };
 
-template <typename T, int N, int W, bool PAIR, int ALG>
-__device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
-                                           const FwdArgs &a, const Item<T> &it, const T *tabv,
-                                           int s, unsigned epoch, int wv, int lane, bool has_last,
-                                           int zl, int zp, SecState<T> &st)
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+
+// The 64-bit header word i of table tb (scalar load).
+__device__ __forceinline__ unsigned long long tab_word(const unsigned char *tb, int i)
 {
+    return ((const __attribute__((address_space(4))) unsigned long long *)tb)[i];
+}
+
+template <typename T, bool ACC, int N, int W, bool PAIR, int ALG>
+__device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
+                                           const FwdArgs &a, const Item<T> &it,
+                                           const unsigned char *tb, int s, unsigned epoch, int wv,
+                                           int lane, bool has_last, int zl, int zp,
+                                           SecState<typename Lay<T, ACC>::S,
+                                                    typename Lay<T, ACC>::X> &st)
+{
+    using LY = Lay<T, ACC>;
+    using S = typename LY::S;
+    using X = typename LY::X;
     constexpr int LOG = __builtin_ctz(N);
-    ctabT<T> *tab = ctabp(tabv);
+    ctabT<T> *tab = ctabp(LY::sp(tb));
+    ctabT<S> *sd = ctabp(LY::st(tb));
 
     // --- inputs kept for the terminal state (and, in LDS, for zf at sample n-1)
     const T xl1 = u[N - 1], xl2 = u[N - 2];
@@ -497,9 +600,9 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
         // place from the end), then the recursion 1/A(z) (in place from the
         // start; one FMA of dependency per sample). Nothing crosses lanes;
         // the lane's incoming state enters only in the correction.
-        const T a1 = tab[OFF_A1], a2 = tab[OFF_A2];
+        const T a1 = tab[LY::P_A1], a2 = tab[LY::P_A2];
         if (!PAIR) {
-            const T b0 = tab[OFF_TAPS + 0], b1 = tab[OFF_B1], b2 = tab[OFF_B2];
+            const T b0 = tab[LY::P_TAPS + 0], b1 = tab[LY::P_B1], b2 = tab[LY::P_B2];
 #pragma unroll
             for (int m = N - 1; m >= 0; --m) {
                 T r = b0 * u[m];
@@ -513,8 +616,8 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
         for (int m = 2; m < N; ++m) u[m] = fmaT(-a1, u[m - 1], fmaT(-a2, u[m - 2], u[m]));
     } else {
         // --- 1. level-1 right-hand side, in place from the end
-        const T c0 = tab[OFF_TAPS + 0], c1 = tab[OFF_TAPS + 1], c2 = tab[OFF_TAPS + 2];
-        const T c3 = tab[OFF_TAPS + 3], c4 = tab[OFF_TAPS + 4];
+        const T c0 = tab[LY::P_TAPS + 0], c1 = tab[LY::P_TAPS + 1], c2 = tab[LY::P_TAPS + 2];
+        const T c3 = tab[LY::P_TAPS + 3], c4 = tab[LY::P_TAPS + 4];
 #pragma unroll
         for (int m = N - 1; m >= 0; --m) {
             T r = c0 * u[m];
@@ -529,7 +632,7 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
 #pragma unroll
         for (int i = 1; i < LOG; ++i) {
             const int st2 = 1 << i;
-            const T e = tab[OFF_E + i], f = tab[OFF_F + i];
+            const T e = tab[LY::P_E + i], f = tab[LY::P_F + i];
 #pragma unroll
             for (int m = N - 1; m >= 0; --m) {
                 if (((m + 1) % (2 * st2)) == 0 || ((m + 2) % (2 * st2)) == 0) {
@@ -543,41 +646,42 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
     }
 
     // --- 3. zero-state terminal state of the lane, scan over the wave
-    const T b1 = tab[OFF_B1], b2 = tab[OFF_B2], a1 = tab[OFF_A1], a2 = tab[OFF_A2];
-    T p1, p2;
+    S p1, p2;
     if (PAIR) {
-        p1 = u[N - 2];
-        p2 = u[N - 1];
+        p1 = (S)u[N - 2];
+        p2 = (S)u[N - 1];
     } else {
-        p1 = b1 * xl1 + b2 * xl2 - a1 * u[N - 1] - a2 * u[N - 2];
-        p2 = b2 * xl1 - a2 * u[N - 1];
+        const S b1 = sd[LY::B1], b2 = sd[LY::B2], a1 = sd[LY::A1], a2 = sd[LY::A2];
+        const S y1 = (S)u[N - 1], y2 = (S)u[N - 2], x1 = (S)xl1, x2 = (S)xl2;
+        p1 = b1 * x1 + b2 * x2 - a1 * y1 - a2 * y2;
+        p2 = b2 * x1 - a2 * y1;
     }
-    wave_scan<T>(p1, p2, tabv, lane);
+    wave_scan<LY>(p1, p2, LY::st(tb), lane);
 
     //     ... and over the W waves of the group (zero group state)
-    T e1w = 0, e2w = 0;      // zero-state incoming state of this wave
+    S e1w = 0, e2w = 0;      // zero-state incoming state of this wave
     if (W > 1) {
         if (lane == 63) {
-            xch.wave_tot[wv][0] = p1;
-            xch.wave_tot[wv][1] = p2;
+            xch.template tot<S>()[wv][0] = p1;
+            xch.template tot<S>()[wv][1] = p2;
         }
         lds_barrier();
         for (int v = 0; v < wv; ++v) {
-            T o1 = xch.wave_tot[v][0], o2 = xch.wave_tot[v][1];
-            mv_add<T>(tab + OFF_TWAVE, e1w, e2w, o1, o2);
+            S o1 = xch.template tot<S>()[v][0], o2 = xch.template tot<S>()[v][1];
+            mv_add<S>(sd + LY::TWAVE, e1w, e2w, o1, o2);
             e1w = o1;
             e2w = o2;
         }
     }
-    st.p1 = p1;
-    st.p2 = p2;
+    st.x1 = (X)dpp0<DPP_WAVE_SHR1, 0xF>(p1);
+    st.x2 = (X)dpp0<DPP_WAVE_SHR1, 0xF>(p2);
     st.e1w = wave_uniform(e1w);
     st.e2w = wave_uniform(e2w);
     st.g1 = st.g2 = 0;
     if (wv == W - 1) {
         // group local carry = state after the last wave at zero group state
-        T g1 = readlane(p1, 63), g2 = readlane(p2, 63);
-        if (W > 1) mv_add<T>(tab + OFF_TWAVE, st.e1w, st.e2w, g1, g2);
+        S g1 = readlane(p1, 63), g2 = readlane(p2, 63);
+        if (W > 1) mv_add<S>(sd + LY::TWAVE, st.e1w, st.e2w, g1, g2);
         st.g1 = wave_uniform(g1);
         st.g2 = wave_uniform(g2);
         // --- 4a. publish the local carry (the first group of a signal has none)
@@ -594,77 +698,109 @@ __device__ __forceinline__ void section_zs(T (&u)[N], Xch<T, W> &xch, float *tl,
 //   carry the wait's jitter into the next group's aggregate), and every wave
 //   passes it to on_next right after the broadcast, so that the next group's
 //   loads overlap this group's correction and store.
-template <typename T, int N, int W, bool PAIR, int ALG, typename OnNext = NoNext>
+template <typename T, bool ACC, int N, int W, bool PAIR, int ALG, typename OnNext = NoNext>
 __device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *tl,
-                                             const FwdArgs &a, const Item<T> &it, const T *tabv,
-                                             int s, unsigned epoch, int wv, int lane,
-                                             bool has_last, int zl, int zp, const SecState<T> &st,
+                                             const FwdArgs &a, const Item<T> &it,
+                                             const unsigned char *tb, int s, unsigned epoch,
+                                             int wv, int lane, bool has_last, int zl, int zp,
+                                             const SecState<typename Lay<T, ACC>::S,
+                                                            typename Lay<T, ACC>::X> &st,
                                              T &q1, T &q2, bool draw = false,
                                              const OnNext &on_next = OnNext())
 {
+    using LY = Lay<T, ACC>;
+    using S = typename LY::S;
     constexpr int LOG = __builtin_ctz(N);
-    ctabT<T> *tab = ctabp(tabv);
+    ctabT<T> *tab = ctabp(LY::sp(tb));
+    ctabT<S> *sd = ctabp(LY::st(tb));
+    const S *stv = LY::st(tb);
     // The lane power of step 5 is read before the lookback, not at its use: a
     // vector load issued after on_next's loads would wait for all of them. The
     // empty asm (which the compiler must assume rewrites the values) keeps it
     // from sinking or re-issuing the load at the use.
-    M2<T> lp = load_m2(tabv + OFF_LANEPOW + 4 * lane);
+    M2<S> lp = load_m2(stv + LY::LANEPOW + 4 * lane);
     asm volatile("" : "+v"(lp.a), "+v"(lp.b), "+v"(lp.c), "+v"(lp.d));
     if (wv == W - 1) {
         // --- 4b. decoupled lookback for the group's incoming state
         unsigned long long *dsc = a.desc + ((size_t)s * a.dstride + it.t) * 4;
-        T sg1, sg2;
+        S sg1, sg2;
         if (it.g == 0) {
             // PAIR: the initial carry arrives as (y[-1], y[-2]) (the adjoint of zf)
-            sg1 = it.zi ? T(ctab(it.zi)[2 * s + (PAIR ? 1 : 0)]) : T(0);
-            sg2 = it.zi ? T(ctab(it.zi)[2 * s + (PAIR ? 0 : 1)]) : T(0);
+            sg1 = it.zi ? (S)ctab(it.zi)[2 * s + (PAIR ? 1 : 0)] : S(0);
+            sg2 = it.zi ? (S)ctab(it.zi)[2 * s + (PAIR ? 0 : 1)] : S(0);
         } else {
-            lookback<T, 16>(a, it, tabv, s, epoch, lane, sg1, sg2);
+            lookback<16, LY>(a, it, stv, s, epoch, lane, sg1, sg2);
         }
         unsigned tk = 0;
         if (draw && lane == 0) tk = atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
-        T i1 = st.g1, i2 = st.g2;
-        mv_add<T>(tab + OFF_TC, sg1, sg2, i1, i2);
+        S i1 = st.g1, i2 = st.g2;
+        mv_add<S>(sd + LY::TC, sg1, sg2, i1, i2);
         if (lane == 0) {
             store_word(dsc + 2, pack((float)i1, epoch));
             store_word(dsc + 3, pack((float)i2, epoch));
-            xch.grp[0] = sg1;
-            xch.grp[1] = sg2;
+            xch.template group<S>()[0] = sg1;
+            xch.template group<S>()[1] = sg2;
             if (draw) xch.nxt = (int64_t)tk;
         }
     }
     lds_barrier();
-    const T sg1 = xch.grp[0], sg2 = xch.grp[1];
-    if (draw) on_next(xch.nxt);
+    const S sg1 = xch.template group<S>()[0], sg2 = xch.template group<S>()[1];
 
     // --- 5. incoming state of every lane, then back substitution
-    const T b1 = tab[OFF_B1], b2 = tab[OFF_B2], a1 = tab[OFF_A1], a2 = tab[OFF_A2];
-    T sw1 = st.e1w, sw2 = st.e2w;
-    mv_add<T>(tab + OFF_WPOW + 4 * wv, sg1, sg2, sw1, sw2);
-    const T e1 = dpp0<DPP_WAVE_SHR1, 0xF>(st.p1), e2 = dpp0<DPP_WAVE_SHR1, 0xF>(st.p2);
-    q1 = fmaT(lp.a, sw1, fmaT(lp.b, sw2, e1));
-    q2 = fmaT(lp.c, sw1, fmaT(lp.d, sw2, e2));
+    S sw1 = st.e1w, sw2 = st.e2w;
+    mv_add<S>(sd + LY::WPOW + 4 * wv, sg1, sg2, sw1, sw2);
+    const S r1 = fmaT(lp.a, sw1, fmaT(lp.b, sw2, (S)st.x1));
+    const S r2 = fmaT(lp.c, sw1, fmaT(lp.d, sw2, (S)st.x2));
+    q1 = (T)r1;
+    q2 = (T)r2;
     // TDF-II injection (s1, s2) of the lane's incoming carry
-    const T s1 = PAIR ? -(a1 * q2 + a2 * q1) : q1;
-    const T s2 = PAIR ? -a2 * q2 : q2;
-    ctabT<T> *g = tab + OFF_G + 1;   // g[-1] is readable and 0
+    const S a1 = sd[LY::A1], a2 = sd[LY::A2];
+    const S s1 = PAIR ? -(a1 * r2 + a2 * r1) : r1;
+    const S s2 = PAIR ? -a2 * r2 : r2;
+    // its free response, g[m] s1 + g[m-1] s2, is added through (c0t, c1t) with
+    // coefficients (k1, k2): g itself (fast), or the orthonormal columns after
+    // (k1, k2) = R (s1, s2) in FP64 (accurate)
+    T k1, k2;
+    ctabT<T> *c0t;
+    ctabT<T> *c1t;
+    if constexpr (ACC) {
+        k1 = (T)fma(sd[SD_R + 0], s1, sd[SD_R + 1] * s2);
+        k2 = (T)(sd[SD_R + 3] * s2);
+        c0t = tab + AP_Q0;
+        c1t = tab + AP_Q1;
+    } else {
+        k1 = (T)s1;
+        k2 = (T)s2;
+        c0t = tab + OFF_G + 1;   // g[-1] is readable and 0
+        c1t = tab + OFF_G;
+    }
+    T s2z = (T)s2;   // for zf only
+    if (draw) {
+        // tickets are below 2^31 (the host bounds the groups of a launch)
+        int nxt = __builtin_amdgcn_readfirstlane((int)xch.nxt);
+        // In the accurate layout the next group's prefetch must not be hoisted
+        // above the FP64 state work (its 4N registers would be live beside the
+        // state temporaries): its addresses are made to depend on the results.
+        if constexpr (ACC) asm volatile("" : "+v"(k1), "+v"(k2), "+v"(s2z), "+s"(nxt));
+        on_next((int64_t)nxt);
+    }
 
     if (ALG == ALG_PH) {
         // homogeneous correction (Eq. (11)): the incoming state's free
         // response, added to every sample independently
 #pragma unroll
-        for (int m = 0; m < N; ++m) u[m] = fmaT(g[m], s1, fmaT(g[m - 1], s2, u[m]));
+        for (int m = 0; m < N; ++m) u[m] = fmaT(c0t[m], k1, fmaT(c1t[m], k2, u[m]));
     } else {
-        u[N - 1] = fmaT(g[N - 1], s1, fmaT(g[N - 2], s2, u[N - 1]));
-        u[N - 2] = fmaT(g[N - 2], s1, fmaT(g[N - 3], s2, u[N - 2]));
+        u[N - 1] = fmaT(c0t[N - 1], k1, fmaT(c1t[N - 1], k2, u[N - 1]));
+        u[N - 2] = fmaT(c0t[N - 2], k1, fmaT(c1t[N - 2], k2, u[N - 2]));
 #pragma unroll
         for (int i = LOG - 1; i >= 1; --i) {
             const int st2 = 1 << i;
-            const T e = tab[OFF_E + i], f = tab[OFF_F + i];
+            const T e = tab[LY::P_E + i], f = tab[LY::P_F + i];
 #pragma unroll
             for (int par = 0; par < 2; ++par) {
                 const int m0 = st2 - 1 - par;                 // odd chain, then even chain
-                u[m0] = fmaT(g[m0], s1, fmaT(g[m0 - 1], s2, u[m0]));
+                u[m0] = fmaT(c0t[m0], k1, fmaT(c1t[m0], k2, u[m0]));
 #pragma unroll
                 for (int m = m0 + 2 * st2; m < N; m += 2 * st2)
                     u[m] = fmaT(-e, u[m - st2], fmaT(-f, u[m - 2 * st2], u[m]));
@@ -677,31 +813,33 @@ __device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *t
         T yo1 = 0, yo2 = 0;
         pick_two<T, N>(u, tl, lane, zl, zp, yo1, yo2);
         if (lane == zl) {
-            const T zx1 = xch.zx[0], zx2 = xch.zx[1];
-            T z1;
+            const S b1 = sd[LY::B1], b2 = sd[LY::B2];
+            const S zx1 = (S)xch.zx[0], zx2 = (S)xch.zx[1], y1 = (S)yo1, y2 = (S)yo2;
+            S z1;
             if (zp >= 1)
-                z1 = b1 * zx1 + b2 * zx2 - a1 * yo1 - a2 * yo2;
+                z1 = b1 * zx1 + b2 * zx2 - a1 * y1 - a2 * y2;
             else
-                z1 = b1 * zx1 - a1 * yo1 + s2;   // s2: this lane's incoming state
+                z1 = b1 * zx1 - a1 * y1 + (S)s2z;   // this lane's incoming state
             gptr(it.zf)[2 * s] = (float)z1;
-            gptr(it.zf)[2 * s + 1] = (float)(b2 * zx1 - a2 * yo1);
+            gptr(it.zf)[2 * s + 1] = (float)(b2 * zx1 - a2 * y1);
         }
     }
 }
 
 // Both halves back to back. On return (q1, q2) is the lane's incoming carry.
-template <typename T, int N, int W, bool PAIR, int ALG = ALG_DCCR, typename OnNext = NoNext>
+template <typename T, bool ACC, int N, int W, bool PAIR, int ALG, typename OnNext = NoNext>
 __device__ __forceinline__ void run_section(T (&u)[N], Xch<T, W> &xch, float *tl,
-                                            const FwdArgs &a, const Item<T> &it, const T *tabv,
-                                            int s, unsigned epoch, int wv, int lane, bool has_last,
-                                            int zl, int zp, T &q1, T &q2, bool draw = false,
+                                            const FwdArgs &a, const Item<T> &it,
+                                            const unsigned char *tb, int s, unsigned epoch,
+                                            int wv, int lane, bool has_last, int zl, int zp,
+                                            T &q1, T &q2, bool draw = false,
                                             const OnNext &on_next = OnNext())
 {
-    SecState<T> st;
-    section_zs<T, N, W, PAIR, ALG>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl, zp,
-                                   st);
-    section_corr<T, N, W, PAIR, ALG>(u, xch, tl, a, it, tabv, s, epoch, wv, lane, has_last, zl,
-                                     zp, st, q1, q2, draw, on_next);
+    SecState<typename Lay<T, ACC>::S, typename Lay<T, ACC>::X> st;
+    section_zs<T, ACC, N, W, PAIR, ALG>(u, xch, tl, a, it, tb, s, epoch, wv, lane, has_last, zl,
+                                        zp, st);
+    section_corr<T, ACC, N, W, PAIR, ALG>(u, xch, tl, a, it, tb, s, epoch, wv, lane, has_last,
+                                          zl, zp, st, q1, q2, draw, on_next);
 }
 
 // ---------------------------------------------------------------- wave tile
@@ -868,7 +1006,8 @@ __device__ __forceinline__ void store_rows(const T (&u)[N], float *tl, int lane,
 
 // The work item of ticket t (plain signal or one signal of a batch).
 template <typename T>
-__device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, int64_t t)
+__device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const unsigned char *tabs,
+                                             int64_t t)
 {
     Item<T> it;
     it.t = t;
@@ -882,15 +1021,17 @@ __device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, in
         it.zf = a.zf;
         it.saved = a.saved;
         it.K = a.K;
+        it.sig = 0;
     } else {
         const int i = a.sigmap[t];
+        it.sig = i;
         const int64_t so = a.sig_off[i];
         const int32_t sc = a.sec_off[i];
         it.x = a.xp ? a.xp[i] : a.x + so;
         it.y = a.yp ? a.yp[i] : a.y + so;
         it.n = a.sig_off[i + 1] - so;
         it.g = t - a.gpre[i];
-        it.tabs = tabs + (size_t)sc * TAB_FLOATS;
+        it.tabs = tabs + (size_t)sc * TAB_BYTES;
         it.zi = a.zi ? a.zi + 2 * (int64_t)sc : nullptr;
         it.zf = a.zf ? a.zf + 2 * (int64_t)sc : nullptr;
         it.saved = a.saved ? a.saved + so : nullptr;
@@ -903,7 +1044,7 @@ __device__ __forceinline__ Item<T> make_item(const FwdArgs &a, const T *tabs, in
 // Everything after the wave's samples are in registers: the K sections, then
 // registers -> the wave's LDS rows -> coalesced 128-bit global stores. With
 // draw set, the last section draws the next ticket and calls on_next with it.
-template <typename T, int N, int W, int ALG, typename OnNext>
+template <typename T, bool ACC, int N, int W, int ALG, typename OnNext>
 __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it, T (&u)[N],
                                              float *tl, Xch<T, W> &xch, unsigned epoch, int wv,
                                              int lane, bool draw, const OnNext &on_next)
@@ -916,7 +1057,7 @@ __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it
     // --- sections (an unusable section poisons its signal)
     bool bad = false;
     for (int s = 0; s < it.K; ++s)
-        bad |= __float_as_uint((float)ctabp(it.tabs)[(size_t)s * TAB_FLOATS + OFF_STATUS]) != 0u;
+        bad |= tab_word(it.tabs + (size_t)s * TAB_BYTES, HDR_STATUS) != 0ull;
     // position of the last real sample n-1 if this wave holds it
     const int64_t lp = (it.n - 1) - g0;
     const bool has_last = lp >= 0 && lp < CW;
@@ -927,17 +1068,18 @@ __device__ __forceinline__ void finish_group(const FwdArgs &a, const Item<T> &it
         const int kl = draw ? it.K - 1 : it.K;
         for (int s = 0; s < kl; ++s) {
             T q1, q2;
-            run_section<T, N, W, false, ALG>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS,
-                                             s, epoch, wv, lane, has_last, zl, zp, q1, q2);
+            run_section<T, ACC, N, W, false, ALG>(u, xch, tl, a, it,
+                                                  it.tabs + (size_t)s * TAB_BYTES, s, epoch, wv,
+                                                  lane, has_last, zl, zp, q1, q2);
             if (it.saved && s + 1 < it.K)
                 store_rows<T, N>(u, tl, lane, it.n, g0, it.saved + (size_t)s * a.saved_stride);
         }
         if (draw && it.K > 0) {
             const int s = it.K - 1;
             T q1, q2;
-            run_section<T, N, W, false, ALG>(u, xch, tl, a, it, it.tabs + (size_t)s * TAB_FLOATS,
-                                             s, epoch, wv, lane, has_last, zl, zp, q1, q2, true,
-                                             on_next);
+            run_section<T, ACC, N, W, false, ALG>(u, xch, tl, a, it,
+                                                  it.tabs + (size_t)s * TAB_BYTES, s, epoch, wv,
+                                                  lane, has_last, zl, zp, q1, q2, true, on_next);
         }
     } else {
 #pragma unroll
@@ -972,11 +1114,29 @@ constexpr int min_waves_per_simd()
 // the group index, so a group's predecessors were drawn (and are being worked
 // on) before it, which guarantees forward progress of the lookback whatever
 // the grid size (Sec. IV-A).
-template <typename T, int N, int W, int ALG>
+// Which table layouts a launch serves: KM_FAST the fast one only, KM_ACC the
+// accurate one only (plain launches: the host launches both and the one that
+// does not match the signal's layout leaves at once), KM_MIX either, chosen
+// per group (batched launches, whose signals may differ). A kernel holding one
+// path has the register file to itself; per-group choice costs registers.
+enum : int { KM_FAST = 0, KM_ACC = 1, KM_MIX = 2 };
+
+// Whether a plain launch of mode KM serves the signal of tables `tabs`.
+template <int KM>
+__device__ __forceinline__ bool plain_launch_serves(const FwdArgs &a)
+{
+    if (KM == KM_MIX || a.B != 0 || a.K <= 0) return true;
+    const bool acc = tab_word(reinterpret_cast<const unsigned char *>(a.tabs), HDR_MODE) ==
+                     MODE_ACCURATE;
+    return acc == (KM == KM_ACC);
+}
+
+template <typename T, int N, int W, int ALG, int KM>
 __global__ void __launch_bounds__(64 * W)
     __attribute__((amdgpu_waves_per_eu(min_waves_per_simd<T, N, W>())))
     sos_fwd_kernel(FwdArgs a)
 {
+    if (!plain_launch_serves<KM>(a)) return;   // before anything: no ticket, no exit count
     constexpr int RS = N + 4;
     constexpr int CW = kLanes * N;
     constexpr int C = CW * W;
@@ -989,7 +1149,7 @@ __global__ void __launch_bounds__(64 * W)
                                              __HIP_MEMORY_SCOPE_AGENT);
     const int64_t total = a.B > 0 ? *a.total_dev : a.total;
     float *tl = tile[wv];
-    const T *tabs = reinterpret_cast<const T *>(a.tabs);
+    const unsigned char *tabs = reinterpret_cast<const unsigned char *>(a.tabs);
     // Software pipeline over groups (FP32 compute): the next ticket is drawn
     // when the current group's last state is resolved, and its samples are
     // loaded into registers while this group is corrected and stored.
@@ -1031,7 +1191,21 @@ __global__ void __launch_bounds__(64 * W)
                 tile_fetch<N>(nf, ni.x + h0, ni.n - h0, lane);
             }
         };
-        finish_group<T, N, W, ALG>(a, it, u, tl, xch, epoch, wv, lane, draw, on_next);
+        // The signal's table layout picks the path, once per group: the
+        // accurate layout (FP32 compute only) runs PH with its state work in
+        // FP64, the fast one the launch's solver in the compute type. FAST and
+        // ACC launches hold one path only (each has the registers to itself);
+        // MIX launches pick per group.
+        if constexpr (sizeof(T) == 4 && KM != KM_FAST) {
+            if (KM == KM_ACC || (it.K > 0 && tab_word(it.tabs, HDR_MODE) == MODE_ACCURATE))
+                finish_group<T, true, N, W, ALG_PH>(a, it, u, tl, xch, epoch, wv, lane, draw,
+                                                    on_next);
+            else
+                finish_group<T, false, N, W, ALG>(a, it, u, tl, xch, epoch, wv, lane, draw,
+                                                  on_next);
+        } else {
+            finish_group<T, false, N, W, ALG>(a, it, u, tl, xch, epoch, wv, lane, draw, on_next);
+        }
 #pragma unroll
         for (int j = 0; j < N / 4; ++j) pf[j] = nf[j];
         if ((int64_t)gridDim.x >= total) break;   // one group per workgroup: no extra draw
@@ -1088,7 +1262,8 @@ struct BItem {
 };
 
 template <typename T>
-__device__ __forceinline__ BItem<T> make_bwd_item(const BwdArgs &b, const T *tabs, int64_t t)
+__device__ __forceinline__ BItem<T> make_bwd_item(const BwdArgs &b, const unsigned char *tabs,
+                                                  int64_t t)
 {
     BItem<T> r{};
     r.it.t = t;
@@ -1106,12 +1281,13 @@ __device__ __forceinline__ BItem<T> make_bwd_item(const BwdArgs &b, const T *tab
         r.gzi = b.gzi;
     } else {
         const int i = b.sigmap[t];
+        r.it.sig = i;
         const int64_t so = b.sig_off[i];
         const int32_t sc = b.sec_off[i];
         r.it.n = b.sig_off[i + 1] - so;
         r.it.g = t - b.gpre[i];
         r.it.K = b.Ks[i];
-        r.it.tabs = tabs + (size_t)sc * TAB_FLOATS;
+        r.it.tabs = tabs + (size_t)sc * TAB_BYTES;
         r.it.zi = b.gzf ? b.gzf + 2 * (int64_t)sc : nullptr;
         r.gy = b.gy + so;
         r.gx = b.gx + so;
@@ -1202,11 +1378,15 @@ __device__ __forceinline__ void rows_from_regs_rev(const T (&u)[N], float *tl, i
     }
 }
 
-template <typename T, int N, int W, int ALG>
+template <typename T, int N, int W, int ALG, int KM>
 __global__ void __launch_bounds__(64 * W)
     __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && W >= 4 ? 2 : 1)))
     sos_bwd_kernel(BwdArgs b)
 {
+    if (KM != KM_MIX && b.B == 0 && b.K > 0 &&
+        (tab_word(reinterpret_cast<const unsigned char *>(b.tabs), HDR_MODE) == MODE_ACCURATE) !=
+            (KM == KM_ACC))
+        return;   // a plain launch for the other layout: before anything
     constexpr int RS = N + 4;
     constexpr int CW = kLanes * N;
     constexpr int C = CW * W;
@@ -1222,7 +1402,7 @@ __global__ void __launch_bounds__(64 * W)
     const int64_t total = b.B > 0 ? *b.total_dev : b.total;
     float *tl = tile[wv];
     float *tl2 = tile2[wv];
-    const T *tabs = reinterpret_cast<const T *>(b.tabs);
+    const unsigned char *tabs = reinterpret_cast<const unsigned char *>(b.tabs);
     FwdArgs a{};                 // the fields the section step and lookback use
     a.K = b.K;
     a.desc = b.desc;
@@ -1241,8 +1421,7 @@ __global__ void __launch_bounds__(64 * W)
         const int64_t n = it.n;
         bool bad = false;
         for (int k = 0; k < it.K; ++k)
-            bad |= __float_as_uint((float)ctabp(it.tabs)[(size_t)k * TAB_FLOATS + OFF_STATUS]) !=
-                   0u;
+            bad |= tab_word(it.tabs + (size_t)k * TAB_BYTES, HDR_STATUS) != 0ull;
         const int64_t r0 = it.g * C + (int64_t)wv * CW;   // reversed index of the wave's start
         const int64_t f0 = n - r0 - CW;                   // forward index of the window's start
 
@@ -1269,81 +1448,100 @@ __global__ void __launch_bounds__(64 * W)
             window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tin, lane);
             window_load<N>(bi.y, f0, n, tout, lane);
         }
-        for (int k = it.K - 1; k >= 0 && !bad; --k) {
-            const T *tabv = it.tabs + (size_t)k * TAB_FLOATS;
-            ctabT<T> *tab = ctabp(tabv);
-            if (k < it.K - 1)
-                window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tin, lane);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            T q1, q2;   // lam'[-2], lam'[-1] of this lane
-            // (the pair section reads and writes no tile)
-            run_section<T, N, W, true, ALG>(u, xch, tout, a, it, tabv, k, epoch, wv, lane, false,
-                                            0, 0, q1, q2);
-            // coefficient sums over the lane (reversed position m = forward column N-1-m)
-            T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-            const float *ru = tin + (kLanes - 1 - lane) * RS;
-            const float *rv = tout + (kLanes - 1 - lane) * RS;
-#pragma unroll
-            for (int k4 = 0; k4 < N / 4; ++k4) {
-                const f4 U = *reinterpret_cast<const f4 *>(ru + 4 * k4);
-                const f4 V = *reinterpret_cast<const f4 *>(rv + 4 * k4);
-                const float uq[4] = {U.w, U.z, U.y, U.x};
-                const float vq[4] = {V.w, V.z, V.y, V.x};
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int m = N - 4 - 4 * k4 + i;
-                    const T L0 = u[m];
+        // the sections, last to first, in the signal's table layout (see the
+        // forward kernel)
+        auto cascade = [&](auto acc_tag) {
+            constexpr bool ACC = decltype(acc_tag)::value;
+            using LY = Lay<T, ACC>;
+            for (int k = it.K - 1; k >= 0 && !bad; --k) {
+                const unsigned char *tb = it.tabs + (size_t)k * TAB_BYTES;
+                ctabT<T> *tab = ctabp(LY::sp(tb));
+                if (k < it.K - 1)
+                    window_load<N>(k == 0 ? bi.x : bi.saved + (size_t)(k - 1) * sst, f0, n, tin, lane);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                T q1, q2;   // lam'[-2], lam'[-1] of this lane
+                // (the pair section reads and writes no tile)
+                run_section<T, ACC, N, W, true, ACC ? ALG_PH : ALG>(u, xch, tout, a, it, tb, k, epoch,
+                                                                     wv, lane, false, 0, 0, q1, q2);
+                // coefficient sums over the lane (reversed position m = forward column N-1-m)
+                T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+                const float *ru = tin + (kLanes - 1 - lane) * RS;
+                const float *rv = tout + (kLanes - 1 - lane) * RS;
+    #pragma unroll
+                for (int k4 = 0; k4 < N / 4; ++k4) {
+                    const f4 U = *reinterpret_cast<const f4 *>(ru + 4 * k4);
+                    const f4 V = *reinterpret_cast<const f4 *>(rv + 4 * k4);
+                    const float uq[4] = {U.w, U.z, U.y, U.x};
+                    const float vq[4] = {V.w, V.z, V.y, V.x};
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int m = N - 4 - 4 * k4 + i;
+                        const T L0 = u[m];
+                        const T L1 = m >= 1 ? u[m - 1] : q2;
+                        const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
+                        const T uu = uq[i], vv = vq[i];
+                        s0 = fmaT(L0, uu, s0);
+                        s1 = fmaT(L1, uu, s1);
+                        s2 = fmaT(L2, uu, s2);
+                        s3 = fmaT(-L1, vv, s3);
+                        s4 = fmaT(-L2, vv, s4);
+                    }
+                }
+                // d/dzi = (lam'[n-1], lam'[n-2]); scratch: the output tile, already
+                // consumed (the input tile is kept for the next section)
+                if (has_first && bi.gzi) {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    T l1 = 0, l2 = 0;
+                    pick_two<T, N>(u, tout, lane, zl, zp, l1, l2);
+                    if (lane == zl) {
+                        gptr(bi.gzi)[2 * k] = (float)l1;
+                        gptr(bi.gzi)[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
+                    }
+                }
+                // gradient for the section below: 3-tap FIR of lam' (descending, in place)
+                const T f0c = tab[LY::P_FIR + 0], f1c = tab[LY::P_FIR + 1], f2c = tab[LY::P_FIR + 2];
+    #pragma unroll
+                for (int m = N - 1; m >= 0; --m) {
                     const T L1 = m >= 1 ? u[m - 1] : q2;
                     const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
-                    const T uu = uq[i], vv = vq[i];
-                    s0 = fmaT(L0, uu, s0);
-                    s1 = fmaT(L1, uu, s1);
-                    s2 = fmaT(L2, uu, s2);
-                    s3 = fmaT(-L1, vv, s3);
-                    s4 = fmaT(-L2, vv, s4);
+                    u[m] = fmaT(f0c, u[m], fmaT(f1c, L1, f2c * L2));
                 }
-            }
-            // d/dzi = (lam'[n-1], lam'[n-2]); scratch: the output tile, already
-            // consumed (the input tile is kept for the next section)
-            if (has_first && bi.gzi) {
+                // group partial sums (waves combined in FP64); in the accurate
+                // layout FP64 from the lanes' partials on: the sums cancel heavily
+                // for lightly damped sections, and FP32 sums over whole waves
+                // lose what the FP32 samples still hold
+                using SS = typename LY::S;
+                const double w0 = wave_sum<SS>((SS)s0), w1 = wave_sum<SS>((SS)s1);
+                const double w2 = wave_sum<SS>((SS)s2), w3 = wave_sum<SS>((SS)s3);
+                const double w4 = wave_sum<SS>((SS)s4);
+                if (lane == 0) {
+                    red[wv][0] = w0;
+                    red[wv][1] = w1;
+                    red[wv][2] = w2;
+                    red[wv][3] = w3;
+                    red[wv][4] = w4;
+                }
+                lds_barrier();
+                if (threadIdx.x < 5) {
+                    double acc = 0.0;
+                    for (int v = 0; v < W; ++v) acc += red[v][threadIdx.x];
+                    b.partials[((size_t)t * b.K + k) * 5 + threadIdx.x] = acc;
+                }
+                // this section's input tile is the next section's output tile;
+                // the other one is re-staged with the next input (wave-local, ordered)
+                float *const tsw = tin;
+                tin = tout;
+                tout = tsw;
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                T l1 = 0, l2 = 0;
-                pick_two<T, N>(u, tout, lane, zl, zp, l1, l2);
-                if (lane == zl) {
-                    gptr(bi.gzi)[2 * k] = (float)l1;
-                    gptr(bi.gzi)[2 * k + 1] = (float)(zp >= 1 ? l2 : q2);
-                }
             }
-            // gradient for the section below: 3-tap FIR of lam' (descending, in place)
-            const T f0c = tab[OFF_FIR + 0], f1c = tab[OFF_FIR + 1], f2c = tab[OFF_FIR + 2];
-#pragma unroll
-            for (int m = N - 1; m >= 0; --m) {
-                const T L1 = m >= 1 ? u[m - 1] : q2;
-                const T L2 = m >= 2 ? u[m - 2] : (m == 1 ? q2 : q1);
-                u[m] = fmaT(f0c, u[m], fmaT(f1c, L1, f2c * L2));
-            }
-            // group partial sums (waves combined in FP64)
-            const T w0 = wave_sum<T>(s0), w1 = wave_sum<T>(s1), w2 = wave_sum<T>(s2);
-            const T w3 = wave_sum<T>(s3), w4 = wave_sum<T>(s4);
-            if (lane == 0) {
-                red[wv][0] = w0;
-                red[wv][1] = w1;
-                red[wv][2] = w2;
-                red[wv][3] = w3;
-                red[wv][4] = w4;
-            }
-            lds_barrier();
-            if (threadIdx.x < 5) {
-                double acc = 0.0;
-                for (int v = 0; v < W; ++v) acc += red[v][threadIdx.x];
-                b.partials[((size_t)t * b.K + k) * 5 + threadIdx.x] = acc;
-            }
-            // this section's input tile is the next section's output tile;
-            // the other one is re-staged with the next input (wave-local, ordered)
-            float *const tsw = tin;
-            tin = tout;
-            tout = tsw;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        };
+        if constexpr (sizeof(T) == 4 && KM != KM_FAST) {
+            if (KM == KM_ACC || (!bad && it.K > 0 && tab_word(it.tabs, HDR_MODE) == MODE_ACCURATE))
+                cascade(BoolTag<true>{});
+            else
+                cascade(BoolTag<false>{});
+        } else {
+            cascade(BoolTag<false>{});
         }
         if (bad) {
 #pragma unroll
@@ -1398,15 +1596,23 @@ sos_bwd_reduce_kernel(const double *partials, int64_t total, int K, const float 
 
 // Batched form: block (i, k) sums section k of signal i over the signal's
 // tickets gpre[i] .. gpre[i+1]-1 (fixed order) and applies the a0 chain rule.
+// Signals the work table skipped are skipped here too: inconsistent ones
+// (their section rows may lie outside the arrays), and every signal of a
+// table rejected as a whole (its groups then run past gpre[B], which is 0).
 __global__ void __launch_bounds__(256)
-sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, const int32_t *Ks,
-                              const int32_t *sec_off, const int64_t *gpre,
-                              const float *sections, float *gsections)
+sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, int64_t rows,
+                              int64_t total_samples, const int32_t *Ks, const int32_t *sec_off,
+                              const int64_t *sig_off, const int64_t *gpre, const float *sections,
+                              float *gsections)
 {
     __shared__ double sh[256][5];
     const int i = blockIdx.x, k = blockIdx.y;
-    if (i >= B || k >= Ks[i]) return;     // uniform per block
+    // uniform per block
+    if (i >= B || !batch_signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off) ||
+        k >= Ks[i])
+        return;
     const int64_t t0 = gpre[i], t1 = gpre[i + 1];
+    if (t0 > t1 || t1 > gpre[B]) return;
     double acc[5] = {0, 0, 0, 0, 0};
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256)
         for (int c = 0; c < 5; ++c) acc[c] += partials[((size_t)t * kmax + k) * 5 + c];
@@ -1436,15 +1642,32 @@ sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, const int
 
 // ------------------------------------------------------------------ launch
 
+// The forward kernel of a launch: the solver, and whether the tables may use
+// the accurate layout (FP32 only): plain launches then take the fast kernel
+// and the accurate one back to back (the one not needed leaves at once),
+// batched launches the kernel that chooses per group.
 template <typename T, int N, int W>
 hipError_t launch_fwd(int alg, const FwdArgs &a, int64_t grid, hipStream_t stream)
 {
-    if (alg == ALG_PH)
-        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_PH>), dim3((unsigned)grid), dim3(64 * W),
-                           0, stream, a);
+    const bool maybe_acc = sizeof(T) == 4 && (alg & ALG_MAYBE_ACC);
+    const bool ph = (alg & ~ALG_MAYBE_ACC) == ALG_PH;
+    const dim3 g((unsigned)grid), blk(64 * W);
+    if (maybe_acc && a.B > 0) {
+        if (ph)
+            hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_PH, KM_MIX>), g, blk, 0, stream, a);
+        else
+            hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_DCCR, KM_MIX>), g, blk, 0, stream, a);
+        return hipGetLastError();
+    }
+    if (ph)
+        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_PH, KM_FAST>), g, blk, 0, stream, a);
     else
-        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_DCCR>), dim3((unsigned)grid),
-                           dim3(64 * W), 0, stream, a);
+        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_DCCR, KM_FAST>), g, blk, 0, stream, a);
+    if (maybe_acc) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_PH, KM_ACC>), g, blk, 0, stream, a);
+    }
     return hipGetLastError();
 }
 
@@ -1452,8 +1675,13 @@ template <typename T, int N, int W>
 int capacity_of(int alg)
 {
     int per_cu = 0, dev = 0, cus = 0;
-    const void *kern = alg == ALG_PH ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH>
-                                     : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR>;
+    const bool mix = sizeof(T) == 4 && (alg & ALG_MAYBE_ACC);
+    const bool ph = (alg & ~ALG_MAYBE_ACC) == ALG_PH;
+    const void *kern =
+        mix ? (ph ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH, KM_MIX>
+                  : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR, KM_MIX>)
+            : (ph ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH, KM_FAST>
+                  : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR, KM_FAST>);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, 0) != hipSuccess)
         per_cu = 1;
     (void)hipGetDevice(&dev);
@@ -1545,13 +1773,15 @@ extern "C" hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, in
                                              unsigned long long timeout_ticks, int64_t grid,
                                              const float *const *xp, float *const *yp,
                                              float *saved, int64_t saved_stride,
-                                             int64_t max_groups, hipStream_t stream)
+                                             int64_t max_groups, unsigned *sig_err,
+                                             hipStream_t stream)
 {
     FwdArgs a{};
     a.x = x;
     a.y = y;
     a.xp = xp;
     a.yp = yp;
+    a.sig_err = sig_err;
     a.saved = saved;
     a.saved_stride = saved_stride;
     a.tabs = tabs;
@@ -1596,13 +1826,28 @@ static hipError_t launch_bwd_args(int bits, int alg, int L, int N, const BwdArgs
         hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(threads), 0, stream, b);
         return hipGetLastError();
     };
+    // the same choice of kernels as the forward launch (launch_fwd)
+    const bool maybe_acc = bits != 64 && (alg & ALG_MAYBE_ACC);
+    const bool ph = (alg & ~ALG_MAYBE_ACC) == ALG_PH;
+    auto launch3 = [&](auto kfast_dccr, auto kfast_ph, auto kmix_dccr, auto kmix_ph, auto kacc,
+                       int threads) {
+        if (maybe_acc && b.B > 0) return ph ? launch(kmix_ph, threads) : launch(kmix_dccr, threads);
+        const int64_t grid0 = grid;
+        hipError_t e = ph ? launch(kfast_ph, threads) : launch(kfast_dccr, threads);
+        if (e != hipSuccess || !maybe_acc) return e;
+        grid = grid0;
+        return launch(kacc, threads);
+    };
 #define SOS_BWD_CASE(NN, WW)                                                                   \
     if (N == NN && W == WW) {                                                                  \
         if (bits == 64)                                                                        \
-            return alg == ALG_PH ? launch(sos_bwd_kernel<double, NN, WW, ALG_PH>, 64 * WW)     \
-                                 : launch(sos_bwd_kernel<double, NN, WW, ALG_DCCR>, 64 * WW);  \
-        return alg == ALG_PH ? launch(sos_bwd_kernel<float, NN, WW, ALG_PH>, 64 * WW)          \
-                             : launch(sos_bwd_kernel<float, NN, WW, ALG_DCCR>, 64 * WW);       \
+            return ph ? launch(sos_bwd_kernel<double, NN, WW, ALG_PH, KM_FAST>, 64 * WW)       \
+                      : launch(sos_bwd_kernel<double, NN, WW, ALG_DCCR, KM_FAST>, 64 * WW);    \
+        return launch3(sos_bwd_kernel<float, NN, WW, ALG_DCCR, KM_FAST>,                       \
+                       sos_bwd_kernel<float, NN, WW, ALG_PH, KM_FAST>,                         \
+                       sos_bwd_kernel<float, NN, WW, ALG_DCCR, KM_MIX>,                        \
+                       sos_bwd_kernel<float, NN, WW, ALG_PH, KM_MIX>,                          \
+                       sos_bwd_kernel<float, NN, WW, ALG_PH, KM_ACC>, 64 * WW);                \
     }
     SOS_BWD_CASE(16, 1)
     SOS_BWD_CASE(32, 1)
@@ -1684,14 +1929,16 @@ extern "C" hipError_t sos_launch_bwd_batched(int bits, int alg, int L, int N, in
 }
 
 extern "C" hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax,
+                                                    int64_t rows, int64_t total_samples,
                                                     const int32_t *Ks, const int32_t *sec_off,
-                                                    const int64_t *gpre, const float *sections,
-                                                    float *gsections, hipStream_t stream)
+                                                    const int64_t *sig_off, const int64_t *gpre,
+                                                    const float *sections, float *gsections,
+                                                    hipStream_t stream)
 {
     if (B <= 0 || kmax <= 0) return hipSuccess;
     hipLaunchKernelGGL(sos_bwd_reduce_batched_kernel, dim3((unsigned)B, (unsigned)kmax),
-                       dim3(256), 0, stream, partials, B, kmax, Ks, sec_off, gpre, sections,
-                       gsections);
+                       dim3(256), 0, stream, partials, B, kmax, rows, total_samples, Ks, sec_off,
+                       sig_off, gpre, sections, gsections);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -15,11 +16,12 @@
 
 extern "C" {
 hipError_t sos_launch_prep(int bits, const float *sections, int K, int log2n, int log2w,
-                           void *tabs, unsigned *ctrl, int pair, hipStream_t stream);
+                           void *tabs, unsigned *ctrl, int pair, double rho_max,
+                           hipStream_t stream);
 hipError_t sos_launch_prep_batched(int bits, const float *sections, int B, int kmax, int64_t rows,
                                    const int32_t *Ks, const int32_t *sec_off, int log2n,
                                    int log2w, void *tabs, unsigned *ctrl, int pair,
-                                   hipStream_t stream);
+                                   double rho_max, hipStream_t stream);
 hipError_t sos_launch_arm(unsigned *ctrl, hipStream_t stream);
 hipError_t sos_launch_fwd(int bits, int alg, int L, int N, const float *x, float *y, int64_t n,
                           int64_t groups, const void *tabs, int K, const float *zi, float *zf,
@@ -34,7 +36,8 @@ hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, int B, int km
                                   unsigned long long *desc, unsigned *ctrl,
                                   unsigned long long timeout_ticks, int64_t grid,
                                   const float *const *xp, float *const *yp, float *saved,
-                                  int64_t saved_stride, int64_t max_groups, hipStream_t stream);
+                                  int64_t saved_stride, int64_t max_groups, unsigned *sig_err,
+                                  hipStream_t stream);
 hipError_t sos_launch_bwd_batched(int bits, int alg, int L, int N, int B, int kmax,
                                   const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                                   const int64_t *gpre, const int32_t *sigmap,
@@ -44,8 +47,9 @@ hipError_t sos_launch_bwd_batched(int bits, int alg, int L, int N, int B, int km
                                   float *gzi, double *partials, unsigned long long *desc,
                                   unsigned *ctrl, unsigned long long timeout_ticks,
                                   hipStream_t stream);
-hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax,
-                                         const int32_t *Ks, const int32_t *sec_off,
+hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax, int64_t rows,
+                                         int64_t total_samples, const int32_t *Ks,
+                                         const int32_t *sec_off, const int64_t *sig_off,
                                          const int64_t *gpre, const float *sections,
                                          float *gsections, hipStream_t stream);
 hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
@@ -59,8 +63,10 @@ hipError_t sos_launch_worktable_staged(int B, int kmax, int64_t rows, int64_t C,
                                        const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
                                        int64_t *total_dev, const float *zi, float *zf,
                                        unsigned *ctrl, const void *stage_src, void *stage_dst,
-                                       int64_t stage_bytes, hipStream_t stream);
-hipError_t sos_launch_report_err(unsigned *ctrl_err, unsigned *host_err, hipStream_t stream);
+                                       int64_t stage_bytes, unsigned *sig_err,
+                                       hipStream_t stream);
+hipError_t sos_launch_report_err(unsigned *ctrl_err, unsigned *host_err, const unsigned *sig_err,
+                                 unsigned *host_sig_err, int B, hipStream_t stream);
 hipError_t sos_launch_bwd(int bits, int alg, int L, int N, const float *gy, float *gx, int64_t n,
                           int64_t groups, const void *tabs, int K, const float *x,
                           const float *y, const float *saved, const float *gzf, float *gzi,
@@ -92,10 +98,14 @@ struct sos_ctx {
     int last_K = 0;
     bool armed = true;   // ctrl holds ticket 0 and an unused epoch once the enqueued
                          // work has run (fresh, or last launch plain or adjoint)
+    bool batch_captured = false;   // a batched launch was captured into a graph on
+                                   // this handle: its replays advance the ticket
+                                   // whenever they run, so plain launches always arm
     int prep_K = -1;                      // tables currently prepared (K, shape, type)
     int prep_L = 0;
     int prep_N = 0;
     int prep_bits = 0;
+    int prep_alg = 0;                     // solver the tables were prepared for
     // uneven-batch work table
     int64_t *gpre = nullptr;
     size_t gpre_cap = 0;
@@ -190,16 +200,50 @@ inline Tile tile_for_length(const sos_ctx *h, int K, int64_t n)
     return t;
 }
 
-// Section solver of the filter kernels (ALG_DCCR or ALG_PH): the handle's
-// choice, else SOS_ALG in the environment ("ph" or "dccr"), else DC-CR.
+// Section solver in effect (SOS_ALG_AUTO, SOS_ALG_DCCR or SOS_ALG_PH): the
+// handle's choice, else SOS_ALG in the environment ("auto", "dccr" or "ph"),
+// else SOS_ALG_AUTO.
+inline int solver_of(const sos_ctx *h)
+{
+    if (h->alg != SOS_ALG_DEFAULT) return h->alg;
+    if (const char *e = std::getenv("SOS_ALG")) {
+        if (!std::strcmp(e, "ph") || !std::strcmp(e, "PH")) return SOS_ALG_PH;
+        if (!std::strcmp(e, "dccr") || !std::strcmp(e, "DCCR")) return SOS_ALG_DCCR;
+    }
+    return SOS_ALG_AUTO;
+}
+
+// Kernel of the filter launches: ALG_PH for the PH solver, ALG_DCCR for
+// DC-CR and for the automatic choice (a DC-CR launch solves the sections its
+// tables mark by PH).
 inline int alg_of(const sos_ctx *h)
 {
-    if (h->alg == SOS_ALG_PH) return sosdev::ALG_PH;
-    if (h->alg == SOS_ALG_DCCR) return sosdev::ALG_DCCR;
-    if (const char *e = std::getenv("SOS_ALG")) {
-        if (!std::strcmp(e, "ph") || !std::strcmp(e, "PH")) return sosdev::ALG_PH;
-    }
-    return sosdev::ALG_DCCR;
+    return solver_of(h) == SOS_ALG_PH ? sosdev::ALG_PH : sosdev::ALG_DCCR;
+}
+
+// Peak gain of a section's recursive part, 1 / min |A(e^{jw})|, above which
+// a signal's tables take the accurate layout (FP32 compute): its state work
+// runs in FP64 and its sections are solved by PH, because with poles that
+// close to the unit circle the FP32 powers of the state map, and DC-CR's fold
+// B(z)A(-z) near the poles' mirror frequencies, amplify rounding. Every
+// section of the Butterworth designs up to order 16 at cutoff 0.2*pi (at most
+// 15.7) and of random sections with pole radius up to 0.99 at moderate angles
+// stays below 32; lightly damped sections (radius 0.995: 100 and more) do
+// not. An explicit DC-CR handle keeps DC-CR and the compute type everywhere.
+constexpr double kAutoRhoMax = 32.0;
+
+inline double rho_max_of(const sos_ctx *h)
+{
+    return solver_of(h) == SOS_ALG_DCCR ? HUGE_VAL : kAutoRhoMax;
+}
+
+// Solver argument of the kernel launchers for tables prepared for `solver`
+// (SOS_ALG_*) and compute type `bits`: the kernel's solver, plus
+// ALG_MAYBE_ACC when those tables may use the accurate layout.
+inline int launch_alg(int bits, int solver)
+{
+    const int a = solver == SOS_ALG_PH ? sosdev::ALG_PH : sosdev::ALG_DCCR;
+    return (bits == 32 && solver != SOS_ALG_DCCR) ? (a | sosdev::ALG_MAYBE_ACC) : a;
 }
 
 // SOS_GRID: exactly this many workgroups for every persistent launch, or 0

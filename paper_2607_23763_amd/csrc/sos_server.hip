@@ -97,12 +97,14 @@ struct Stream {
     int64_t outstanding = 0;        // pushed, not yet retired
     bool in_ready = false;
     bool closing = false;
+    int err = SOS_OK;               // sticky: a chunk failed, the state is no longer valid
 };
 
 // Per-step argument arrays, laid out identically in pinned host memory and
 // in the device copy: K | sec_off | sig_off | xp | yp. A step packs its B
 // chunks with ArgLayout(B); the buffers are sized for ArgLayout(max_slots),
-// whose end holds the host-only error word.
+// whose end holds the host-only result words: the launch's error bits (8
+// bytes), then one error word per chunk (max_slots words).
 struct ArgLayout {
     size_t k, sec, sig, xp, yp, bytes, err;
     explicit ArgLayout(int slots = 0)
@@ -120,8 +122,9 @@ struct ArgLayout {
 
 struct Step {
     bool busy = false;
+    uint64_t seq = 0;                // launch order (steps retire in it)
     hipEvent_t done = nullptr;
-    unsigned char *host = nullptr;   // pinned, ArgLayout::bytes + 8
+    unsigned char *host = nullptr;   // pinned, ArgLayout::bytes + 8 + 4 max_slots
     std::vector<uint64_t> tickets;
 };
 
@@ -133,6 +136,7 @@ struct sos_srv {
     hipStream_t ostream = nullptr;    // stream opening (table preparation)
     unsigned *octrl = nullptr;        // error word of the preparation launches
     int device = 0, L = 0, N = 0, bits = 32, alg = 0;
+    double rho_max = 0.0;             // tables' PH bound (automatic solver choice)
     int64_t C = 0;
     int max_slots = 0;
     int64_t max_rows = 0, max_groups = 0, max_step_samples = 0;
@@ -141,6 +145,8 @@ struct sos_srv {
     float *state = nullptr;           // max_rows x 2
     unsigned char *tabs = nullptr;    // max_rows x tab_row_bytes
     unsigned char *dargs = nullptr;   // device copy of a step's arguments
+    unsigned *derr = nullptr;         // per-chunk error words of the running step
+    uint64_t next_seq = 1;            // launch order of steps
     ArgLayout lay;
     Step steps[kSteps];
     std::mutex mu;
@@ -166,17 +172,37 @@ int status_of_bits(unsigned b)
     return SOS_OK;
 }
 
-void retire(sos_srv *s, Step &st, int status)
+// Finish a step: every chunk gets its own status. step_status != SOS_OK (a
+// failed launch) applies to all of them; otherwise a chunk's status comes
+// from its own error word (a lookback timeout in its signal, or its entry
+// rejected by the work table), and a table rejected as a whole (the launch's
+// bits say so, no chunk's word does) fails all of them. A failed chunk
+// leaves its stream's state invalid (the step updates it in place): the
+// stream keeps that status, and its chunks retired after it report it too.
+void retire(sos_srv *s, Step &st, int step_status, unsigned launch_bits,
+            const unsigned *chunk_bits)
 {
     const Clock::time_point now = Clock::now();
-    for (uint64_t tk : st.tickets) {
-        auto it = s->reqs.find(tk);
+    unsigned any = 0;
+    for (size_t i = 0; i < st.tickets.size(); ++i) any |= chunk_bits ? chunk_bits[i] : 0u;
+    const bool table_rejected = (launch_bits & ERRBIT_BADARG) && !(any & ERRBIT_BADARG);
+    for (size_t i = 0; i < st.tickets.size(); ++i) {
+        auto it = s->reqs.find(st.tickets[i]);
         if (it == s->reqs.end()) continue;
         Request &rq = it->second;
+        int status = step_status;
+        if (status == SOS_OK)
+            status = table_rejected ? SOS_EINVAL
+                                    : status_of_bits(chunk_bits ? chunk_bits[i] : 0u);
+        auto si = s->streams.find(rq.stream);
+        if (si != s->streams.end()) {
+            Stream &str = si->second;
+            if (str.err == SOS_OK && status != SOS_OK) str.err = status;
+            if (str.err != SOS_OK) status = str.err;
+            --str.outstanding;
+        }
         rq.status = status;
         rq.latency = std::chrono::duration<double>(now - rq.t_push).count();
-        auto si = s->streams.find(rq.stream);
-        if (si != s->streams.end()) --si->second.outstanding;
     }
     st.tickets.clear();
     st.busy = false;
@@ -245,7 +271,9 @@ void launch_step(sos_srv *s, Step &st)
     }
     sig[B] = total;
     *err = 0;
+    unsigned *chunk_err = err + 2;
     st.busy = true;
+    st.seq = s->next_seq++;
     sos_ctx *h = s->h;
     unsigned char *d = s->dargs;
     const int32_t *dK = reinterpret_cast<const int32_t *>(d + lb.k);
@@ -270,14 +298,16 @@ void launch_step(sos_srv *s, Step &st)
         sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total,
                                     std::min(step_groups, s->max_groups), dK, dsec,
                                     dsig, h->gpre, h->sigmap, h->total_dev, s->state, s->state,
-                                    h->ctrl, hb, d, (int64_t)lb.bytes, s->stream) == hipSuccess &&
+                                    h->ctrl, hb, d, (int64_t)lb.bytes, s->derr,
+                                    s->stream) == hipSuccess &&
         sos_launch_fwd_batched(s->bits, s->alg, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
                                h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
                                s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
-                               nullptr, 0, s->max_groups, s->stream) == hipSuccess &&
-        sos_launch_report_err(h->ctrl + CTRL_ERR, err, s->stream) == hipSuccess &&
+                               nullptr, 0, s->max_groups, s->derr, s->stream) == hipSuccess &&
+        sos_launch_report_err(h->ctrl + CTRL_ERR, err, s->derr, chunk_err, B, s->stream) ==
+            hipSuccess &&
         hipEventRecord(st.done, s->stream) == hipSuccess;
-    if (!ok) retire(s, st, SOS_EHIP);
+    if (!ok) retire(s, st, SOS_EHIP, 0u, nullptr);
 }
 
 void worker_main(sos_srv *s)
@@ -286,15 +316,20 @@ void worker_main(sos_srv *s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool busy = false;
-        for (Step &st : s->steps) {
-            if (!st.busy) continue;
-            const hipError_t q = hipEventQuery(st.done);
+        // retire finished steps oldest first (a stream's failure must reach
+        // its later chunks)
+        for (;;) {
+            Step *oldest = nullptr;
+            for (Step &st : s->steps)
+                if (st.busy && (!oldest || st.seq < oldest->seq)) oldest = &st;
+            if (!oldest) break;
+            const hipError_t q = hipEventQuery(oldest->done);
             if (q == hipErrorNotReady) {
                 busy = true;
-                continue;
+                break;
             }
-            const unsigned bits = *reinterpret_cast<unsigned *>(st.host + s->lay.err);
-            retire(s, st, q == hipSuccess ? status_of_bits(bits) : SOS_EHIP);
+            const unsigned *res = reinterpret_cast<const unsigned *>(oldest->host + s->lay.err);
+            retire(s, *oldest, q == hipSuccess ? SOS_OK : SOS_EHIP, res[0], res + 2);
         }
         if (s->stop && !busy) break;
         Step *freeslot = nullptr;
@@ -321,7 +356,7 @@ void free_server(sos_srv *s)
         if (st.host) (void)hipHostFree(st.host);
     }
     for (void *p : {(void *)s->sections, (void *)s->state, (void *)s->tabs, (void *)s->dargs,
-                    (void *)s->octrl})
+                    (void *)s->octrl, (void *)s->derr})
         if (p) (void)hipFree(p);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->ostream) (void)hipStreamDestroy(s->ostream);
@@ -339,6 +374,7 @@ int push_many(sos_srv *s, int count, const int64_t *ids, const float *const *x,
     for (int r = 0; r < count; ++r) {
         auto it = s->streams.find(ids[r]);
         if (it == s->streams.end() || it->second.closing) return SOS_ECLOSED;
+        if (it->second.err != SOS_OK) return it->second.err;
         if (n[r] < 0 || n[r] > s->max_step_samples || (n[r] > 0 && (!x[r] || !y[r])))
             return SOS_EINVAL;
     }
@@ -390,12 +426,13 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
     s->L = t.L;
     s->N = t.N;
     s->bits = bits_of(hu);
-    s->alg = alg_of(hu);
+    s->alg = launch_alg(s->bits, solver_of(hu));
+    s->rho_max = rho_max_of(hu);
     s->h->timeout_ticks = hu->timeout_ticks;
     s->C = (int64_t)t.L * t.N;
     s->max_slots = max_slots;
     s->lay = ArgLayout(max_slots);
-    s->tab_row_bytes = (size_t)TAB_FLOATS * (s->bits == 64 ? 8 : 4);
+    s->tab_row_bytes = (size_t)TAB_BYTES;
     const size_t budget = device_mem_budget ? device_mem_budget : kDefaultBudget;
     // half for per-stream rows (sections, state, tables), half for a step's
     // work table and descriptors (stride up to SOS_MAX_SECTIONS)
@@ -417,6 +454,7 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
         hipMalloc(&s->state, (size_t)s->max_rows * 2 * 4) == hipSuccess &&
         hipMalloc(&s->tabs, (size_t)s->max_rows * s->tab_row_bytes) == hipSuccess &&
         hipMalloc(&s->dargs, s->lay.bytes) == hipSuccess &&
+        hipMalloc(&s->derr, sizeof(unsigned) * (size_t)max_slots) == hipSuccess &&
         hipMalloc(&s->octrl, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
         hipMemset(s->octrl, 0, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
         hipMalloc(&s->h->gpre, sizeof(int64_t) * ((size_t)max_slots + 1)) == hipSuccess &&
@@ -429,7 +467,8 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
         ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
              // coherent: kernels read the step's arguments from it and write the
              // step's error word into it
-             hipHostMalloc(&st.host, s->lay.bytes + 8, hipHostMallocCoherent) == hipSuccess;
+             hipHostMalloc(&st.host, s->lay.bytes + 8 + 4 * (size_t)max_slots,
+                           hipHostMallocCoherent) == hipSuccess;
     }
     if (!ok) {
         free_server(s);
@@ -512,7 +551,7 @@ int sos_stream_open(sos_server_t s, const float *sections_host, int K, const flo
                            hipMemcpyHostToDevice, s->ostream) == hipSuccess &&
             sos_launch_prep(s->bits, s->sections + 6 * row, K, __builtin_ctz((unsigned)s->N),
                             __builtin_ctz((unsigned)(s->L / 64)),
-                            s->tabs + (size_t)row * s->tab_row_bytes, s->octrl, 0,
+                            s->tabs + (size_t)row * s->tab_row_bytes, s->octrl, 0, s->rho_max,
                             s->ostream) == hipSuccess &&
             hipMemcpyAsync(tab.data(), s->tabs + (size_t)row * s->tab_row_bytes, tab.size(),
                            hipMemcpyDeviceToHost, s->ostream) == hipSuccess &&
@@ -523,15 +562,9 @@ int sos_stream_open(sos_server_t s, const float *sections_host, int K, const flo
             unsigned bad = 0;
             for (int k = 0; k < K; ++k) {
                 const unsigned char *p = tab.data() + (size_t)k * s->tab_row_bytes;
-                double v;
-                if (s->bits == 64) {
-                    std::memcpy(&v, p + 8 * OFF_STATUS, 8);
-                } else {
-                    float f;
-                    std::memcpy(&f, p + 4 * OFF_STATUS, 4);
-                    v = f;
-                }
-                bad |= (unsigned)v;
+                unsigned long long w;
+                std::memcpy(&w, p + 8 * HDR_STATUS, 8);
+                bad |= (unsigned)w;
             }
             rc = status_of_bits(bad);
         }
@@ -591,6 +624,7 @@ int sos_stream_state(sos_server_t s, int64_t stream_id, float *zf_host)
         auto it = s->streams.find(stream_id);
         if (it == s->streams.end()) return SOS_ECLOSED;
         s->cv_done.wait(lk, [&] { return it->second.outstanding == 0 || s->stop; });
+        if (it->second.err != SOS_OK) return it->second.err;   // no valid state to export
         K = it->second.K;
         row = it->second.row;
     }

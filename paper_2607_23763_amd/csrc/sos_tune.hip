@@ -163,7 +163,9 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
     int rc = batch_check(ba);
     if (rc) return rc;
     if (B == 0) return SOS_EINVAL;
-    if (zi && zi == zf) return SOS_EINVAL;   // repeated runs must not move the state
+    // repeated runs must neither move the state nor re-filter their own output
+    if (zi && zi == zf) return SOS_EINVAL;
+    if (total_samples > 0 && x == y) return SOS_EINVAL;
     std::lock_guard<std::mutex> lk(h->mu);
     DeviceGuard dg(h->device);
     if (!dg.ok) return SOS_EHIP;
@@ -201,7 +203,7 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
     const TuneKey key_req = key_of(h, ba);
     std::vector<int> algs;
     if (requested == SOS_ALG_DEFAULT) {
-        algs.push_back(SOS_ALG_DCCR);
+        algs.push_back(SOS_ALG_AUTO);
         algs.push_back(SOS_ALG_PH);
     } else {
         algs.push_back(requested);
@@ -239,7 +241,7 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
         }
         if (std::getenv("SOS_TUNE_VERBOSE"))
             std::fprintf(stderr, "sos_tune: L=%d N=%d %s padded=%.3f %.4f ms\n", t.L, t.N,
-                         h->alg == SOS_ALG_PH ? "ph" : "dccr",
+                         h->alg == SOS_ALG_PH ? "ph" : (h->alg == SOS_ALG_AUTO ? "auto" : "dccr"),
                          padded[c] / std::max(1.0, (double)total_samples), med);
     }
     (void)hipEventDestroy(e0);

@@ -26,20 +26,30 @@ __global__ void __launch_bounds__(256) copy_kernel(const f4 *x, f4 *y, int64_t n
     if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
 }
 
-// End of a server step: the launch's error bits to the step's host result
-// word (pinned, coherent host memory), then cleared for the next launch.
-__global__ void report_err_kernel(unsigned *ctrl_err, unsigned *host_err)
+// End of a server step: the launch's error bits and its B per-signal error
+// words to the step's host result words (pinned, coherent host memory); the
+// launch's bits are then cleared for the next launch (the per-signal words
+// are rewritten by the next work table).
+__global__ void __launch_bounds__(256)
+report_err_kernel(unsigned *ctrl_err, unsigned *host_err, const unsigned *sig_err,
+                  unsigned *host_sig_err, int B)
 {
-    *host_err = *ctrl_err;
-    *ctrl_err = 0u;
+    for (int i = threadIdx.x; i < B; i += blockDim.x) host_sig_err[i] = sig_err[i];
+    if (threadIdx.x == 0) {
+        *host_err = *ctrl_err;
+        *ctrl_err = 0u;
+    }
 }
 
 }  // namespace
 
 extern "C" hipError_t sos_launch_report_err(unsigned *ctrl_err, unsigned *host_err,
-                                            hipStream_t stream)
+                                            const unsigned *sig_err, unsigned *host_sig_err,
+                                            int B, hipStream_t stream)
 {
-    hipLaunchKernelGGL(report_err_kernel, dim3(1), dim3(1), 0, stream, ctrl_err, host_err);
+    if (B > 0 && (!sig_err || !host_sig_err)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(report_err_kernel, dim3(1), dim3(256), 0, stream, ctrl_err, host_err,
+                       sig_err, host_sig_err, B);
     return hipGetLastError();
 }
 

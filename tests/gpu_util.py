@@ -23,12 +23,13 @@ def tol_for(K):
 # Ratio allowed between the HIP path's FP32 error and the error of a
 # sequential FP32 cascade on the same input. Measured on MI355X over 320
 # random cascades of orders 2..16 (random stable sections, random initial
-# states, 2^15 samples) at three tiles: median 0.8-1.2, 90th percentile
-# 1.8-2.7, maximum 8.1. The factor only matters when the sequential FP32
-# error itself exceeds the order's bound (a cascade whose output is orders of
-# magnitude below its input); there the FP64 compute type is checked against
-# the order's bound instead.
-FLOOR_FACTOR = 16.0
+# states, 2^15 samples) at three tiles, before cascades with poles near the
+# unit circle moved to the accurate table layout: median 0.8-1.2, 90th
+# percentile 1.8-2.7, maximum 8.1. The factor only matters when the
+# sequential FP32 error itself exceeds the order's bound (a cascade whose
+# output is orders of magnitude below its input); there the FP64 compute type
+# is checked against the order's bound instead.
+FLOOR_FACTOR = 10.0
 
 
 def fp32_floor(sos, x, zi, ref):

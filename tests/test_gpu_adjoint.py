@@ -76,8 +76,10 @@ def test_vjp_small_grid(env, tile, monkeypatch):
 @pytest.mark.parametrize("precision", [64, 32])
 def test_vjp_order16_lightly_damped(env, precision):
     """8 sections, poles at radius 0.995, section 0 scaled to unit white-noise
-    gain. The FP64 compute type meets the order-16 bound; FP32 is reported
-    beside the FP32 sequential floor of the same reversed-time filter."""
+    gain (the differentiation workload's stress case). FP64 compute meets the
+    order-16 bound with room to spare; the default handle (FP32 samples, FP64
+    state path and coefficient sums) meets it for gx, gzi and every
+    coefficient gradient."""
     import scipy.signal
 
     torch, P = env
@@ -100,10 +102,12 @@ def test_vjp_order16_lightly_damped(env, precision):
           "fp32 sequential floor", rel_l2(seq, rx))
     if precision == 64:
         assert rel_l2(gx, rx) <= 1e-5
+        assert rel_l2(gzi, rzi) <= 1e-5
+        assert rel_l2(gs, rs) <= 1e-5
+    else:
+        assert rel_l2(gx, rx) <= 1e-4
         assert rel_l2(gzi, rzi) <= 1e-4
         assert rel_l2(gs, rs) <= 1e-4
-    else:
-        assert np.isfinite(gx).all() and np.isfinite(gs).all()
 
 
 def test_autograd_function(env):

@@ -52,18 +52,20 @@ def test_algorithm_selection(env, monkeypatch):
     torch, P = env
     monkeypatch.delenv("SOS_ALG", raising=False)
     h = P.Handle(0)
-    assert h.algorithm() == "dccr"
+    assert h.algorithm() == "auto"
     h.set_algorithm("ph")
     assert h.algorithm() == "ph"
     h.set_algorithm("dccr")
     assert h.algorithm() == "dccr"
     h.set_algorithm(None)
-    assert h.algorithm() == "dccr"
+    assert h.algorithm() == "auto"
     monkeypatch.setenv("SOS_ALG", "ph")
     assert h.algorithm() == "ph"            # the default follows the environment
-    h.set_algorithm("dccr")
-    assert h.algorithm() == "dccr"          # an explicit choice wins
-    assert P.lib().sos_set_algorithm(h.ptr, 3) == P.SOS_EINVAL
+    monkeypatch.setenv("SOS_ALG", "dccr")
+    assert h.algorithm() == "dccr"
+    h.set_algorithm("auto")
+    assert h.algorithm() == "auto"          # an explicit choice wins
+    assert P.lib().sos_set_algorithm(h.ptr, 4) == P.SOS_EINVAL
     assert P.lib().sos_set_algorithm(h.ptr, -1) == P.SOS_EINVAL
     assert P.lib().sos_set_algorithm(None, P.SOS_ALG_PH) == P.SOS_EINVAL
     assert P.lib().sos_get_algorithm(None) == P.SOS_EINVAL
@@ -164,8 +166,11 @@ def lightly_damped_sections(K=8, r=0.995, seed=9):
 
 @pytest.mark.parametrize("tile", [(64, 16), (512, 64)])
 def test_lightly_damped_order16(env, tile):
-    """Order 16, poles at radius 0.995: FP64 meets the order-16 bound; the FP32
-    errors of both solvers are reported beside the sequential FP32 floor."""
+    """Order 16, poles at radius 0.995: FP64 meets the order-16 bound, and so
+    does FP32 PH (FP64 state path, orthonormal correction basis). FP32 DC-CR
+    forced on every section is reported beside the sequential FP32 floor: its
+    fold amplifies rounding near the mirror frequencies of these poles, which
+    is why the default solver takes PH for them."""
     import scipy.signal
 
     torch, P = env
@@ -181,7 +186,8 @@ def test_lightly_damped_order16(env, tile):
           "dccr fp32", rel_l2(yd, yr), "fp32 sequential floor", floor)
     assert rel_l2(y64, yr) <= 1e-5
     assert rel_l2(zf64, zfr) <= 1e-5
-    assert np.isfinite(y32).all()
+    assert rel_l2(y32, yr) <= 1e-4
+    assert np.isfinite(yd).all()
 
 
 @pytest.mark.parametrize("K", [1, 8])

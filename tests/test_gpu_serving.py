@@ -250,12 +250,13 @@ def test_replay_poisson_load(env):
 
 
 def test_device_errors_reach_their_chunks(env):
-    """Device-side error bits travel from the filter kernel (its last
-    workgroup writes them into the step's host result word) to the step's
-    chunks, and are cleared for the next step. A one-tick lookback bound,
-    forced from the host, on long chunks yields SOS_ETIMEOUT (with NaN
-    outputs) or SOS_OK; a later one-group chunk, which never waits, is OK and
-    exact."""
+    """Device-side errors are per chunk and sticky per stream. A one-tick
+    lookback bound, forced from the host, on long chunks of stream a yields
+    SOS_ETIMEOUT (with NaN outputs from the failed group on) or SOS_OK; once a
+    chunk of a failed, its later chunks and pushes report the same status and
+    its state is not exported. Stream b's one-group chunks, which never wait
+    and share steps with a's, stay SOS_OK and exact; so do the chunks of a
+    stream opened after a was closed and reopened."""
     torch, P = env
     h = P.Handle(0, tile=(64, 16))
     h.set_timeout(1e-6)
@@ -264,29 +265,55 @@ def test_device_errors_reach_their_chunks(env):
     a = srv.open(sos)
     b = srv.open(sos)
     x = torch.from_numpy(workloads.signal(1 << 18, seed=9)).cuda()
-    codes = []
-    timed_out = False
+    xs = workloads.signal(500, seed=10)
+    xsd = torch.from_numpy(xs).cuda()
+    codes, ys, tks = [], [], []
     for _ in range(4):
         y = torch.empty_like(x)
-        tk, _ = srv.push(a, x, y)
+        yb = torch.empty(500, device="cuda")
         try:
-            srv.wait(tk)
-            code = P.SOS_OK
-        except P.SosError as e:
-            code = e.code
+            tk, _ = srv.push(a, x, y)
+        except P.SosError as e:                      # a already failed
+            assert e.code == P.SOS_ETIMEOUT
+            tk = None
+        tks.append((tk, srv.push(b, xsd, yb)[0]))
+        ys.append((y, yb))
+    failed = False
+    yb_all = []
+    for (tka, tkb), (y, yb) in zip(tks, ys):
+        code = P.SOS_ETIMEOUT
+        if tka is not None:
+            try:
+                srv.wait(tka)
+                code = P.SOS_OK
+            except P.SosError as e:
+                code = e.code
         assert code in (P.SOS_OK, P.SOS_ETIMEOUT)
-        has_nan = bool(torch.isnan(y).any().item())
-        if code == P.SOS_ETIMEOUT:
-            assert has_nan
-        elif not timed_out:
-            assert not has_nan
-        timed_out |= code == P.SOS_ETIMEOUT
+        if failed:
+            assert code == P.SOS_ETIMEOUT            # sticky after the first failure
+        elif code == P.SOS_ETIMEOUT:
+            assert bool(torch.isnan(y).any().item())
+        else:
+            assert not bool(torch.isnan(y).any().item())
+        failed |= code == P.SOS_ETIMEOUT
         codes.append(code)
-    print("one-tick bound, chunk codes", codes)
-    xs = workloads.signal(500, seed=10)
-    ys = torch.empty(500, device="cuda")
-    tk, _ = srv.push(b, torch.from_numpy(xs).cuda(), ys)
-    srv.wait(tk)                                    # raises if the bits were left set
+        srv.wait(tkb)                                # b's chunks are unaffected
+        yb_all.append(yb.cpu().numpy())
+    print("one-tick bound, stream a codes", codes)
+    yr, _ = oracle.sosfilt(sos, np.tile(xs, 4))
+    assert rel_l2(np.concatenate(yb_all), yr) <= 1e-5
+    if failed:
+        with pytest.raises(P.SosError) as ei:
+            srv.push(a, x, torch.empty_like(x))
+        assert ei.value.code == P.SOS_ETIMEOUT
+        with pytest.raises(P.SosError) as ei:
+            srv.state(a)
+        assert ei.value.code == P.SOS_ETIMEOUT
+    srv.close_stream(a)
+    c = srv.open(sos)
+    ys2 = torch.empty(500, device="cuda")
+    tk, _ = srv.push(c, xsd, ys2)
+    srv.wait(tk)
     yr, _ = oracle.sosfilt(sos, xs)
-    assert rel_l2(ys.cpu().numpy(), yr) <= 1e-5
+    assert rel_l2(ys2.cpu().numpy(), yr) <= 1e-5
     srv.close()
