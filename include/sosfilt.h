@@ -73,7 +73,8 @@ enum {
     SOS_EHIP = -5,        /* a HIP runtime call failed                                       */
     SOS_ETIMEOUT = -6,    /* a lookback wait exceeded its bound (outputs poisoned with NaN)  */
     SOS_ECLOSED = -7,     /* object already destroyed / stream closed                        */
-    SOS_EBUSY = -8        /* resource temporarily exhausted                                  */
+    SOS_EBUSY = -8,       /* resource temporarily exhausted                                  */
+    SOS_ELIMIT = -9       /* beyond the fixed workspace of sos_filter_noalloc                */
 };
 
 #define SOS_MAX_SECTIONS 64
@@ -333,6 +334,28 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
                      float *zf, hipStream_t stream, int reps, int *L, int *N, float *ms);
 /* A cached tuning result for the key above, or SOS_EINVAL if none. */
 int sos_tune_lookup(sos_handle_t h, int B, int kmax, int64_t total_samples, int *L, int *N);
+
+/* Plain filter that allocates nothing: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation). Same arguments, conventions and result as
+ * sos_filter on a default handle (FP32 compute, the automatic solver choice,
+ * the group shape chosen from n), without a handle: its workspace (control
+ * words, coefficient tables, lookback descriptors) is a fixed device array of
+ * about 16.6 MiB in the library, one per device, kept until the process ends.
+ * No hipMalloc, hipFree or allocating library routine is called.
+ * Limits: K <= SOS_MAX_SECTIONS, and ceil(n / C) * K <= 2^19 group-sections
+ * (C = 8192 samples per group up to 2^20 samples, 16384 up to 2^22, else
+ * 32768: for example n = 2^28 with K up to 64 would need 2^19 at K = 64);
+ * beyond them it returns SOS_ELIMIT and enqueues nothing.
+ * err (nullable, DEVICE, one unsigned): receives the call's device-side error
+ * bits in stream order (0 = none; 1 a0 == 0, 2 unstable section, 4 lookback
+ * timeout), as sos_last_error reports them for a handle.
+ * All calls on one device share the array, which keeps the last call's
+ * contents: calls that overlap on one device (other streams, other host
+ * threads) race and must be serialised by the caller. Stream-ordered on
+ * `stream`; SOS_EINVAL / SOS_EHIP as sos_filter. */
+int sos_filter_noalloc(const float *sections, int K, const float *x, float *y, int64_t n,
+                       const float *zi, float *zf, unsigned *err, hipStream_t stream);
 
 /* ------------------------------------------------------------------ serving
  * Many long signals ("streams") that arrive in chunks, each filtered by its

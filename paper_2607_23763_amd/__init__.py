@@ -26,6 +26,7 @@ SOS_EHIP = -5
 SOS_ETIMEOUT = -6
 SOS_ECLOSED = -7
 SOS_EBUSY = -8
+SOS_ELIMIT = -9
 SOS_MAX_SECTIONS = 64
 SOS_ALG_DEFAULT = 0
 SOS_ALG_DCCR = 1
@@ -68,6 +69,8 @@ def lib():
             L.sos_prepare.argtypes = [vp, vp, i32, vp]
             L.sos_filter_prepared.argtypes = [vp, vp, vp, i64, vp, vp, vp]
             L.sos_bench_copy.argtypes = [vp, vp, i64, vp]
+            L.sos_filter_noalloc.argtypes = [vp, i32, vp, vp, i64, vp, vp, vp, vp]
+            L.sos_filter_noalloc.restype = i32
             L.sos_filter_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp, vp,
                                              vp, vp]
             L.sos_set_precision.argtypes = [vp, i32]
@@ -249,6 +252,26 @@ def _as_dev_f32(t, name):
     if t.dtype != torch.float32:
         raise TypeError("%s must be float32" % name)
     return t.contiguous()
+
+
+def sosfilt_noalloc(x, sos, y, zi=None, zf=None, err=None):
+    """The plain filter through sos_filter_noalloc (no handle, no allocation in
+    the library): y (and zf, err) are caller-provided float32 / int32 GPU
+    tensors; err receives the call's device-side error bits."""
+    x = _as_dev_f32(x, "x").reshape(-1)
+    sos = _as_dev_f32(sos, "sos").reshape(-1, 6)
+    K = sos.shape[0]
+    if zi is not None:
+        zi = _as_dev_f32(zi, "zi").reshape(K, 2)
+    if zf is not None:
+        zf = _as_dev_f32(zf, "zf").reshape(K, 2)
+    y = _as_dev_f32(y, "y").reshape(-1)
+    if y.numel() != x.numel():
+        raise ValueError("y must have x's length")
+    _check(lib().sos_filter_noalloc(_p(sos) if K else None, K, _p(x), _p(y), x.numel(), _p(zi),
+                                    _p(zf), _p(err), _stream_ptr(x.device)),
+           "sos_filter_noalloc")
+    return y, zf
 
 
 def sosfilt_(x, sos, y=None, zi=None, zf=None, handle: Handle | None = None):

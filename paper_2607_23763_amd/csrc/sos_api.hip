@@ -231,6 +231,7 @@ const char *sos_strerror(int code)
     case SOS_ETIMEOUT: return "lookback wait timed out";
     case SOS_ECLOSED: return "closed";
     case SOS_EBUSY: return "busy";
+    case SOS_ELIMIT: return "beyond the fixed workspace of the no-allocation entry point";
     default: return "unknown status";
     }
 }

@@ -90,3 +90,24 @@ def test_strerror_and_null_handle_rejections():
     assert lib.sos_bench_copy(None, None, 10, None) == P.SOS_EINVAL
     assert lib.sos_destroy(None) == P.SOS_EINVAL
     assert lib.sos_create(None, 0) == P.SOS_EINVAL
+    for name, val in re.findall(r"(SOS_E[A-Z]+) = (-\d+)", hdr):
+        assert getattr(P, name) == int(val), name      # status codes too
+
+
+def test_noalloc_rejects_before_touching_the_device():
+    """sos_filter_noalloc checks its arguments and its fixed workspace's
+    limits before any HIP call (so these run without a GPU)."""
+    import paper_2607_23763_amd as P
+
+    lib = P.lib()
+    assert lib.sos_strerror(P.SOS_ELIMIT).startswith(b"beyond the fixed workspace")
+    assert lib.sos_filter_noalloc(None, 1, None, None, 10, None, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_filter_noalloc(None, 65, None, None, 0, None, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_filter_noalloc(None, 0, None, None, -1, None, None, None, None) == P.SOS_EINVAL
+    buf = (ctypes.c_float * 16)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    # x and y overlapping without being equal
+    assert lib.sos_filter_noalloc(p, 1, p, ctypes.c_void_p(p.value + 4), 8, None, None, None,
+                                  None) == P.SOS_EINVAL
+    # 2^40 samples at order 16: far beyond the 2^19 group-sections of the workspace
+    assert lib.sos_filter_noalloc(p, 8, p, p, 1 << 40, None, None, None, None) == P.SOS_ELIMIT
