@@ -77,3 +77,90 @@ def zf_bound(K, by, bz, y_ref, zf_ref):
     zn = max(float(np.linalg.norm(zf_ref)), 1e-300)
     scale = 4.0 * float(np.sqrt(np.mean(y_ref ** 2))) * np.sqrt(2 * K) if y_ref.size else 0.0
     return max(bz, by * max(1.0, scale / zn))
+
+
+def sequential_gzi(sos, gy, gzf, dtype=np.float32):
+    """The initial-state gradient by a sequential reversed-time pass in `dtype`
+    (scipy's lfilter, a third-party routine used only as a yardstick): per
+    section, last to first, the recursion lam[r] = g[r] - a1 lam[r-1] -
+    a2 lam[r-2] from (lam[-1], lam[-2]) = gzf[k], gzi[k] = (lam[n-1],
+    lam[n-2]), and the cotangent passed down is b0 lam[r] + b1 lam[r-1] +
+    b2 lam[r-2]."""
+    import scipy.signal
+
+    sos = np.asarray(sos, dtype=np.float64)
+    K = sos.shape[0]
+    g = np.asarray(gy, dtype=dtype)[::-1].copy()
+    gzf = np.zeros((K, 2)) if gzf is None else np.asarray(gzf, dtype=np.float64).reshape(K, 2)
+    gzi = np.zeros((K, 2))
+    for k in range(K - 1, -1, -1):
+        b = (sos[k, :3] / sos[k, 3]).astype(dtype)
+        a = np.array([1.0, sos[k, 4] / sos[k, 3], sos[k, 5] / sos[k, 3]], dtype=dtype)
+        l1, l2 = dtype(gzf[k, 0]), dtype(gzf[k, 1])
+        # TDF-II state of 1/A(z) after the outputs lam[-2], lam[-1]
+        z = np.array([-a[1] * l1 - a[2] * l2, -a[2] * l1], dtype=dtype)
+        lam, _ = scipy.signal.lfilter(np.array([1.0], dtype), a, g, zi=z)
+        lam = lam.astype(dtype)
+        n = lam.size
+        gzi[k] = [lam[n - 1] if n >= 1 else l1, lam[n - 2] if n >= 2 else (l1 if n == 1 else l2)]
+        lp1 = np.r_[l1, lam[:-1]].astype(dtype)
+        lp2 = np.r_[l2, l1, lam[:-2]][:n].astype(dtype)
+        g = (b[0] * lam + b[1] * lp1 + b[2] * lp2).astype(dtype)
+    return gzi
+
+
+def fp32_gzi_floor(sos, gy, gzf, gzi_ref):
+    """Relative L2 error of the initial-state gradient of a sequential FP32
+    reversed-time pass (sequential_gzi in float32) against `gzi_ref`."""
+    return rel_l2(sequential_gzi(sos, gy, gzf, np.float32), gzi_ref)
+
+
+def sequential_gs(sos, x, zi, gy, dtype=np.float32):
+    """The coefficient gradient of <gy, y> (no final-state cotangent) by a
+    sequential pass whose signals are held in `dtype`: each section's input
+    and output from a forward sweep (scipy's lfilter, a third-party routine
+    used only as a yardstick), then per section, last to first, the adjoint
+    lam[r] = g[r] - a1 lam[r+1] - a2 lam[r+2] (lam = 0 past the end), the sums
+    over r of lam[r] times the input at r - j (b_j) and minus the output at
+    r - j (a_j, j = 1, 2) in FP64, and the cotangent b0 lam[r] + b1 lam[r+1] +
+    b2 lam[r+2] passed down. Coefficients are the normalised b/a0, a/a0; the
+    gradient is carried back to the raw rows (b0, b1, b2, a0, a1, a2)."""
+    import scipy.signal
+
+    sos = np.asarray(sos, dtype=np.float64).reshape(-1, 6)
+    K = sos.shape[0]
+    zi = np.zeros((K, 2)) if zi is None else np.asarray(zi, dtype=np.float64).reshape(K, 2)
+    bn = sos[:, :3] / sos[:, 3:4]
+    an = sos[:, 4:] / sos[:, 3:4]
+    sig = [np.asarray(x, dtype=dtype)]
+    for k in range(K):
+        y, _ = scipy.signal.lfilter(bn[k].astype(dtype), np.r_[1.0, an[k]].astype(dtype), sig[-1],
+                                    zi=zi[k].astype(dtype))
+        sig.append(y.astype(dtype))
+    n = sig[0].size
+    g = np.asarray(gy, dtype=dtype)
+    gs = np.zeros((K, 6))
+    for k in range(K - 1, -1, -1):
+        a = np.r_[1.0, an[k]].astype(dtype)
+        lam = scipy.signal.lfilter(np.array([1.0], dtype), a, g[::-1])[::-1].astype(dtype)
+        u, v, l64 = sig[k].astype(np.float64), sig[k + 1].astype(np.float64), lam.astype(np.float64)
+        gb = [float(l64[j:] @ u[:n - j]) for j in range(3)]
+        ga = [-float(l64[j:] @ v[:n - j]) for j in (1, 2)]
+        a0 = sos[k, 3]
+        gs[k, :3] = np.array(gb) / a0
+        gs[k, 4:] = np.array(ga) / a0
+        gs[k, 3] = -(bn[k] @ np.array(gb) + an[k] @ np.array(ga)) / a0
+        b = bn[k].astype(dtype)
+        nxt = (b[0] * lam).astype(dtype)
+        nxt[:-1] += b[1] * lam[1:]
+        nxt[:-2] += b[2] * lam[2:]
+        g = nxt.astype(dtype)
+    return gs
+
+
+def fp32_gs_floor(sos, x, zi, gy, gs_ref):
+    """Relative L2 error of the coefficient gradient of a sequential FP32 pass
+    (sequential_gs in float32) against `gs_ref`. Signals saved in FP32 alone
+    (the saved section outputs of a training forward are FP32) already set
+    most of this floor when the gradient's sums cancel."""
+    return rel_l2(sequential_gs(sos, x, zi, gy, np.float32), gs_ref)

@@ -154,49 +154,6 @@ def test_inconsistent_empty_signal_leaves_zf_alone(env, B):
         assert rel_l2(y[a:b], yr) <= 1e-5, i
 
 
-def test_full_size_uneven_batch_graph_tuned(env):
-    """The benchmarked uneven batch at full size (4096 signals, ~2e9 samples,
-    device-drawn samples) in the benchmarked launch configuration: autotuned
-    (L, N), captured graph. The longest signal and 7 random ones are compared
-    with the oracle."""
-    torch, P = env
-    dev = torch.device("cuda", 0)
-    Ks, rows, sig_off, zi = workloads.uneven_batch(B=4096, seed=3)
-    total = int(sig_off[-1])
-    gen = torch.Generator(device=dev).manual_seed(3)
-    x = torch.randn(total, generator=gen, device=dev, dtype=torch.float32)
-    y = torch.empty_like(x)
-    Kd = torch.from_numpy(Ks.astype(np.int32)).to(dev)
-    so = torch.from_numpy(sig_off.astype(np.int64)).to(dev)
-    rows_d = torch.from_numpy(rows).to(dev)
-    zi_d = torch.from_numpy(zi).to(dev)
-    zf = torch.empty_like(zi_d)
-    h = P.Handle(0)
-    (L, N), _, _, _ = P.tune_batched(x, rows_d, Kd, so, zi=zi_d, y=y, zf=zf, handle=h, reps=1)
-    y.fill_(float("nan"))
-    g = P.BatchGraph(x, rows_d, Kd, so, zi=zi_d, y=y, zf=zf, handle=h)
-    g.launch()
-    torch.cuda.synchronize()
-    assert g.last_error() == P.SOS_OK
-    lens = np.diff(sig_off)
-    rng = np.random.default_rng(5)
-    pick = [int(np.argmax(lens))] + [int(v) for v in rng.choice(len(Ks), 7, replace=False)]
-    sec = np.r_[0, np.cumsum(Ks)]
-    zfh = zf.cpu().numpy()
-    for i in pick:
-        a, b = int(sig_off[i]), int(sig_off[i + 1])
-        xi = x[a:b].cpu().numpy()
-        r = rows[sec[i]:sec[i + 1]]
-        zii = zi[sec[i]:sec[i + 1]]
-        yr, zfr = oracle.sosfilt(r, xi, zii)
-        by, bz = fp32_bounds(int(Ks[i]), r, xi, zii, yr, zfr)
-        e = rel_l2(y[a:b].cpu().numpy(), yr)
-        print("signal", i, "K", Ks[i], "n", b - a, "tile", (L, N), "rel_l2", e, "bound", by)
-        assert e <= by, (i, e, by)
-        assert rel_l2(zfh[sec[i]:sec[i + 1]], zfr) <= zf_bound(int(Ks[i]), by, bz, yr, zfr)
-    g.close()
-
-
 @pytest.mark.parametrize("alg", ["dccr", "ph"])
 @pytest.mark.parametrize("tile", [(512, 64), (256, 32), (64, 16)])
 def test_small_grid_many_groups_per_workgroup(env, tile, alg, monkeypatch):

@@ -211,25 +211,6 @@ def test_bad_sections_report_and_poison(torch_cuda, P, alg):
     assert rel_l2(y.cpu().numpy(), yr) <= 1e-5
 
 
-@pytest.mark.parametrize("K", [1, 8])
-def test_full_size_2p28(torch_cuda, P, K):
-    """2^28 samples in the launch configuration the benchmark times."""
-    torch = torch_cuda
-    sos = workloads.sweep_sections(K, "butter")
-    n = 1 << 28
-    x = workloads.signal(n, seed=2)
-    xd = torch.from_numpy(x).cuda()
-    y, zf = P.sosfilt(xd, torch.from_numpy(sos).cuda())
-    torch.cuda.synchronize()
-    yh = y.cpu().numpy()
-    del y, xd
-    yr, zfr = oracle.sosfilt(sos, x)
-    e = rel_l2(yh, yr)
-    print("2^28 K", K, "rel_l2", e, "max/peak", max_over_peak(yh, yr))
-    assert e <= tol_for(K)
-    assert rel_l2(zf.cpu().numpy(), zfr) <= tol_for(K)
-
-
 def lightly_damped_sections(K=8, r=0.995, seed=9):
     """K sections with every pole at radius r (random angles and zeros), the
     first section scaled so the cascade has unit white-noise gain (sum of the
