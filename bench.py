@@ -8,20 +8,32 @@ Butterworth low-pass at 0.2*Nyquist and random stable sections. The JSON
 whole step (coefficient preparation + filter kernel) with input and output
 resident in HBM, in GS/s, with the divide-and-conquer cyclic-reduction
 section solver (--alg ph: the PH solver). The other orders are reported under
-"sweep", each timed with both solvers; "plateau" gives the kernel rate against
-the signal length, 2^24..2^28 samples, at orders 2 and 16.
+"sweep", each timed with both solvers and with the library default (the
+solver chosen per signal); alu_roof_frac is against the unpacked FP32 rate
+(78.6 TFLOP/s), which is what the kernels are built for.
 
 Timing: W untimed warm-up steps, then exactly K timed steps between
 torch.cuda.synchronize() calls; two rotating input/output buffer pairs of
 1 GiB each (beyond the 256 MB Infinity Cache). HIP events recorded on the
 launch stream around every filter-kernel launch give the kernel's own average
-duration for the roofline figure.
+duration for the roofline figure. "paper_protocol" times the same kernel the
+paper's way (Sec. IV-F): 1000 warm-up launches, 20 batches of 200, the
+20th-percentile batch mean beside the plain mean. "plateau" holds length
+curves under that protocol (orders 2 and 16, 2^16..2^28 samples) and the
+paper's plateau, the mean of the 2^24 and 2^25 points, for every order and
+both solvers.
+
+CPU legs (skipped with --no-cpu): "cpu_baseline" is the FP64 oracle on one
+thread (one signal is one sequential recursion) over the whole headline
+signal, median of 5; "cpu_baselines_multicore" runs the oracle on the host's
+cores (at most 16 threads) over bounded samples of the batched, served and
+differentiated workloads; "host" records nproc and the CPU model.
 
 Beside the headline, on the same GPU (skipped with --quick):
 * "batched": 4096 signals, lengths floor(2^U), U ~ U[10, 22], orders 2..16,
   random stable sections, random initial states, in one persistent launch
   captured in a HIP graph at the autotuned (L, N); GS/s over all samples (its
-  parity at this size is a GPU test: tests/test_gpu_batched.py).
+  parity at this size is a GPU test: tests/test_gpu_fullsize.py).
 * "served": 1024 streams of orders 2..16, chunks of 4096..65536 samples
   arriving as a Poisson process at swept aggregate rates, pushed by the
   library's native replay driver; achieved GS/s and p50/p99 chunk latency
@@ -57,8 +69,10 @@ BYTES_PER_SAMPLE = 8            # 4 B FP32 in + 4 B FP32 out (Eq. (28))
 # (2 flop each): DC-CR fold 5 + reduction 2 + back substitution 2; PH
 # feed-forward 3 + recursion 2 + homogeneous correction 2 (Table III).
 OPS_PER_SAMPLE_SECTION = {"dccr": 9, "ph": 7}
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X, packed FP32
-FP32_UNPACKED_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# The kernels are built without packed FP32 instructions, so their ALU roof is
+# the unpacked rate: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+FP32_UNPACKED_PEAK_TFLOPS = 78.6
+FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X with packed FP32 (context only)
 KERNEL_SOURCES = ("paper_2607_23763_amd/csrc/sos_fwd.hip", "paper_2607_23763_amd/csrc/sos_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sos_fwd_kernel_k1_2p28.json")
 
@@ -95,6 +109,77 @@ def time_steps(torch, P, h, sos_d, xs, ys, steps, warmup):
     t1 = time.perf_counter()
     kern = sum(a.elapsed_time(b) for a, b in ev) / steps
     return (t1 - t0) * 1e3 / steps, kern
+
+
+def paper_protocol(torch, P, h, xs, ys, batches=20, per_batch=200, warmup=1000):
+    """The paper's timing protocol (Sec. IV-F) for filter launches with the
+    handle's prepared tables: `warmup` untimed launches, then `batches`
+    batches of `per_batch` launches over the rotating buffers, each batch
+    bracketed by HIP events on the launch stream. Returns the 20th-percentile
+    batch mean and the plain mean (ms per launch), and the host time per
+    launch call (us), which shows whether launches were issued faster than
+    they ran."""
+    import ctypes
+
+    import numpy as np
+
+    lib = P.lib()
+    st = P._stream_ptr(xs[0].device)
+    args = [(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel())
+            for x, y in zip(xs, ys)]
+    nb = len(args)
+    f, hp = lib.sos_filter_prepared, h.ptr
+
+    def launch(i):
+        a = args[i % nb]
+        rc = f(hp, a[0], a[1], a[2], None, None, st)
+        if rc:
+            raise RuntimeError("sos_filter_prepared returned %d" % rc)
+
+    for i in range(warmup):
+        launch(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(batches)]
+    t0 = time.perf_counter()
+    for b in range(batches):
+        ev[b][0].record()
+        for i in range(per_batch):
+            launch(b * per_batch + i)
+        ev[b][1].record()
+    host = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(e) / per_batch for a, e in ev])
+    return float(np.percentile(ms, 20)), float(ms.mean()), 1e6 * host / (batches * per_batch)
+
+
+def length_curve(torch, P, h, sos_d, xs, ys, log2ns):
+    """Kernel GS/s against the signal length under the paper's protocol:
+    disjoint slices of the two 1 GiB buffer pairs rotate so that every cycle
+    touches >= 512 MiB (beyond the 256 MB Infinity Cache). With no tile set,
+    one sos_filter call per length prepares the tables at the shape sos_filter
+    picks for that length."""
+    n = xs[0].numel()
+    pts = []
+    for lg in log2ns:
+        m = 1 << lg
+        k = min(n // m, max(1, (1 << 29) // (8 * m)))
+        sx = [xs[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
+        sy = [ys[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
+        P.sosfilt_(sx[0], sos_d, y=sy[0], handle=h)
+        p20, mean, host_us = paper_protocol(torch, P, h, sx, sy)
+        assert h.last_error() == P.SOS_OK
+        pts.append({"log2n": lg, "kernel_GS_per_s": round(m / (p20 * 1e-3) / 1e9, 2),
+                    "mean_GS_per_s": round(m / (mean * 1e-3) / 1e9, 2),
+                    "ms_p20": round(p20, 5), "host_us_per_launch": round(host_us, 2)})
+    return pts
+
+
+def plateau_of(pts):
+    """The paper's plateau of a length curve: the mean of its 2^24 and 2^25
+    points (GS/s)."""
+    v = [p["kernel_GS_per_s"] for p in pts if p["log2n"] in (24, 25)]
+    return round(sum(v) / len(v), 2) if len(v) == 2 else None
 
 
 def bench_toeplitz_bound(torch, n, order16_kernel_gss, log):
@@ -147,13 +232,15 @@ def time_copy(torch, P, xs, ys, steps, warmup):
     return sum(a.elapsed_time(b) for a, b in ev) / steps
 
 
-def cpu_baseline(sos, x_host, n_sample, reps=3):
-    """The FP64 oracle (sequential, one thread) on the first n_sample samples."""
+def cpu_baseline(sos, x_host, reps=5):
+    """The FP64 oracle (sequential, one thread) on the whole signal: GS/s and
+    seconds, median of `reps` runs (the FP64 copy of the input is made before
+    the timing; the oracle allocates its output in each run)."""
     import numpy as np
 
     import oracle
 
-    xs = np.ascontiguousarray(x_host[:n_sample], dtype=np.float64)
+    xs = np.ascontiguousarray(x_host, dtype=np.float64)
     oracle.sosfilt(sos, xs[:1024])             # load / build outside the timing
     ts = []
     for _ in range(reps):
@@ -161,7 +248,116 @@ def cpu_baseline(sos, x_host, n_sample, reps=3):
         oracle.sosfilt(sos, xs)
         ts.append(time.perf_counter() - t)
     ts.sort()
-    return n_sample / ts[len(ts) // 2] / 1e9, ts[len(ts) // 2]
+    return xs.size / ts[len(ts) // 2] / 1e9, ts[len(ts) // 2]
+
+
+def host_info():
+    """Host cores and CPU model, and the worker threads the CPU legs use (the
+    cores this process may run on, at most 16)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "available": avail, "cpu_model": model,
+            "threads": max(1, min(16, avail))}
+
+
+def _median_time(fn, reps):
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def cpu_baselines_multi(workloads, np, threads, log):
+    """The FP64 oracle on the host's cores for the batched, served and
+    differentiated workloads (bounded samples of each; median of 3 runs)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    out = {}
+    g = np.random.default_rng(11)
+    # uneven batch: the first signals of the benchmarked batch, >= 2^27 samples
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=4096, seed=3)
+    S = int(np.searchsorted(sig_off, 1 << 27)) or 1
+    sec = int(np.sum(Ks[:S]))
+    x = g.standard_normal(int(sig_off[S]))
+    run = lambda: oracle.sosfilt_batched(Ks[:S], rows[:sec], sig_off[:S + 1], x, zi[:sec],
+                                         nthreads=threads)
+    oracle.sosfilt_batched(Ks[:1], rows[:int(Ks[0])], sig_off[:2], x, zi[:int(Ks[0])])
+    t = _median_time(run, 3)
+    out["batched"] = {"value": round(x.size / t / 1e9, 4), "unit": "GS/s", "cores": threads,
+                      "kind": "oracle", "seconds": round(t, 3),
+                      "sample": "the first %d of the 4096 signals of the uneven batch (%d "
+                                "samples), oracle_sosfilt_batched with %d threads (signals "
+                                "dealt round-robin)" % (S, x.size, threads)}
+    del x
+    # serving: the first 5000 chunks of the trace; one stream's chunks in
+    # arrival order, concatenated, give the outputs of chunk-by-chunk
+    # filtering with the state carried (streams run in parallel)
+    Ks_s, secs, ids, lens, offs, arrival = workloads.serving_trace(S=1024, R=20000,
+                                                                   rate_chunks_per_s=1e9, seed=4)
+    R = 5000
+    per = np.bincount(ids[:R], minlength=len(Ks_s)).astype(np.int64)
+    lens_s = np.zeros(len(Ks_s), np.int64)
+    np.add.at(lens_s, ids[:R], lens[:R])
+    keep = np.nonzero(per)[0]
+    so = np.r_[0, np.cumsum(lens_s[keep])].astype(np.int64)
+    rws = np.concatenate([secs[s] for s in keep])
+    kk = np.array([secs[s].shape[0] for s in keep], np.int32)
+    x = g.standard_normal(int(so[-1]))
+    run = lambda: oracle.sosfilt_batched(kk, rws, so, x, None, nthreads=threads)
+    t = _median_time(run, 3)
+    out["served"] = {"value": round(x.size / t / 1e9, 4), "unit": "GS/s", "cores": threads,
+                     "kind": "oracle", "seconds": round(t, 3),
+                     "sample": "the first %d of the 20000 chunks (%d samples, %d streams), all "
+                               "queued at once; each stream's chunks concatenated in arrival "
+                               "order, streams on %d threads" % (R, x.size, keep.size, threads)}
+    del x
+    # differentiation: 256 signals of 2^16 samples, order-8 Butterworth
+    sos = workloads.sweep_sections(4, "butter")
+    B, m = 256, 1 << 16
+    x = g.standard_normal(B * m)
+    gy = g.standard_normal(B * m)
+    K = sos.shape[0]
+    rb = np.tile(sos, (B, 1))
+    sob = np.arange(B + 1, dtype=np.int64) * m
+    t_f = _median_time(lambda: oracle.sosfilt_batched(np.full(B, K, np.int32), rb, sob, x, None,
+                                                      nthreads=threads), 3)
+
+    def vjp_all():
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda i: oracle.sosfilt_vjp(sos, x[i * m:(i + 1) * m], None,
+                                                     gy[i * m:(i + 1) * m], None), range(B)))
+
+    t_b = _median_time(vjp_all, 3)
+    x1 = g.standard_normal(1 << 24)
+    g1 = g.standard_normal(1 << 24)
+    t1 = _median_time(lambda: (oracle.sosfilt(sos, x1), oracle.sosfilt_vjp(sos, x1, None, g1)), 3)
+    out["fwd_bwd"] = {"value": round(B * m / (t_f + t_b) / 1e9, 4), "unit": "GS/s",
+                      "cores": threads, "kind": "oracle",
+                      "fwd_GS_per_s": round(B * m / t_f / 1e9, 4),
+                      "vjp_GS_per_s": round(B * m / t_b / 1e9, 4),
+                      "one_signal_2p24_fwd_bwd_GS_per_s": round((1 << 24) / t1 / 1e9, 4),
+                      "sample": "the whole 256 x 2^16 batch, order-8 Butterworth: "
+                                "oracle_sosfilt_batched (forward) and one oracle_sosfilt_vjp "
+                                "per signal on %d threads; one 2^24-sample signal forward + "
+                                "VJP on one thread" % threads}
+    log("cpu baselines", out)
+    return out
 
 
 def cpu_wavefront_rate(sos, x_host, n_sample, reps=3):
@@ -402,11 +598,25 @@ def main():
     ms_step, ms_kern = time_steps(torch, P, h, sos1_d, xs, ys, args.steps, args.warmup)
     assert h.last_error() == P.SOS_OK
     log("K=%d step %.4f ms (%.1f GS/s), kernel %.4f ms" % (K1, ms_step, gss(ms_step), ms_kern))
+    # the same kernel under the paper's protocol (Sec. IV-F)
+    paper_stat = None
+    if not args.quick and not args.only_k:
+        P.prepare(sos1_d, handle=h)
+        p20, pmean, host_us = paper_protocol(torch, P, h, xs, ys)
+        assert h.last_error() == P.SOS_OK
+        paper_stat = {"protocol": "1000 warm-up launches, 20 batches of 200 launches, "
+                                  "20th-percentile batch mean (Sec. IV-F)",
+                      "kernel_ms_p20": round(p20, 4), "kernel_GS_per_s": round(gss(p20), 2),
+                      "kernel_ms_mean": round(pmean, 4), "mean_GS_per_s": round(gss(pmean), 2),
+                      "hbm_roof_frac": round(gss(p20) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
+                      "host_us_per_launch": round(host_us, 2)}
+        log("paper protocol", paper_stat)
 
     result_sweep = {}
     if not args.no_sweep and not args.only_k:
         other = "ph" if args.alg == "dccr" else "dccr"
         h2 = P.Handle(0, tile=tile, algorithm=other)
+        h3 = P.Handle(0, tile=tile)         # the library default: per-signal choice
         for kind in ("butter", "random"):
             result_sweep[kind] = {}
             for K in (1, 2, 4, 8):
@@ -415,6 +625,8 @@ def main():
                 assert h.last_error() == P.SOS_OK
                 ms2, mk2 = time_steps(torch, P, h2, sos_d, xs, ys, max(10, args.steps // 2), 3)
                 assert h2.last_error() == P.SOS_OK
+                ms3, mk3 = time_steps(torch, P, h3, sos_d, xs, ys, max(10, args.steps // 2), 3)
+                assert h3.last_error() == P.SOS_OK
                 tf = gss(mk) * 2 * OPS_PER_SAMPLE_SECTION[args.alg] * K / 1e3
                 tf2 = gss(mk2) * 2 * OPS_PER_SAMPLE_SECTION[other] * K / 1e3
                 result_sweep[kind][str(K)] = {
@@ -422,32 +634,37 @@ def main():
                     "kernel_GS_per_s": round(gss(mk), 2),
                     "hbm_roof_frac": round(gss(mk) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
                     "alu_TFLOPs": round(tf, 2),
-                    "alu_roof_frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
-                    "alu_unpacked_roof_frac": round(tf / FP32_UNPACKED_PEAK_TFLOPS, 4),
+                    "alu_roof_frac": round(tf / FP32_UNPACKED_PEAK_TFLOPS, 4),
+                    "alu_packed_roof_frac": round(tf / FP32_PACKED_PEAK_TFLOPS, 4),
                     other + "_GS_per_s": round(gss(ms2), 2),
                     other + "_kernel_GS_per_s": round(gss(mk2), 2),
-                    other + "_alu_roof_frac": round(tf2 / FP32_VECTOR_PEAK_TFLOPS, 4)}
+                    other + "_alu_roof_frac": round(tf2 / FP32_UNPACKED_PEAK_TFLOPS, 4),
+                    "auto_GS_per_s": round(gss(ms3), 2),
+                    "auto_kernel_GS_per_s": round(gss(mk3), 2)}
                 log(kind, K, result_sweep[kind][str(K)])
         h2.close()
+        h3.close()
 
-    # plateau: kernel GS/s against the signal length (disjoint slices of the
-    # two 1 GiB buffer pairs, rotated so that >= 512 MiB is touched per cycle,
-    # beyond the 256 MB Infinity Cache)
+    # length curves and the paper's plateau (mean of the 2^24 and 2^25
+    # points), Butterworth, under the paper's protocol: orders 2 and 16 over
+    # 2^16..2^28 samples with the headline solver, the plateau points of
+    # every order with both solvers
     plateau = {}
-    if not args.no_sweep and not args.only_k and args.log2n == 28:
-        for K in (1, 8):
+    if not args.no_sweep and not args.only_k and args.log2n == 28 and not args.quick:
+        hp = P.Handle(0, tile=tile, algorithm="ph" if args.alg == "dccr" else "dccr")
+        for K in (1, 2, 4, 8):
             sos_d = torch.from_numpy(workloads.sweep_sections(K, "butter")).to(dev)
-            pts = []
-            for lg in (24, 25, 26, 27, 28):
-                m = 1 << lg
-                k = min(8, n // m)
-                sx = [xs[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
-                sy = [ys[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
-                _, mk = time_steps(torch, P, h, sos_d, sx, sy, 20, 4)
-                assert h.last_error() == P.SOS_OK
-                pts.append({"log2n": lg, "kernel_GS_per_s": round(m / (mk * 1e-3) / 1e9, 2)})
-            plateau["order_%d" % (2 * K)] = pts
-            log("plateau", K, pts)
+            lgs = range(16, 29) if K in (1, 8) else (24, 25)
+            pts = length_curve(torch, P, h, sos_d, xs, ys, lgs)
+            pts2 = length_curve(torch, P, hp, sos_d, xs, ys, (24, 25))
+            plateau["order_%d" % (2 * K)] = {
+                "plateau_GS_per_s": plateau_of(pts),
+                "plateau_hbm_roof_frac": round(plateau_of(pts) * BYTES_PER_SAMPLE / HBM_PEAK_GBS,
+                                               4),
+                hp.algorithm() + "_plateau_GS_per_s": plateau_of(pts2),
+                "curve": pts}
+            log("plateau", 2 * K, plateau["order_%d" % (2 * K)])
+        hp.close()
 
     copy_ms = time_copy(torch, P, xs, ys, 20, 3)
     copy_gbs = n * BYTES_PER_SAMPLE / (copy_ms * 1e-3) / 1e9
@@ -473,14 +690,18 @@ def main():
 
     cpu = None
     cpu_extra = None
+    cpu_multi = None
+    host = host_info()
     if not args.no_cpu:
-        n_cpu = min(n, 1 << 27)
-        v, secs = cpu_baseline(sos1, x_host, n_cpu)
+        v, secs = cpu_baseline(sos1, x_host)
         cpu = {"value": round(v, 4), "unit": "GS/s", "cores": 1, "kind": "oracle",
-               "sample": "FP64 sequential oracle, one thread, first 2^%d samples of the same "
-                         "K=%d Butterworth signal, median of 3 runs (%.2f s each)"
-                         % (n_cpu.bit_length() - 1, K1, secs)}
+               "sample": "FP64 sequential oracle, one thread (one signal is one sequential "
+                         "recursion), the whole 2^%d-sample K=%d Butterworth signal, median of "
+                         "5 runs (%.2f s each)" % (args.log2n, K1, secs),
+               "nproc": host["nproc"], "cpu_model": host["cpu_model"]}
         log("cpu", cpu)
+        if not args.quick and not args.only_k:
+            cpu_multi = cpu_baselines_multi(workloads, np, host["threads"], log)
         # the paper's multi-core CPU method, beside the oracle (not the baseline)
         wf = {}
         for K in (K1, 8):
@@ -513,7 +734,10 @@ def main():
         "hbm_roof_frac_step": round(gss(ms_step) * BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baselines_multicore": cpu_multi,
+        "host": host,
         "cpu_wavefront": cpu_extra,
+        "paper_protocol": paper_stat,
         "sweep": result_sweep,
         "plateau": plateau,
     }

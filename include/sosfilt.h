@@ -109,16 +109,19 @@ int sos_get_tile(sos_handle_t h, int *L, int *N);
 
 /* Arithmetic type of the per-sample work of the filter kernels: 32 (FP32,
  * the default) or 64 (FP64; 0 restores the default). Data in memory stay FP32
- * either way, and everything that acts on carried states (the lanes' and
- * groups' terminal states, the scans over lanes, waves and groups through
- * powers of the state map, the lanes' incoming states and zf) is computed in
- * FP64 whatever the type: those powers are badly conditioned for lightly
- * damped sections with poles near the real axis, and FP32 rounding of them
- * would be amplified into every sample of a group. With FP32, a cascade is
- * about as accurate as a sequential FP32 filter; FP64 goes further where a
- * cascade's own FP32 error floor is too high. MI355X issues FP64 FMAs at the
- * unpacked-FP32 rate, so the cost of FP64 is register pressure. Applies to
- * later calls. */
+ * either way. In FP32 each signal's tables take one of two layouts, chosen by
+ * the preparation kernel from the peak gain 1 / min |A(e^{jw})| of its
+ * sections (thresholds under sos_set_algorithm): the fast layout (everything
+ * in FP32) or the accurate one, where everything that acts on carried states
+ * (the lanes' and groups' terminal states, the scans over lanes, waves and
+ * groups through powers of the state map, the lanes' incoming states and zf)
+ * runs in FP64 and the homogeneous correction uses an orthonormal basis of
+ * the lane's free responses: with poles near the unit circle those powers
+ * are badly conditioned and FP32 rounding of them would be amplified into
+ * every sample of a group. With FP32, a cascade is about as accurate as a
+ * sequential FP32 filter; FP64 goes further where a cascade's own FP32 error
+ * floor is too high. MI355X issues FP64 FMAs at the unpacked-FP32 rate, so
+ * the cost of FP64 is register pressure. Applies to later calls. */
 int sos_set_precision(sos_handle_t h, int bits);
 int sos_get_precision(sos_handle_t h);
 
@@ -132,14 +135,20 @@ int sos_get_precision(sos_handle_t h);
  *                 Eq. (9)), then the homogeneous correction of every sample
  *                 from the lane's incoming state (Eq. (11)); about 7 FMAs per
  *                 sample and section and a lane-sequential chain of N FMAs.
- *   SOS_ALG_AUTO  DC-CR for every section except those whose recursive part
- *                 has a peak gain 1 / min |A(e^{jw})| above 32 (poles very
- *                 close to the unit circle), which are solved by PH in the
- *                 same launch. DC-CR's fold multiplies by A(-z), which
- *                 amplifies rounding near the mirror frequency of such poles
- *                 when an earlier section has put the signal's energy there;
- *                 PH applies no such factor. Butterworth designs up to order
- *                 16 stay on DC-CR entirely.
+ *   SOS_ALG_AUTO  per signal, in FP32: DC-CR on the fast layout when every
+ *                 section's recursive part has a peak gain 1 / min
+ *                 |A(e^{jw})| of at most 32, else PH on the accurate layout
+ *                 (see sos_set_precision), in the same launch. DC-CR's fold
+ *                 multiplies by A(-z), which amplifies rounding near the
+ *                 mirror frequency of poles close to the unit circle; PH
+ *                 applies no such factor. Butterworth designs up to order 16
+ *                 at cutoff 0.2*pi peak at 15.7 and stay on DC-CR. In FP64:
+ *                 DC-CR.
+ * In FP32, SOS_ALG_PH takes the accurate layout for signals with a section
+ * of peak gain above 128 (its fast layout stays within about 3x of a
+ * sequential FP32 filter's error up to there); SOS_ALG_DCCR always takes the
+ * fast layout. SOS_ACCURATE_GAIN in the environment (a positive number, or
+ * "inf" for never) replaces the thresholds of SOS_ALG_AUTO and SOS_ALG_PH.
  * All share the cross-lane scan, the decoupled lookback, the tables and the
  * state conventions, and accept every tile and compute type. SOS_ALG_DEFAULT
  * (0) restores the default: SOS_ALG in the environment ("auto", "dccr" or
@@ -272,6 +281,21 @@ int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
                            const float *y, const float *saved, const float *gy,
                            const float *gzf, float *gx, float *gzi, float *gsections,
                            hipStream_t stream);
+
+/* The batched adjoint for a batch whose signals share one cascade (the rows
+ * of every signal hold the same sections, as when one filter is trained on a
+ * batch): sos_filter_vjp_batched's arguments, with gsections replaced by
+ * `gsum`, DEVICE kmax x 6 floats (required): row k receives the sum over the
+ * signals i with K[i] > k of the gradient of signal i's row k. Each signal's
+ * gradient is formed in FP64, the sum over signals runs in FP64 in a fixed
+ * order and is rounded once. With B = 0 nothing is written. For callers
+ * that differentiate a shared filter; the paper does not treat gradients. */
+int sos_filter_vjp_batched_sum(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                               int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                               const float *sections, const int64_t *sig_off, const float *x,
+                               const float *y, const float *saved, const float *gy,
+                               const float *gzf, float *gx, float *gzi, float *gsum,
+                               hipStream_t stream);
 
 /* Memory-floor reference (the t_mem = b_s / BW term of the cost model,
  * Eq. (28), with b_s = 8 bytes per sample): a plain streaming copy y = x of n

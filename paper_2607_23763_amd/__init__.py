@@ -108,8 +108,10 @@ def lib():
                                                    vp, vp, vp, vp, vp]
             L.sos_filter_vjp_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp,
                                                  vp, vp, vp, vp, vp, vp, vp]
+            L.sos_filter_vjp_batched_sum.argtypes = L.sos_filter_vjp_batched.argtypes
             L.sos_filter_train_batched.restype = i32
             L.sos_filter_vjp_batched.restype = i32
+            L.sos_filter_vjp_batched_sum.restype = i32
             for name in ("sos_graph_create_batched", "sos_graph_launch", "sos_graph_last_error",
                          "sos_graph_destroy", "sos_tune_batched", "sos_tune_lookup"):
                 getattr(L, name).restype = i32
@@ -401,10 +403,12 @@ def sosfilt_train_batched(x, sections, K, sig_off, zi=None, sec_off=None, kmax=N
 
 
 def sosfilt_vjp_batched(sections, K, sig_off, x, y, saved, gy, gzf=None, sec_off=None,
-                        kmax=None, handle: Handle | None = None):
+                        kmax=None, handle: Handle | None = None, shared: bool = False):
     """Vector-Jacobian product of a batched forward (sos_filter_vjp_batched).
     Returns (gx, gzi, gsections), gzi and gsections shaped like zi and
-    sections (rows of the batch's signals)."""
+    sections (rows of the batch's signals). With shared=True (every signal's
+    rows hold the same cascade) gsections is kmax x 6, the gradients summed
+    over the signals in FP64 by the library (sos_filter_vjp_batched_sum)."""
     import torch
 
     a = _batch_args(x, sections, K, sig_off, None, None, None, sec_off, kmax)
@@ -414,14 +418,14 @@ def sosfilt_vjp_batched(sections, K, sig_off, x, y, saved, gy, gzf=None, sec_off
         gzf = _as_dev_f32(gzf, "gzf").reshape(-1, 2)
     gx = torch.empty_like(a["x"])
     gzi = torch.zeros((a["nsec"], 2), dtype=torch.float32, device=a["x"].device)
-    gs = torch.zeros((a["nsec"], 6), dtype=torch.float32, device=a["x"].device)
+    gs = torch.zeros((max(a["kmax"], 1) if shared else a["nsec"], 6), dtype=torch.float32,
+                     device=a["x"].device)
     h = handle or default_handle(a["x"].device.index or 0)
-    _check(lib().sos_filter_vjp_batched(h.ptr, a["B"], a["kmax"], a["nsec"], a["x"].numel(),
-                                        _p(a["K"]), _p(a["sec_off"]), _p(a["sections"]),
-                                        _p(a["sig_off"]), _p(a["x"]), _p(y), _p(saved), _p(gy),
-                                        _p(gzf), _p(gx), _p(gzi), _p(gs),
-                                        _stream_ptr(a["x"].device)),
-           "sos_filter_vjp_batched")
+    fn = lib().sos_filter_vjp_batched_sum if shared else lib().sos_filter_vjp_batched
+    _check(fn(h.ptr, a["B"], a["kmax"], a["nsec"], a["x"].numel(), _p(a["K"]), _p(a["sec_off"]),
+              _p(a["sections"]), _p(a["sig_off"]), _p(a["x"]), _p(y), _p(saved), _p(gy), _p(gzf),
+              _p(gx), _p(gzi), _p(gs), _stream_ptr(a["x"].device)),
+           "sos_filter_vjp_batched_sum" if shared else "sos_filter_vjp_batched")
     return gx, gzi, gs
 
 
@@ -555,8 +559,8 @@ def _autograd_fn():
         """A batch of equal-length signals x (B x n): forward =
         sos_filter_train_batched, backward = sos_filter_vjp_batched (one
         persistent adjoint launch for the whole batch). sos is K x 6 (shared
-        by the batch: its gradient is summed over the signals) or B x K x 6;
-        zi is B x K x 2."""
+        by the batch: its gradient is summed over the signals by the library,
+        sos_filter_vjp_batched_sum) or B x K x 6; zi is B x K x 2."""
 
         @staticmethod
         def forward(ctx, x, sos, zi):
@@ -581,9 +585,9 @@ def _autograd_fn():
             gy = torch.zeros_like(y) if gy is None else gy.reshape(-1).contiguous()
             gzf = None if gzf is None else gzf.reshape(-1, 2).contiguous()
             gx, gzi, gs = sosfilt_vjp_batched(rows, Ks, sig_off, xf, y, saved, gy, gzf,
-                                              sec_off=sec_off, kmax=K)
-            gs = gs.reshape(B, K, 6)
-            return gx.reshape(B, n), (gs.sum(0) if sdim == 2 else gs), gzi.reshape(B, K, 2)
+                                              sec_off=sec_off, kmax=K, shared=sdim == 2)
+            return gx.reshape(B, n), gs.reshape(K, 6) if sdim == 2 else gs.reshape(B, K, 6), \
+                gzi.reshape(B, K, 2)
 
     return SosFilterFn, SosFilterBatchFn
 

@@ -70,12 +70,14 @@ int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream,
     const int bits = bits_of(h);
     int rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes(K > 8 ? K : 8, bits), stream);
     if (rc) return rc;
+    const double rho_max = rho_max_of(h);
     if (sos_launch_prep(bits, sections, K, __builtin_ctz((unsigned)t.N),
-                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl, 0, rho_max_of(h),
+                        __builtin_ctz((unsigned)(t.L / 64)), h->tabs, h->ctrl, 0, rho_max,
                         stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = K;
     h->prep_alg = solver_of(h);
+    h->prep_rho = rho_max;
     h->prep_L = t.L;
     h->prep_N = t.N;
     h->prep_bits = bits;
@@ -121,7 +123,7 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     const bool cap = capturing(stream);
     if ((!h->armed || cap || h->batch_captured) && sos_launch_arm(h->ctrl, stream) != hipSuccess)
         return SOS_EHIP;
-    const int alg = launch_alg(bits, h->prep_alg);
+    const int alg = launch_alg(bits, h->prep_alg, h->prep_rho);
     if (sos_launch_fwd(bits, alg, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
                        h->timeout_ticks, grid_of(bits, alg, L, N), saved, stream) != hipSuccess)
         return SOS_EHIP;
@@ -147,6 +149,7 @@ void mark_degenerate(sos_ctx *h, int K)
     h->prep_N = t.N;
     h->prep_bits = bits_of(h);
     h->prep_alg = solver_of(h);
+    h->prep_rho = rho_max_of(h);
 }
 
 }  // namespace
@@ -202,7 +205,7 @@ int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t
                              ba.zf, h->ctrl, stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    const int alg = launch_alg(bits, solver_of(h));
+    const int alg = launch_alg(bits, solver_of(h), rho_max_of(h));
     int64_t grid = grid_of(bits, alg, t.L, t.N);
     if (grid <= 0 || grid > max_groups) grid = max_groups;
     if (sos_launch_fwd_batched(bits, alg, t.L, t.N, ba.B, kd, ba.K, ba.sec_off, ba.sig_off, h->gpre,
@@ -294,7 +297,7 @@ int sos_destroy(sos_handle_t h)
         (void)hipDeviceSynchronize();
         for (void *p : {(void *)h->desc, (void *)h->tabs, (void *)h->ctrl, (void *)h->gpre,
                         (void *)h->sigmap, (void *)h->total_dev, (void *)h->tabs_bwd,
-                        (void *)h->partials})
+                        (void *)h->partials, (void *)h->grow})
             if (p) (void)hipFree(p);
     }
     delete h;
@@ -496,7 +499,7 @@ int sos_filter_vjp(sos_handle_t h, const float *sections, int K, const float *x,
                         rho_max_of(h), stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_bwd(bits, launch_alg(bits, solver_of(h)), t.L, t.N, gy, gx, n, groups,
+    if (sos_launch_bwd(bits, launch_alg(bits, solver_of(h), rho_max_of(h)), t.L, t.N, gy, gx, n, groups,
                        h->tabs_bwd, K, x, y, saved,
                        gzf, gzi, h->partials, h->desc, h->ctrl, h->timeout_ticks, grid_override(),
                        stream) != hipSuccess)
@@ -532,12 +535,15 @@ int sos_filter_train_batched(sos_handle_t h, int B, int kmax, int64_t total_rows
     return batch_enqueue(h, t, bits, ba, stream);
 }
 
-int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
-                           int64_t total_samples, const int32_t *K, const int32_t *sec_off,
-                           const float *sections, const int64_t *sig_off, const float *x,
-                           const float *y, const float *saved, const float *gy,
-                           const float *gzf, float *gx, float *gzi, float *gsections,
-                           hipStream_t stream)
+namespace {
+
+// The batched adjoint; coefficient gradients per signal row (gsections) or,
+// for a shared cascade, summed over the signals (gsum, kmax x 6).
+int vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_t total_samples,
+                const int32_t *K, const int32_t *sec_off, const float *sections,
+                const int64_t *sig_off, const float *x, const float *y, const float *saved,
+                const float *gy, const float *gzf, float *gx, float *gzi, float *gsections,
+                float *gsum, hipStream_t stream)
 {
     if (!h || B < 0 || kmax < 0 || kmax > SOS_MAX_SECTIONS || total_samples < 0 ||
         total_rows < 0)
@@ -580,20 +586,50 @@ int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
                              stream) != hipSuccess)
         return SOS_EHIP;
     if (sos_launch_arm(h->ctrl, stream) != hipSuccess) return SOS_EHIP;
-    if (sos_launch_bwd_batched(bits, launch_alg(bits, solver_of(h)), t.L, t.N, B, kd, K, sec_off,
+    if (sos_launch_bwd_batched(bits, launch_alg(bits, solver_of(h), rho_max_of(h)), t.L, t.N, B, kd, K, sec_off,
                                sig_off, h->gpre,
                                h->sigmap, h->total_dev, max_groups, gy, gx, h->tabs_bwd, x, y, saved,
                                total_samples, gzf, gzi, h->partials, h->desc, h->ctrl,
                                h->timeout_ticks, stream) != hipSuccess)
         return SOS_EHIP;
-    if (gsections && sos_launch_bwd_reduce_batched(h->partials, B, kmax, total_rows,
-                                                   total_samples, K, sec_off, sig_off, h->gpre,
-                                                   sections, gsections, stream) != hipSuccess)
+    if (gsum) {
+        rc = ensure_buf(h->grow, h->grow_cap, (size_t)B * kd * 6, stream);
+        if (rc) return rc;
+    }
+    if ((gsections || gsum) &&
+        sos_launch_bwd_reduce_batched(h->partials, B, kmax, total_rows, total_samples, K,
+                                      sec_off, sig_off, h->gpre, sections, gsections,
+                                      gsum ? h->grow : nullptr, gsum, stream) != hipSuccess)
         return SOS_EHIP;
     h->prep_K = -1;
     h->last_groups = 0;
     h->last_K = 0;
     return SOS_OK;
+}
+
+}  // namespace
+
+int sos_filter_vjp_batched(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                           int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                           const float *sections, const int64_t *sig_off, const float *x,
+                           const float *y, const float *saved, const float *gy,
+                           const float *gzf, float *gx, float *gzi, float *gsections,
+                           hipStream_t stream)
+{
+    return vjp_batched(h, B, kmax, total_rows, total_samples, K, sec_off, sections, sig_off, x, y,
+                       saved, gy, gzf, gx, gzi, gsections, nullptr, stream);
+}
+
+int sos_filter_vjp_batched_sum(sos_handle_t h, int B, int kmax, int64_t total_rows,
+                               int64_t total_samples, const int32_t *K, const int32_t *sec_off,
+                               const float *sections, const int64_t *sig_off, const float *x,
+                               const float *y, const float *saved, const float *gy,
+                               const float *gzf, float *gx, float *gzi, float *gsum,
+                               hipStream_t stream)
+{
+    if (!gsum) return SOS_EINVAL;
+    return vjp_batched(h, B, kmax, total_rows, total_samples, K, sec_off, sections, sig_off, x, y,
+                       saved, gy, gzf, gx, gzi, nullptr, gsum, stream);
 }
 
 int sos_bench_copy(const float *x, float *y, int64_t n, hipStream_t stream)

@@ -1603,16 +1603,20 @@ __global__ void __launch_bounds__(256)
 sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, int64_t rows,
                               int64_t total_samples, const int32_t *Ks, const int32_t *sec_off,
                               const int64_t *sig_off, const int64_t *gpre, const float *sections,
-                              float *gsections)
+                              float *gsections, double *grow)
 {
     __shared__ double sh[256][5];
     const int i = blockIdx.x, k = blockIdx.y;
-    // uniform per block
-    if (i >= B || !batch_signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off) ||
-        k >= Ks[i])
+    // uniform per block; a (signal, section) pair without a gradient leaves
+    // zeros in the FP64 rows, which are summed over signals afterwards
+    bool ok = i < B && batch_signal_ok(i, kmax, rows, total_samples, Ks, sec_off, sig_off) &&
+              k < Ks[i];
+    const int64_t t0 = ok ? gpre[i] : 0, t1 = ok ? gpre[i + 1] : 0;
+    ok = ok && t0 <= t1 && t1 <= gpre[B];
+    if (!ok) {
+        if (grow && threadIdx.x < 6 && i < B) grow[((size_t)i * kmax + k) * 6 + threadIdx.x] = 0.0;
         return;
-    const int64_t t0 = gpre[i], t1 = gpre[i + 1];
-    if (t0 > t1 || t1 > gpre[B]) return;
+    }
     double acc[5] = {0, 0, 0, 0, 0};
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256)
         for (int c = 0; c < 5; ++c) acc[c] += partials[((size_t)t * kmax + k) * 5 + c];
@@ -1630,14 +1634,36 @@ sos_bwd_reduce_batched_kernel(const double *partials, int B, int kmax, int64_t r
         const double bn0 = row[0] / a0, bn1 = row[1] / a0, bn2 = row[2] / a0;
         const double an1 = row[4] / a0, an2 = row[5] / a0;
         const double *g = sh[0];
-        float *o = gsections + 6 * row_i;
-        o[0] = (float)(g[0] / a0);
-        o[1] = (float)(g[1] / a0);
-        o[2] = (float)(g[2] / a0);
-        o[4] = (float)(g[3] / a0);
-        o[5] = (float)(g[4] / a0);
-        o[3] = (float)(-(g[0] * bn0 + g[1] * bn1 + g[2] * bn2 + g[3] * an1 + g[4] * an2) / a0);
+        const double v[6] = {g[0] / a0, g[1] / a0, g[2] / a0,
+                             -(g[0] * bn0 + g[1] * bn1 + g[2] * bn2 + g[3] * an1 + g[4] * an2) /
+                                 a0,
+                             g[3] / a0, g[4] / a0};
+        if (gsections)
+            for (int c = 0; c < 6; ++c) gsections[6 * row_i + c] = (float)v[c];
+        if (grow)
+            for (int c = 0; c < 6; ++c) grow[((size_t)i * kmax + k) * 6 + c] = v[c];
     }
+}
+
+// Sum over the signals of each section's coefficient gradient, for a batch
+// whose signals share one cascade: block k adds the FP64 rows of every signal
+// in a fixed order (strided partial sums, then a tree) and rounds once.
+__global__ void __launch_bounds__(256)
+sos_bwd_sum_rows_kernel(const double *grow, int B, int kmax, float *gsum)
+{
+    __shared__ double sh[256][6];
+    const int k = blockIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < B; i += 256)
+        for (int c = 0; c < 6; ++c) acc[c] += grow[((size_t)i * kmax + k) * 6 + c];
+    for (int c = 0; c < 6; ++c) sh[threadIdx.x][c] = acc[c];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d)
+            for (int c = 0; c < 6; ++c) sh[threadIdx.x][c] += sh[threadIdx.x + d][c];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) gsum[6 * k + threadIdx.x] = (float)sh[0][threadIdx.x];
 }
 
 // ------------------------------------------------------------------ launch
@@ -1933,12 +1959,18 @@ extern "C" hipError_t sos_launch_bwd_reduce_batched(const double *partials, int 
                                                     const int32_t *Ks, const int32_t *sec_off,
                                                     const int64_t *sig_off, const int64_t *gpre,
                                                     const float *sections, float *gsections,
+                                                    double *grow, float *gsum,
                                                     hipStream_t stream)
 {
     if (B <= 0 || kmax <= 0) return hipSuccess;
+    if (gsum && !grow) return hipErrorInvalidValue;
     hipLaunchKernelGGL(sos_bwd_reduce_batched_kernel, dim3((unsigned)B, (unsigned)kmax),
                        dim3(256), 0, stream, partials, B, kmax, rows, total_samples, Ks, sec_off,
-                       sig_off, gpre, sections, gsections);
+                       sig_off, gpre, sections, gsections, gsum ? grow : nullptr);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    if (gsum)
+        hipLaunchKernelGGL(sos_bwd_sum_rows_kernel, dim3((unsigned)kmax), dim3(256), 0, stream,
+                           grow, B, kmax, gsum);
     return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ hipError_t sos_launch_bwd_reduce_batched(const double *partials, int B, int kmax
                                          int64_t total_samples, const int32_t *Ks,
                                          const int32_t *sec_off, const int64_t *sig_off,
                                          const int64_t *gpre, const float *sections,
-                                         float *gsections, hipStream_t stream);
+                                         float *gsections, double *grow, float *gsum,
+                                         hipStream_t stream);
 hipError_t sos_launch_worktable(int B, int kmax, int64_t rows, int64_t C, int64_t total_samples,
                                 int64_t max_groups, const int32_t *Ks, const int32_t *sec_off,
                                 const int64_t *sig_off, int64_t *gpre, int32_t *sigmap,
@@ -106,6 +107,7 @@ struct sos_ctx {
     int prep_N = 0;
     int prep_bits = 0;
     int prep_alg = 0;                     // solver the tables were prepared for
+    double prep_rho = 0.0;                // and their peak-gain threshold
     // uneven-batch work table
     int64_t *gpre = nullptr;
     size_t gpre_cap = 0;
@@ -117,6 +119,8 @@ struct sos_ctx {
     size_t tabs_bwd_cap = 0;
     double *partials = nullptr;
     size_t partials_cap = 0;
+    double *grow = nullptr;               // FP64 per-signal coefficient gradients
+    size_t grow_cap = 0;                  // (summed over a shared cascade)
     std::mutex mu;
 };
 
@@ -237,27 +241,45 @@ inline int alg_of(const sos_ctx *h)
 
 // Peak gain of a section's recursive part, 1 / min |A(e^{jw})|, above which
 // a signal's tables take the accurate layout (FP32 compute): its state work
-// runs in FP64 and its sections are solved by PH, because with poles that
-// close to the unit circle the FP32 powers of the state map, and DC-CR's fold
-// B(z)A(-z) near the poles' mirror frequencies, amplify rounding. Every
-// section of the Butterworth designs up to order 16 at cutoff 0.2*pi (at most
-// 15.7) and of random sections with pole radius up to 0.99 at moderate angles
-// stays below 32; lightly damped sections (radius 0.995: 100 and more) do
-// not. An explicit DC-CR handle keeps DC-CR and the compute type everywhere.
+// runs in FP64, its correction uses an orthonormal basis, and its sections
+// are solved by PH. With poles close to the unit circle the FP32 powers of
+// the state map, and DC-CR's fold B(z)A(-z) near the poles' mirror
+// frequencies, amplify rounding. Measured on MI355X (2^20 samples, cascades
+// of 4 and 8 sections, against a sequential FP32 filter's error): the fast
+// DC-CR layout already reaches 3-6x that error at peak gains of 120-360,
+// the fast PH layout stays within 3x up to 128 and reaches 3-18x from about
+// 800 on (the lightly damped order-16 cascade, pole radius 0.995, peak gain
+// 5673: 18x), the accurate layout stays within 2x throughout.
+//   automatic choice: DC-CR's fast layout up to 32, else the accurate one
+//                     (Butterworth designs up to order 16 at cutoff 0.2*pi
+//                     peak at 15.7);
+//   PH:               PH's fast layout up to 128, else the accurate one.
+// An explicit DC-CR handle keeps DC-CR and the compute type everywhere.
 constexpr double kAutoRhoMax = 32.0;
+constexpr double kPhRhoMax = 128.0;
 
+// The threshold of the handle's solver (DC-CR: none); SOS_ACCURATE_GAIN in
+// the environment (a positive number, "inf" for none) overrides it for the
+// automatic choice and PH.
 inline double rho_max_of(const sos_ctx *h)
 {
-    return solver_of(h) == SOS_ALG_DCCR ? HUGE_VAL : kAutoRhoMax;
+    const int s = solver_of(h);
+    if (s == SOS_ALG_DCCR) return HUGE_VAL;
+    if (const char *e = std::getenv("SOS_ACCURATE_GAIN")) {
+        const double v = std::strtod(e, nullptr);
+        if (v > 0.0) return v;
+    }
+    return s == SOS_ALG_PH ? kPhRhoMax : kAutoRhoMax;
 }
 
 // Solver argument of the kernel launchers for tables prepared for `solver`
-// (SOS_ALG_*) and compute type `bits`: the kernel's solver, plus
-// ALG_MAYBE_ACC when those tables may use the accurate layout.
-inline int launch_alg(int bits, int solver)
+// (SOS_ALG_*) at compute type `bits` with peak-gain threshold `rho_max`: the
+// kernel's solver, plus ALG_MAYBE_ACC when those tables may use the accurate
+// layout (FP32 with a finite threshold).
+inline int launch_alg(int bits, int solver, double rho_max)
 {
     const int a = solver == SOS_ALG_PH ? sosdev::ALG_PH : sosdev::ALG_DCCR;
-    return (bits == 32 && solver != SOS_ALG_DCCR) ? (a | sosdev::ALG_MAYBE_ACC) : a;
+    return (bits == 32 && std::isfinite(rho_max)) ? (a | sosdev::ALG_MAYBE_ACC) : a;
 }
 
 // SOS_GRID: exactly this many workgroups for every persistent launch, or 0

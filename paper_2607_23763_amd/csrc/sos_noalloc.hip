@@ -131,7 +131,7 @@ int sos_filter_noalloc(const float *sections, int K, const float *x, float *y, i
                             __builtin_ctz((unsigned)(t.L / 64)), tabs, ctrl, 0, kAutoRhoMax,
                             stream) != hipSuccess)
             return SOS_EHIP;
-        const int alg = launch_alg(bits, SOS_ALG_AUTO);
+        const int alg = launch_alg(bits, SOS_ALG_AUTO, kAutoRhoMax);
         if (sos_launch_fwd(bits, alg, t.L, t.N, x, y, n, groups, tabs, K, zi, zf, desc, ctrl,
                            ticks, grid_of(bits, alg, t.L, t.N), nullptr,
                            stream) != hipSuccess)

@@ -426,8 +426,8 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
     s->L = t.L;
     s->N = t.N;
     s->bits = bits_of(hu);
-    s->alg = launch_alg(s->bits, solver_of(hu));
     s->rho_max = rho_max_of(hu);
+    s->alg = launch_alg(s->bits, solver_of(hu), s->rho_max);
     s->h->timeout_ticks = hu->timeout_ticks;
     s->C = (int64_t)t.L * t.N;
     s->max_slots = max_slots;

@@ -58,6 +58,8 @@ def test_strerror_and_null_handle_rejections():
                                         None, None, None, None) == P.SOS_EINVAL
     assert lib.sos_filter_vjp_batched(None, 1, 1, 1, 10, None, None, None, None, None, None, None,
                                       None, None, None, None, None, None) == P.SOS_EINVAL
+    assert lib.sos_filter_vjp_batched_sum(None, 1, 1, 1, 10, None, None, None, None, None, None,
+                                          None, None, None, None, None, None, None) == P.SOS_EINVAL
     # graph and tuning entry points
     assert lib.sos_graph_create_batched(None, None, 1, 1, 1, 10, None, None, None, None, None,
                                         None, None, None) == P.SOS_EINVAL
