@@ -337,15 +337,92 @@ int sos_graph_launch(sos_graph_t g, hipStream_t stream);
 int sos_graph_last_error(sos_graph_t g);
 int sos_graph_destroy(sos_graph_t g);
 
+/* The cost model of Sec. IV-C, on a device described by its per-SM (per-CU)
+ * budgets. Host arithmetic only: no device is touched, so these run anywhere.
+ *   sos_model_floors: Eq. (28)'s throughput roof BW / 8 bytes per sample
+ *     (GS/s) and Eq. (29)'s hiding floor W_min = ceil(I lambda / ILP) (warps
+ *     per SM; the paper's ILP is 3).
+ *   sos_model_config: a tile of L lanes x N samples per lane: Eq. (26)'s
+ *     staging buffer 4 L (N + pad) bytes (pad: the row padding in words; the
+ *     paper's kernels pad by 1, these by 4 for 128-bit rows), the resident
+ *     groups per SM under every budget (shared memory / LDS, group slots,
+ *     threads and warps, registers at `regs_per_thread`, 0 = not counted),
+ *     the warps that makes (Eq. (30)), which budget binds
+ *     (SOS_MODEL_LIMIT_*), whether the buffer fits one group's cap and at
+ *     least one group is resident (feasible), and whether the warps fall
+ *     below W_min (starved).
+ *   sos_model_device_gfx950: MI355X's budgets (256 CUs, 160 KiB LDS per CU
+ *     and per workgroup, 4 SIMDs of 512 VGPRs per lane, 32 wave64 slots,
+ *     one wave instruction per cycle per CU with an 8-cycle dependent FMA,
+ *     8 TB/s, 2.4 GHz, 78.6 TFLOP/s unpacked FP32).
+ * All return SOS_EINVAL for null pointers or non-positive sizes. */
+typedef struct {
+    int sms;                    /* SMs / CUs */
+    double smem_per_sm;         /* bytes of shared memory (LDS) per SM */
+    double smem_per_tb;         /* bytes one thread block (workgroup) may take */
+    int regs_per_sm;            /* 32-bit registers per SM */
+    int regs_per_simd_lane;     /* AMD: registers per lane of one SIMD (0: NVIDIA-style pool) */
+    int simds;                  /* AMD: SIMDs per CU */
+    int reg_granule;            /* per-thread register allocation granule */
+    int max_threads_per_sm;
+    int max_warps_per_sm;
+    int max_tbs_per_sm;
+    int warp;                   /* threads per warp / wavefront */
+    double issue_rate;          /* I: warp instructions issued per cycle per SM */
+    double fma_latency;         /* lambda: cycles of a dependent FMA */
+    double bandwidth_gbs;       /* DRAM bandwidth, GB/s */
+    double clock_ghz;
+    double fp32_tflops;         /* FP32 FMA rate the kernels can use */
+} sos_model_device;
+typedef struct {
+    double roof_gss;            /* GS/s at 8 bytes per sample */
+    int w_min;                  /* warps per SM */
+} sos_model_floors_t;
+enum { SOS_MODEL_LIMIT_SMEM = 1, SOS_MODEL_LIMIT_TBS = 2, SOS_MODEL_LIMIT_THREADS = 3,
+       SOS_MODEL_LIMIT_REGS = 4 };
+typedef struct {
+    double s_buf;               /* bytes of staging per group */
+    int tbs_per_sm;             /* resident groups per SM */
+    int warps_per_sm;
+    int limit;                  /* SOS_MODEL_LIMIT_* that binds */
+    int feasible;
+    int starved;
+} sos_model_config_t;
+int sos_model_floors(const sos_model_device *d, double ilp, sos_model_floors_t *out);
+int sos_model_config(const sos_model_device *d, int L, int N, int pad, int regs_per_thread,
+                     double ilp, sos_model_config_t *out);
+int sos_model_device_gfx950(sos_model_device *out);
+/* The compiled forward kernels: whether a tile (L lanes, N samples per lane)
+ * is compiled in (1) or not (0); a tile's kernel's vector registers per lane
+ * and static LDS bytes as its code object records them (SOS_EINVAL for a
+ * tile not compiled in, SOS_EHIP if the runtime cannot say); and the
+ * workgroups of that shape resident on the whole device at once (the
+ * runtime's occupancy count times the CUs; 0 for a tile not compiled in).
+ * bits: 32 or 64; alg: the solver kernel (0 DC-CR, 1 PH; +4 for the kernel
+ * that picks the table layout per group). */
+int sos_fwd_shape_supported(int L, int N);
+int sos_fwd_kernel_attrs(int bits, int alg, int L, int N, int *regs, int *lds);
+int sos_fwd_capacity(int bits, int alg, int L, int N);
+
 /* Autotuner for the two parameters of the multi-block layout (Sec. IV-A/C):
  * lanes per group L and samples per lane N (group size C = N L). Runs the
- * batch on its own buffers: the compiled (L, N) shapes are first pruned by a
- * padding model (a signal of n samples costs ceil(n / C) groups of C, so
- * tiles whose padded work exceeds 1.5x the best tile's are dropped), then
- * each survivor is timed (one warm-up, `reps` timed runs, median, HIP events
- * on `stream`). When h has no section solver set (SOS_ALG_DEFAULT), every
- * tile is timed with SOS_ALG_AUTO and SOS_ALG_PH and the winning solver
- * becomes h's too; otherwise only h's solver is timed. The fastest tile
+ * batch on its own buffers. Each compiled (L, N) shape and candidate solver
+ * is first priced by the cost model on this device's budgets (the kernel's
+ * own register count, the staging buffer, residency): shapes the budgets
+ * exclude or that fall below the hiding floor are dropped, as are shapes
+ * whose padded work (a signal of n samples costs ceil(n / C) groups of C)
+ * exceeds 1.5x the best shape's. The rest are ranked by the model's
+ * predicted time: the larger of the memory floor (8 bytes per sample at the
+ * HBM bandwidth) and the FMAs of the padded work at the FP32 rate, plus a
+ * fixed 1.5 us per round of resident groups (the per-group overhead F of
+ * Eq. (27), measured on MI355X as the 2^28-sample filter's excess over the
+ * copy kernel spread over its rounds). Only the 6 best-ranked (shape,
+ * solver) pairs are timed (one warm-up, `reps` timed runs, median, HIP events
+ * on `stream`); SOS_TUNE_EXHAUSTIVE=1 in the environment times every pair
+ * the budgets admit (for checking the ranking). When h has no section
+ * solver set (SOS_ALG_DEFAULT), the pairs span SOS_ALG_AUTO and SOS_ALG_PH
+ * and the winning solver becomes h's too; otherwise only h's solver is
+ * priced. The fastest tile
  * becomes h's tile and is cached per (compute type, requested solver, kmax,
  * B, floor(log2 total_samples)) for sos_tune_lookup (a default request is
  * also cached under the winning solver); y and zf end up holding the

@@ -104,6 +104,18 @@ def lib():
                                            ctypes.POINTER(ctypes.c_float)]
             L.sos_tune_lookup.argtypes = [vp, i32, i32, i64, ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+            L.sos_model_floors.argtypes = [ctypes.POINTER(ModelDevice), ctypes.c_double,
+                                           ctypes.POINTER(ModelFloors)]
+            L.sos_model_config.argtypes = [ctypes.POINTER(ModelDevice), i32, i32, i32, i32,
+                                           ctypes.c_double, ctypes.POINTER(ModelConfig)]
+            L.sos_model_device_gfx950.argtypes = [ctypes.POINTER(ModelDevice)]
+            L.sos_fwd_kernel_attrs.argtypes = [i32, i32, i32, i32, ctypes.POINTER(i32),
+                                               ctypes.POINTER(i32)]
+            L.sos_fwd_capacity.argtypes = [i32, i32, i32, i32]
+            L.sos_fwd_shape_supported.argtypes = [i32, i32]
+            for name in ("sos_model_floors", "sos_model_config", "sos_model_device_gfx950",
+                         "sos_fwd_kernel_attrs", "sos_fwd_capacity", "sos_fwd_shape_supported"):
+                getattr(L, name).restype = i32
             L.sos_filter_train_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp,
                                                    vp, vp, vp, vp, vp]
             L.sos_filter_vjp_batched.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp, vp, vp,
@@ -427,6 +439,63 @@ def sosfilt_vjp_batched(sections, K, sig_off, x, y, saved, gy, gzf=None, sec_off
               _p(gx), _p(gzi), _p(gs), _stream_ptr(a["x"].device)),
            "sos_filter_vjp_batched_sum" if shared else "sos_filter_vjp_batched")
     return gx, gzi, gs
+
+
+class ModelDevice(ctypes.Structure):
+    """sos_model_device: a device's per-SM (per-CU) budgets for the cost model."""
+    _fields_ = [("sms", ctypes.c_int), ("smem_per_sm", ctypes.c_double),
+                ("smem_per_tb", ctypes.c_double), ("regs_per_sm", ctypes.c_int),
+                ("regs_per_simd_lane", ctypes.c_int), ("simds", ctypes.c_int),
+                ("reg_granule", ctypes.c_int), ("max_threads_per_sm", ctypes.c_int),
+                ("max_warps_per_sm", ctypes.c_int), ("max_tbs_per_sm", ctypes.c_int),
+                ("warp", ctypes.c_int), ("issue_rate", ctypes.c_double),
+                ("fma_latency", ctypes.c_double), ("bandwidth_gbs", ctypes.c_double),
+                ("clock_ghz", ctypes.c_double), ("fp32_tflops", ctypes.c_double)]
+
+
+class ModelFloors(ctypes.Structure):
+    _fields_ = [("roof_gss", ctypes.c_double), ("w_min", ctypes.c_int)]
+
+
+class ModelConfig(ctypes.Structure):
+    _fields_ = [("s_buf", ctypes.c_double), ("tbs_per_sm", ctypes.c_int),
+                ("warps_per_sm", ctypes.c_int), ("limit", ctypes.c_int),
+                ("feasible", ctypes.c_int), ("starved", ctypes.c_int)]
+
+
+SOS_MODEL_LIMIT_SMEM, SOS_MODEL_LIMIT_TBS, SOS_MODEL_LIMIT_THREADS, SOS_MODEL_LIMIT_REGS = 1, 2, 3, 4
+
+
+def fwd_kernel_attrs(bits: int, alg: int, L: int, N: int):
+    """(vector registers per lane, static LDS bytes) of a compiled forward
+    kernel (sos_fwd_kernel_attrs)."""
+    r, s = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().sos_fwd_kernel_attrs(bits, alg, L, N, ctypes.byref(r), ctypes.byref(s)),
+           "sos_fwd_kernel_attrs")
+    return r.value, s.value
+
+
+def model_device_gfx950() -> ModelDevice:
+    d = ModelDevice()
+    _check(lib().sos_model_device_gfx950(ctypes.byref(d)), "sos_model_device_gfx950")
+    return d
+
+
+def model_floors(dev: ModelDevice, ilp: float = 3.0) -> ModelFloors:
+    """Eq. (28)'s roof (GS/s) and Eq. (29)'s hiding floor (sos_model_floors)."""
+    f = ModelFloors()
+    _check(lib().sos_model_floors(ctypes.byref(dev), float(ilp), ctypes.byref(f)),
+           "sos_model_floors")
+    return f
+
+
+def model_config(dev: ModelDevice, L: int, N: int, pad: int = 1, regs: int = 0,
+                 ilp: float = 3.0) -> ModelConfig:
+    """Staging buffer, residency and hiding of an (L, N) tile (sos_model_config)."""
+    c = ModelConfig()
+    _check(lib().sos_model_config(ctypes.byref(dev), int(L), int(N), int(pad), int(regs),
+                                  float(ilp), ctypes.byref(c)), "sos_model_config")
+    return c
 
 
 def tune_batched(x, sections, K, sig_off, zi=None, y=None, zf=None, sec_off=None, kmax=None,

@@ -68,6 +68,7 @@
 // are armed by their work-table kernel and skip this (it would lengthen every
 // served step).
 #include "sos_device.h"
+#include "sosfilt.h"
 
 using namespace sosdev;
 
@@ -1697,17 +1698,34 @@ hipError_t launch_fwd(int alg, const FwdArgs &a, int64_t grid, hipStream_t strea
     return hipGetLastError();
 }
 
+// The forward kernel a launch of `alg` runs (for batched launches: the one
+// that chooses the layout per group when the tables may be accurate).
+template <typename T, int N, int W>
+const void *kernel_of(int alg)
+{
+    const bool mix = sizeof(T) == 4 && (alg & ALG_MAYBE_ACC);
+    const bool ph = (alg & ~ALG_MAYBE_ACC) == ALG_PH;
+    return mix ? (ph ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH, KM_MIX>
+                     : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR, KM_MIX>)
+               : (ph ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH, KM_FAST>
+                     : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR, KM_FAST>);
+}
+
+template <typename T, int N, int W>
+int attrs_of(int alg, int *regs, int *lds)
+{
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, kernel_of<T, N, W>(alg)) != hipSuccess) return SOS_EHIP;
+    if (regs) *regs = fa.numRegs;
+    if (lds) *lds = (int)fa.sharedSizeBytes;
+    return SOS_OK;
+}
+
 template <typename T, int N, int W>
 int capacity_of(int alg)
 {
     int per_cu = 0, dev = 0, cus = 0;
-    const bool mix = sizeof(T) == 4 && (alg & ALG_MAYBE_ACC);
-    const bool ph = (alg & ~ALG_MAYBE_ACC) == ALG_PH;
-    const void *kern =
-        mix ? (ph ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH, KM_MIX>
-                  : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR, KM_MIX>)
-            : (ph ? (const void *)sos_fwd_kernel<T, N, W, ALG_PH, KM_FAST>
-                  : (const void *)sos_fwd_kernel<T, N, W, ALG_DCCR, KM_FAST>);
+    const void *kern = kernel_of<T, N, W>(alg);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, 0) != hipSuccess)
         per_cu = 1;
     (void)hipGetDevice(&dev);
@@ -1745,6 +1763,20 @@ extern "C" int sos_fwd_shape_supported(int L, int N)
     SOS_SHAPES(SOS_CASE)
 #undef SOS_CASE
     return 0;
+}
+
+// Vector registers per lane and static LDS bytes of the forward kernel of
+// shape (L, N).
+extern "C" int sos_fwd_kernel_attrs(int bits, int alg, int L, int N, int *regs, int *lds)
+{
+    if (L <= 0 || (L % 64)) return SOS_EINVAL;
+    const int W = L / 64;
+#define SOS_CASE(NN, WW)                                                                  \
+    if (N == NN && W == WW) return bits == 64 ? attrs_of<double, NN, WW>(alg, regs, lds)   \
+                                              : attrs_of<float, NN, WW>(alg, regs, lds);
+    SOS_SHAPES(SOS_CASE)
+#undef SOS_CASE
+    return SOS_EINVAL;
 }
 
 // Workgroups of shape (L, N) that can be resident on the whole device at once.

@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "sosfilt.h"
 #include "sos_device.h"
@@ -79,6 +80,7 @@ hipError_t sos_launch_fill(float *dst, const float *src, int64_t count, hipStrea
 hipError_t sos_launch_copy(const float *x, float *y, int64_t n, hipStream_t stream);
 int sos_fwd_shape_supported(int L, int N);
 int sos_fwd_capacity(int bits, int alg, int L, int N);
+int sos_fwd_kernel_attrs(int bits, int alg, int L, int N, int *regs, int *lds);
 int sos_bwd_shape_supported(int L, int N);
 }
 
@@ -326,5 +328,15 @@ int batch_check(const BatchArgs &ba);
 int batch_reserve(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream);
 // Enqueue prep, work table, arm and filter launches only (graph-capturable).
 int batch_enqueue(sos_ctx *h, Tile t, int bits, const BatchArgs &ba, hipStream_t stream);
+
+
+// A batch as the cost model sees it: signal lengths, sections, total samples.
+struct ModelBatch {
+    std::vector<int64_t> len;
+    std::vector<int> K;
+    int64_t total = 0;
+};
+double model_batch_ms(const sos_model_device &d, const ModelBatch &b, int L, int N, int pad,
+                      int regs, double ops, double F_us);
 
 }  // namespace sosint

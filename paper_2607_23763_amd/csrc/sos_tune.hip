@@ -50,6 +50,13 @@ void destroy_graph(sos_graph *g)
     delete g;
 }
 
+// Model-ranked (shape, solver) pairs timed per tuning call, and the fixed
+// per-group cost F of the model's prediction (the 2^28-sample order-2
+// filter's excess over the copy kernel on MI355X, 374 - 330 us, over its 32
+// rounds of resident groups).
+constexpr size_t kTuneTimed = 6;
+constexpr double kTuneGroupUs = 1.5;
+
 // Candidate tiles: every compiled forward shape, minus FP64 shapes whose
 // registers spill (N = 64 holds 128 registers of samples per lane).
 std::vector<Tile> candidates(int bits)
@@ -171,33 +178,26 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
     if (!dg.ok) return SOS_EHIP;
     const int bits = bits_of(h);
 
-    // model pruning: padding. A group is C samples whatever the signal's
-    // length, so the padded work sum_i ceil(n_i / C) C decides short-signal
-    // batches; drop tiles whose padded work exceeds 1.5x the best tile's.
+    // the batch as the cost model sees it
     std::vector<int64_t> off((size_t)B + 1);
+    std::vector<int32_t> kh((size_t)B);
     if (hipMemcpy(off.data(), sig_off, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost) !=
-        hipSuccess)
+            hipSuccess ||
+        hipMemcpy(kh.data(), K, kh.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return SOS_EHIP;
-    std::vector<Tile> cand = candidates(bits);
-    std::vector<double> padded(cand.size(), 0.0);
-    double best_pad = 1e300;
-    for (size_t c = 0; c < cand.size(); ++c) {
-        const int64_t C = (int64_t)cand[c].L * cand[c].N;
-        double w = 0.0;
-        for (int i = 0; i < B; ++i) {
-            const int64_t n = std::max<int64_t>(off[(size_t)i + 1] - off[(size_t)i], 0);
-            w += (double)((n + C - 1) / C * C);
-        }
-        padded[c] = w;
-        best_pad = std::min(best_pad, w);
+    ModelBatch mb;
+    mb.total = total_samples;
+    for (int i = 0; i < B; ++i) {
+        mb.len.push_back(std::max<int64_t>(off[(size_t)i + 1] - off[(size_t)i], 0));
+        mb.K.push_back(std::min(std::max(kh[(size_t)i], 0), kmax));
     }
+    sos_model_device md;
+    (void)sos_model_device_gfx950(&md);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) ==
+            hipSuccess && cus > 0)
+        md.sms = cus;
 
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return SOS_EHIP;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return SOS_EHIP;
-    }
     // the section solvers to try: the handle's, or both when it has none set
     const int requested = h->alg;
     const TuneKey key_req = key_of(h, ba);
@@ -208,14 +208,69 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
     } else {
         algs.push_back(requested);
     }
+    // price every (shape, solver) pair; drop what the budgets exclude, what
+    // falls below the hiding floor, and shapes whose padded work exceeds 1.5x
+    // the best shape's (a group is C samples whatever the signal's length)
+    struct Pair {
+        Tile t;
+        int alg;
+        double pred, pad;
+    };
+    const std::vector<Tile> shapes = candidates(bits);
+    std::vector<double> padded(shapes.size(), 0.0);
+    double best_pad = 1e300;
+    for (size_t c = 0; c < shapes.size(); ++c) {
+        const int64_t C = (int64_t)shapes[c].L * shapes[c].N;
+        for (int64_t n : mb.len) padded[c] += (double)((n + C - 1) / C * C);
+        best_pad = std::min(best_pad, padded[c]);
+    }
+    std::vector<Pair> pairs;
+    for (size_t c = 0; c < shapes.size(); ++c) {
+        if (padded[c] > 1.5 * best_pad) continue;
+        for (int a : algs) {
+            h->alg = a;
+            const int la = launch_alg(bits, solver_of(h), rho_max_of(h));
+            int regs = 0, lds = 0;
+            if (sos_fwd_kernel_attrs(bits, la, shapes[c].L, shapes[c].N, &regs, &lds) != SOS_OK)
+                continue;
+            // the kernel's whole LDS (staging rows plus the wave exchange) as
+            // row padding of the model's staging buffer
+            const int pad = std::max(0, (lds + 4 * shapes[c].L - 1) / (4 * shapes[c].L) -
+                                            shapes[c].N);
+            const double ops = solver_of(h) == SOS_ALG_PH ? 7.0 : 9.0;
+            const double pred = model_batch_ms(md, mb, shapes[c].L, shapes[c].N, pad, regs, ops,
+                                               kTuneGroupUs);
+            if (pred >= 0.0) pairs.push_back(Pair{shapes[c], a, pred, padded[c]});
+        }
+    }
+    h->alg = requested;
+    std::stable_sort(pairs.begin(), pairs.end(),
+                     [](const Pair &p, const Pair &q) { return p.pred < q.pred; });
+    const char *ex = std::getenv("SOS_TUNE_EXHAUSTIVE");
+    const size_t timed = (ex && std::atoi(ex) == 1) ? pairs.size()
+                                                    : std::min<size_t>(pairs.size(), kTuneTimed);
+    const bool verbose = std::getenv("SOS_TUNE_VERBOSE") != nullptr;
+
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SOS_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SOS_EHIP;
+    }
     Tile best{0, 0};
     int best_alg = requested;
     float best_ms = 1e30f;
-    for (size_t k = 0; k < cand.size() * algs.size() && rc == SOS_OK; ++k) {
-        const size_t c = k / algs.size();
-        if (padded[c] > 1.5 * best_pad) continue;
-        const Tile t = cand[c];
-        h->alg = algs[k % algs.size()];
+    for (size_t k = 0; k < pairs.size() && rc == SOS_OK; ++k) {
+        const Tile t = pairs[k].t;
+        h->alg = pairs[k].alg;
+        const char *an =
+            h->alg == SOS_ALG_PH ? "ph" : (h->alg == SOS_ALG_AUTO ? "auto" : "dccr");
+        if (k >= timed) {
+            if (verbose)
+                std::fprintf(stderr, "sos_tune: L=%d N=%d %s predicted %.4f ms (not timed)\n",
+                             t.L, t.N, an, pairs[k].pred);
+            continue;
+        }
         rc = batch_reserve(h, t, bits, ba, stream);
         if (rc) break;
         rc = batch_enqueue(h, t, bits, ba, stream);   // warm-up
@@ -239,10 +294,10 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
             best = t;
             best_alg = h->alg;
         }
-        if (std::getenv("SOS_TUNE_VERBOSE"))
-            std::fprintf(stderr, "sos_tune: L=%d N=%d %s padded=%.3f %.4f ms\n", t.L, t.N,
-                         h->alg == SOS_ALG_PH ? "ph" : (h->alg == SOS_ALG_AUTO ? "auto" : "dccr"),
-                         padded[c] / std::max(1.0, (double)total_samples), med);
+        if (verbose)
+            std::fprintf(stderr, "sos_tune: L=%d N=%d %s padded=%.3f predicted %.4f ms, %.4f ms\n",
+                         t.L, t.N, an, pairs[k].pad / std::max(1.0, (double)total_samples),
+                         pairs[k].pred, med);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -117,3 +117,35 @@ def test_tuner_keeps_an_explicit_solver(env):
                                        P.ctypes.byref(Lc), P.ctypes.byref(Nc)) == P.SOS_OK
         assert (Lc.value, Nc.value) == (L, N)
         check_vs_oracle(Ks, rows, sig_off, x, zi, y.cpu().numpy(), zf.cpu().numpy())
+
+
+def test_cost_model_residency_matches_the_runtime(env):
+    """The tuner's model on MI355X's budgets, fed each compiled forward
+    kernel's own register count, gives the resident workgroups per CU that
+    the runtime's occupancy calculator reports, for every shape, both compute
+    types and every kernel variant the launches use."""
+    torch, P = env
+    L = P.lib()
+    d = P.model_device_gfx950()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert cus == d.sms
+    checked = 0
+    for bits in (32, 64):
+        for alg in (0, 1, 4, 5):
+            if bits == 64 and alg >= 4:
+                continue
+            for Lg in (64, 256, 512, 1024):
+                for N in (16, 32, 64):
+                    if not L.sos_fwd_shape_supported(Lg, N):
+                        continue
+                    regs, lds = P.fwd_kernel_attrs(bits, alg, Lg, N)
+                    cap = L.sos_fwd_capacity(bits, alg, Lg, N)
+                    assert regs > 0 and cap > 0 and lds >= 4 * Lg * (N + 4)
+                    # the kernel's whole LDS (staging rows plus the wave
+                    # exchange) as row padding
+                    pad = -(-lds // (4 * Lg)) - N
+                    c = P.model_config(d, Lg, N, pad=pad, regs=regs)
+                    assert cap // cus == c.tbs_per_sm and cap % cus == 0, \
+                        (bits, alg, Lg, N, regs, lds, cap // cus, c.tbs_per_sm, c.limit)
+                    checked += 1
+    assert checked >= 30
