@@ -34,10 +34,11 @@ Beside the headline, on the same GPU (skipped with --quick):
   random stable sections, random initial states, in one persistent launch
   captured in a HIP graph at the autotuned (L, N); GS/s over all samples (its
   parity at this size is a GPU test: tests/test_gpu_fullsize.py).
-* "served": 1024 streams of orders 2..16, chunks of 4096..65536 samples
-  arriving as a Poisson process at swept aggregate rates, pushed by the
-  library's native replay driver; achieved GS/s and p50/p99 chunk latency
-  (tile (256, 16), PH solver: 10-13 % lower latency than DC-CR there).
+* "served": 1024 streams of orders 2..16, chunks of 4096..65536 samples,
+  pushed by the library's native replay driver: first the saturated rate
+  (100000 chunks queued at once), then Poisson arrivals at 0.1..1.2 times
+  that rate, 100000 chunks per point; achieved GS/s and p50/p99 chunk
+  latency (tile (256, 16), PH solver).
 * "fwd_bwd": forward (keeping the section outputs) plus the adjoint, on one
   2^24-sample signal and on 256 signals of 2^16 samples, order 8, PH solver.
 * "toeplitz_mfma_bound": a lower bound for a block-Toeplitz (matrix-core)
@@ -466,37 +467,68 @@ def bench_batched(torch, P, workloads, np, log):
     return out
 
 
-def bench_served(torch, P, workloads, np, log, rates=(5e4, 1e5, 2e5, 4e5, 8e5, 0.0), R=20000):
-    """1024 streams, Poisson chunk arrivals at each aggregate rate (0 = all at once)."""
+SERVED_LOADS = (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
+
+
+def bench_served(torch, P, workloads, np, log, loads=SERVED_LOADS, R=100000, tile=(256, 16),
+                 alg="ph", rates=None):
+    """1024 streams. First the saturated rate: all R chunks queued at t = 0
+    (after a short warm-up replay); then Poisson arrivals at each fraction of
+    that rate (`loads`), R chunks per point; or, with `rates`, at those
+    aggregate rates in chunks/s (0 = all at t = 0)."""
     dev = torch.device("cuda", 0)
-    res = []
-    for rate in rates:
+    gen = torch.Generator(device=dev).manual_seed(4)
+    buf = {}
+
+    def run(rate, RR):
         Ks, secs, ids, lens, offs, arrival = workloads.serving_trace(
-            S=1024, R=R, rate_chunks_per_s=rate if rate > 0 else 1e9, seed=4)
+            S=1024, R=RR, rate_chunks_per_s=rate if rate > 0 else 1e9, seed=4)
         if rate <= 0:
             arrival = np.zeros_like(arrival)
         total = int(lens.sum())
-        gen = torch.Generator(device=dev).manual_seed(4)
-        x = torch.randn(total, generator=gen, device=dev, dtype=torch.float32)
-        y = torch.empty_like(x)
-        srv = P.Server(handle=P.Handle(0, tile=(256, 16), algorithm="ph"), max_slots=1024,
+        if buf.get("n", 0) < total:
+            buf.clear()
+            buf["x"] = torch.randn(total, generator=gen, device=dev, dtype=torch.float32)
+            buf["y"] = torch.empty_like(buf["x"])
+            buf["n"] = total
+        srv = P.Server(handle=P.Handle(0, tile=tile, algorithm=alg), max_slots=1024,
                        budget=1 << 30)
         sid = np.array([srv.open(secs[s]) for s in range(len(Ks))], dtype=np.int64)
-        lat, wall = srv.replay(sid[ids], offs, lens, arrival, x, y)
+        lat, wall = srv.replay(sid[ids], offs, lens, arrival, buf["x"], buf["y"])
         srv.close()
-        gs = total / wall / 1e9
-        offered = rate * float(lens.mean()) / 1e9 if rate > 0 else None
-        r = {"rate_chunks_per_s": rate if rate > 0 else "all at t=0",
-             "offered_GS_per_s": None if offered is None else round(offered, 3),
-             "GS_per_s": round(gs, 3), "p50_us": round(1e6 * float(np.percentile(lat, 50)), 1),
-             "p99_us": round(1e6 * float(np.percentile(lat, 99)), 1), "chunks": R}
-        log("served", r)
-        res.append(r)
-        del x, y
+        return total, wall, lat, float(lens.mean())
+
+    def point(rate, RR, label, load=None):
+        total, wall, lat, mean_len = run(rate, RR)
+        r = {"rate_chunks_per_s": round(rate, 1) if rate > 0 else "all at t=0",
+             "offered_GS_per_s": round(rate * mean_len / 1e9, 3) if rate > 0 else None,
+             "GS_per_s": round(total / wall / 1e9, 3),
+             "p50_us": round(1e6 * float(np.percentile(lat, 50)), 1),
+             "p99_us": round(1e6 * float(np.percentile(lat, 99)), 1), "chunks": RR}
+        if load is not None:
+            r["load"] = load
+        log("served", label, r)
+        return r, RR / wall
+
+    run(0.0, 2000)                                       # warm-up
+    res = []
+    if rates is not None:
+        for rate in rates:
+            res.append(point(rate, R, "rate")[0])
+        capacity = None
+    else:
+        sat, cap_cps = point(0.0, R, "saturated")
+        capacity = {"GS_per_s": sat["GS_per_s"], "chunks_per_s": round(cap_cps, 1)}
+        res.append(sat)
+        for f in loads:
+            res.append(point(f * cap_cps, R, "load %.2f" % f, load=f)[0])
+    buf.clear()
     torch.cuda.empty_cache()
     return {"workload": "1024 streams, K~U{1..8} random stable SOS, chunks floor(2^U) samples "
-                        "U~U[12,16], Poisson arrivals, state on device, FIFO per stream",
-            "tile_L_N": [256, 16], "section_solver": "ph", "points": res}
+                        "U~U[12,16], Poisson arrivals at fractions of the saturated rate, state "
+                        "on device, FIFO per stream, two step lanes",
+            "tile_L_N": list(tile), "section_solver": alg, "saturated": capacity,
+            "points": res}
 
 
 def bench_fwd_bwd(torch, P, workloads, np, log):
@@ -577,6 +609,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline and sweep only")
     ap.add_argument("--only-fwd-bwd", action="store_true",
                     help="profile helper: only the forward + adjoint leg, printed as its own JSON")
+    ap.add_argument("--only-served", default="",
+                    help="profile helper: only the serving leg, as its own JSON: 'loads' (the "
+                         "default sweep) or comma-separated aggregate rates in chunks/s "
+                         "(0 = all chunks at t=0)")
+    ap.add_argument("--served-tile", default="256,16",
+                    help="profile helper: the server's tile with --only-served")
     ap.add_argument("--only-batched", action="store_true",
                     help="profile helper: only the uneven-batch leg, printed as its own JSON")
     ap.add_argument("--alg", default="dccr", choices=("dccr", "ph"),
@@ -598,6 +636,13 @@ def main():
     P.lib()
     if args.only_fwd_bwd:
         print(json.dumps({"fwd_bwd": bench_fwd_bwd(torch, P, workloads, np, log)}), flush=True)
+        return
+    if args.only_served:
+        st = tuple(int(v) for v in args.served_tile.split(","))
+        rates = None if args.only_served == "loads" else \
+            tuple(float(v) for v in args.only_served.split(","))
+        print(json.dumps({"served": bench_served(torch, P, workloads, np, log, rates=rates,
+                                                 tile=st)}), flush=True)
         return
     if args.only_batched:
         print(json.dumps({"batched": bench_batched(torch, P, workloads, np, log)}), flush=True)

@@ -467,9 +467,11 @@ int sos_filter_noalloc(const float *sections, int K, const float *x, float *y, i
  * sections, their prepared tables and its K TDF-II states in device memory
  * between chunks, and batches pending chunks continuously: one scheduler
  * thread forms steps of at most one chunk per stream (oldest first), each
- * step one persistent launch of the uneven-batch path, queued in order on
- * one HIP stream so a stream's chunks run in FIFO order, while chunks that
- * arrive during a step join the next one.
+ * step one persistent launch of the uneven-batch path. Streams are dealt to
+ * two lanes, each with its own HIP stream and workspace and at most two
+ * steps in flight: a stream's chunks run in its lane's stream order (FIFO),
+ * the lanes' steps over disjoint streams overlap on the device, and chunks
+ * that arrive during a step join their lane's next one.
  *
  * Chunk and output buffers are DEVICE pointers owned by the caller, who keeps
  * them alive until sos_stream_wait returns for that chunk; out may equal
@@ -478,10 +480,10 @@ typedef struct sos_srv *sos_server_t;
 
 /* Create a server on the device of `h`, with h's tile (L, N), compute type
  * and lookback bound (h itself is not used afterwards; the server has its own
- * workspace). device_mem_budget bytes (0 = 256 MiB) are split between stream
- * rows (sections, states and tables: K rows per stream) and one step's work
- * table and descriptors, which bounds the samples of a step and of a chunk
- * (sos_server_limits). max_slots (>= 1) bounds the chunks of one step.
+ * workspaces). device_mem_budget bytes (0 = 256 MiB) are split between
+ * stream rows (sections, states and tables: K rows per stream) and, in equal
+ * parts, the two lanes' work tables and descriptors, which bound the samples
+ * of a step and of a chunk (sos_server_limits). max_slots (>= 1) bounds the chunks of one step.
  * Allocates everything up front; no device allocation happens while serving. */
 int sos_server_create(sos_server_t *s, sos_handle_t h, size_t device_mem_budget, int max_slots);
 /* Stop the scheduler, let steps on the device finish, fail chunks not yet in

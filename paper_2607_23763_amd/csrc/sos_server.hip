@@ -10,12 +10,15 @@
 // (the uneven-batch path: work table, arm, filter) over at most one chunk of
 // each stream with work pending, taken in arrival order of the streams, up
 // to `max_slots` chunks and a sample budget derived from the device memory
-// budget. Steps are queued on one HIP stream, so a stream's next chunk may
-// enter the next step while the current one runs: HIP stream order keeps
-// each stream's chunks in FIFO order, and chunks that arrive while steps are
-// on the device join the next step as soon as a step slot frees up. Chunk
-// buffers are the caller's device memory, addressed through per-signal
-// pointer tables (no gather copies).
+// budget. The streams are dealt to two lanes; a lane queues its steps on its
+// own HIP stream with its own workspace, so a stream's next chunk may enter
+// its lane's next step while the current one runs (HIP stream order keeps
+// each stream's chunks in FIFO order), and the two lanes' steps, over
+// disjoint sets of streams, overlap on the device: one lane's small kernels
+// and launch gaps run under the other lane's filter. Chunks that arrive
+// while steps are on the device join their lane's next step as soon as a
+// step slot frees up. Chunk buffers are the caller's device memory,
+// addressed through per-signal pointer tables (no gather copies).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +41,12 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
-constexpr int kSteps = 3;                        // steps in flight
+// Steps in flight per lane. Same-box A/B at 0.5 / 2 / 4 / 5.2 M chunks/s
+// (100000 chunks each, tile (256, 16)): two lanes of two steps gave p50
+// 84 / 175 / 1000 / 2500 us, one lane of three 134 / 180 / 480 / 1650 us
+// and two lanes of three 104-111 / 290-560 / 780-1360 / 1700-2700 us, the
+// achieved rates within 10 % of each other (75-89 GS/s at 5.2 M/s).
+constexpr int kSteps = 2;
 constexpr size_t kDefaultBudget = 256ull << 20;  // bytes
 constexpr int kPending = 1;                      // request status while not finished
 
@@ -92,6 +100,7 @@ struct Request {
 
 struct Stream {
     int K = 0;
+    int lane = 0;                   // the lane whose steps run its chunks
     int64_t row = 0;
     std::deque<uint64_t> pending;   // pushed, not yet in a step
     int64_t outstanding = 0;        // pushed, not yet retired
@@ -128,11 +137,23 @@ struct Step {
     std::vector<uint64_t> tickets;
 };
 
+// An independent step pipeline: its HIP stream, its workspace (control
+// block, descriptors, work table), the device copy of a step's arguments and
+// per-chunk error words, its step slots and its ready streams.
+constexpr int kStepLanes = 2;
+struct Lane {
+    sos_ctx *h = nullptr;
+    hipStream_t stream = nullptr;
+    unsigned char *dargs = nullptr;
+    unsigned *derr = nullptr;
+    Step steps[kSteps];
+    std::deque<int64_t> ready;        // its streams with pending chunks
+};
+
 }  // namespace
 
 struct sos_srv {
-    sos_ctx *h = nullptr;             // own workspace: ctrl, descriptors, work table
-    hipStream_t stream = nullptr;     // steps
+    Lane lanes[kStepLanes];               // step pipelines over disjoint streams
     hipStream_t ostream = nullptr;    // stream opening (table preparation)
     unsigned *octrl = nullptr;        // error word of the preparation launches
     int device = 0, L = 0, N = 0, bits = 32, alg = 0;
@@ -144,11 +165,8 @@ struct sos_srv {
     float *sections = nullptr;        // max_rows x 6
     float *state = nullptr;           // max_rows x 2
     unsigned char *tabs = nullptr;    // max_rows x tab_row_bytes
-    unsigned char *dargs = nullptr;   // device copy of a step's arguments
-    unsigned *derr = nullptr;         // per-chunk error words of the running step
     uint64_t next_seq = 1;            // launch order of steps
     ArgLayout lay;
-    Step steps[kSteps];
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::thread worker;
@@ -157,7 +175,6 @@ struct sos_srv {
     int64_t next_stream = 1;
     std::unordered_map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
-    std::deque<int64_t> ready;        // streams with pending chunks
     RowPool rows;
 };
 
@@ -209,8 +226,9 @@ void retire(sos_srv *s, Step &st, int step_status, unsigned launch_bits,
     s->cv_done.notify_all();
 }
 
-// Form a step from the ready streams and enqueue it (lock held).
-void launch_step(sos_srv *s, Step &st)
+// Form a step from a lane's ready streams and enqueue it on the lane (lock
+// held).
+void launch_step(sos_srv *s, Lane &ln, Step &st)
 {
     unsigned char *hb = st.host;
     unsigned *err = reinterpret_cast<unsigned *>(hb + s->lay.err);
@@ -224,9 +242,9 @@ void launch_step(sos_srv *s, Step &st)
     int B = 0, kmax = 0;
     int64_t total = 0;
     std::deque<int64_t> deferred;
-    while (!s->ready.empty() && B < s->max_slots) {
-        const int64_t sid = s->ready.front();
-        s->ready.pop_front();
+    while (!ln.ready.empty() && B < s->max_slots) {
+        const int64_t sid = ln.ready.front();
+        ln.ready.pop_front();
         Stream &str = s->streams[sid];
         str.in_ready = false;
         if (str.pending.empty()) continue;
@@ -248,7 +266,7 @@ void launch_step(sos_srv *s, Step &st)
         Stream &str = s->streams[sid];
         if (!str.in_ready) {
             str.in_ready = true;
-            s->ready.push_back(sid);
+            ln.ready.push_back(sid);
         }
     }
     if (B == 0) return;
@@ -274,8 +292,8 @@ void launch_step(sos_srv *s, Step &st)
     unsigned *chunk_err = err + 2;
     st.busy = true;
     st.seq = s->next_seq++;
-    sos_ctx *h = s->h;
-    unsigned char *d = s->dargs;
+    sos_ctx *h = ln.h;
+    unsigned char *d = ln.dargs;
     const int32_t *dK = reinterpret_cast<const int32_t *>(d + lb.k);
     const int32_t *dsec = reinterpret_cast<const int32_t *>(d + lb.sec);
     const int64_t *dsig = reinterpret_cast<const int64_t *>(d + lb.sig);
@@ -298,15 +316,15 @@ void launch_step(sos_srv *s, Step &st)
         sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total,
                                     std::min(step_groups, s->max_groups), dK, dsec,
                                     dsig, h->gpre, h->sigmap, h->total_dev, s->state, s->state,
-                                    h->ctrl, hb, d, (int64_t)lb.bytes, s->derr,
-                                    s->stream) == hipSuccess &&
+                                    h->ctrl, hb, d, (int64_t)lb.bytes, ln.derr,
+                                    ln.stream) == hipSuccess &&
         sos_launch_fwd_batched(s->bits, s->alg, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
                                h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
                                s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
-                               nullptr, 0, s->max_groups, s->derr, s->stream) == hipSuccess &&
-        sos_launch_report_err(h->ctrl + CTRL_ERR, err, s->derr, chunk_err, B, s->stream) ==
+                               nullptr, 0, s->max_groups, ln.derr, ln.stream) == hipSuccess &&
+        sos_launch_report_err(h->ctrl + CTRL_ERR, err, ln.derr, chunk_err, B, ln.stream) ==
             hipSuccess &&
-        hipEventRecord(st.done, s->stream) == hipSuccess;
+        hipEventRecord(st.done, ln.stream) == hipSuccess;
     if (!ok) retire(s, st, SOS_EHIP, 0u, nullptr);
 }
 
@@ -316,32 +334,36 @@ void worker_main(sos_srv *s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool busy = false;
-        // retire finished steps oldest first (a stream's failure must reach
-        // its later chunks)
-        for (;;) {
-            Step *oldest = nullptr;
-            for (Step &st : s->steps)
-                if (st.busy && (!oldest || st.seq < oldest->seq)) oldest = &st;
-            if (!oldest) break;
-            const hipError_t q = hipEventQuery(oldest->done);
-            if (q == hipErrorNotReady) {
-                busy = true;
-                break;
+        // retire each lane's finished steps oldest first (a stream's failure
+        // must reach its later chunks, which run in the same lane)
+        for (Lane &ln : s->lanes)
+            for (;;) {
+                Step *oldest = nullptr;
+                for (Step &st : ln.steps)
+                    if (st.busy && (!oldest || st.seq < oldest->seq)) oldest = &st;
+                if (!oldest) break;
+                const hipError_t q = hipEventQuery(oldest->done);
+                if (q == hipErrorNotReady) {
+                    busy = true;
+                    break;
+                }
+                const unsigned *res =
+                    reinterpret_cast<const unsigned *>(oldest->host + s->lay.err);
+                retire(s, *oldest, q == hipSuccess ? SOS_OK : SOS_EHIP, res[0], res + 2);
             }
-            const unsigned *res = reinterpret_cast<const unsigned *>(oldest->host + s->lay.err);
-            retire(s, *oldest, q == hipSuccess ? SOS_OK : SOS_EHIP, res[0], res + 2);
-        }
         if (s->stop && !busy) break;
-        Step *freeslot = nullptr;
-        for (Step &st : s->steps)
-            if (!st.busy) {
-                freeslot = &st;
-                break;
+        bool launched = false;
+        if (!s->stop)
+            for (Lane &ln : s->lanes) {
+                if (ln.ready.empty()) continue;
+                for (Step &st : ln.steps)
+                    if (!st.busy) {
+                        launch_step(s, ln, st);
+                        launched = true;
+                        break;
+                    }
             }
-        if (!s->stop && freeslot && !s->ready.empty()) {
-            launch_step(s, *freeslot);
-            continue;
-        }
+        if (launched) continue;
         if (busy)
             s->cv_work.wait_for(lk, std::chrono::microseconds(5));
         else
@@ -351,16 +373,19 @@ void worker_main(sos_srv *s)
 
 void free_server(sos_srv *s)
 {
-    for (Step &st : s->steps) {
-        if (st.done) (void)hipEventDestroy(st.done);
-        if (st.host) (void)hipHostFree(st.host);
+    for (Lane &ln : s->lanes) {
+        for (Step &st : ln.steps) {
+            if (st.done) (void)hipEventDestroy(st.done);
+            if (st.host) (void)hipHostFree(st.host);
+        }
+        for (void *p : {(void *)ln.dargs, (void *)ln.derr})
+            if (p) (void)hipFree(p);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
+        if (ln.h) (void)sos_destroy(ln.h);
     }
-    for (void *p : {(void *)s->sections, (void *)s->state, (void *)s->tabs, (void *)s->dargs,
-                    (void *)s->octrl, (void *)s->derr})
+    for (void *p : {(void *)s->sections, (void *)s->state, (void *)s->tabs, (void *)s->octrl})
         if (p) (void)hipFree(p);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->ostream) (void)hipStreamDestroy(s->ostream);
-    if (s->h) (void)sos_destroy(s->h);
     delete s;
 }
 
@@ -392,7 +417,7 @@ int push_many(sos_srv *s, int count, const int64_t *ids, const float *const *x,
         ++str.outstanding;
         if (!str.in_ready) {
             str.in_ready = true;
-            s->ready.push_back(ids[r]);
+            s->lanes[str.lane].ready.push_back(ids[r]);
         }
         tickets[r] = tk;
     }
@@ -417,10 +442,13 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
         delete s;
         return SOS_EHIP;
     }
-    int rc = sos_create(&s->h, s->device);
-    if (rc) {
-        delete s;
-        return rc;
+    for (Lane &ln : s->lanes) {
+        const int rc = sos_create(&ln.h, s->device);
+        if (rc) {
+            free_server(s);
+            return rc;
+        }
+        ln.h->timeout_ticks = hu->timeout_ticks;
     }
     const Tile t = tile_of(hu);
     s->L = t.L;
@@ -428,18 +456,17 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
     s->bits = bits_of(hu);
     s->rho_max = rho_max_of(hu);
     s->alg = launch_alg(s->bits, solver_of(hu), s->rho_max);
-    s->h->timeout_ticks = hu->timeout_ticks;
     s->C = (int64_t)t.L * t.N;
     s->max_slots = max_slots;
     s->lay = ArgLayout(max_slots);
     s->tab_row_bytes = (size_t)TAB_BYTES;
     const size_t budget = device_mem_budget ? device_mem_budget : kDefaultBudget;
-    // half for per-stream rows (sections, state, tables), half for a step's
-    // work table and descriptors (stride up to SOS_MAX_SECTIONS)
+    // half for per-stream rows (sections, state, tables), half for the
+    // lanes' work tables and descriptors (stride up to SOS_MAX_SECTIONS)
     const size_t row_bytes = 6 * 4 + 2 * 4 + s->tab_row_bytes;
     s->max_rows = (int64_t)((budget / 2) / row_bytes);
     const size_t group_bytes = (size_t)SOS_MAX_SECTIONS * 4 * 8 + 4;
-    s->max_groups = (int64_t)((budget / 2) / group_bytes);
+    s->max_groups = (int64_t)((budget / 2) / kStepLanes / group_bytes);
     s->max_step_samples = (s->max_groups - max_slots) * s->C;
     if (s->max_rows < 1 || s->max_step_samples < s->C || s->max_rows >= ((int64_t)1 << 31) ||
         s->max_groups >= ((int64_t)1 << 31)) {
@@ -448,35 +475,39 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
     }
     s->rows.init(s->max_rows);
     bool ok =
-        hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
         hipStreamCreateWithFlags(&s->ostream, hipStreamNonBlocking) == hipSuccess &&
         hipMalloc(&s->sections, (size_t)s->max_rows * 6 * 4) == hipSuccess &&
         hipMalloc(&s->state, (size_t)s->max_rows * 2 * 4) == hipSuccess &&
         hipMalloc(&s->tabs, (size_t)s->max_rows * s->tab_row_bytes) == hipSuccess &&
-        hipMalloc(&s->dargs, s->lay.bytes) == hipSuccess &&
-        hipMalloc(&s->derr, sizeof(unsigned) * (size_t)max_slots) == hipSuccess &&
         hipMalloc(&s->octrl, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
-        hipMemset(s->octrl, 0, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
-        hipMalloc(&s->h->gpre, sizeof(int64_t) * ((size_t)max_slots + 1)) == hipSuccess &&
-        hipMalloc(&s->h->sigmap, sizeof(int32_t) * (size_t)s->max_groups) == hipSuccess &&
-        hipMalloc(&s->h->total_dev, sizeof(int64_t)) == hipSuccess &&
-        hipMalloc(&s->h->desc, (size_t)s->max_groups * SOS_MAX_SECTIONS * 4 * 8) == hipSuccess &&
-        hipMemset(s->h->desc, 0, (size_t)s->max_groups * SOS_MAX_SECTIONS * 4 * 8) ==
-            hipSuccess;
-    for (Step &st : s->steps) {
-        ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
-             // coherent: kernels read the step's arguments from it and write the
-             // step's error word into it
-             hipHostMalloc(&st.host, s->lay.bytes + 8 + 4 * (size_t)max_slots,
-                           hipHostMallocCoherent) == hipSuccess;
+        hipMemset(s->octrl, 0, sizeof(unsigned) * CTRL_WORDS) == hipSuccess;
+    const size_t desc_bytes = (size_t)s->max_groups * SOS_MAX_SECTIONS * 4 * 8;
+    for (Lane &ln : s->lanes) {
+        sos_ctx *h = ln.h;
+        ok = ok && hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess &&
+             hipMalloc(&ln.dargs, s->lay.bytes) == hipSuccess &&
+             hipMalloc(&ln.derr, sizeof(unsigned) * (size_t)max_slots) == hipSuccess &&
+             hipMalloc(&h->gpre, sizeof(int64_t) * ((size_t)max_slots + 1)) == hipSuccess &&
+             hipMalloc(&h->sigmap, sizeof(int32_t) * (size_t)s->max_groups) == hipSuccess &&
+             hipMalloc(&h->total_dev, sizeof(int64_t)) == hipSuccess &&
+             hipMalloc(&h->desc, desc_bytes) == hipSuccess &&
+             hipMemset(h->desc, 0, desc_bytes) == hipSuccess;
+        for (Step &st : ln.steps) {
+            ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
+                 // coherent: kernels read the step's arguments from it and write
+                 // the step's error word into it
+                 hipHostMalloc(&st.host, s->lay.bytes + 8 + 4 * (size_t)max_slots,
+                               hipHostMallocCoherent) == hipSuccess;
+        }
+        if (!ok) break;
+        h->gpre_cap = (size_t)max_slots + 1;
+        h->sigmap_cap = (size_t)s->max_groups;
+        h->desc_cap = (size_t)s->max_groups * SOS_MAX_SECTIONS * 4;
     }
     if (!ok) {
         free_server(s);
         return SOS_ENOMEM;
     }
-    s->h->gpre_cap = (size_t)max_slots + 1;
-    s->h->sigmap_cap = (size_t)s->max_groups;
-    s->h->desc_cap = (size_t)s->max_groups * SOS_MAX_SECTIONS * 4;
     try {
         s->worker = std::thread(worker_main, s);
     } catch (...) {
@@ -501,13 +532,13 @@ int sos_server_destroy(sos_server_t s)
             }
             kv.second.pending.clear();
         }
-        s->ready.clear();
+        for (Lane &ln : s->lanes) ln.ready.clear();
         s->cv_work.notify_all();
         s->cv_done.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
     DeviceGuard g(s->device);
-    (void)hipStreamSynchronize(s->stream);
+    for (Lane &ln : s->lanes) (void)hipStreamSynchronize(ln.stream);
     free_server(s);
     return SOS_OK;
 }
@@ -578,6 +609,7 @@ int sos_stream_open(sos_server_t s, const float *sections_host, int K, const flo
     const int64_t sid = s->next_stream++;
     Stream &str = s->streams[sid];
     str.K = K;
+    str.lane = (int)(sid % kStepLanes);
     str.row = row;
     *stream_id = sid;
     return SOS_OK;

@@ -550,3 +550,29 @@ def test_batched_launch_captured_then_plain_calls(torch_cuda, P):
         torch.cuda.synchronize()
         assert rel_l2(yd.cpu().numpy(), yr) <= tol_for(K), rep
     assert h.last_error() == P.SOS_OK
+
+
+@pytest.mark.parametrize("alg", ["dccr", "ph", None])
+@pytest.mark.parametrize("a1,a2", [(-2 * np.cos(0.3), 1.0),   # pair of poles on the unit circle
+                                   (1.5, 0.5),                # real pole at z = -1
+                                   (-1.5, 0.5),               # real pole at z = +1
+                                   (0.0, -1.0)])              # poles at z = +1 and -1
+def test_poles_on_the_unit_circle_are_rejected(torch_cuda, P, alg, a1, a2):
+    """The stability check is the open triangle |a2| < 1, |a1| < 1 + a2:
+    poles on the unit circle (where the state-map powers do not decay across
+    groups) report SOS_EUNSTABLE and poison the output; a section just
+    inside is filtered."""
+    torch = torch_cuda
+    h = P.Handle(0, algorithm=alg)
+    x = torch.from_numpy(workloads.signal(5000, 3)).cuda()
+    sos = np.array([[1.0, 0.3, 0.2, 1.0, a1, a2]], np.float32)
+    y, zf = P.sosfilt(x, torch.from_numpy(sos).cuda(), handle=h)
+    assert h.last_error() == P.SOS_EUNSTABLE
+    assert torch.isnan(y).all().item()
+    inside = sos.copy()
+    inside[0, 4:] *= np.float32(0.999)               # both poles pulled inside
+    y, zf = P.sosfilt(x, torch.from_numpy(inside).cuda(), handle=h)
+    assert h.last_error() == P.SOS_OK
+    yr, _ = oracle.sosfilt(inside.astype(np.float64), x.cpu().numpy())
+    assert np.all(np.isfinite(y.cpu().numpy()))
+    assert rel_l2(y.cpu().numpy(), yr) <= 1e-3
