@@ -67,12 +67,31 @@ __device__ inline double peak_gain(const float *row)
 // section's peak gain exceeds rho_max (the FP32 state path and, in DC-CR
 // launches, the fold B(z)A(-z) lose accuracy with such poles), else fast.
 // rows: the signal's K rows. Each block of the signal decides alike.
+// peak_gain(row) <= rho_max without the square root and the reciprocal:
+// min |A|^2 rho_max^2 >= 1.
+__device__ inline bool gain_within(const float *row, double rho_max)
+{
+    if (isinf(rho_max)) return true;
+    const double a0 = row[3];
+    if (a0 == 0.0) return false;
+    const double a1 = row[4] / a0, a2 = row[5] / a0;
+    // |A|^2 = 4 a2 c^2 + l c + q on c = cos(w) in [-1, 1] (see peak_gain)
+    const double q = 1.0 + a1 * a1 + a2 * a2 - 2.0 * a2, l = 2.0 * a1 * (1.0 + a2);
+    auto f = [&](double c) { return (4.0 * a2 * c + l) * c + q; };
+    double m = fmin(f(-1.0), f(1.0));
+    if (a2 > 0.0) {
+        const double cv = -l / (8.0 * a2);
+        if (cv > -1.0 && cv < 1.0) m = fmin(m, f(cv));
+    }
+    return m > 0.0 && m * rho_max * rho_max >= 1.0;
+}
+
 template <typename T>
 __device__ inline unsigned signal_mode(const float *rows, int K, double rho_max)
 {
     if (sizeof(T) != 4) return MODE_FAST;
     for (int k = 0; k < K; ++k)
-        if (!(peak_gain(rows + 6 * k) <= rho_max)) return MODE_ACCURATE;
+        if (!gain_within(rows + 6 * k, rho_max)) return MODE_ACCURATE;
     return MODE_FAST;
 }
 
@@ -153,6 +172,19 @@ __device__ void prep_fast(const Norm &c, const float *row, T *t, int log2n, int 
     if (l < kMaxWaves) put(t, OFF_WPOW + 4 * l, P.wave);
     put(t, OFF_SCANPOW + 8 * l, P.scan_a);
     put(t, OFF_SCANPOW + 8 * l + 4, P.scan_b);
+    // impulse response of 1/A(z), stored with g[-1] = 0 first: lane l writes
+    // g[l] and g[l + 64] = (T^m)[0][0] of the TDF-II state map T (binary
+    // powers, so that no lane runs the length-N recursion)
+    {
+        m2 p2[7];
+        p2[0] = m2{-c.a1, 1.0, -c.a2, 0.0};
+        for (int k = 1; k < 7; ++k) p2[k] = mmul(p2[k - 1], p2[k - 1]);
+        for (int h = 0; h < 2; ++h) {
+            const int m = l + 64 * h;
+            t[OFF_G + 1 + m] = (m < N) ? (T)mpow_bits(p2, 7, m).a : T(0);
+        }
+        if (l == 0) t[OFF_G] = T(0);
+    }
     if (l != 0) return;
     if (pair) {
         t[OFF_FIR + 0] = (T)(row[0] * c.inv);
@@ -177,15 +209,6 @@ __device__ void prep_fast(const Norm &c, const float *row, T *t, int log2n, int 
         const double en = 2.0 * f - e * e;
         f = f * f;
         e = en;
-    }
-    // impulse response of 1/A(z), stored with g[-1] = 0 first
-    t[OFF_G] = T(0);
-    double gm2 = 0.0, gm1 = 0.0;
-    for (int m = 0; m < kMaxN; ++m) {
-        const double g = (m == 0) ? 1.0 : (-c.a1 * gm1 - c.a2 * gm2);
-        t[OFF_G + 1 + m] = (m < N) ? (T)g : T(0);
-        gm2 = gm1;
-        gm1 = g;
     }
     for (int k = 0; k < 6; ++k) put(t, OFF_KS + 4 * k, P.ks[k]);
     put(t, OFF_TC, P.tc);
