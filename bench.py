@@ -41,6 +41,10 @@ Beside the headline, on the same GPU (skipped with --quick):
   latency (tile (256, 16), PH solver).
 * "fwd_bwd": forward (keeping the section outputs) plus the adjoint, on one
   2^24-sample signal and on 256 signals of 2^16 samples, order 8, PH solver.
+* "dtcr_bound": an upper bound for DTCR's gain on short signals: the tile
+  with twice the lanes and half the samples per lane at the same group size
+  (DTCR's extra waves without its per-section hand-off) against the base
+  tile, 2^14..2^18 samples, orders 2 and 16, both solvers.
 * "toeplitz_mfma_bound": a lower bound for a block-Toeplitz (matrix-core)
   form of the whole cascade, not part of the filter: the FP32 library GEMM
   that maps every 64-sample chunk of a 2^28-sample signal through a 64 x 64
@@ -174,6 +178,46 @@ def length_curve(torch, P, h, sos_d, xs, ys, log2ns):
                     "mean_GS_per_s": round(m / (mean * 1e-3) / 1e9, 2),
                     "ms_p20": round(p20, 5), "host_us_per_launch": round(host_us, 2)})
     return pts
+
+
+def bench_dtcr_bound(torch, P, workloads, xs, ys, log):
+    """What DTCR's extra waves could buy (Sec. IV-E): DTCR splits a group's
+    two parity chains over two thread groups, doubling the waves per group at
+    the same staging, and pays an LDS hand-off per section. The tile with
+    twice the lanes and half the samples per lane at the same group size C
+    has those waves and the half-length chains without the hand-off, so its
+    gain bounds DTCR's. Short signals (2^14..2^18 samples), orders 2 and 16,
+    both solvers, under the paper's protocol (200 warm-up launches, 20
+    batches of 50)."""
+    out = {}
+    pairs = (((256, 32), (512, 16)), ((512, 32), (1024, 16)))
+    for K in (1, 8):
+        sos_d = torch.from_numpy(workloads.sweep_sections(K, "butter")).to(xs[0].device)
+        for alg in ("dccr", "ph"):
+            rows = []
+            for base, wide in pairs:
+                for lg in range(14, 19):
+                    m = 1 << lg
+                    k = min(xs[0].numel() // m, 64)
+                    sx = [xs[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
+                    sy = [ys[b][j * m:(j + 1) * m] for j in range(k) for b in (0, 1)]
+                    r = {"log2n": lg}
+                    for name, tile in (("base", base), ("wide", wide)):
+                        h = P.Handle(0, tile=tile, algorithm=alg)
+                        P.sosfilt_(sx[0], sos_d, y=sy[0], handle=h)
+                        p20, _, _ = paper_protocol(torch, P, h, sx, sy, batches=20, per_batch=50,
+                                                   warmup=200)
+                        assert h.last_error() == P.SOS_OK
+                        h.close()
+                        r[name] = {"tile_L_N": list(tile),
+                                   "kernel_GS_per_s": round(m / (p20 * 1e-3) / 1e9, 2)}
+                    r["wide_over_base"] = round(r["wide"]["kernel_GS_per_s"] /
+                                                r["base"]["kernel_GS_per_s"], 3)
+                    rows.append(r)
+            out["order_%d_%s" % (2 * K, alg)] = rows
+            log("dtcr bound", 2 * K, alg, [(r["log2n"], r["base"]["tile_L_N"], r["wide_over_base"])
+                                            for r in rows])
+    return out
 
 
 def plateau_of(pts):
@@ -736,6 +780,9 @@ def main():
                 "curve": pts}
             log("plateau", 2 * K, plateau["order_%d" % (2 * K)])
         hp.close()
+        extra_dtcr = bench_dtcr_bound(torch, P, workloads, xs, ys, log)
+    else:
+        extra_dtcr = None
 
     copy_ms = time_copy(torch, P, xs, ys, 20, 3)
     copy_gbs = n * BYTES_PER_SAMPLE / (copy_ms * 1e-3) / 1e9
@@ -809,6 +856,7 @@ def main():
         "host": host,
         "cpu_wavefront": cpu_extra,
         "paper_protocol": paper_stat,
+        "dtcr_bound": extra_dtcr,
         "sweep": result_sweep,
         "plateau": plateau,
     }
