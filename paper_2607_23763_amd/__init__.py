@@ -176,10 +176,11 @@ class Handle:
             self.set_algorithm(algorithm)
 
     def set_algorithm(self, alg):
-        """Section solver: "auto" (cyclic reduction, with PH for sections whose
-        poles lie very close to the unit circle), "dccr" (cyclic reduction
-        throughout), "ph" (particular + homogeneous), or None / "default"
-        (the environment's SOS_ALG, else "auto")."""
+        """Section solver: "auto" (per signal: cyclic reduction, or PH on the
+        accurate table layout when a section's poles lie close to the unit
+        circle), "dccr" (cyclic reduction throughout), "ph" (particular +
+        homogeneous), or None / "default" (the environment's SOS_ALG, else
+        "auto")."""
         code = _ALGS.get(alg if not isinstance(alg, str) else alg.lower())
         if code is None:
             raise ValueError("unknown algorithm %r" % (alg,))

@@ -38,22 +38,22 @@
 // sample and section instead of about 9, and one lane-sequential chain of N
 // dependent FMAs instead of the reduction's log-depth levels.
 //
-// Compute type T of the per-sample work: float, or double. Everything that
-// acts on carried states (the lanes' terminal states, the scans, the wave
-// combination, the lookback composition, the lanes' incoming states and zf)
-// is computed in FP64 with FP64 tables whatever T is: it is O(1) per lane and
-// section, and MI355X issues FP64 FMAs at the unpacked FP32 rate, while FP32
-// powers of the state map of a lightly damped section near the real axis
-// lose accuracy in proportion to 1/sin(theta). Each lane's incoming state is
-// applied to its samples through two orthonormal columns spanning the free
-// responses, after the FP64 change of basis R, so the two correction terms do
-// not cancel. Data in HBM, LDS staging and descriptor values are FP32.
-//
-// Inside a DC-CR launch, a section whose recursive part has a peak gain
-// above the handle's bound (marked in its table) is solved by PH: the fold
-// B(z)A(-z) amplifies rounding near the mirror frequency pi - theta of a
-// pole close to the unit circle, where an earlier section's resonance may
-// have put the signal's energy; PH applies no such factor.
+// Compute type T of the per-sample work: float, or double. In FP32 each
+// signal's tables take one of two layouts (chosen by the preparation kernel
+// from its sections' peak gains): the fast layout, where everything runs in
+// T, or the accurate layout, where everything that acts on carried states
+// (the lanes' terminal states, the scans, the wave combination, the lookback
+// composition, the lanes' incoming states and zf) runs in FP64 with FP64
+// tables, and each lane's incoming state reaches its samples through two
+// orthonormal columns spanning the free responses, after the FP64 change of
+// basis R, so that the two correction terms do not cancel. FP32 powers of the
+// state map of a lightly damped section lose accuracy in proportion to its
+// peak gain; the state path is O(1) per lane and section, and MI355X issues
+// FP64 FMAs at the unpacked FP32 rate. Accurate-layout signals are solved by
+// PH: DC-CR's fold B(z)A(-z) amplifies rounding near the mirror frequency of
+// a pole close to the unit circle. Launch modes: fast-layout tables only,
+// accurate-layout tables only, or per group (batched launches). Data in HBM,
+// LDS staging and descriptor values are FP32 in every layout.
 //
 // Descriptors: per (group, section) four 64-bit words {agg.z1, agg.z2,
 // inc.z1, inc.z2}, each {float value | 32-bit epoch tag}, stored

@@ -234,8 +234,8 @@ inline int solver_of(const sos_ctx *h)
 }
 
 // Kernel of the filter launches: ALG_PH for the PH solver, ALG_DCCR for
-// DC-CR and for the automatic choice (a DC-CR launch solves the sections its
-// tables mark by PH).
+// DC-CR and for the automatic choice (signals whose tables took the accurate
+// layout are solved by PH in any launch).
 inline int alg_of(const sos_ctx *h)
 {
     return solver_of(h) == SOS_ALG_PH ? sosdev::ALG_PH : sosdev::ALG_DCCR;
