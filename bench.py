@@ -412,9 +412,10 @@ def cpu_baselines_multi(workloads, np, threads, log):
     return out
 
 
-def cpu_wavefront_rate(sos, x_host, n_sample, reps=3):
+def cpu_wavefront_rate(sos, x_host, n_sample, reps=3, node="serial"):
     """The paper's multi-core CPU method (wavefront over groups and sections,
-    Sec. III-A) on the first n_sample samples: GS/s, seconds, threads."""
+    Sec. III-A, with serial or multi-block node kernels) on the first
+    n_sample samples: GS/s, seconds, threads."""
     import numpy as np
 
     import cpu_wavefront
@@ -422,11 +423,11 @@ def cpu_wavefront_rate(sos, x_host, n_sample, reps=3):
     xs = np.ascontiguousarray(x_host[:n_sample], dtype=np.float32)
     ys = np.empty_like(xs)
     threads = cpu_wavefront.default_threads()
-    cpu_wavefront.sosfilt(sos, xs[:4096], threads=threads)     # load outside the timing
+    cpu_wavefront.sosfilt(sos, xs[:4096], threads=threads, node=node)   # load outside the timing
     ts = []
     for _ in range(reps):
         t = time.perf_counter()
-        cpu_wavefront.sosfilt(sos, xs, threads=threads, out=ys)
+        cpu_wavefront.sosfilt(sos, xs, threads=threads, out=ys, node=node)
         ts.append(time.perf_counter() - t)
     ts.sort()
     return n_sample / ts[len(ts) // 2] / 1e9, ts[len(ts) // 2], threads
@@ -829,13 +830,16 @@ def main():
             cpu_multi = cpu_baselines_multi(workloads, np, host["threads"], log)
         # the paper's multi-core CPU method, beside the oracle (not the baseline)
         wf = {}
-        for K in (K1, 8):
-            v, secs, thr = cpu_wavefront_rate(workloads.sweep_sections(K, "butter"), x_host,
-                                              min(n, 1 << 26))
-            wf["order_%d" % (2 * K)] = {"value": round(v, 4), "unit": "GS/s", "threads": thr,
-                                        "seconds": round(secs, 3)}
+        for node in ("serial", "multiblock"):
+            for K in (K1, 8):
+                v, secs, thr = cpu_wavefront_rate(workloads.sweep_sections(K, "butter"), x_host,
+                                                  min(n, 1 << 26), node=node)
+                wf["%s_order_%d" % (node, 2 * K)] = {"value": round(v, 4), "unit": "GS/s",
+                                                    "threads": thr, "seconds": round(secs, 3)}
         cpu_extra = {"kind": "wavefront over groups of 2^16 samples and sections, FP32, "
-                             "pthreads (Sec. III-A); first 2^26 samples, median of 3 runs",
+                             "pthreads (Sec. III-A); nodes: the serial filter, or the "
+                             "multi-block node kernel (32 lanes x 64 samples per block, 8-wide "
+                             "AVX2 vectors, PH per section); first 2^26 samples, median of 3",
                      **wf}
         log("cpu wavefront", cpu_extra)
 

@@ -58,3 +58,42 @@ def test_degenerate_and_in_place():
     bad[1, 3] = 0.0
     with pytest.raises(ValueError):
         W.sosfilt(bad, x)
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+@pytest.mark.parametrize("K", [1, 4, 8])
+def test_multiblock_nodes_match_oracle(K, threads):
+    """The multi-block node kernels (lanes run from rest, a scan of the lanes'
+    states through T^NB, the homogeneous correction) against the oracle:
+    whole blocks, a group's serial tail, groups smaller than a block, a0 != 1
+    and random initial states. Bounds: the order's, or 10x the error of a
+    sequential FP32 filter on the same input."""
+    from tests.gpu_util import fp32_bounds
+
+    g = workloads.rng(600 + K)
+    for kind in ("butter", "random"):
+        sos = workloads.sweep_sections(K, kind) if kind == "butter" else \
+            workloads.random_stable_sos(K, g)
+        sos = sos * np.float32(1.25)                   # a0 != 1, same filter
+        zi = workloads.initial_state(K, g)
+        for n, group in ((1, 7), (3000, 1000), (70001, 8192), ((1 << 18) + 5, 1 << 16)):
+            x = workloads.signal(n, seed=n + K)
+            y, zf = W.sosfilt(sos, x, zi, group=group, threads=threads, node="multiblock")
+            yr, zfr = oracle.sosfilt(sos, x, zi)
+            by, bz = fp32_bounds(K, sos / sos[:, 3:4], x, zi, yr, zfr)
+            assert rel(y, yr) <= max(by, 1e-5 if K <= 4 else 1e-4), (kind, K, n, group)
+            assert rel(zf, zfr) <= max(bz, 1e-5 if K <= 4 else 1e-4), (kind, K, n, group)
+
+
+def test_multiblock_nodes_degenerate_and_in_place():
+    sos = workloads.sweep_sections(2, "butter")
+    zi = workloads.initial_state(2, workloads.rng(2))
+    y, zf = W.sosfilt(sos, np.zeros(0, np.float32), zi, node="multiblock")
+    assert y.size == 0 and np.array_equal(zf, zi)
+    x = workloads.signal(40000, seed=5)
+    xc = x.copy()
+    W.sosfilt(sos, xc, zi, group=4096, threads=4, out=xc, node="multiblock")
+    yr, _ = oracle.sosfilt(sos, x, zi)
+    assert rel(xc, yr) <= 1e-5
+    with pytest.raises(KeyError):
+        W.sosfilt(sos, x, node="nope")
