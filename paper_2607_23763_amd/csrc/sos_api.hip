@@ -62,11 +62,9 @@ int check_signal(const float *x, const float *y, int64_t n)
 
 // Tables for `sections` at the handle's shape (or, without one, the shape for
 // a signal of n samples; n < 0: unknown) and type (caller holds the lock).
-int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream, int64_t n = -1,
-                   bool train = false)
+int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream, int64_t n = -1)
 {
-    Tile t = tile_for_length(h, K, n);
-    if (train) t = train_tile(h, t);
+    const Tile t = tile_for_length(h, K, n);
     const int bits = bits_of(h);
     int rc = ensure_buf(h->tabs, h->tabs_cap, tab_bytes(K > 8 ? K : 8, bits), stream);
     if (rc) return rc;
@@ -451,7 +449,7 @@ int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     if (n > 0 && K > 0) {
-        rc = prepare_locked(h, sections, K, stream, n, true);
+        rc = prepare_locked(h, sections, K, stream, n);
         if (rc) return rc;
     } else {
         mark_degenerate(h, K);
@@ -528,7 +526,7 @@ int sos_filter_train_batched(sos_handle_t h, int B, int kmax, int64_t total_rows
     std::lock_guard<std::mutex> lk(h->mu);
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
-    const Tile t = train_tile(h, tile_of(h, kmax));
+    const Tile t = tile_of(h, kmax);
     const int bits = bits_of(h);
     rc = batch_reserve(h, t, bits, ba, stream);
     if (rc) return rc;

@@ -197,20 +197,6 @@ inline bool tile_is_set(const sos_ctx *h)
 // time at orders 8-16 up to 2^20 samples with (512, 16), 8-10 % at 2^21-2^22
 // with (512, 32), which at 2^23 is already 8 % slower than the default).
 // n < 0: unknown, the default tile.
-// The group shape of a training forward (one that keeps the section outputs
-// for the adjoint) when no tile is set: at most 32 samples per lane, the
-// adjoint's own limit. On the accurate layout a lane's particular solution
-// over 64 samples grows against resonant sections and cancels against the
-// correction, and the coefficient gradients, sums over these saved outputs,
-// inherit the rounding (measured on MI355X, order 16 at pole radius 0.995,
-// 2^16 samples: 1.2-1.4e-4 with N = 64 against 3.5e-5 with N = 32); the
-// outputs themselves are equally accurate either way.
-inline Tile train_tile(const sos_ctx *h, Tile t)
-{
-    if (!tile_is_set(h) && t.N > 32) t.N = 32;
-    return t;
-}
-
 inline Tile tile_for_length(const sos_ctx *h, int K, int64_t n)
 {
     const Tile t = tile_of(h, K);
