@@ -245,3 +245,55 @@ def test_vjp_batched_sum_is_the_fp64_sum_of_rows(env):
         ref[:k] += gs[so[i]:so[i + 1]]
     got = gsum.cpu().numpy()
     assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref).max(axis=1, keepdims=True) + 1e-30)
+
+
+def test_vjp_batched_skips_an_inconsistent_signal(env):
+    """A signal whose section offset runs past the rows is skipped and
+    reported by the batched adjoint: its coefficient-gradient rows are not
+    written (a guard region after the gradient rows keeps its sentinel), its
+    gx is left alone, and the other signals' gradients equal those of the
+    consistent call."""
+    import ctypes
+
+    torch, P = env
+    rng = workloads.rng(91)
+    B, K = 3, 2
+    rows = np.concatenate([workloads.random_stable_sos(K, rng) for _ in range(B)])
+    R = rows.shape[0]
+    Ks = np.full(B, K, dtype=np.int32)
+    so = (np.arange(B + 1) * K).astype(np.int32)
+    lens = np.array([3000, 2500, 4000], np.int64)
+    sig_off = np.r_[0, np.cumsum(lens)].astype(np.int64)
+    n = int(sig_off[-1])
+    x = workloads.batch_signal(n, seed=92)
+    gy = workloads.batch_signal(n, seed=93)
+    zi = workloads.initial_state(R, rng)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h = P.Handle(0)
+    xd, rd, Kd, sd = dev(x), dev(rows), dev(Ks), dev(sig_off)
+    y, zf, saved = P.sosfilt_train_batched(xd, rd, Kd, sd, zi=dev(zi), sec_off=dev(so), kmax=K,
+                                           handle=h)
+    gx_ref, gzi_ref, gs_ref = P.sosfilt_vjp_batched(rd, Kd, sd, xd, y, saved, dev(gy),
+                                                    sec_off=dev(so), kmax=K, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    so_bad = so.copy()
+    so_bad[1] = R - 1                                  # so + K = R + 1 > R
+    gx = torch.full((n,), 7.0, device="cuda")
+    gzi = torch.zeros((R, 2), device="cuda")
+    gs_full = torch.full((R + 4, 6), 7.0, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    sod, gyd = dev(so_bad), dev(gy)                    # kept alive while the launch runs
+    rc = P.lib().sos_filter_vjp_batched(h.ptr, B, K, R, n, p(Kd), p(sod), p(rd), p(sd), p(xd),
+                                        p(y), p(saved), p(gyd), None, p(gx), p(gzi),
+                                        p(gs_full), P._stream_ptr())
+    torch.cuda.synchronize()
+    assert rc == P.SOS_OK and h.last_error() == P.SOS_EINVAL
+    assert torch.all(gs_full[R:] == 7.0).item()
+    a, b = int(sig_off[1]), int(sig_off[2])
+    assert torch.all(gx[a:b] == 7.0).item()
+    for i in (0, 2):
+        a, b = int(sig_off[i]), int(sig_off[i + 1])
+        assert rel_l2(gx[a:b].cpu().numpy(), gx_ref[a:b].cpu().numpy()) <= 1e-6, i
+        r0, r1 = int(so[i]), int(so[i + 1])
+        assert rel_l2(gs_full[r0:r1].cpu().numpy(), gs_ref[r0:r1].cpu().numpy()) <= 1e-6, i

@@ -149,3 +149,25 @@ def test_cost_model_residency_matches_the_runtime(env):
                         (bits, alg, Lg, N, regs, lds, cap // cus, c.tbs_per_sm, c.limit)
                     checked += 1
     assert checked >= 30
+
+
+def test_tuner_rejects_filtering_in_place(env):
+    """The tuner runs the batch many times, so it cannot filter in place: x
+    as y (with samples) and zi as zf are rejected before anything runs."""
+    torch, P = env
+    Ks, rows, sig_off, zi = workloads.uneven_batch(B=8, log2_lo=10, log2_hi=12, seed=95)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x = dev(workloads.batch_signal(int(sig_off[-1]), seed=96))
+    x0 = x.clone()
+    zid = dev(zi)
+    h = P.Handle(0)
+    with pytest.raises(Exception) as e:
+        P.tune_batched(x, dev(rows), dev(Ks.astype(np.int32)), dev(sig_off), zi=zid, y=x,
+                       handle=h)
+    assert getattr(e.value, "code", None) == P.SOS_EINVAL
+    with pytest.raises(Exception) as e:
+        P.tune_batched(x, dev(rows), dev(Ks.astype(np.int32)), dev(sig_off), zi=zid, zf=zid,
+                       handle=h)
+    assert getattr(e.value, "code", None) == P.SOS_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(x, x0)
