@@ -1670,16 +1670,23 @@ sos_bwd_sum_rows_kernel(const double *grow, int B, int kmax, float *gsum)
 // ------------------------------------------------------------------ launch
 
 // The forward kernel of a launch: the solver, and whether the tables may use
-// the accurate layout (FP32 only): plain launches then take the fast kernel
-// and the accurate one back to back (the one not needed leaves at once),
-// batched launches the kernel that chooses per group.
+// the accurate layout (FP32 only): plain launches of at least kMixPlainGroups
+// groups then take the fast kernel and the accurate one back to back (the one
+// not needed leaves at once), batched and shorter plain launches the kernel
+// that chooses per group.
+constexpr int64_t kMixPlainGroups = 512;   // plain launches of fewer groups: per-group kernel
+
 template <typename T, int N, int W>
 hipError_t launch_fwd(int alg, const FwdArgs &a, int64_t grid, hipStream_t stream)
 {
     const bool maybe_acc = sizeof(T) == 4 && (alg & ALG_MAYBE_ACC);
     const bool ph = (alg & ~ALG_MAYBE_ACC) == ALG_PH;
     const dim3 g((unsigned)grid), blk(64 * W);
-    if (maybe_acc && a.B > 0) {
+    // short plain launches too: the second kernel's launch and exit cost more
+    // than the per-group choice there (same-box A/B, order 2: 8.8 -> 7.3 us
+    // per call at 2^16 samples, 11.6 -> 10.2 at 2^20, equal at 2^24, 3 %
+    // slower at 2^28)
+    if (maybe_acc && (a.B > 0 || a.total < kMixPlainGroups)) {
         if (ph)
             hipLaunchKernelGGL((sos_fwd_kernel<T, N, W, ALG_PH, KM_MIX>), g, blk, 0, stream, a);
         else
