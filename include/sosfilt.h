@@ -484,6 +484,9 @@ typedef struct sos_srv *sos_server_t;
  * stream rows (sections, states and tables: K rows per stream) and, in equal
  * parts, the two lanes' work tables and descriptors, which bound the samples
  * of a step and of a chunk (sos_server_limits). max_slots (>= 1) bounds the chunks of one step.
+ * When h's tile has fewer than 16384 samples per group, every stream's
+ * tables are also prepared for the throughput tile (512, 32), and steps of
+ * at least 2^22 samples (a loaded server's) run at that tile.
  * Allocates everything up front; no device allocation happens while serving. */
 int sos_server_create(sos_server_t *s, sos_handle_t h, size_t device_mem_budget, int max_slots);
 /* Stop the scheduler, let steps on the device finish, fail chunks not yet in

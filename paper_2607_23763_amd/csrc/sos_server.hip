@@ -47,6 +47,14 @@ namespace {
 // and two lanes of three 104-111 / 290-560 / 780-1360 / 1700-2700 us, the
 // achieved rates within 10 % of each other (75-89 GS/s at 5.2 M/s).
 constexpr int kSteps = 2;
+
+// A step of at least this many samples runs at the throughput tile (512, 32)
+// when the server's own tile is smaller: a saturated server forms steps of
+// hundreds of chunks, where a smaller tile's per-group costs dominate, while
+// steps under light load stay on the latency tile. Same-box sweep of whole
+// servers, 100000 chunks queued at once: (256, 16) 97 GS/s, (512, 32) 132;
+// p50 at 50 k chunks/s: 82 and 102 us.
+constexpr int64_t kBigStepSamples = (int64_t)1 << 22;
 constexpr size_t kDefaultBudget = 256ull << 20;  // bytes
 constexpr int kPending = 1;                      // request status while not finished
 
@@ -157,6 +165,9 @@ struct sos_srv {
     hipStream_t ostream = nullptr;    // stream opening (table preparation)
     unsigned *octrl = nullptr;        // error word of the preparation launches
     int device = 0, L = 0, N = 0, bits = 32, alg = 0;
+    int L2 = 0, N2 = 0;               // throughput tile of large steps (0: none)
+    int64_t C2 = 0;
+    unsigned char *tabs2 = nullptr;   // max_rows x tab_row_bytes, prepared for (L2, N2)
     double rho_max = 0.0;             // tables' PH bound (automatic solver choice)
     int64_t C = 0;
     int max_slots = 0;
@@ -302,8 +313,12 @@ void launch_step(sos_srv *s, Lane &ln, Step &st)
     // persistent grid, but no more workgroups than the step has groups (each
     // chunk adds at most one partial group): a step of a few chunks launches
     // a few workgroups, not a device-filling grid that mostly exits at once
-    const int64_t step_groups = total / s->C + B;
-    int64_t grid = grid_of(s->bits, s->alg, s->L, s->N);
+    const bool big = s->tabs2 && total >= kBigStepSamples;
+    const int L = big ? s->L2 : s->L, N = big ? s->N2 : s->N;
+    const int64_t C = big ? s->C2 : s->C;
+    const unsigned char *tabs = big ? s->tabs2 : s->tabs;
+    const int64_t step_groups = total / C + B;
+    int64_t grid = grid_of(s->bits, s->alg, L, N);
     if (grid <= 0 || grid > s->max_groups) grid = s->max_groups;
     if (grid > step_groups) grid = step_groups;
     // Three or four launches, no copy operations: the work-table kernel copies
@@ -313,13 +328,13 @@ void launch_step(sos_srv *s, Lane &ln, Step &st)
     // buffer and clears them. The step's own group bound (each chunk adds at
     // most one partial group) sizes the work table.
     bool ok =
-        sos_launch_worktable_staged(B, kmax, s->max_rows, s->C, total,
+        sos_launch_worktable_staged(B, kmax, s->max_rows, C, total,
                                     std::min(step_groups, s->max_groups), dK, dsec,
                                     dsig, h->gpre, h->sigmap, h->total_dev, s->state, s->state,
                                     h->ctrl, hb, d, (int64_t)lb.bytes, ln.derr,
                                     ln.stream) == hipSuccess &&
-        sos_launch_fwd_batched(s->bits, s->alg, s->L, s->N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
-                               h->sigmap, h->total_dev, nullptr, nullptr, s->tabs, s->state,
+        sos_launch_fwd_batched(s->bits, s->alg, L, N, B, std::max(kmax, 1), dK, dsec, dsig, h->gpre,
+                               h->sigmap, h->total_dev, nullptr, nullptr, tabs, s->state,
                                s->state, h->desc, h->ctrl, h->timeout_ticks, grid, dxp, dyp,
                                nullptr, 0, s->max_groups, ln.derr, ln.stream) == hipSuccess &&
         sos_launch_report_err(h->ctrl + CTRL_ERR, err, ln.derr, chunk_err, B, ln.stream) ==
@@ -383,7 +398,8 @@ void free_server(sos_srv *s)
         if (ln.stream) (void)hipStreamDestroy(ln.stream);
         if (ln.h) (void)sos_destroy(ln.h);
     }
-    for (void *p : {(void *)s->sections, (void *)s->state, (void *)s->tabs, (void *)s->octrl})
+    for (void *p : {(void *)s->sections, (void *)s->state, (void *)s->tabs, (void *)s->tabs2,
+                    (void *)s->octrl})
         if (p) (void)hipFree(p);
     if (s->ostream) (void)hipStreamDestroy(s->ostream);
     delete s;
@@ -457,13 +473,18 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
     s->rho_max = rho_max_of(hu);
     s->alg = launch_alg(s->bits, solver_of(hu), s->rho_max);
     s->C = (int64_t)t.L * t.N;
+    if (s->C < 512 * 32 && sos_fwd_shape_supported(512, 32)) {
+        s->L2 = 512;
+        s->N2 = 32;
+        s->C2 = 512 * 32;
+    }
     s->max_slots = max_slots;
     s->lay = ArgLayout(max_slots);
     s->tab_row_bytes = (size_t)TAB_BYTES;
     const size_t budget = device_mem_budget ? device_mem_budget : kDefaultBudget;
     // half for per-stream rows (sections, state, tables), half for the
     // lanes' work tables and descriptors (stride up to SOS_MAX_SECTIONS)
-    const size_t row_bytes = 6 * 4 + 2 * 4 + s->tab_row_bytes;
+    const size_t row_bytes = 6 * 4 + 2 * 4 + s->tab_row_bytes * (s->L2 ? 2 : 1);
     s->max_rows = (int64_t)((budget / 2) / row_bytes);
     const size_t group_bytes = (size_t)SOS_MAX_SECTIONS * 4 * 8 + 4;
     s->max_groups = (int64_t)((budget / 2) / kStepLanes / group_bytes);
@@ -479,6 +500,8 @@ int sos_server_create(sos_server_t *out, sos_handle_t hu, size_t device_mem_budg
         hipMalloc(&s->sections, (size_t)s->max_rows * 6 * 4) == hipSuccess &&
         hipMalloc(&s->state, (size_t)s->max_rows * 2 * 4) == hipSuccess &&
         hipMalloc(&s->tabs, (size_t)s->max_rows * s->tab_row_bytes) == hipSuccess &&
+        (!s->L2 ||
+         hipMalloc(&s->tabs2, (size_t)s->max_rows * s->tab_row_bytes) == hipSuccess) &&
         hipMalloc(&s->octrl, sizeof(unsigned) * CTRL_WORDS) == hipSuccess &&
         hipMemset(s->octrl, 0, sizeof(unsigned) * CTRL_WORDS) == hipSuccess;
     const size_t desc_bytes = (size_t)s->max_groups * SOS_MAX_SECTIONS * 4 * 8;
@@ -584,6 +607,11 @@ int sos_stream_open(sos_server_t s, const float *sections_host, int K, const flo
                             __builtin_ctz((unsigned)(s->L / 64)),
                             s->tabs + (size_t)row * s->tab_row_bytes, s->octrl, 0, s->rho_max,
                             s->ostream) == hipSuccess &&
+            (!s->tabs2 ||
+             sos_launch_prep(s->bits, s->sections + 6 * row, K, __builtin_ctz((unsigned)s->N2),
+                             __builtin_ctz((unsigned)(s->L2 / 64)),
+                             s->tabs2 + (size_t)row * s->tab_row_bytes, s->octrl, 0, s->rho_max,
+                             s->ostream) == hipSuccess) &&
             hipMemcpyAsync(tab.data(), s->tabs + (size_t)row * s->tab_row_bytes, tab.size(),
                            hipMemcpyDeviceToHost, s->ostream) == hipSuccess &&
             hipStreamSynchronize(s->ostream) == hipSuccess;

@@ -317,3 +317,30 @@ def test_device_errors_reach_their_chunks(env):
     yr, _ = oracle.sosfilt(sos, xs)
     assert rel_l2(ys2.cpu().numpy(), yr) <= 1e-5
     srv.close()
+
+
+def test_large_steps_on_the_throughput_tile(env):
+    """Steps of at least 2^22 samples run at the throughput tile (512, 32) with
+    tables prepared for it at stream open; here 8 streams push 4 chunks of
+    2^19 samples each at once, so steps carry up to 4.2e6 samples. Every
+    stream against the oracle over its concatenated chunks, FP32 and FP64."""
+    torch, P = env
+    S, per, m = 8, 4, 1 << 19
+    g = workloads.rng(47)
+    Ks = g.integers(1, 9, size=S).astype(np.int32)
+    secs = [workloads.random_stable_sos(int(k), g) for k in Ks]
+    ids = np.tile(np.arange(S), per)
+    lens = np.full(S * per, m, dtype=np.int64)
+    offs = (np.arange(S * per) * m).astype(np.int64)
+    x = workloads.signal(S * per * m, seed=48)
+    xd = torch.from_numpy(x).cuda()
+    y, states, _ = serve_all(torch, P, Ks, secs, ids, lens, offs, xd, max_slots=S)
+    y64, states64, _ = serve_all(torch, P, Ks, secs, ids, lens, offs, xd, max_slots=S,
+                                 precision=64)
+    yr, zfr, bnd = oracle_per_stream(Ks, secs, ids, lens, offs, x)
+    for s in yr:
+        e = rel_l2(gathered(y, ids, lens, offs, s), yr[s])
+        assert e <= bnd[s][0], (s, Ks[s], e, bnd[s])
+        assert rel_l2(states[s], zfr[s]) <= bnd[s][1], s
+        e64 = rel_l2(gathered(y64, ids, lens, offs, s), yr[s])
+        assert e64 <= tol_for(int(Ks[s])), (s, Ks[s], e64)
