@@ -151,15 +151,40 @@ int sos_get_precision(sos_handle_t h);
  * "inf" for never) replaces the thresholds of SOS_ALG_AUTO and SOS_ALG_PH.
  * All share the cross-lane scan, the decoupled lookback, the tables and the
  * state conventions, and accept every tile and compute type. SOS_ALG_DEFAULT
- * (0) restores the default: SOS_ALG in the environment ("auto", "dccr" or
- * "ph"), else SOS_ALG_AUTO. Applies to later launches of the handle: plain,
+ * (0) restores the default: SOS_ALG in the environment ("auto", "dccr",
+ * "ph" or "toeplitz"), else SOS_ALG_AUTO. Applies to later launches of the handle: plain,
  * batched, captured batches, servers created afterwards, and both passes of
  * the adjoint (the training forward and the reversed-time recursion of the
  * VJP). Tables prepared by sos_prepare belong to the solver in effect then.
  * sos_set_algorithm returns SOS_EINVAL for an unknown value or a null
  * handle; sos_get_algorithm returns the solver in effect (SOS_ALG_AUTO,
- * SOS_ALG_DCCR or SOS_ALG_PH), or SOS_EINVAL for a null handle. */
-enum { SOS_ALG_DEFAULT = 0, SOS_ALG_DCCR = 1, SOS_ALG_PH = 2, SOS_ALG_AUTO = 3 };
+ * SOS_ALG_DCCR, SOS_ALG_PH or SOS_ALG_TOEPLITZ), or SOS_EINVAL for a null
+ * handle.
+ *
+ * Whole-cascade block-Toeplitz form (Sec. II-B taken over the whole cascade):
+ * for a plain FP32 forward filter (sos_filter, sos_filter_prepared) of a
+ * cascade of at most 8 sections, the cascade's 2K TDF-II states are stacked
+ * into one state, and every 64-sample column is filtered as y = T x + O s,
+ * s' = A s + Gam x with T the lower-triangular Toeplitz matrix of the
+ * cascade's impulse response, on the matrix cores (FP32 MFMA), with one
+ * 16-word lookback per group of 16384 samples instead of one per section.
+ * Its cost per sample does not grow with K, but a call has a fixed cost of
+ * about 0.1 ms (its tables, and chunks of 131072 samples that must fill the
+ * device). SOS_ALG_AUTO takes it for plain FP32 forward calls with K >= 7 on
+ * at least 2^27 samples when every section's peak gain is at most 128
+ * (decided on the device by the table preparation; other signals run as
+ * before, in the same call).
+ * SOS_ALG_TOEPLITZ takes it for every plain FP32 forward call with K <= 8,
+ * whatever the gains; its batched, training, adjoint and served launches,
+ * and FP64 ones, run PH. Results follow the same conventions (zi, zf, in
+ * place); the error is about that of a sequential FP32 filter. */
+enum {
+    SOS_ALG_DEFAULT = 0,
+    SOS_ALG_DCCR = 1,
+    SOS_ALG_PH = 2,
+    SOS_ALG_AUTO = 3,
+    SOS_ALG_TOEPLITZ = 4
+};
 int sos_set_algorithm(sos_handle_t h, int alg);
 int sos_get_algorithm(sos_handle_t h);
 

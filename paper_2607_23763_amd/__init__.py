@@ -32,9 +32,11 @@ SOS_ALG_DEFAULT = 0
 SOS_ALG_DCCR = 1
 SOS_ALG_PH = 2
 SOS_ALG_AUTO = 3
+SOS_ALG_TOEPLITZ = 4
 _ALGS = {None: SOS_ALG_DEFAULT, "default": SOS_ALG_DEFAULT, "dccr": SOS_ALG_DCCR,
-         "ph": SOS_ALG_PH, "auto": SOS_ALG_AUTO, SOS_ALG_DEFAULT: SOS_ALG_DEFAULT,
-         SOS_ALG_DCCR: SOS_ALG_DCCR, SOS_ALG_PH: SOS_ALG_PH, SOS_ALG_AUTO: SOS_ALG_AUTO}
+         "ph": SOS_ALG_PH, "auto": SOS_ALG_AUTO, "toeplitz": SOS_ALG_TOEPLITZ,
+         SOS_ALG_DEFAULT: SOS_ALG_DEFAULT, SOS_ALG_DCCR: SOS_ALG_DCCR, SOS_ALG_PH: SOS_ALG_PH,
+         SOS_ALG_AUTO: SOS_ALG_AUTO, SOS_ALG_TOEPLITZ: SOS_ALG_TOEPLITZ}
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -179,8 +181,12 @@ class Handle:
         """Section solver: "auto" (per signal: cyclic reduction, or PH on the
         accurate table layout when a section's poles lie close to the unit
         circle), "dccr" (cyclic reduction throughout), "ph" (particular +
-        homogeneous), or None / "default" (the environment's SOS_ALG, else
-        "auto")."""
+        homogeneous), "toeplitz" (plain FP32 forward calls of up to 8
+        sections through the whole-cascade block-Toeplitz kernel on the
+        matrix cores, everything else as "ph"), or None / "default" (the
+        environment's SOS_ALG, else "auto"; "auto" also takes the
+        block-Toeplitz kernel for plain calls of order 8-16 on at least 2^20
+        samples)."""
         code = _ALGS.get(alg if not isinstance(alg, str) else alg.lower())
         if code is None:
             raise ValueError("unknown algorithm %r" % (alg,))
@@ -188,7 +194,8 @@ class Handle:
 
     def algorithm(self) -> str:
         code = int(lib().sos_get_algorithm(self._h))
-        return {SOS_ALG_DCCR: "dccr", SOS_ALG_PH: "ph", SOS_ALG_AUTO: "auto"}[code]
+        return {SOS_ALG_DCCR: "dccr", SOS_ALG_PH: "ph", SOS_ALG_AUTO: "auto",
+                SOS_ALG_TOEPLITZ: "toeplitz"}[code]
 
     def set_precision(self, bits: int):
         """Compute type of the kernels: 32 or 64 (0 = default)."""

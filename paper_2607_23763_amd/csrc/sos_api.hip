@@ -2,6 +2,7 @@
 // argument checks and kernel launches. No exception or abort crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -60,9 +61,16 @@ int check_signal(const float *x, const float *y, int64_t n)
     return SOS_OK;
 }
 
+// Shortest signal a plain launch of `solver` filters by the whole-cascade path.
+int64_t toep_min_n(int solver)
+{
+    return solver == SOS_ALG_TOEPLITZ ? 1 : kToepAutoMinN;
+}
+
 // Tables for `sections` at the handle's shape (or, without one, the shape for
 // a signal of n samples; n < 0: unknown) and type (caller holds the lock).
-int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream, int64_t n = -1)
+int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream, int64_t n = -1,
+                   bool plain = true)
 {
     const Tile t = tile_for_length(h, K, n);
     const int bits = bits_of(h);
@@ -79,6 +87,20 @@ int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream,
     h->prep_L = t.L;
     h->prep_N = t.N;
     h->prep_bits = bits;
+    h->prep_toep = false;
+    // the whole-cascade tables, when a plain launch may take that path; the
+    // preparation decides on the device whether it does (gate word)
+    const int s = h->prep_alg;
+    if (plain && bits == 32 && K >= 1 && K <= kToepMaxK &&
+        (s == SOS_ALG_TOEPLITZ || (s == SOS_ALG_AUTO && K >= kToepAutoMinK)) &&
+        (n < 0 || n >= toep_min_n(s))) {
+        rc = ensure_buf(h->ttab, h->ttab_cap, (size_t)sos_toep_table_floats(), stream);
+        if (rc) return rc;
+        if (sos_launch_toep_prep(sections, K, s == SOS_ALG_TOEPLITZ ? HUGE_VAL : kToepRhoMax,
+                                 h->ttab, stream) != hipSuccess)
+            return SOS_EHIP;
+        h->prep_toep = true;
+    }
     return SOS_OK;
 }
 
@@ -112,7 +134,14 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     const int64_t C = (int64_t)L * N;
     const int64_t groups = (n + C - 1) / C;
     if (groups >= (int64_t)1 << 31) return SOS_EINVAL;
-    const int rc = ensure_desc(h, (size_t)groups * (size_t)K * 4u, stream);
+    // the whole-cascade kernel first when its tables are there: it filters
+    // the signal unless the preparation's gate sent it to the per-section
+    // kernels, which then skip it (and otherwise filter it as before)
+    const bool toep = h->prep_toep && !saved && n >= toep_min_n(h->prep_alg);
+    const int64_t tgroups = toep ? (n + sos_toep_group_samples() - 1) / sos_toep_group_samples() : 0;
+    size_t words = (size_t)groups * (size_t)K * 4u;
+    if (toep) words = std::max(words, (size_t)tgroups * (size_t)sos_toep_desc_words());
+    const int rc = ensure_desc(h, words, stream);
     if (rc) return rc;
     // Ticket 0 and a fresh epoch: left by the previous plain or adjoint launch
     // on this workspace (their last workgroup re-arms) or by its creation,
@@ -121,9 +150,16 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     const bool cap = capturing(stream);
     if ((!h->armed || cap || h->batch_captured) && sos_launch_arm(h->ctrl, stream) != hipSuccess)
         return SOS_EHIP;
+    if (toep) {
+        const int64_t g = grid_override();
+        if (sos_launch_toep(x, y, n, h->ttab, K, zi, zf, h->desc, h->ctrl, h->timeout_ticks,
+                            g ? g : sos_toep_capacity(), stream) != hipSuccess)
+            return SOS_EHIP;
+    }
     const int alg = launch_alg(bits, h->prep_alg, h->prep_rho);
     if (sos_launch_fwd(bits, alg, L, N, x, y, n, groups, h->tabs, K, zi, zf, h->desc, h->ctrl,
-                       h->timeout_ticks, grid_of(bits, alg, L, N), saved, stream) != hipSuccess)
+                       h->timeout_ticks, grid_of(bits, alg, L, N), saved,
+                       toep ? h->ttab : nullptr, stream) != hipSuccess)
         return SOS_EHIP;
     h->last_groups = groups;
     h->last_K = K;
@@ -148,6 +184,7 @@ void mark_degenerate(sos_ctx *h, int K)
     h->prep_bits = bits_of(h);
     h->prep_alg = solver_of(h);
     h->prep_rho = rho_max_of(h);
+    h->prep_toep = false;
 }
 
 }  // namespace
@@ -295,7 +332,7 @@ int sos_destroy(sos_handle_t h)
         (void)hipDeviceSynchronize();
         for (void *p : {(void *)h->desc, (void *)h->tabs, (void *)h->ctrl, (void *)h->gpre,
                         (void *)h->sigmap, (void *)h->total_dev, (void *)h->tabs_bwd,
-                        (void *)h->partials, (void *)h->grow})
+                        (void *)h->partials, (void *)h->grow, (void *)h->ttab})
             if (p) (void)hipFree(p);
     }
     delete h;
@@ -358,7 +395,7 @@ int sos_get_precision(sos_handle_t h)
 int sos_set_algorithm(sos_handle_t h, int alg)
 {
     if (!h || (alg != SOS_ALG_DEFAULT && alg != SOS_ALG_DCCR && alg != SOS_ALG_PH &&
-               alg != SOS_ALG_AUTO))
+               alg != SOS_ALG_AUTO && alg != SOS_ALG_TOEPLITZ))
         return SOS_EINVAL;
     h->alg = alg;
     return SOS_OK;
@@ -449,7 +486,7 @@ int sos_filter_train(sos_handle_t h, const float *sections, int K, const float *
     DeviceGuard g(h->device);
     if (!g.ok) return SOS_EHIP;
     if (n > 0 && K > 0) {
-        rc = prepare_locked(h, sections, K, stream, n);
+        rc = prepare_locked(h, sections, K, stream, n, false);
         if (rc) return rc;
     } else {
         mark_degenerate(h, K);

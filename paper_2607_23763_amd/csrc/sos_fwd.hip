@@ -103,6 +103,8 @@ struct FwdArgs {
     int64_t dstride;        // descriptor slots per section (>= the number of work items)
     unsigned *ctrl;
     unsigned long long timeout_ticks;
+    const float *skip_gate;  // plain, optional: a nonzero word here means the
+                             // whole-cascade kernel filtered this signal
 };
 
 // One unit of work: group g of one signal, drawn as ticket t.
@@ -1126,6 +1128,7 @@ enum : int { KM_FAST = 0, KM_ACC = 1, KM_MIX = 2 };
 template <int KM>
 __device__ __forceinline__ bool plain_launch_serves(const FwdArgs &a)
 {
+    if (a.B == 0 && a.skip_gate && ctab(a.skip_gate)[0] != 0.0f) return false;
     if (KM == KM_MIX || a.B != 0 || a.K <= 0) return true;
     const bool acc = tab_word(reinterpret_cast<const unsigned char *>(a.tabs), HDR_MODE) ==
                      MODE_ACCURATE;
@@ -1804,9 +1807,10 @@ extern "C" hipError_t sos_launch_fwd(int bits, int alg, int L, int N, const floa
                                      const float *zi, float *zf, unsigned long long *desc,
                                      unsigned *ctrl,
                                      unsigned long long timeout_ticks, int64_t grid, float *saved,
-                                     hipStream_t stream)
+                                     const float *skip_gate, hipStream_t stream)
 {
     FwdArgs a{};
+    a.skip_gate = skip_gate;
     a.saved = saved;
     a.saved_stride = n;
     a.x = x;

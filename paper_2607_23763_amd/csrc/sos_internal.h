@@ -28,7 +28,16 @@ hipError_t sos_launch_fwd(int bits, int alg, int L, int N, const float *x, float
                           int64_t groups, const void *tabs, int K, const float *zi, float *zf,
                           unsigned long long *desc, unsigned *ctrl,
                           unsigned long long timeout_ticks, int64_t grid, float *saved,
-                          hipStream_t stream);
+                          const float *skip_gate, hipStream_t stream);
+hipError_t sos_launch_toep_prep(const float *sections, int K, double rho_gate, float *tt,
+                                hipStream_t stream);
+hipError_t sos_launch_toep(const float *x, float *y, int64_t n, const float *tt, int K,
+                           const float *zi, float *zf, unsigned long long *desc, unsigned *ctrl,
+                           unsigned long long timeout_ticks, int64_t grid, hipStream_t stream);
+int sos_toep_capacity(void);
+int sos_toep_group_samples(void);
+int sos_toep_desc_words(void);
+int sos_toep_table_floats(void);
 hipError_t sos_launch_fwd_batched(int bits, int alg, int L, int N, int B, int kmax,
                                   const int32_t *Ks, const int32_t *sec_off, const int64_t *sig_off,
                                   const int64_t *gpre, const int32_t *sigmap,
@@ -110,6 +119,9 @@ struct sos_ctx {
     int prep_bits = 0;
     int prep_alg = 0;                     // solver the tables were prepared for
     double prep_rho = 0.0;                // and their peak-gain threshold
+    bool prep_toep = false;               // block-Toeplitz tables prepared too
+    float *ttab = nullptr;                // block-Toeplitz tables (sos_toep.hip)
+    size_t ttab_cap = 0;
     // uneven-batch work table
     int64_t *gpre = nullptr;
     size_t gpre_cap = 0;
@@ -215,16 +227,37 @@ inline int solver_of(const sos_ctx *h)
     if (const char *e = std::getenv("SOS_ALG")) {
         if (!std::strcmp(e, "ph") || !std::strcmp(e, "PH")) return SOS_ALG_PH;
         if (!std::strcmp(e, "dccr") || !std::strcmp(e, "DCCR")) return SOS_ALG_DCCR;
+        if (!std::strcmp(e, "toeplitz")) return SOS_ALG_TOEPLITZ;
     }
     return SOS_ALG_AUTO;
 }
+
+// Per-section solver behind a handle's solver: the block-Toeplitz choice
+// runs PH wherever the whole-cascade form does not apply.
+inline bool ph_sections(int solver)
+{
+    return solver == SOS_ALG_PH || solver == SOS_ALG_TOEPLITZ;
+}
+
+// Whole-cascade block-Toeplitz path (sos_toep.hip): at most 8 sections (a
+// 16-dimensional state); the automatic choice for K >= 7 on at least 2^27
+// samples, for cascades whose sections all peak at most kToepRhoMax.
+// Measured on MI355X, per call (tables included), against the faster
+// per-section solver: 2^28 samples, K = 8 / 7 / 6 / 5: 279 / 280 / 281 / 280
+// GS/s against 219 / 243 / 273 / 312; at 2^24 samples, K = 8: 100 against
+// 154 (a call costs about 114 us before its first sample: the tables and
+// too few chunks to fill the device).
+constexpr int kToepMaxK = 8;
+constexpr int kToepAutoMinK = 7;
+constexpr int64_t kToepAutoMinN = (int64_t)1 << 27;
+constexpr double kToepRhoMax = 128.0;
 
 // Kernel of the filter launches: ALG_PH for the PH solver, ALG_DCCR for
 // DC-CR and for the automatic choice (signals whose tables took the accurate
 // layout are solved by PH in any launch).
 inline int alg_of(const sos_ctx *h)
 {
-    return solver_of(h) == SOS_ALG_PH ? sosdev::ALG_PH : sosdev::ALG_DCCR;
+    return ph_sections(solver_of(h)) ? sosdev::ALG_PH : sosdev::ALG_DCCR;
 }
 
 // Peak gain of a section's recursive part, 1 / min |A(e^{jw})|, above which
@@ -257,7 +290,7 @@ inline double rho_max_of(const sos_ctx *h)
         const double v = std::strtod(e, nullptr);
         if (v > 0.0) return v;
     }
-    return s == SOS_ALG_PH ? kPhRhoMax : kAutoRhoMax;
+    return ph_sections(s) ? kPhRhoMax : kAutoRhoMax;
 }
 
 // Solver argument of the kernel launchers for tables prepared for `solver`
@@ -266,7 +299,7 @@ inline double rho_max_of(const sos_ctx *h)
 // layout (FP32 with a finite threshold).
 inline int launch_alg(int bits, int solver, double rho_max)
 {
-    const int a = solver == SOS_ALG_PH ? sosdev::ALG_PH : sosdev::ALG_DCCR;
+    const int a = ph_sections(solver) ? sosdev::ALG_PH : sosdev::ALG_DCCR;
     return (bits == 32 && std::isfinite(rho_max)) ? (a | sosdev::ALG_MAYBE_ACC) : a;
 }
 

@@ -133,7 +133,7 @@ int sos_filter_noalloc(const float *sections, int K, const float *x, float *y, i
             return SOS_EHIP;
         const int alg = launch_alg(bits, SOS_ALG_AUTO, kAutoRhoMax);
         if (sos_launch_fwd(bits, alg, t.L, t.N, x, y, n, groups, tabs, K, zi, zf, desc, ctrl,
-                           ticks, grid_of(bits, alg, t.L, t.N), nullptr,
+                           ticks, grid_of(bits, alg, t.L, t.N), nullptr, nullptr,
                            stream) != hipSuccess)
             return SOS_EHIP;
     }

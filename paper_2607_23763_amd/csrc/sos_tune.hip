@@ -237,7 +237,7 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
             // row padding of the model's staging buffer
             const int pad = std::max(0, (lds + 4 * shapes[c].L - 1) / (4 * shapes[c].L) -
                                             shapes[c].N);
-            const double ops = solver_of(h) == SOS_ALG_PH ? 7.0 : 9.0;
+            const double ops = ph_sections(solver_of(h)) ? 7.0 : 9.0;
             const double pred = model_batch_ms(md, mb, shapes[c].L, shapes[c].N, pad, regs, ops,
                                                kTuneGroupUs);
             if (pred >= 0.0) pairs.push_back(Pair{shapes[c], a, pred, padded[c]});
@@ -264,7 +264,10 @@ int sos_tune_batched(sos_handle_t h, int B, int kmax, int64_t total_rows, int64_
         const Tile t = pairs[k].t;
         h->alg = pairs[k].alg;
         const char *an =
-            h->alg == SOS_ALG_PH ? "ph" : (h->alg == SOS_ALG_AUTO ? "auto" : "dccr");
+            h->alg == SOS_ALG_PH ? "ph"
+                                 : (h->alg == SOS_ALG_AUTO
+                                        ? "auto"
+                                        : (h->alg == SOS_ALG_TOEPLITZ ? "toeplitz" : "dccr"));
         if (k >= timed) {
             if (verbose)
                 std::fprintf(stderr, "sos_tune: L=%d N=%d %s predicted %.4f ms (not timed)\n",

@@ -63,9 +63,13 @@ def test_algorithm_selection(env, monkeypatch):
     assert h.algorithm() == "ph"            # the default follows the environment
     monkeypatch.setenv("SOS_ALG", "dccr")
     assert h.algorithm() == "dccr"
+    monkeypatch.setenv("SOS_ALG", "toeplitz")
+    assert h.algorithm() == "toeplitz"
     h.set_algorithm("auto")
     assert h.algorithm() == "auto"          # an explicit choice wins
-    assert P.lib().sos_set_algorithm(h.ptr, 4) == P.SOS_EINVAL
+    h.set_algorithm("toeplitz")
+    assert h.algorithm() == "toeplitz"
+    assert P.lib().sos_set_algorithm(h.ptr, 5) == P.SOS_EINVAL
     assert P.lib().sos_set_algorithm(h.ptr, -1) == P.SOS_EINVAL
     assert P.lib().sos_set_algorithm(None, P.SOS_ALG_PH) == P.SOS_EINVAL
     assert P.lib().sos_get_algorithm(None) == P.SOS_EINVAL

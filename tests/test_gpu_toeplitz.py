@@ -1,0 +1,199 @@
+"""GPU parity of the whole-cascade block-Toeplitz path (sos_toep.hip): the
+multi-block split of Sec. II-B taken over the whole cascade (zero-state
+output T x, column end states Gam x, column and tile scans, a 16-word
+decoupled lookback per chunk of eight groups, y += O s), on the matrix cores. Same FP64 oracle and
+bounds as the per-section kernels: relative L2 error <= 1e-5 up to order 8
+and <= 1e-4 at order 16 (or 10x the sequential FP32 error, where that is
+larger), zf to the same bounds; exact, ragged and one-group lengths, initial
+states, in place, many groups per workgroup, and the automatic choice."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import fp32_bounds, rel_l2, zf_bound
+
+pytestmark = pytest.mark.gpu
+
+CG = 16384   # samples per group of the block-Toeplitz kernel
+CHUNK = 8 * CG   # groups per ticket (one lookback per chunk)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_23763_amd as P
+
+    P.lib()
+    return torch, P
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(torch, P, sos, x, zi=None, algorithm="toeplitz"):
+    h = P.Handle(0, algorithm=algorithm)
+    y, zf = P.sosfilt(dev(torch, x), dev(torch, np.asarray(sos, np.float32)),
+                      None if zi is None else dev(torch, np.asarray(zi, np.float32)), handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    return y.cpu().numpy(), zf.cpu().numpy()
+
+
+def check(sos, x, zi, y, zf, label):
+    K = sos.shape[0]
+    ref, zref = oracle.sosfilt(np.asarray(sos, np.float64), np.asarray(x, np.float64),
+                               None if zi is None else np.asarray(zi, np.float64))
+    ref = np.asarray(ref)
+    zref = np.asarray(zref).reshape(K, 2)
+    by, bz = fp32_bounds(K, sos, x, zi, ref, zref)
+    ey, ez = rel_l2(y, ref), rel_l2(zf, zref)
+    print(label, "y", ey, "bound", by, "zf", ez)
+    assert ey <= by, (label, ey, by)
+    assert ez <= zf_bound(K, by, bz, ref, zref), (label, ez, bz)
+
+
+@pytest.mark.parametrize("kind", ["butter", "random"])
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("n", [5 * CG, 3 * CG + 1237, 100, 1])
+def test_parity_with_initial_state(env, kind, K, n):
+    torch, P = env
+    sos = workloads.sweep_sections(K, kind)
+    x = workloads.signal(n, 40 + K)
+    zi = workloads.initial_state(K, workloads.rng(7 + K))
+    y, zf = run(torch, P, sos, x, zi)
+    check(sos, x, zi, y, zf, "%s K=%d n=%d" % (kind, K, n))
+
+
+@pytest.mark.parametrize("n", [64, 1024, CG - 1, CG, CG + 1, 2 * CG + 64, CHUNK - 1, CHUNK,
+                               CHUNK + 1, 7 * CG + 4097, 2 * CHUNK, 9 * CG + 5])
+def test_lengths_across_column_tile_and_group_edges(env, n):
+    torch, P = env
+    sos = workloads.butterworth_sos(8)
+    x = workloads.signal(n, n % 1000)
+    y, zf = run(torch, P, sos, x)
+    check(sos, x, None, y, zf, "edges n=%d" % n)
+
+
+def test_in_place_with_ragged_end(env):
+    """x == y: every tile is loaded before it is stored, and the final state of
+    a ragged end reads its column's input before the tile is written."""
+    torch, P = env
+    K, n = 6, 4 * CG + 777
+    sos = workloads.sweep_sections(K, "random")
+    x = workloads.signal(n, 11)
+    zi = workloads.initial_state(K, workloads.rng(3))
+    h = P.Handle(0, algorithm="toeplitz")
+    xd = dev(torch, x)
+    zf = torch.empty((K, 2), dtype=torch.float32, device="cuda")
+    P.sosfilt_(xd, dev(torch, sos), y=xd, zi=dev(torch, zi), zf=zf, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    check(sos, x, zi, xd.cpu().numpy(), zf.cpu().numpy(), "in place")
+
+
+@pytest.mark.parametrize("grid", [1, 3])
+def test_many_groups_per_workgroup(env, monkeypatch, grid):
+    """A persistent grid of 1 or 3 workgroups walks 25 chunks of 8 groups:
+    the next group's samples are always in flight, and lookbacks find their
+    predecessors already resolved."""
+    torch, P = env
+    monkeypatch.setenv("SOS_GRID", str(grid))
+    K, n = 8, 200 * CG + 3
+    sos = workloads.sweep_sections(K, "random")
+    x = workloads.signal(n, 5)
+    zi = workloads.initial_state(K, workloads.rng(5))
+    y, zf = run(torch, P, sos, x, zi)
+    check(sos, x, zi, y, zf, "grid %d" % grid)
+
+
+@pytest.mark.parametrize("K", [4, 8])
+def test_full_device_lookback_2p25(env, K):
+    """2^25 samples (256 chunks) on the whole device: every workgroup's
+    lookback walks windows of in-flight predecessors."""
+    torch, P = env
+    n = 1 << 25
+    sos = workloads.butterworth_sos(K)
+    x = workloads.signal(n, 77)
+    y, zf = run(torch, P, sos, x)
+    check(sos, x, None, y, zf, "2^25 K=%d" % K)
+
+
+def test_automatic_choice_takes_the_toeplitz_path(env, monkeypatch):
+    """The automatic solver runs orders 14-16 of at least 2^27 samples through
+    the block-Toeplitz kernel (its output equals an explicit block-Toeplitz
+    handle's bit for bit, and differs from the per-section kernels'), lower
+    orders and shorter signals through the per-section kernels. The check
+    against the oracle uses a 2^20-sample prefix (causal: the same outputs)."""
+    torch, P = env
+    monkeypatch.delenv("SOS_ALG", raising=False)
+    n = (1 << 27) + 12345
+    x = workloads.signal(n, 8)
+    sos = workloads.butterworth_sos(8)
+    ya, _ = run(torch, P, sos, x, algorithm="auto")
+    yt, _ = run(torch, P, sos, x, algorithm="toeplitz")
+    yp, _ = run(torch, P, sos, x, algorithm="ph")
+    assert np.array_equal(ya, yt)
+    assert not np.array_equal(ya, yp)
+    m = 1 << 20
+    ref, _ = oracle.sosfilt(sos.astype(np.float64), x[:m].astype(np.float64))
+    assert rel_l2(ya[:m], ref) <= 1e-4
+    del ya, yt, yp
+    sos6 = workloads.butterworth_sos(6)
+    ya6, _ = run(torch, P, sos6, x, algorithm="auto")
+    yt6, _ = run(torch, P, sos6, x, algorithm="toeplitz")
+    assert not np.array_equal(ya6, yt6)
+    del ya6, yt6
+    # below 2^27 samples the per-section kernels keep even order 16
+    xs = x[: 1 << 26]
+    ys, _ = run(torch, P, sos, xs, algorithm="auto")
+    yts, _ = run(torch, P, sos, xs, algorithm="toeplitz")
+    assert not np.array_equal(ys, yts)
+
+
+def lightly_damped_sections(K=8, r=0.995, seed=9):
+    sos = workloads.random_stable_sos(K, workloads.rng(seed), r_fixed=r)
+    imp = np.zeros(40000)
+    imp[0] = 1.0
+    hr, _ = oracle.sosfilt(sos, imp)
+    sos[0, :3] /= np.sqrt(np.sum(hr ** 2))
+    return sos.astype(np.float32)
+
+
+def test_gate_keeps_resonant_cascades_on_the_section_kernels(env, monkeypatch):
+    """Poles at radius 0.995 (peak gains far above 128): the automatic choice
+    leaves the cascade to the per-section kernels (the accurate layout, as an
+    explicit PH handle), while an explicit block-Toeplitz handle filters it
+    within the order-16 bound or 10x the sequential FP32 error."""
+    torch, P = env
+    monkeypatch.delenv("SOS_ALG", raising=False)
+    sos = lightly_damped_sections()
+    n = (1 << 27) + 5
+    x = workloads.signal(n, 21)
+    ya, _ = run(torch, P, sos, x, algorithm="auto")
+    yp, _ = run(torch, P, sos, x, algorithm="ph")
+    assert rel_l2(ya, yp) < 1e-6
+    yt, _ = run(torch, P, sos, x, algorithm="toeplitz")
+    assert not np.array_equal(yt, ya)
+    del ya, yp, yt
+    m = (1 << 20) + 5
+    yt, zt = run(torch, P, sos, x[:m], algorithm="toeplitz")
+    check(sos, x[:m], None, yt, zt, "damped16 toeplitz")
+
+
+def test_unstable_section_is_reported(env):
+    """A section on the stability boundary is never taken by the block-Toeplitz
+    kernel: the per-section kernels run and report it."""
+    torch, P = env
+    sos = workloads.butterworth_sos(4).copy()
+    sos[2, 5] = 1.0           # a2 = 1: poles on the unit circle
+    x = workloads.signal(2 * CG, 1)
+    h = P.Handle(0, algorithm="toeplitz")
+    y, _ = P.sosfilt(dev(torch, x), dev(torch, sos), handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_EUNSTABLE
+    assert torch.isnan(y).all().item()
