@@ -9,8 +9,10 @@ whole step (coefficient preparation + filter kernel) with input and output
 resident in HBM, in GS/s, with the divide-and-conquer cyclic-reduction
 section solver (--alg ph: the PH solver). The other orders are reported under
 "sweep", each timed with both solvers and with the library default (the
-solver chosen per signal); alu_roof_frac is against the unpacked FP32 rate
-(78.6 TFLOP/s), which is what the kernels are built for.
+solver chosen per signal), and with the whole-cascade block-Toeplitz kernel
+on the matrix cores ("toeplitz_*": its MFMA rate against the 157.3 TFLOP/s
+dense FP32 MFMA peak); alu_roof_frac is against the unpacked FP32 rate
+(78.6 TFLOP/s), which is what the per-section kernels are built for.
 
 Timing: W untimed warm-up steps, then exactly K timed steps between
 torch.cuda.synchronize() calls; two rotating input/output buffer pairs of
@@ -45,12 +47,6 @@ Beside the headline, on the same GPU (skipped with --quick):
   with twice the lanes and half the samples per lane at the same group size
   (DTCR's extra waves without its per-section hand-off) against the base
   tile, 2^14..2^18 samples, orders 2 and 16, both solvers.
-* "toeplitz_mfma_bound": a lower bound for a block-Toeplitz (matrix-core)
-  form of the whole cascade, not part of the filter: the FP32 library GEMM
-  that maps every 64-sample chunk of a 2^28-sample signal through a 64 x 64
-  lower-triangular operator (the zero-state response), and through 80 x 64
-  (plus the 16 terminal states of an order-16 cascade), beside the order-16
-  filter kernel.
 
 Prints one JSON line on stdout. `python bench.py --gpus N` with N > 1 exits:
 this build runs on one GPU.
@@ -77,6 +73,12 @@ OPS_PER_SAMPLE_SECTION = {"dccr": 9, "ph": 7}
 # The kernels are built without packed FP32 instructions, so their ALU roof is
 # the unpacked rate: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP32_UNPACKED_PEAK_TFLOPS = 78.6
+# Whole-cascade block-Toeplitz kernel: MFMA instructions (16x16x4 FP32, 2048
+# flops each) per 1024 samples: 32 in the first sweep (Gam x, column scan), 88
+# in the second (T x on the lower block triangle, Gam x, column scan, O s), 1
+# for the tile scans; the same whatever the order (the state is padded to 16)
+TOEP_MFMA_FLOPS_PER_SAMPLE = 121 * 2048 / 1024
+FP32_MFMA_PEAK_TFLOPS = 157.3
 FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X with packed FP32 (context only)
 KERNEL_SOURCES = ("paper_2607_23763_amd/csrc/sos_fwd.hip", "paper_2607_23763_amd/csrc/sos_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sos_fwd_kernel_k1_2p28.json")
@@ -232,42 +234,6 @@ def plateau_of(pts):
     points (GS/s)."""
     v = [p["kernel_GS_per_s"] for p in pts if p["log2n"] in (24, 25)]
     return round(sum(v) / len(v), 2) if len(v) == 2 else None
-
-
-def bench_toeplitz_bound(torch, n, order16_kernel_gss, log):
-    """Chunk-by-operator products of a whole block-Toeplitz cascade form, as
-    FP32 library GEMMs (matrix cores), timed with HIP events: a lower bound
-    for that design's zero-state stage, with nothing fused."""
-    prev = torch.backends.cuda.matmul.allow_tf32
-    torch.backends.cuda.matmul.allow_tf32 = False
-    g = torch.Generator(device="cuda").manual_seed(7)
-    x = [torch.randn(n, device="cuda", generator=g) for _ in range(2)]
-    out = {"chunk": 64, "n": n, "order16_filter_kernel_GS_per_s": order16_kernel_gss}
-    for rows in (64, 80):
-        op = torch.randn(rows, 64, device="cuda", generator=g)
-        if rows == 64:
-            op = op.tril()
-        opt = op.t().contiguous()
-        ys = [torch.empty(n // 64, rows, device="cuda") for _ in range(2)]
-        xv = [v.view(-1, 64) for v in x]
-        for i in range(5):
-            torch.mm(xv[i % 2], opt, out=ys[i % 2])
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for i in range(20):
-            torch.mm(xv[i % 2], opt, out=ys[i % 2])
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 20
-        out["rows_%d" % rows] = {"ms": round(ms, 4), "GS_per_s": round(n / (ms * 1e-3) / 1e9, 1),
-                                 "TFLOP_per_s": round(2.0 * n * rows / (ms * 1e-3) / 1e12, 1)}
-        del ys
-    torch.backends.cuda.matmul.allow_tf32 = prev
-    del x
-    torch.cuda.empty_cache()
-    log("toeplitz_mfma_bound", out)
-    return out
 
 
 def time_copy(torch, P, xs, ys, steps, warmup):
@@ -669,9 +635,12 @@ def main():
                     help="profile helper: the server's tile with --only-served")
     ap.add_argument("--only-batched", action="store_true",
                     help="profile helper: only the uneven-batch leg, printed as its own JSON")
-    ap.add_argument("--alg", default="dccr", choices=("dccr", "ph"),
-                    help="section solver of the headline (the sweep times both)")
+    ap.add_argument("--alg", default="dccr", choices=("dccr", "ph", "toeplitz"),
+                    help="section solver of the headline (the sweep times all); "
+                         "toeplitz: with --only-k only (profile helper)")
     args = ap.parse_args()
+    if args.alg == "toeplitz" and not args.only_k:
+        ap.error("--alg toeplitz is a profile helper: give --only-k")
 
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
@@ -740,6 +709,7 @@ def main():
         other = "ph" if args.alg == "dccr" else "dccr"
         h2 = P.Handle(0, tile=tile, algorithm=other)
         h3 = P.Handle(0, tile=tile)         # the library default: per-signal choice
+        h4 = P.Handle(0, tile=tile, algorithm="toeplitz")   # whole-cascade MFMA form
         for kind in ("butter", "random"):
             result_sweep[kind] = {}
             for K in (1, 2, 4, 8):
@@ -750,6 +720,9 @@ def main():
                 assert h2.last_error() == P.SOS_OK
                 ms3, mk3 = time_steps(torch, P, h3, sos_d, xs, ys, max(10, args.steps // 2), 3)
                 assert h3.last_error() == P.SOS_OK
+                ms4, mk4 = time_steps(torch, P, h4, sos_d, xs, ys, max(10, args.steps // 2), 3)
+                assert h4.last_error() == P.SOS_OK
+                mf = gss(mk4) * TOEP_MFMA_FLOPS_PER_SAMPLE / 1e3
                 tf = gss(mk) * 2 * OPS_PER_SAMPLE_SECTION[args.alg] * K / 1e3
                 tf2 = gss(mk2) * 2 * OPS_PER_SAMPLE_SECTION[other] * K / 1e3
                 result_sweep[kind][str(K)] = {
@@ -763,10 +736,15 @@ def main():
                     other + "_kernel_GS_per_s": round(gss(mk2), 2),
                     other + "_alu_roof_frac": round(tf2 / FP32_UNPACKED_PEAK_TFLOPS, 4),
                     "auto_GS_per_s": round(gss(ms3), 2),
-                    "auto_kernel_GS_per_s": round(gss(mk3), 2)}
+                    "auto_kernel_GS_per_s": round(gss(mk3), 2),
+                    "toeplitz_GS_per_s": round(gss(ms4), 2),
+                    "toeplitz_kernel_GS_per_s": round(gss(mk4), 2),
+                    "toeplitz_mfma_TFLOPs": round(mf, 2),
+                    "toeplitz_mfma_roof_frac": round(mf / FP32_MFMA_PEAK_TFLOPS, 4)}
                 log(kind, K, result_sweep[kind][str(K)])
         h2.close()
         h3.close()
+        h4.close()
 
     # length curves and the paper's plateau (mean of the 2^24 and 2^25
     # points), Butterworth, under the paper's protocol: orders 2 and 16 over
@@ -811,8 +789,6 @@ def main():
         extra["batched"] = bench_batched(torch, P, workloads, np, log)
         extra["served"] = bench_served(torch, P, workloads, np, log)
         extra["fwd_bwd"] = bench_fwd_bwd(torch, P, workloads, np, log)
-        k16 = (result_sweep or {}).get("butter", {}).get("8", {}).get("kernel_GS_per_s")
-        extra["toeplitz_mfma_bound"] = bench_toeplitz_bound(torch, n, k16, log)
 
     cpu = None
     cpu_extra = None
