@@ -736,8 +736,12 @@ __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)
     while (t < a.total) {
         const int64_t gfirst = t * NG;
         const int ng = (int)(a.groups - gfirst < NG ? a.groups - gfirst : NG);
-        // ---- sweep 1: tile totals from rest
-        for (int j = 0; j < ng; ++j) {
+        // ---- sweep 1: tile totals from rest; the columns' scans are kept
+        // for the second sweep
+        v4f Pk[NG][TPW];
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            if (j >= ng) break;
             v4f gop[4], aop[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -760,8 +764,8 @@ __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)
             for (int tw = 0; tw < TPW; ++tw) load_tile(xb[tw], a.x, a.n, tile0(nxt, tw), lane);
 #pragma unroll
             for (int tw = 0; tw < TPW; ++tw) {
-                const v4f P = scan16(U[tw], aop);
-                if (n16 == 15) *reinterpret_cast<v4f *>(&aggs[j][wv * TPW + tw][4 * g4]) = P;
+                Pk[j][tw] = scan16(U[tw], aop);
+                if (n16 == 15) *reinterpret_cast<v4f *>(&aggs[j][wv * TPW + tw][4 * g4]) = Pk[j][tw];
             }
         }
         lds_sync();
@@ -839,18 +843,15 @@ __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)
         }
         // ---- sweep 2: outputs
         int64_t tn = a.total;
-        for (int j = 0; j < ng; ++j) {
-            const int64_t grp = gfirst + j;
-            v4f Y[TPW][4], P[TPW];
-            {
-                v4f top[4], gop[4], aop[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    top[i] = opnd(0, i);
-                    gop[i] = opnd(1, i);
-                    aop[i] = opnd(3, i);
-                }
-                v4f U[TPW];
+        for (int j = 0; j < NG; ++j) {
+            if (j >= ng) break;
+            const int64_t grp = gfirst + j;
+            v4f Y[TPW][4];
+            {
+                v4f top[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) top[i] = opnd(0, i);
 #pragma unroll
                 for (int tw = 0; tw < TPW; ++tw) {
 #pragma unroll
@@ -862,11 +863,6 @@ __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)
 #pragma unroll
                             for (int s = 0; s < 4; ++s)
                                 Y[tw][r] = mfma4(top[r - b][s], xb[tw][b][s], Y[tw][r]);
-                    U[tw] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) U[tw] = mfma4(gop[b][s], xb[tw][b][s], U[tw]);
                 }
                 if (j == 0) {
                     // the chunk's states (and the next ticket) from wave 0
@@ -882,9 +878,8 @@ __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)
                     for (int tw = 0; tw < TPW; ++tw)
                         load_tile(xb[tw], a.x, a.n, tile0(nxt, tw), lane);
                 }
-#pragma unroll
-                for (int tw = 0; tw < TPW; ++tw) P[tw] = scan16(U[tw], aop);
             }
+            const v4f (&P)[TPW] = Pk[j];
             v4f oop[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) oop[i] = opnd(2, i);
