@@ -63,7 +63,7 @@ constexpr int TPW = 2;           // tiles per wave
 constexpr int NT = WT * TPW;     // tiles per group
 constexpr int CG = TS * NT;      // samples per group
 constexpr int NG = 8;            // groups per chunk (one ticket, one lookback)
-constexpr int kMaxDist = 64;     // lookback reach in chunks: powers H^d, d < kMaxDist
+constexpr int kMaxDist = 32;     // lookback reach in chunks: powers H^d, d < kMaxDist
 constexpr int kDescWords = 32;   // per group: 16 aggregate words, 16 inclusive words
 constexpr int kPowStride = 260;  // LDS stride of a 16 x 16 power (bank-spread across lanes)
 static_assert(NT == 16, "the group-level scan covers one 16-column MFMA tile");
@@ -293,8 +293,9 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     }
     __syncthreads();
     tt[TT_G1 + tid] = (float)sh.pw[8][ent(tid)];
-    // chunk map H = G^NG by squaring (work[18]), then its powers H^d, d < 64,
-    // as (H^8)^a H^b: low factors work[0..7], high factors work[8..15]
+    // chunk map H = G^NG by squaring (work[18]), then its powers H^d,
+    // d < kMaxDist, as (H^8)^a H^b: low factors work[0..7], high factors
+    // work[8..11]
     sh.work[18][ent(tid)] = sh.pw[8][ent(tid)];
     __syncthreads();
     for (int k = 1; k < NG; k <<= 1) {
@@ -320,10 +321,8 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     mm16(sh.work[9], sh.work[9], sh.work[10], tid);        // H^16
     __syncthreads();
     mm16(sh.work[10], sh.work[9], sh.work[11], tid);       // H^24
-    mm16(sh.work[10], sh.work[10], sh.work[12], tid);      // H^32
     __syncthreads();
-    for (int c = 0; c < 3; ++c) mm16(sh.work[12], sh.work[9 + c], sh.work[13 + c], tid);   // H^40..56
-    __syncthreads();
+    static_assert(kMaxDist <= 32, "high factors H^0, H^8, H^16, H^24");
     for (int d = 0; d < kMaxDist; ++d) {
         const double *Hi = sh.work[8 + (d >> 3)];
         const double *Lo = sh.work[d & 7];
@@ -476,8 +475,9 @@ __device__ __forceinline__ unsigned long long get_word(const unsigned long long 
 // Decoupled lookback of chunk t (t > 0) over 16-word descriptors, by one
 // whole wave; leaves the chunk's incoming state in sg[16].
 //
-// Each round every lane reads one of the 64 nearest unconsumed predecessors
-// (its 16 aggregate and 16 inclusive words); the wave takes the longest
+// Each round lane p reads the unconsumed predecessor p places back (up to
+// kMaxDist chunks back; its 16 aggregate and 16 inclusive words); the wave
+// takes the longest
 // ready prefix and, when an inclusive state lies in it, ends with that state.
 // A consumed state at distance d reaches this chunk through H^d (H the state
 // map across a chunk), from the LDS copy of the table: each lane forms H^d v
