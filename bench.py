@@ -74,10 +74,10 @@ OPS_PER_SAMPLE_SECTION = {"dccr": 9, "ph": 7}
 # the unpacked rate: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # Whole-cascade block-Toeplitz kernel: MFMA instructions (16x16x4 FP32, 2048
-# flops each) per 1024 samples: 32 in the first sweep (Gam x, column scan), 88
-# in the second (T x on the lower block triangle, Gam x, column scan, O s), 1
-# for the tile scans; the same whatever the order (the state is padded to 16)
-TOEP_MFMA_FLOPS_PER_SAMPLE = 121 * 2048 / 1024
+# flops each) per 1024 samples: 32 in the first sweep (Gam x, column scan), 56
+# in the second (T x on the lower block triangle, O s), 1 for the tile scans;
+# the same whatever the order (the state is padded to 16)
+TOEP_MFMA_FLOPS_PER_SAMPLE = 89 * 2048 / 1024
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP32_PACKED_PEAK_TFLOPS = 157.3   # MI355X with packed FP32 (context only)
 KERNEL_SOURCES = ("paper_2607_23763_amd/csrc/sos_fwd.hip", "paper_2607_23763_amd/csrc/sos_device.h")

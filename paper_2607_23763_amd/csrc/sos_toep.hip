@@ -16,11 +16,11 @@
 // consecutive samples) is one MFMA operand, the columns being the MFMA's N
 // dimension. The per-sample cost no longer grows with K (about 40 MACs per
 // sample for T and 16 each for Gam and O, against about 8 FMAs per sample and
-// section for the per-section recurrences), which is why this path serves
-// orders 8-16.
+// section for the per-section recurrences), which is why this path serves the
+// highest orders.
 //
-// Group structure (one workgroup of 8 waves, two tiles per wave, C = 16384
-// samples):
+// Group structure (one workgroup of 8 waves, two tiles per wave, CG = 16384
+// samples per group, NG = 8 groups per chunk, one chunk per ticket):
 //   1. Each wave forms T x and Gam x for its tiles straight from the 128-bit
 //      loads: lane l holds samples 16b + 4(l/16) + {0..3} of column l%16
 //      for blocks b = 0..3, which is exactly the MFMA's B operand for the
@@ -31,14 +31,15 @@
 //      end states from rest: each level shifts the 16 x 16 state matrix by
 //      2^j columns with one DPP row shift per register (the 16 columns are
 //      the 16 lanes of a DPP row) and adds A^(2^j) times it with four MFMAs.
-//   3. Wave 0 scans the 16 tile totals the same way (powers of Phi^1024),
-//      publishes the group's aggregate (16 words), resolves the group's
-//      incoming state by decoupled lookback over 16-word descriptors
-//      (Sec. IV-B, one lookback per group instead of one per section), and
-//      publishes the group's inclusive state.
-//   4. Every tile's incoming state, then every column's, follow from powers
-//      of Phi^1024 and Phi^64 applied to the resolved state; y += O s with
-//      four MFMAs per 16 output rows, and the tile is stored.
+//   3. Wave 0 scans each group's 16 tile totals the same way (powers of
+//      Phi^1024), chains the chunk's groups into its end state from rest,
+//      publishes that aggregate (16 words), resolves the chunk's incoming
+//      state by decoupled lookback over 16-word descriptors (Sec. IV-B; one
+//      lookback per chunk instead of one per group and section), publishes
+//      the chunk's inclusive state and derives every tile's incoming state.
+//   4. Every column's incoming state follows from its tile's through powers
+//      of Phi^64; y += O s with four MFMAs per 16 output rows, and the tile
+//      is stored.
 // Conditioning: the state is scaled by a power-of-two diagonal D (exact) that
 // balances Gam's rows against O's columns, so every table entry is O(1)
 // whatever the scaling of the TDF-II states. The tables are built in FP64 by
@@ -671,18 +672,17 @@ __device__ __forceinline__ v4f mat_rows(const float *Mx, const float *v_lds, int
 // One chunk of NG groups per ticket, in two sweeps with no barrier inside a
 // sweep:
 //   sweep 1: per group and tile, the columns' end states from rest (Gam x,
-//     column scan); each tile's total is kept in LDS for the whole chunk;
+//     column scan); each tile's total is kept in LDS and each column scan in
+//     registers for the whole chunk;
 //   one barrier; then wave 0 alone: the tile scans of the chunk's groups,
 //     the chunk's end state from rest (its aggregate), the lookback for its
 //     incoming state, the inclusive state, and every tile's incoming state
 //     (LDS), then a flag; meanwhile the other waves already start sweep 2;
-//   sweep 2: per group, T x, Gam x and the column scan again (they need no
-//     state), then, once the flag is set, the columns' incoming states,
-//     y += O s, store.
-// The input is read twice (the second read mostly from the device's last
-// level cache), the output written once; the next group's samples are always
-// in flight while the current one is processed, and wave 0's serial work
-// overlaps the MFMA work of the wave sharing its SIMD.
+//   sweep 2: per group, T x (it needs no state), then, once the flag is set,
+//     the columns' incoming states, y += O s, store.
+// The input is read twice, the output written once; the next group's samples
+// are always in flight while the current one is processed, and wave 0's
+// serial work overlaps the MFMA work of the wave sharing its SIMD.
 __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)))
     sos_toep_kernel(ToepArgs a)
 {
