@@ -171,9 +171,9 @@ int sos_get_precision(sos_handle_t h);
  * Its cost per sample does not grow with K, but a call has a fixed cost of
  * about 0.1 ms (its tables, and chunks of 131072 samples that must fill the
  * device). SOS_ALG_AUTO takes it for plain FP32 forward calls with K >= 7 on
- * at least 2^27 samples when every section's peak gain is at most 128
- * (decided on the device by the table preparation; other signals run as
- * before, in the same call).
+ * at least 2^26 samples, or K = 6 on at least 2^27, when every section's
+ * peak gain is at most 128 (decided on the device by the table preparation;
+ * other signals run as before, in the same call).
  * SOS_ALG_TOEPLITZ takes it for every plain FP32 forward call with K <= 8,
  * whatever the gains; its batched, training, adjoint and served launches,
  * and FP64 ones, run PH. Results follow the same conventions (zi, zf, in

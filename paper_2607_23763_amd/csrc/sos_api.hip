@@ -61,10 +61,11 @@ int check_signal(const float *x, const float *y, int64_t n)
     return SOS_OK;
 }
 
-// Shortest signal a plain launch of `solver` filters by the whole-cascade path.
-int64_t toep_min_n(int solver)
+// Shortest signal a plain launch of `solver` filters by the whole-cascade path
+// for K sections.
+int64_t toep_min_n(int solver, int K)
 {
-    return solver == SOS_ALG_TOEPLITZ ? 1 : kToepAutoMinN;
+    return solver == SOS_ALG_TOEPLITZ ? 1 : toep_auto_min_n(K);
 }
 
 // Tables for `sections` at the handle's shape (or, without one, the shape for
@@ -92,8 +93,8 @@ int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream,
     // preparation decides on the device whether it does (gate word)
     const int s = h->prep_alg;
     if (plain && bits == 32 && K >= 1 && K <= kToepMaxK &&
-        (s == SOS_ALG_TOEPLITZ || (s == SOS_ALG_AUTO && K >= kToepAutoMinK)) &&
-        (n < 0 || n >= toep_min_n(s))) {
+        (s == SOS_ALG_TOEPLITZ || (s == SOS_ALG_AUTO && toep_auto_min_n(K) != INT64_MAX)) &&
+        (n < 0 || n >= toep_min_n(s, K))) {
         rc = ensure_buf(h->ttab, h->ttab_cap, (size_t)sos_toep_table_floats(), stream);
         if (rc) return rc;
         if (sos_launch_toep_prep(sections, K, s == SOS_ALG_TOEPLITZ ? HUGE_VAL : kToepRhoMax,
@@ -137,7 +138,7 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     // the whole-cascade kernel first when its tables are there: it filters
     // the signal unless the preparation's gate sent it to the per-section
     // kernels, which then skip it (and otherwise filter it as before)
-    const bool toep = h->prep_toep && !saved && n >= toep_min_n(h->prep_alg);
+    const bool toep = h->prep_toep && !saved && n >= toep_min_n(h->prep_alg, K);
     const int64_t tgroups = toep ? (n + sos_toep_group_samples() - 1) / sos_toep_group_samples() : 0;
     size_t words = (size_t)groups * (size_t)K * 4u;
     if (toep) words = std::max(words, (size_t)tgroups * (size_t)sos_toep_desc_words());

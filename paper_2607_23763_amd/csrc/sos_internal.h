@@ -240,16 +240,24 @@ inline bool ph_sections(int solver)
 }
 
 // Whole-cascade block-Toeplitz path (sos_toep.hip): at most 8 sections (a
-// 16-dimensional state); the automatic choice for K >= 7 on at least 2^27
-// samples, for cascades whose sections all peak at most kToepRhoMax.
-// Measured on MI355X, per call (tables included), against the faster
-// per-section solver: 2^28 samples, K = 8 / 7 / 6 / 5: 279 / 280 / 281 / 280
-// GS/s against 219 / 243 / 273 / 312; at 2^24 samples, K = 8: 100 against
-// 154 (a call costs about 114 us before its first sample: the tables and
-// too few chunks to fill the device).
+// 16-dimensional state), for cascades whose sections all peak at most
+// kToepRhoMax. The automatic choice takes it where it was measured faster
+// than the faster per-section solver (MI355X, per call, tables included):
+// K >= 7 from 2^26 samples (K = 8 / 7: +18 / +6 % at 2^26, +28 / +15 % at
+// 2^27, +34 / +21 % at 2^28) and K = 6 from 2^27 (+3 %, +7 % at 2^28; -5 %
+// at 2^26); K = 5 stays on the section kernels (-9 % at 2^28). A call costs
+// about 0.1 ms before its first sample (the tables, and chunks that must
+// fill the device), which is what shorter signals cannot amortise.
 constexpr int kToepMaxK = 8;
-constexpr int kToepAutoMinK = 7;
-constexpr int64_t kToepAutoMinN = (int64_t)1 << 27;
+
+// Shortest signal the automatic choice filters by the block-Toeplitz path for
+// K sections (none: INT64_MAX).
+inline int64_t toep_auto_min_n(int K)
+{
+    if (K >= 7 && K <= kToepMaxK) return (int64_t)1 << 26;
+    if (K == 6) return (int64_t)1 << 27;
+    return INT64_MAX;
+}
 constexpr double kToepRhoMax = 128.0;
 
 // Kernel of the filter launches: ALG_PH for the PH solver, ALG_DCCR for

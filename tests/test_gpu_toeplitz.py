@@ -124,11 +124,12 @@ def test_full_device_lookback_2p25(env, K):
 
 
 def test_automatic_choice_takes_the_toeplitz_path(env, monkeypatch):
-    """The automatic solver runs orders 14-16 of at least 2^27 samples through
-    the block-Toeplitz kernel (its output equals an explicit block-Toeplitz
-    handle's bit for bit, and differs from the per-section kernels'), lower
-    orders and shorter signals through the per-section kernels. The check
-    against the oracle uses a 2^20-sample prefix (causal: the same outputs)."""
+    """The automatic solver runs orders 14-16 of at least 2^26 samples and
+    order 12 of at least 2^27 through the block-Toeplitz kernel (its output
+    equals an explicit block-Toeplitz handle's bit for bit, and differs from
+    the per-section kernels'), lower orders and shorter signals through the
+    per-section kernels. The check against the oracle uses a 2^20-sample
+    prefix (causal: the same outputs)."""
     torch, P = env
     monkeypatch.delenv("SOS_ALG", raising=False)
     n = (1 << 27) + 12345
@@ -146,10 +147,18 @@ def test_automatic_choice_takes_the_toeplitz_path(env, monkeypatch):
     sos6 = workloads.butterworth_sos(6)
     ya6, _ = run(torch, P, sos6, x, algorithm="auto")
     yt6, _ = run(torch, P, sos6, x, algorithm="toeplitz")
-    assert not np.array_equal(ya6, yt6)
-    del ya6, yt6
-    # below 2^27 samples the per-section kernels keep even order 16
+    assert np.array_equal(ya6, yt6)
+    sos5 = workloads.butterworth_sos(5)
+    ya5, _ = run(torch, P, sos5, x, algorithm="auto")
+    yt5, _ = run(torch, P, sos5, x, algorithm="toeplitz")
+    assert not np.array_equal(ya5, yt5)
+    del ya6, yt6, ya5, yt5
+    # order 12 below 2^27 samples, order 16 below 2^26: the section kernels
     xs = x[: 1 << 26]
+    ys, _ = run(torch, P, sos6, xs, algorithm="auto")
+    yts, _ = run(torch, P, sos6, xs, algorithm="toeplitz")
+    assert not np.array_equal(ys, yts)
+    xs = x[: 1 << 25]
     ys, _ = run(torch, P, sos, xs, algorithm="auto")
     yts, _ = run(torch, P, sos, xs, algorithm="toeplitz")
     assert not np.array_equal(ys, yts)
