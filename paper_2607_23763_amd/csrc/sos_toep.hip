@@ -103,14 +103,30 @@ constexpr int RS = 17;
 constexpr int MSZ = 16 * RS;
 __device__ __forceinline__ int ent(int tid) { return (tid >> 4) * RS + (tid & 15); }
 
-// Z = X Y, entry (tid / 16, tid % 16) by thread tid of a 256-thread block.
-__device__ inline void mm16(const double *X, const double *Y, double *Z, int tid)
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Z = X Y by one wave on the FP64 matrix cores (v_mfma_f64_16x16x4f64, four
+// k-steps): lane l supplies X[l%16][4s + l/16] and Y[4s + l/16][l%16] at step
+// s and receives Z[4 r + l/16][l%16] in register r (the FP64 instruction's
+// result layout, unlike the FP32 one's 4 (l/16) + r); each lane reads 8
+// doubles from LDS instead of the 32 a product per thread reads.
+__device__ inline v4d mm16m_acc(const double *X, const double *Y, int lane)
 {
-    const int i = tid >> 4, j = tid & 15;
-    double acc = 0.0;
+    const int n = lane & 15, g = lane >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc = fma(X[i * RS + k], Y[k * RS + j], acc);
-    Z[i * RS + j] = acc;
+    for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[n * RS + 4 * s + g], Y[(4 * s + g) * RS + n],
+                                                   acc, 0, 0, 0);
+    return acc;
+}
+
+__device__ inline void mm16m(const double *X, const double *Y, double *Z, int lane)
+{
+    const v4d acc = mm16m_acc(X, Y, lane);
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Z[(4 * r + g) * RS + n] = acc[r];
 }
 
 __device__ inline void ident16(double *Z, int tid)
@@ -143,6 +159,7 @@ struct PrepLds {
     double v[64][16];         // Phi^i gamma
     double o[64][16];         // c Phi^i
     double dsc[16];           // state scale D
+    double h[64];             // the cascade's impulse response
     double pw[9][MSZ];        // A^(1,2,4,8), B^(1,2,4,8), G (scaled basis)
     double work[32][MSZ];     // power tables, reused
     int gate;
@@ -155,6 +172,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
 {
     __shared__ PrepLds sh;
     const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;   // 16 x 16 products: one wave each
     if (tid == 0) sh.gate = (K >= 1 && K <= 8) ? 1 : 0;
     for (int e = tid; e < MSZ; e += 256) sh.phi[e] = 0.0;
     if (tid < 16) { sh.gam[tid] = 0.0; sh.crow[tid] = 0.0; }
@@ -212,7 +230,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     sh.q[0][ent(tid)] = sh.phi[ent(tid)];
     __syncthreads();
     for (int j = 0; j < 6; ++j) {
-        mm16(sh.q[j], sh.q[j], sh.q[j + 1], tid);
+        if (wv == 0) mm16m(sh.q[j], sh.q[j], sh.q[j + 1], lane);
         __syncthreads();
     }
     // v_i = Phi^i gamma and o_i = c Phi^i, i < 64, by doubling
@@ -237,6 +255,13 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
             }
         }
         __syncthreads();
+    }
+    // impulse response h[0] = d, h[m] = c Phi^(m-1) gamma
+    if (tid < 64) {
+        double acc = tid == 0 ? sh.dd : 0.0;
+        if (tid > 0)
+            for (int k = 0; k < 16; ++k) acc = fma(sh.o[tid - 1][k], sh.gam[k], acc);
+        sh.h[tid] = acc;
     }
     // balancing scale: a power of two per state entry equalising the energy
     // of its Gam row and O column over one column (exact in every format)
@@ -271,7 +296,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     __syncthreads();
     // A^2, A^4, A^8, B = A^16, B^2, B^4, B^8, G = B^16 = Phi'^C
     for (int j = 0; j < 8; ++j) {
-        mm16(sh.pw[j], sh.pw[j], sh.pw[j + 1], tid);
+        if (wv == 0) mm16m(sh.pw[j], sh.pw[j], sh.pw[j + 1], lane);
         __syncthreads();
     }
     // column powers A^c (work[0..15]) and tile powers B^t (work[16..31])
@@ -282,9 +307,12 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     __syncthreads();
     for (int j = 1; j < 4; ++j) {
         const int half = 1 << j;
-        for (int c = 0; c < half; ++c) {
-            mm16(sh.pw[j], sh.work[c], sh.work[half + c], tid);
-            mm16(sh.pw[4 + j], sh.work[16 + c], sh.work[16 + half + c], tid);
+        for (int p = wv; p < 2 * half; p += 4) {   // products spread over the waves
+            const int c = p >> 1;
+            if (p & 1)
+                mm16m(sh.pw[4 + j], sh.work[16 + c], sh.work[16 + half + c], lane);
+            else
+                mm16m(sh.pw[j], sh.work[c], sh.work[half + c], lane);
         }
         __syncthreads();
     }
@@ -300,7 +328,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     sh.work[18][ent(tid)] = sh.pw[8][ent(tid)];
     __syncthreads();
     for (int k = 1; k < NG; k <<= 1) {
-        mm16(sh.work[18], sh.work[18], sh.work[19], tid);
+        if (wv == 0) mm16m(sh.work[18], sh.work[18], sh.work[19], lane);
         __syncthreads();
         sh.work[18][ent(tid)] = sh.work[19][ent(tid)];
         __syncthreads();
@@ -309,29 +337,26 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     ident16(sh.work[8], tid);
     sh.work[1][ent(tid)] = sh.work[18][ent(tid)];
     __syncthreads();
-    mm16(sh.work[18], sh.work[18], sh.work[16], tid);      // H^2
+    if (wv == 0) mm16m(sh.work[18], sh.work[18], sh.work[16], lane);      // H^2
     __syncthreads();
-    mm16(sh.work[16], sh.work[16], sh.work[17], tid);      // H^4
-    mm16(sh.work[16], sh.work[1], sh.work[3], tid);        // H^3
+    if (wv == 0) mm16m(sh.work[16], sh.work[16], sh.work[17], lane);      // H^4
+    if (wv == 1) mm16m(sh.work[16], sh.work[1], sh.work[3], lane);        // H^3
     sh.work[2][ent(tid)] = sh.work[16][ent(tid)];
     __syncthreads();
-    for (int c = 0; c < 4; ++c) mm16(sh.work[17], sh.work[c], sh.work[4 + c], tid);   // H^4..7
+    mm16m(sh.work[17], sh.work[wv], sh.work[4 + wv], lane);               // H^4..7
     __syncthreads();
-    mm16(sh.work[17], sh.work[17], sh.work[9], tid);       // H^8
+    if (wv == 0) mm16m(sh.work[17], sh.work[17], sh.work[9], lane);       // H^8
     __syncthreads();
-    mm16(sh.work[9], sh.work[9], sh.work[10], tid);        // H^16
+    if (wv == 0) mm16m(sh.work[9], sh.work[9], sh.work[10], lane);        // H^16
     __syncthreads();
-    mm16(sh.work[10], sh.work[9], sh.work[11], tid);       // H^24
+    if (wv == 0) mm16m(sh.work[10], sh.work[9], sh.work[11], lane);       // H^24
     __syncthreads();
     static_assert(kMaxDist <= 32, "high factors H^0, H^8, H^16, H^24");
-    for (int d = 0; d < kMaxDist; ++d) {
-        const double *Hi = sh.work[8 + (d >> 3)];
-        const double *Lo = sh.work[d & 7];
-        const int i = tid >> 4, j = tid & 15;
-        double acc = 0.0;
+    for (int d = wv; d < kMaxDist; d += 4) {
+        const v4d acc = mm16m_acc(sh.work[8 + (d >> 3)], sh.work[d & 7], lane);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc = fma(Hi[i * RS + k], Lo[k * RS + j], acc);
-        tt[TT_HPOW + d * 256 + tid] = (float)acc;
+        for (int r = 0; r < 4; ++r)
+            tt[TT_HPOW + d * 256 + (4 * r + (lane >> 4)) * 16 + (lane & 15)] = (float)acc[r];
     }
     // per-lane MFMA operands: lane l = 16 g + n, k-step s
     for (int e = tid; e < 5 * 1024; e += 256) {
@@ -341,12 +366,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
         double val;
         if (blk == 0) {            // T: h[16 delta + n - 4g - s]
             const int m = 16 * idx + n - 4 * g - s;
-            val = m < 0 ? 0.0 : (m == 0 ? sh.dd : 0.0);
-            if (m > 0) {
-                double acc = 0.0;
-                for (int k = 0; k < 16; ++k) acc = fma(sh.o[m - 1][k], sh.gam[k], acc);
-                val = acc;
-            }
+            val = m < 0 ? 0.0 : sh.h[m];
         } else if (blk == 1) {     // Gam'[n][16 b + 4 g + s] = (Phi^(63-k) gamma)[n] / D[n]
             const int k = 16 * idx + 4 * g + s;
             val = sh.v[63 - k][n] / sh.dsc[n];
