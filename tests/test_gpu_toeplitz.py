@@ -206,3 +206,79 @@ def test_unstable_section_is_reported(env):
     torch.cuda.synchronize()
     assert h.last_error() == P.SOS_EUNSTABLE
     assert torch.isnan(y).all().item()
+
+
+def test_misaligned_buffers(env):
+    """Input and output at every 4-byte offset from a 16-byte boundary (the
+    128-bit accesses at dword alignment), the two offsets differing, with a
+    ragged end: results and zf as aligned, nothing written outside."""
+    torch, P = env
+    K, n = 8, 3 * CHUNK + 4097
+    sos = workloads.sweep_sections(K, "random")
+    x = workloads.signal(n, 12)
+    ref, zref = oracle.sosfilt(sos.astype(np.float64), x.astype(np.float64))
+    zref = np.asarray(zref).reshape(K, 2)
+    h = P.Handle(0, algorithm="toeplitz")
+    sd = dev(torch, sos)
+    zf = torch.empty((K, 2), dtype=torch.float32, device="cuda")
+    for oi, oo in ((1, 1), (2, 3), (3, 2), (0, 1), (1, 0)):
+        buf = torch.zeros(n + 4, device="cuda")
+        buf[oi:oi + n] = dev(torch, x)
+        out = torch.zeros(n + 4, device="cuda")
+        P.sosfilt_(buf[oi:oi + n], sd, y=out[oo:oo + n], zf=zf, handle=h)
+        torch.cuda.synchronize()
+        assert h.last_error() == P.SOS_OK
+        o = out.cpu().numpy()
+        assert rel_l2(o[oo:oo + n], ref) <= 1e-4, (oi, oo)
+        assert not o[:oo].any() and not o[oo + n:].any(), (oi, oo)
+        assert rel_l2(zf.cpu().numpy(), zref) <= 1e-4, (oi, oo)
+
+
+def test_captured_in_a_graph(env):
+    """A block-Toeplitz call captured into a graph (both preparations, the arm
+    step, the filter and the section kernels that leave at once), replayed
+    three times with eager batched launches (which run PH on this handle and
+    leave the ticket counter advanced) and eager plain calls in between: every
+    replay and every eager call matches the oracle."""
+    torch, P = env
+    h = P.Handle(0, algorithm="toeplitz")
+    K, n = 8, 2 * CHUNK + 777
+    sos = workloads.sweep_sections(K, "random")
+    sosd = dev(torch, sos)
+    x = workloads.signal(n, 93)
+    xd = dev(torch, x)
+    yd = torch.empty_like(xd)
+    yr, _ = oracle.sosfilt(sos.astype(np.float64), x.astype(np.float64))
+    Ks, rows, sig_off, bzi = workloads.uneven_batch(B=16, log2_lo=4, log2_hi=15, seed=92)
+    bx = workloads.batch_signal(int(sig_off[-1]), seed=94)
+    bargs = (dev(torch, bx), dev(torch, rows), dev(torch, Ks.astype(np.int32)),
+             dev(torch, sig_off.astype(np.int64)))
+    so = np.r_[0, np.cumsum(Ks)]
+    i = 5
+    ybr, _ = oracle.sosfilt(rows[so[i]:so[i + 1]].astype(np.float64),
+                            bx[sig_off[i]:sig_off[i + 1]].astype(np.float64),
+                            bzi[so[i]:so[i + 1]].astype(np.float64))
+
+    def batched():
+        yb, _ = P.sosfilt_batched(*bargs, zi=dev(torch, bzi), handle=h)
+        torch.cuda.synchronize()
+        assert rel_l2(yb.cpu().numpy()[sig_off[i]:sig_off[i + 1]], ybr) <= 1e-4
+
+    P.sosfilt_(xd, sosd, yd, handle=h)
+    batched()
+    P.sosfilt_(xd, sosd, yd, handle=h)
+    torch.cuda.synchronize()
+    assert rel_l2(yd.cpu().numpy(), yr) <= 1e-4
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.sosfilt_(xd, sosd, yd, handle=h)
+    for rep in range(3):
+        batched()
+        yd.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert rel_l2(yd.cpu().numpy(), yr) <= 1e-4, rep
+        P.sosfilt_(xd, sosd, yd, handle=h)
+        torch.cuda.synchronize()
+        assert rel_l2(yd.cpu().numpy(), yr) <= 1e-4, rep
+    assert h.last_error() == P.SOS_OK
