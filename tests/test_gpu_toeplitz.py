@@ -282,3 +282,32 @@ def test_captured_in_a_graph(env):
         torch.cuda.synchronize()
         assert rel_l2(yd.cpu().numpy(), yr) <= 1e-4, rep
     assert h.last_error() == P.SOS_OK
+
+
+def test_lookback_timeout_is_bounded_and_reported(env):
+    """A one-tick bound on each chunk's lookback wait, forced from the host:
+    the launch still ends (a chunk whose wait ran out publishes a NaN state,
+    so its successors finish too), any NaN output comes with SOS_ETIMEOUT, and
+    with the default bound restored the same handle is exact."""
+    torch, P = env
+    K, n = 8, 1 << 24
+    sos = workloads.sweep_sections(K, "random")
+    x = workloads.signal(n, 31)
+    h = P.Handle(0, algorithm="toeplitz")
+    xd, sd = dev(torch, x), dev(torch, sos)
+    h.set_timeout(1e-6)
+    y, _ = P.sosfilt(xd, sd, handle=h)
+    torch.cuda.synchronize()
+    err = h.last_error()
+    has_nan = bool(torch.isnan(y).any().item())
+    print("one-tick bound: status", err, "NaN outputs", has_nan)
+    assert err in (P.SOS_OK, P.SOS_ETIMEOUT)
+    assert has_nan == (err == P.SOS_ETIMEOUT)
+    h.set_timeout(0)
+    y, _ = P.sosfilt(xd, sd, handle=h)
+    torch.cuda.synchronize()
+    assert h.last_error() == P.SOS_OK
+    m = 1 << 20
+    yr, _ = oracle.sosfilt(sos.astype(np.float64), x[:m].astype(np.float64))
+    assert rel_l2(y.cpu().numpy()[:m], yr) <= 1e-4
+    assert bool(torch.isfinite(y).all().item())
