@@ -123,6 +123,26 @@ __device__ inline bool batch_signal_ok(int i, int kmax, int64_t rows, int64_t to
            b <= total_samples;
 }
 
+// Whether the recursive part of section `row` ([b0 b1 b2 a0 a1 a2]) has peak
+// gain 1 / min |A(e^{jw})| at most rho_max (always, for rho_max = inf), without
+// a square root or a reciprocal: min |A|^2 rho_max^2 >= 1, with
+// |A|^2 = 4 a2 c^2 + l c + q on c = cos(w) in [-1, 1] after dividing by a0.
+__device__ inline bool gain_within(const float *row, double rho_max)
+{
+    if (isinf(rho_max)) return true;
+    const double a0 = row[3];
+    if (a0 == 0.0) return false;
+    const double a1 = row[4] / a0, a2 = row[5] / a0;
+    const double q = 1.0 + a1 * a1 + a2 * a2 - 2.0 * a2, l = 2.0 * a1 * (1.0 + a2);
+    auto f = [&](double c) { return (4.0 * a2 * c + l) * c + q; };
+    double m = fmin(f(-1.0), f(1.0));
+    if (a2 > 0.0) {
+        const double cv = -l / (8.0 * a2);
+        if (cv > -1.0 && cv < 1.0) m = fmin(m, f(cv));
+    }
+    return m > 0.0 && m * rho_max * rho_max >= 1.0;
+}
+
 // 2x2 row-major matrices (T acts on TDF-II states (z1, z2)).
 struct m2 {
     double a, b, c, d;

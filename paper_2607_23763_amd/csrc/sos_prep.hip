@@ -67,25 +67,6 @@ __device__ inline double peak_gain(const float *row)
 // section's peak gain exceeds rho_max (the FP32 state path and, in DC-CR
 // launches, the fold B(z)A(-z) lose accuracy with such poles), else fast.
 // rows: the signal's K rows. Each block of the signal decides alike.
-// peak_gain(row) <= rho_max without the square root and the reciprocal:
-// min |A|^2 rho_max^2 >= 1.
-__device__ inline bool gain_within(const float *row, double rho_max)
-{
-    if (isinf(rho_max)) return true;
-    const double a0 = row[3];
-    if (a0 == 0.0) return false;
-    const double a1 = row[4] / a0, a2 = row[5] / a0;
-    // |A|^2 = 4 a2 c^2 + l c + q on c = cos(w) in [-1, 1] (see peak_gain)
-    const double q = 1.0 + a1 * a1 + a2 * a2 - 2.0 * a2, l = 2.0 * a1 * (1.0 + a2);
-    auto f = [&](double c) { return (4.0 * a2 * c + l) * c + q; };
-    double m = fmin(f(-1.0), f(1.0));
-    if (a2 > 0.0) {
-        const double cv = -l / (8.0 * a2);
-        if (cv > -1.0 && cv < 1.0) m = fmin(m, f(cv));
-    }
-    return m > 0.0 && m * rho_max * rho_max >= 1.0;
-}
-
 template <typename T>
 __device__ inline unsigned signal_mode(const float *rows, int K, double rho_max)
 {

@@ -134,23 +134,6 @@ __device__ inline void ident16(double *Z, int tid)
     Z[ent(tid)] = (tid >> 4) == (tid & 15) ? 1.0 : 0.0;
 }
 
-// Peak gain of a row's recursive part within rho_max (see the per-section
-// preparation): min |A(e^jw)|^2 rho_max^2 >= 1, without a square root.
-__device__ inline bool toep_gain_within(const float *row, double rho_max)
-{
-    if (isinf(rho_max)) return true;
-    const double a0 = row[3];
-    const double a1 = row[4] / a0, a2 = row[5] / a0;
-    const double q = 1.0 + a1 * a1 + a2 * a2 - 2.0 * a2, l = 2.0 * a1 * (1.0 + a2);
-    auto f = [&](double c) { return (4.0 * a2 * c + l) * c + q; };
-    double m = fmin(f(-1.0), f(1.0));
-    if (a2 > 0.0) {
-        const double cv = -l / (8.0 * a2);
-        if (cv > -1.0 && cv < 1.0) m = fmin(m, f(cv));
-    }
-    return m > 0.0 && m * rho_max * rho_max >= 1.0;
-}
-
 struct PrepLds {
     double co[8][5];          // b0 b1 b2 a1 a2 per section (normalised)
     double phi[MSZ];          // one-sample state map
@@ -189,7 +172,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
         const double a0 = r[3];
         const double a1 = r[4] / a0, a2 = r[5] / a0;
         const bool stable = a0 != 0.0 && fabs(a2) < 1.0 && fabs(a1) < 1.0 + a2;
-        if (!stable || !toep_gain_within(r, rho_gate)) atomicAnd(&sh.gate, 0);
+        if (!stable || !gain_within(r, rho_gate)) atomicAnd(&sh.gate, 0);
         sh.co[tid][0] = r[0] / a0;
         sh.co[tid][1] = r[1] / a0;
         sh.co[tid][2] = r[2] / a0;
