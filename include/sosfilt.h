@@ -167,7 +167,8 @@ int sos_get_precision(sos_handle_t h);
  * into one state, and every 64-sample column is filtered as y = T x + O s,
  * s' = A s + Gam x with T the lower-triangular Toeplitz matrix of the
  * cascade's impulse response, on the matrix cores (FP32 MFMA), with one
- * 16-word lookback per group of 16384 samples instead of one per section.
+ * 16-word lookback per chunk of 131072 samples instead of one per group and
+ * section.
  * Its cost per sample does not grow with K, but a call has a fixed cost of
  * about 0.1 ms (its tables, and chunks of 131072 samples that must fill the
  * device). SOS_ALG_AUTO takes it for plain FP32 forward calls with K >= 7 on
