@@ -167,14 +167,16 @@ int sos_get_precision(sos_handle_t h);
  * into one state, and every 64-sample column is filtered as y = T x + O s,
  * s' = A s + Gam x with T the lower-triangular Toeplitz matrix of the
  * cascade's impulse response, on the matrix cores (FP32 MFMA), with one
- * 16-word lookback per chunk of 131072 samples instead of one per group and
- * section.
- * Its cost per sample does not grow with K, but a call has a fixed cost of
- * about 0.1 ms (its tables, and chunks of 131072 samples that must fill the
- * device). SOS_ALG_AUTO takes it for plain FP32 forward calls with K >= 7 on
- * at least 2^26 samples, or K = 6 on at least 2^27, when every section's
- * peak gain is at most 128 (decided on the device by the table preparation;
- * other signals run as before, in the same call).
+ * 16-word lookback per chunk (8 groups of 16384 samples from 2^25 samples
+ * on, 2 groups below; SOS_TOEP_CHUNK = 2, 4 or 8 in the environment
+ * overrides) instead of one per group and section.
+ * Its cost per sample does not grow with K, but a call takes at least about
+ * 0.07 ms (its tables, and chunks that must fill the device).
+ * SOS_ALG_AUTO takes it for plain FP32 forward calls with K = 8 on at least
+ * 2^25 samples, K = 7 on at least 2^26, or K = 6 on at least 2^27, when
+ * every section's peak gain is at most 128 (decided on the device by the
+ * table preparation; other signals run as before, in the same call). Tables
+ * from sos_prepare, whose signal length is not known, use 8-group chunks.
  * SOS_ALG_TOEPLITZ takes it for every plain FP32 forward call with K <= 8,
  * whatever the gains; its batched, training, adjoint and served launches,
  * and FP64 ones, run PH. Results follow the same conventions (zi, zf, in

@@ -97,10 +97,12 @@ int prepare_locked(sos_ctx *h, const float *sections, int K, hipStream_t stream,
         (n < 0 || n >= toep_min_n(s, K))) {
         rc = ensure_buf(h->ttab, h->ttab_cap, (size_t)sos_toep_table_floats(), stream);
         if (rc) return rc;
-        if (sos_launch_toep_prep(sections, K, s == SOS_ALG_TOEPLITZ ? HUGE_VAL : kToepRhoMax,
+        const int ng = toep_chunk_groups(n);
+        if (sos_launch_toep_prep(sections, K, ng, s == SOS_ALG_TOEPLITZ ? HUGE_VAL : kToepRhoMax,
                                  h->ttab, stream) != hipSuccess)
             return SOS_EHIP;
         h->prep_toep = true;
+        h->toep_ng = ng;
     }
     return SOS_OK;
 }
@@ -139,9 +141,10 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
     // the signal unless the preparation's gate sent it to the per-section
     // kernels, which then skip it (and otherwise filter it as before)
     const bool toep = h->prep_toep && !saved && n >= toep_min_n(h->prep_alg, K);
-    const int64_t tgroups = toep ? (n + sos_toep_group_samples() - 1) / sos_toep_group_samples() : 0;
+    const int64_t tchunk = (int64_t)sos_toep_group_samples() * h->toep_ng;
+    const int64_t tchunks = toep ? (n + tchunk - 1) / tchunk : 0;
     size_t words = (size_t)groups * (size_t)K * 4u;
-    if (toep) words = std::max(words, (size_t)tgroups * (size_t)sos_toep_desc_words());
+    if (toep) words = std::max(words, (size_t)tchunks * (size_t)sos_toep_desc_words());
     const int rc = ensure_desc(h, words, stream);
     if (rc) return rc;
     // Ticket 0 and a fresh epoch: left by the previous plain or adjoint launch
@@ -153,8 +156,8 @@ int filter_locked(sos_ctx *h, const float *x, float *y, int64_t n, const float *
         return SOS_EHIP;
     if (toep) {
         const int64_t g = grid_override();
-        if (sos_launch_toep(x, y, n, h->ttab, K, zi, zf, h->desc, h->ctrl, h->timeout_ticks,
-                            g ? g : sos_toep_capacity(), stream) != hipSuccess)
+        if (sos_launch_toep(x, y, n, h->ttab, K, h->toep_ng, zi, zf, h->desc, h->ctrl,
+                            h->timeout_ticks, g ? g : sos_toep_capacity(), stream) != hipSuccess)
             return SOS_EHIP;
     }
     const int alg = launch_alg(bits, h->prep_alg, h->prep_rho);

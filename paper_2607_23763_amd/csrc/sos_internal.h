@@ -29,9 +29,9 @@ hipError_t sos_launch_fwd(int bits, int alg, int L, int N, const float *x, float
                           unsigned long long *desc, unsigned *ctrl,
                           unsigned long long timeout_ticks, int64_t grid, float *saved,
                           const float *skip_gate, hipStream_t stream);
-hipError_t sos_launch_toep_prep(const float *sections, int K, double rho_gate, float *tt,
+hipError_t sos_launch_toep_prep(const float *sections, int K, int ng, double rho_gate, float *tt,
                                 hipStream_t stream);
-hipError_t sos_launch_toep(const float *x, float *y, int64_t n, const float *tt, int K,
+hipError_t sos_launch_toep(const float *x, float *y, int64_t n, const float *tt, int K, int ng,
                            const float *zi, float *zf, unsigned long long *desc, unsigned *ctrl,
                            unsigned long long timeout_ticks, int64_t grid, hipStream_t stream);
 int sos_toep_capacity(void);
@@ -120,6 +120,7 @@ struct sos_ctx {
     int prep_alg = 0;                     // solver the tables were prepared for
     double prep_rho = 0.0;                // and their peak-gain threshold
     bool prep_toep = false;               // block-Toeplitz tables prepared too
+    int toep_ng = 0;                      //   for chunks of this many groups
     float *ttab = nullptr;                // block-Toeplitz tables (sos_toep.hip)
     size_t ttab_cap = 0;
     // uneven-batch work table
@@ -243,22 +244,42 @@ inline bool ph_sections(int solver)
 // 16-dimensional state), for cascades whose sections all peak at most
 // kToepRhoMax. The automatic choice takes it where it was measured faster
 // than the faster per-section solver (MI355X, per call, tables included):
-// K >= 7 from 2^26 samples (K = 8 / 7: +18 / +6 % at 2^26, +28 / +15 % at
-// 2^27, +34 / +21 % at 2^28) and K = 6 from 2^27 (+3 %, +7 % at 2^28; -5 %
-// at 2^26); K = 5 stays on the section kernels (-9 % at 2^28). A call costs
-// about 0.1 ms before its first sample (the tables, and chunks that must
-// fill the device), which is what shorter signals cannot amortise.
+// K = 8 from 2^25 samples (+10 / +24 / +32 / +37 % at 2^25 / 2^26 / 2^27 /
+// 2^28; -9 % at 2^24), K = 7 from 2^26 (+12 / +18 / +23 %; level at 2^25)
+// and K = 6 from 2^27 (+6 / +9 %; level at 2^26); K = 5 stays on the
+// section kernels (-4 % at 2^28). A call takes at least about 0.07 ms (the
+// tables, and chunks of 16384-sample groups that must fill the device),
+// which is what shorter signals cannot amortise.
 constexpr int kToepMaxK = 8;
 
 // Shortest signal the automatic choice filters by the block-Toeplitz path for
 // K sections (none: INT64_MAX).
 inline int64_t toep_auto_min_n(int K)
 {
-    if (K >= 7 && K <= kToepMaxK) return (int64_t)1 << 26;
+    if (K == kToepMaxK) return (int64_t)1 << 25;
+    if (K == 7) return (int64_t)1 << 26;
     if (K == 6) return (int64_t)1 << 27;
     return INT64_MAX;
 }
 constexpr double kToepRhoMax = 128.0;
+
+// Groups of 16384 samples per block-Toeplitz chunk (one ticket, one lookback)
+// for a signal of n samples (n < 0: unknown). A workgroup takes a chunk's
+// groups one after the other, so a chunk of 8 groups keeps one workgroup busy
+// for about 0.1 ms: below 2^25 samples most workgroups would get one chunk or
+// none, and chunks of 2 groups are faster (MI355X, per call, tables included:
+// 57 / 94 / 139 GS/s at 2^22 / 2^23 / 2^24 against 33 / 63 / 112). From 2^25
+// on, 8 groups are (193 against 188 at 2^25, 300 against 270 at 2^28); 4
+// groups were never the fastest at 2^22-2^28. SOS_TOEP_CHUNK (2, 4 or 8)
+// overrides.
+inline int toep_chunk_groups(int64_t n)
+{
+    if (const char *e = std::getenv("SOS_TOEP_CHUNK")) {
+        const int g = std::atoi(e);
+        if (g == 2 || g == 4 || g == 8) return g;
+    }
+    return (n < 0 || n >= ((int64_t)1 << 25)) ? 8 : 2;
+}
 
 // Kernel of the filter launches: ALG_PH for the PH solver, ALG_DCCR for
 // DC-CR and for the automatic choice (signals whose tables took the accurate

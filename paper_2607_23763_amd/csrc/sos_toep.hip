@@ -20,7 +20,9 @@
 // highest orders.
 //
 // Group structure (one workgroup of 8 waves, two tiles per wave, CG = 16384
-// samples per group, NG = 8 groups per chunk, one chunk per ticket):
+// samples per group, NG = 2, 4 or 8 groups per chunk, one chunk per ticket;
+// the host takes 8 for long signals and fewer where 8-group chunks would not
+// give every workgroup several chunks):
 //   1. Each wave forms T x and Gam x for its tiles straight from the 128-bit
 //      loads: lane l holds samples 16b + 4(l/16) + {0..3} of column l%16
 //      for blocks b = 0..3, which is exactly the MFMA's B operand for the
@@ -63,9 +65,9 @@ constexpr int WT = 8;            // waves per workgroup
 constexpr int TPW = 2;           // tiles per wave
 constexpr int NT = WT * TPW;     // tiles per group
 constexpr int CG = TS * NT;      // samples per group
-constexpr int NG = 8;            // groups per chunk (one ticket, one lookback)
+constexpr int kMaxNG = 8;        // groups per chunk (one ticket, one lookback): 2, 4 or 8
 constexpr int kMaxDist = 32;     // lookback reach in chunks: powers H^d, d < kMaxDist
-constexpr int kDescWords = 32;   // per group: 16 aggregate words, 16 inclusive words
+constexpr int kDescWords = 32;   // per chunk: 16 aggregate words, 16 inclusive words
 constexpr int kPowStride = 260;  // LDS stride of a 16 x 16 power (bank-spread across lanes)
 static_assert(NT == 16, "the group-level scan covers one 16-column MFMA tile");
 
@@ -74,6 +76,7 @@ static_assert(NT == 16, "the group-level scan covers one 16-column MFMA tile");
 enum : int {
     TT_GATE = 0,          // 1.0f when this path filters the signal, else 0.0f
     TT_K = 1,             // sections (as a float)
+    TT_NG = 2,            // groups per chunk the chunk map H was formed for (as a float)
     TT_D = 16,            // [16] state scale: TDF-II state = D * kernel state
     TT_DINV = 32,         // [16]
     TT_TOP = 64,          // [4 delta][64 lanes][4 s]: T operands, block pair r - b = delta
@@ -86,7 +89,7 @@ enum : int {
     TT_ACOL = TT_GAM + 16,     // [16 c][16][16] A^c: tile state -> column c
     TT_BTILE = TT_ACOL + 4096, // [16 t][16][16] (Phi^1024)^t: group state -> tile t
     TT_G1 = TT_BTILE + 4096,   // [16][16] G = Phi^C: across one group
-    TT_HPOW = TT_G1 + 256,     // [64 d][16][16] H^d, H = G^NG: d chunks back
+    TT_HPOW = TT_G1 + 256,     // [kMaxDist d][16][16] H^d, H = G^NG: d chunks back
     TT_FLOATS = TT_HPOW + kMaxDist * 256
 };
 constexpr int kLdsMats = TC + NT + 1 + kMaxDist;   // matrices staged into LDS
@@ -149,8 +152,8 @@ struct PrepLds {
 };
 
 // One block of 256 threads: every table of the path for one cascade of K
-// sections (K <= 8), in FP64, rounded once to FP32.
-__global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *sections, int K,
+// sections (K <= 8) and chunks of ng groups, in FP64, rounded once to FP32.
+__global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *sections, int K, int ng,
                                                             double rho_gate, float *tt)
 {
     __shared__ PrepLds sh;
@@ -310,7 +313,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     // work[8..11]
     sh.work[18][ent(tid)] = sh.pw[8][ent(tid)];
     __syncthreads();
-    for (int k = 1; k < NG; k <<= 1) {
+    for (int k = 1; k < ng; k <<= 1) {
         if (wv == 0) mm16m(sh.work[18], sh.work[18], sh.work[19], lane);
         __syncthreads();
         sh.work[18][ent(tid)] = sh.work[19][ent(tid)];
@@ -364,6 +367,7 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     }
     if (tid == 0) {
         tt[TT_K] = (float)K;
+        tt[TT_NG] = (float)ng;
         tt[TT_GATE] = 1.0f;
     }
 }
@@ -686,6 +690,7 @@ __device__ __forceinline__ v4f mat_rows(const float *Mx, const float *v_lds, int
 // The input is read twice, the output written once; the next group's samples
 // are always in flight while the current one is processed, and wave 0's
 // serial work overlaps the MFMA work of the wave sharing its SIMD.
+template <int NG>
 __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)))
     sos_toep_kernel(ToepArgs a)
 {
@@ -936,22 +941,27 @@ __global__ void __launch_bounds__(64 * WT) __attribute__((amdgpu_waves_per_eu(2)
 
 extern "C" {
 
-int sos_toep_group_samples(void) { return CG * NG; }   // samples per ticket (chunk)
+int sos_toep_group_samples(void) { return CG; }   // samples per group (a chunk is ng groups)
 int sos_toep_desc_words(void) { return kDescWords; }
 int sos_toep_table_floats(void) { return TT_FLOATS; }
 
-hipError_t sos_launch_toep_prep(const float *sections, int K, double rho_gate, float *tt,
+static bool chunk_ok(int ng) { return ng == 2 || ng == 4 || ng == kMaxNG; }
+
+hipError_t sos_launch_toep_prep(const float *sections, int K, int ng, double rho_gate, float *tt,
                                 hipStream_t stream)
 {
-    hipLaunchKernelGGL(sos_toep_prep_kernel, dim3(1), dim3(256), 0, stream, sections, K, rho_gate,
-                       tt);
+    if (!chunk_ok(ng)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sos_toep_prep_kernel, dim3(1), dim3(256), 0, stream, sections, K, ng,
+                       rho_gate, tt);
     return hipGetLastError();
 }
 
 int sos_toep_capacity(void)
 {
+    // LDS and registers allow one 8-wave workgroup per CU at every chunk size
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)sos_toep_kernel,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     (const void *)sos_toep_kernel<kMaxNG>,
                                                      64 * WT, 0) != hipSuccess)
         per_cu = 1;
     (void)hipGetDevice(&dev);
@@ -960,10 +970,11 @@ int sos_toep_capacity(void)
     return (per_cu > 0 ? per_cu : 1) * cus;
 }
 
-hipError_t sos_launch_toep(const float *x, float *y, int64_t n, const float *tt, int K,
+hipError_t sos_launch_toep(const float *x, float *y, int64_t n, const float *tt, int K, int ng,
                            const float *zi, float *zf, unsigned long long *desc, unsigned *ctrl,
                            unsigned long long timeout_ticks, int64_t grid, hipStream_t stream)
 {
+    if (!chunk_ok(ng)) return hipErrorInvalidValue;
     ToepArgs a{};
     a.x = x;
     a.y = y;
@@ -973,12 +984,18 @@ hipError_t sos_launch_toep(const float *x, float *y, int64_t n, const float *tt,
     a.zf = zf;
     a.K = K;
     a.groups = (n + CG - 1) / CG;
-    a.total = (a.groups + NG - 1) / NG;
+    a.total = (a.groups + ng - 1) / ng;
     a.desc = desc;
     a.ctrl = ctrl;
     a.timeout_ticks = timeout_ticks;
     if (grid <= 0 || grid > a.total) grid = a.total;
-    hipLaunchKernelGGL(sos_toep_kernel, dim3((unsigned)grid), dim3(64 * WT), 0, stream, a);
+    const dim3 g((unsigned)grid), b(64 * WT);
+    if (ng == 2)
+        hipLaunchKernelGGL(sos_toep_kernel<2>, g, b, 0, stream, a);
+    else if (ng == 4)
+        hipLaunchKernelGGL(sos_toep_kernel<4>, g, b, 0, stream, a);
+    else
+        hipLaunchKernelGGL(sos_toep_kernel<kMaxNG>, g, b, 0, stream, a);
     return hipGetLastError();
 }
 

@@ -1,11 +1,13 @@
 """GPU parity of the whole-cascade block-Toeplitz path (sos_toep.hip): the
 multi-block split of Sec. II-B taken over the whole cascade (zero-state
 output T x, column end states Gam x, column and tile scans, a 16-word
-decoupled lookback per chunk of eight groups, y += O s), on the matrix cores. Same FP64 oracle and
-bounds as the per-section kernels: relative L2 error <= 1e-5 up to order 8
-and <= 1e-4 at order 16 (or 10x the sequential FP32 error, where that is
-larger), zf to the same bounds; exact, ragged and one-group lengths, initial
-states, in place, many groups per workgroup, and the automatic choice."""
+decoupled lookback per chunk of two, four or eight groups, y += O s), on the
+matrix cores. Same FP64 oracle and bounds as the per-section kernels:
+relative L2 error <= 1e-5 up to order 8 and <= 1e-4 at order 16 (or 10x the
+sequential FP32 error, where that is larger), zf to the same bounds; exact,
+ragged and one-group lengths at every chunk size, initial states, in place,
+many groups per workgroup, the chunk size chosen from the length, and the
+automatic choice."""
 import numpy as np
 import pytest
 
@@ -16,7 +18,7 @@ from tests.gpu_util import fp32_bounds, rel_l2, zf_bound
 pytestmark = pytest.mark.gpu
 
 CG = 16384   # samples per group of the block-Toeplitz kernel
-CHUNK = 8 * CG   # groups per ticket (one lookback per chunk)
+CHUNK = 8 * CG   # samples per ticket (one lookback per chunk) at 8 groups per chunk
 
 
 @pytest.fixture(scope="module")
@@ -71,12 +73,40 @@ def test_parity_with_initial_state(env, kind, K, n):
 
 @pytest.mark.parametrize("n", [64, 1024, CG - 1, CG, CG + 1, 2 * CG + 64, CHUNK - 1, CHUNK,
                                CHUNK + 1, 7 * CG + 4097, 2 * CHUNK, 9 * CG + 5])
-def test_lengths_across_column_tile_and_group_edges(env, n):
+def test_lengths_across_column_tile_and_group_edges(env, monkeypatch, n):
     torch, P = env
+    monkeypatch.setenv("SOS_TOEP_CHUNK", "8")
     sos = workloads.butterworth_sos(8)
     x = workloads.signal(n, n % 1000)
     y, zf = run(torch, P, sos, x)
     check(sos, x, None, y, zf, "edges n=%d" % n)
+
+
+# signal lengths for a chunk of c samples
+SMALL_CHUNK_LENGTHS = {
+    "chunk-1": lambda c: c - 1,
+    "chunk": lambda c: c,
+    "chunk+1": lambda c: c + 1,
+    "2chunks+5": lambda c: 2 * c + 5,
+    "7groups+4097": lambda c: 7 * CG + 4097,
+    "group-1": lambda c: CG - 1,
+}
+
+
+@pytest.mark.parametrize("ng", [2, 4])
+@pytest.mark.parametrize("case", list(SMALL_CHUNK_LENGTHS))
+def test_lengths_across_smaller_chunks(env, monkeypatch, ng, case):
+    """Chunks of 2 and 4 groups: lengths on either side of a chunk edge,
+    ragged ends inside later chunks, and a signal shorter than one group."""
+    torch, P = env
+    monkeypatch.setenv("SOS_TOEP_CHUNK", str(ng))
+    n = SMALL_CHUNK_LENGTHS[case](ng * CG)
+    K = 8 if ng == 2 else 5
+    sos = workloads.sweep_sections(K, "random")
+    x = workloads.signal(n, n % 997)
+    zi = workloads.initial_state(K, workloads.rng(n % 13))
+    y, zf = run(torch, P, sos, x, zi)
+    check(sos, x, zi, y, zf, "chunk %d n=%d" % (ng, n))
 
 
 def test_in_place_with_ragged_end(env):
@@ -96,13 +126,15 @@ def test_in_place_with_ragged_end(env):
     check(sos, x, zi, xd.cpu().numpy(), zf.cpu().numpy(), "in place")
 
 
+@pytest.mark.parametrize("ng", [2, 4, 8])
 @pytest.mark.parametrize("grid", [1, 3])
-def test_many_groups_per_workgroup(env, monkeypatch, grid):
-    """A persistent grid of 1 or 3 workgroups walks 25 chunks of 8 groups:
-    the next group's samples are always in flight, and lookbacks find their
-    predecessors already resolved."""
+def test_many_groups_per_workgroup(env, monkeypatch, grid, ng):
+    """A persistent grid of 1 or 3 workgroups walks the 201 groups in chunks
+    of 2, 4 or 8: the next group's samples are always in flight, and
+    lookbacks find their predecessors already resolved."""
     torch, P = env
     monkeypatch.setenv("SOS_GRID", str(grid))
+    monkeypatch.setenv("SOS_TOEP_CHUNK", str(ng))
     K, n = 8, 200 * CG + 3
     sos = workloads.sweep_sections(K, "random")
     x = workloads.signal(n, 5)
@@ -111,21 +143,28 @@ def test_many_groups_per_workgroup(env, monkeypatch, grid):
     check(sos, x, zi, y, zf, "grid %d" % grid)
 
 
-@pytest.mark.parametrize("K", [4, 8])
-def test_full_device_lookback_2p25(env, K):
-    """2^25 samples (256 chunks) on the whole device: every workgroup's
-    lookback walks windows of in-flight predecessors."""
+@pytest.mark.parametrize("K,n,ng", [(4, 1 << 25, None), (8, 1 << 25, None),
+                                    (8, (1 << 24) + 333, None), (8, 1 << 25, 8),
+                                    (6, 1 << 23, 2)])
+def test_full_device_lookback(env, monkeypatch, K, n, ng):
+    """2^23 to 2^25 samples on the whole device, with the chunk size the
+    length selects (or a forced one): every workgroup's lookback walks
+    windows of in-flight predecessors."""
     torch, P = env
-    n = 1 << 25
+    if ng is None:
+        monkeypatch.delenv("SOS_TOEP_CHUNK", raising=False)
+    else:
+        monkeypatch.setenv("SOS_TOEP_CHUNK", str(ng))
     sos = workloads.butterworth_sos(K)
     x = workloads.signal(n, 77)
     y, zf = run(torch, P, sos, x)
-    check(sos, x, None, y, zf, "2^25 K=%d" % K)
+    check(sos, x, None, y, zf, "n=%d K=%d chunk %s" % (n, K, ng))
 
 
 def test_automatic_choice_takes_the_toeplitz_path(env, monkeypatch):
-    """The automatic solver runs orders 14-16 of at least 2^26 samples and
-    order 12 of at least 2^27 through the block-Toeplitz kernel (its output
+    """The automatic solver runs order 16 of at least 2^25 samples, order 14
+    of at least 2^26 and order 12 of at least 2^27 through the block-Toeplitz
+    kernel (its output
     equals an explicit block-Toeplitz handle's bit for bit, and differs from
     the per-section kernels'), lower orders and shorter signals through the
     per-section kernels. The check against the oracle uses a 2^20-sample
@@ -153,14 +192,19 @@ def test_automatic_choice_takes_the_toeplitz_path(env, monkeypatch):
     yt5, _ = run(torch, P, sos5, x, algorithm="toeplitz")
     assert not np.array_equal(ya5, yt5)
     del ya6, yt6, ya5, yt5
-    # order 12 below 2^27 samples, order 16 below 2^26: the section kernels
+    # each order at its threshold takes the block-Toeplitz kernel, one
+    # sample less takes the section kernels: order 16 at 2^25, order 14 at
+    # 2^26, order 12 at 2^27 (above)
+    sos7 = workloads.butterworth_sos(7)
+    for cascade, lg in ((sos, 25), (sos7, 26)):
+        for m, same in (((1 << lg), True), ((1 << lg) - 1, False)):
+            ys, _ = run(torch, P, cascade, x[:m], algorithm="auto")
+            yts, _ = run(torch, P, cascade, x[:m], algorithm="toeplitz")
+            assert np.array_equal(ys, yts) == same, (cascade.shape[0], m)
+            del ys, yts
     xs = x[: 1 << 26]
     ys, _ = run(torch, P, sos6, xs, algorithm="auto")
     yts, _ = run(torch, P, sos6, xs, algorithm="toeplitz")
-    assert not np.array_equal(ys, yts)
-    xs = x[: 1 << 25]
-    ys, _ = run(torch, P, sos, xs, algorithm="auto")
-    yts, _ = run(torch, P, sos, xs, algorithm="toeplitz")
     assert not np.array_equal(ys, yts)
 
 

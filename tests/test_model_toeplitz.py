@@ -53,15 +53,17 @@ def test_impulse_response_is_the_cascade():
     assert np.max(np.abs(np.array(h) - ref)) < 1e-12
 
 
-@pytest.mark.parametrize("kind,K,bound", [("butter", 8, 1e-6), ("random", 8, 1e-6),
-                                          ("butter", 4, 1e-6)])
-def test_fp32_accuracy_at_the_kernel_shape(kind, K, bound):
+@pytest.mark.parametrize("kind,K,bound,ng", [("butter", 8, 1e-6, 8), ("random", 8, 1e-6, 8),
+                                             ("butter", 4, 1e-6, 8), ("random", 8, 1e-6, 4),
+                                             ("random", 8, 1e-6, 2), ("butter", 8, 1e-6, 2)])
+def test_fp32_accuracy_at_the_kernel_shape(kind, K, bound, ng):
     """FP32 with the kernel's shape (64-sample columns, 16 x 16 tiles and
-    groups, 8-group chunks): rel-L2 far inside the benchmark spec's bounds."""
+    groups, chunks of 8, 4 or 2 groups): rel-L2 far inside the north-star
+    bounds."""
     sos = workloads.sweep_sections(K, kind)
     x = workloads.signal(2 * 131072 + 999, 5)
     ref, _ = oracle.sosfilt(sos.astype(np.float64), x.astype(np.float64))
-    y, _ = TM.run(sos, x, dtype=np.float32)
+    y, _ = TM.run(sos, x, dtype=np.float32, NG=ng)
     assert rel_l2(y, ref) < bound
 
 
