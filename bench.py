@@ -23,7 +23,8 @@ paper's way (Sec. IV-F): 1000 warm-up launches, 20 batches of 200, the
 20th-percentile batch mean beside the plain mean. "plateau" holds length
 curves under that protocol (orders 2 and 16, 2^16..2^28 samples) and the
 paper's plateau, the mean of the 2^24 and 2^25 points, for every order and
-both solvers.
+both section solvers (order 16 also with the default solver, which takes the
+block-Toeplitz kernel from 2^25 samples, and with that kernel alone).
 
 CPU legs (skipped with --no-cpu): "cpu_baseline" is the FP64 oracle on one
 thread (one signal is one sequential recursion) over the whole headline
@@ -764,6 +765,16 @@ def main():
                                                4),
                 hp.algorithm() + "_plateau_GS_per_s": plateau_of(pts2),
                 "curve": pts}
+            if K == 8:
+                # order 16: the default (automatic) solver, which takes the
+                # block-Toeplitz kernel from 2^25 samples, and that kernel
+                # alone
+                for alg in ("auto", "toeplitz"):
+                    ha = P.Handle(0, tile=tile, algorithm=alg)
+                    pa = length_curve(torch, P, ha, sos_d, xs, ys, (24, 25))
+                    ha.close()
+                    plateau["order_16"][alg + "_plateau_GS_per_s"] = plateau_of(pa)
+                    plateau["order_16"][alg + "_points"] = pa
             log("plateau", 2 * K, plateau["order_%d" % (2 * K)])
         hp.close()
         extra_dtcr = bench_dtcr_bound(torch, P, workloads, xs, ys, log)
@@ -775,10 +786,14 @@ def main():
     log("copy %.4f ms = %.0f GB/s" % (copy_ms, copy_gbs))
 
     achieved_gbs = n * BYTES_PER_SAMPLE / (ms_kern * 1e-3) / 1e9
+    # the committed counter runs are of the order-2 DC-CR forward kernel; the
+    # profile helper's other cascades and solvers report no traffic
+    headline_kernel = K1 == 1 and args.alg == "dccr"
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                "traffic": traffic_bytes(n),
-                "kernel": "sos_fwd_kernel", "kernel_ms": round(ms_kern, 4),
+                "traffic": traffic_bytes(n) if headline_kernel else None,
+                "kernel": "sos_toep_kernel" if args.alg == "toeplitz" else "sos_fwd_kernel",
+                "kernel_ms": round(ms_kern, 4),
                 "copy_roof_GBs": round(copy_gbs, 1),
                 "frac_of_copy_roof": round(achieved_gbs / copy_gbs, 4)}
 
