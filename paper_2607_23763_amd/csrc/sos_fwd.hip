@@ -366,9 +366,11 @@ __device__ __forceinline__ void pick_two(const T (&u)[N], float *tl, int lane, i
 // and the walk ends; otherwise the prefix's aggregates are added and the walk
 // slides past them, into the next window of the same round when the whole
 // window was consumed. When the newest unconsumed predecessor is not ready,
-// the wave waits on that single descriptor with exponential backoff, so
-// waiting waves issue one request per poll. On timeout it returns NaNs and
-// sets the error bit (the caller still publishes, so successors terminate).
+// the wave polls that single descriptor, one request per poll, with a short
+// fixed sleep between polls (an exponential backoff up to 16 times as long
+// overslept the publication: order 16 and the uneven batch ran 0.6-1.5 %
+// slower, same-box A/B on MI355X). On timeout it returns NaNs and sets the
+// error bit (the caller still publishes, so successors terminate).
 template <int kSpan, typename LY, typename It, typename T>
 __device__ void lookback(const FwdArgs &a, const It &it, const T *stv, int s,
                          unsigned epoch, int lane, T &r1, T &r2)
@@ -386,7 +388,6 @@ __device__ void lookback(const FwdArgs &a, const It &it, const T *stv, int s,
     const int64_t first = it.t - it.g;      // ticket of the signal's first group
     int64_t base = it.t - 1;                // newest unconsumed predecessor
     bool single = false;                    // waiting on the newest one only
-    int nap = 0;
     const unsigned long long t0 = wall_clock64();
     while (true) {
         unsigned long long w[kWin][4];
@@ -451,7 +452,6 @@ __device__ void lookback(const FwdArgs &a, const It &it, const T *stv, int s,
         }
         if (done) break;
         if (progressed) {
-            nap = 0;
             single = false;
             continue;
         }
@@ -463,8 +463,7 @@ __device__ void lookback(const FwdArgs &a, const It &it, const T *stv, int s,
             r1 = r2 = T(__builtin_nanf(""));
             return;
         }
-        for (int i = 0; i < (1 << nap); ++i) __builtin_amdgcn_s_sleep(2);
-        if (nap < 4) ++nap;
+        __builtin_amdgcn_s_sleep(2);
         single = true;
     }
     r1 = acc1;

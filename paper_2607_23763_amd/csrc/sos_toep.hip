@@ -497,7 +497,7 @@ __device__ void toep_lookback(const ToepArgs &a, const float *hpow, int64_t t, u
                               int lane, float *sg)
 {
     float acc = 0.0f;
-    int dbase = 0, nap = 0;
+    int dbase = 0;
     const unsigned long long t0 = wall_clock64();
     for (;;) {
         const int dist = dbase + lane;
@@ -548,7 +548,6 @@ __device__ void toep_lookback(const ToepArgs &a, const float *hpow, int64_t t, u
             acc += reduce16(z, lane);
             if (done) break;
             dbase += c;
-            nap = 0;
             continue;
         }
         if (wall_clock64() - t0 > a.timeout_ticks) {
@@ -556,8 +555,7 @@ __device__ void toep_lookback(const ToepArgs &a, const float *hpow, int64_t t, u
             acc = __builtin_nanf("");
             break;
         }
-        for (int i = 0; i < (1 << nap); ++i) __builtin_amdgcn_s_sleep(2);
-        if (nap < 4) ++nap;
+        __builtin_amdgcn_s_sleep(2);   // a short fixed sleep between polls
     }
     if ((lane & 3) == 0) sg[lane >> 2] = acc;
 }
