@@ -132,6 +132,19 @@ __device__ inline void mm16m(const double *X, const double *Y, double *Z, int la
     for (int r = 0; r < 4; ++r) Z[(4 * r + g) * RS + n] = acc[r];
 }
 
+// The same product with the operands read through accessors x(row, k) and
+// y(k, column).
+template <typename FX, typename FY>
+__device__ inline v4d mm16f_acc(FX x, FY y, int lane)
+{
+    const int n = lane & 15, g = lane >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x(n, 4 * s + g), y(4 * s + g, n), acc, 0, 0, 0);
+    return acc;
+}
+
 __device__ inline void ident16(double *Z, int tid)
 {
     Z[ent(tid)] = (tid >> 4) == (tid & 15) ? 1.0 : 0.0;
@@ -142,8 +155,8 @@ struct PrepLds {
     double phi[MSZ];          // one-sample state map
     double gam[16], crow[16], dd;
     double q[7][MSZ];         // Phi^(2^j), j = 0..6
-    double v[64][16];         // Phi^i gamma
-    double o[64][16];         // c Phi^i
+    double v[64][17];         // Phi^i gamma (rows padded: 16 rows at once hit distinct banks)
+    double o[64][17];         // c Phi^i
     double dsc[16];           // state scale D
     double h[64];             // the cascade's impulse response
     double pw[9][MSZ];        // A^(1,2,4,8), B^(1,2,4,8), G (scaled basis)
@@ -195,13 +208,16 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
 #pragma unroll
         for (int i = 0; i < 16; ++i) s[i] = (i == tid && tid < n2) ? 1.0 : 0.0;
         double v = tid == n2 ? 1.0 : 0.0;
-        for (int k = 0; k < K; ++k) {
-            const double y = sh.co[k][0] * v + s[2 * k];
-            const double z1 = sh.co[k][1] * v - sh.co[k][3] * y + s[2 * k + 1];
-            const double z2 = sh.co[k][2] * v - sh.co[k][4] * y;
-            s[2 * k] = z1;
-            s[2 * k + 1] = z2;
-            v = y;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {   // constant indices into s (K <= 8)
+            if (k < K) {
+                const double y = sh.co[k][0] * v + s[2 * k];
+                const double z1 = sh.co[k][1] * v - sh.co[k][3] * y + s[2 * k + 1];
+                const double z2 = sh.co[k][2] * v - sh.co[k][4] * y;
+                s[2 * k] = z1;
+                s[2 * k + 1] = z2;
+                v = y;
+            }
         }
         if (tid < n2) {
             for (int i = 0; i < 16; ++i) sh.phi[i * RS + tid] = s[i];
@@ -212,14 +228,11 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
         }
     }
     __syncthreads();
-    // Phi^(2^j) by squaring
+    // v_i = Phi^i gamma and o_i = c Phi^i, i < 64, by doubling with
+    // Q_j = Phi^(2^j): v_(h+c) = Q_j v_c and o_(h+c) = o_c Q_j for c < h = 2^j,
+    // as 16-column blocks on the FP64 matrix cores, while one wave squares
+    // Q_j into Q_(j+1)
     sh.q[0][ent(tid)] = sh.phi[ent(tid)];
-    __syncthreads();
-    for (int j = 0; j < 6; ++j) {
-        if (wv == 0) mm16m(sh.q[j], sh.q[j], sh.q[j + 1], lane);
-        __syncthreads();
-    }
-    // v_i = Phi^i gamma and o_i = c Phi^i, i < 64, by doubling
     if (tid < 16) {
         sh.v[0][tid] = sh.gam[tid];
         sh.o[0][tid] = sh.crow[tid];
@@ -227,17 +240,37 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     __syncthreads();
     for (int j = 0; j < 6; ++j) {
         const int half = 1 << j;
-        for (int e = tid; e < 2 * half * 16; e += 256) {
-            const int which = e / (half * 16), r = e % (half * 16);
-            const int src = r >> 4, m = r & 15;
-            const double *Q = sh.q[j];
-            double acc = 0.0;
-            if (which == 0) {
-                for (int k = 0; k < 16; ++k) acc = fma(Q[m * RS + k], sh.v[src][k], acc);
-                sh.v[src + half][m] = acc;
+        const int nb = half < 16 ? 1 : half / 16;   // 16-column blocks
+        const double *Q = sh.q[j];
+        const int n = lane & 15, g = lane >> 4;
+        // products of this step: the square, nb blocks of v, nb blocks of o
+        for (int p = wv; p < 1 + 2 * nb; p += 4) {
+            if (p == 0) {
+                mm16m(sh.q[j], sh.q[j], sh.q[j + 1], lane);
+            } else if (p <= nb) {
+                const int b = 16 * (p - 1);   // Z[i][c] = (Q_j v_(b+c))[i]
+                const v4d acc = mm16f_acc(
+                    [&](int i, int k) { return Q[i * RS + k]; },
+                    [&](int k, int c) {
+                        const double e = sh.v[(b + c) & 63][k];
+                        return b + c < half ? e : 0.0;
+                    },
+                    lane);
+                if (b + n < half) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) sh.v[half + b + n][4 * r + g] = acc[r];
+                }
             } else {
-                for (int k = 0; k < 16; ++k) acc = fma(sh.o[src][k], Q[k * RS + m], acc);
-                sh.o[src + half][m] = acc;
+                const int b = 16 * (p - 1 - nb);   // Z[c][m] = (o_(b+c) Q_j)[m]
+                const v4d acc = mm16f_acc(
+                    [&](int c, int k) {
+                        const double e = sh.o[(b + c) & 63][k];
+                        return b + c < half ? e : 0.0;
+                    },
+                    [&](int k, int m) { return Q[k * RS + m]; }, lane);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (b + 4 * r + g < half) sh.o[half + b + 4 * r + g][n] = acc[r];
             }
         }
         __syncthreads();
@@ -250,12 +283,27 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
         sh.h[tid] = acc;
     }
     // balancing scale: a power of two per state entry equalising the energy
-    // of its Gam row and O column over one column (exact in every format)
+    // of its Gam row and O column over one column (exact in every format);
+    // each energy is summed in 16 parts (work[0..1] hold them) and then added
+    {
+        const int e = tid & 15, part = tid >> 4;
+        double sv = 0.0, so = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = part + 16 * q;
+            sv = fma(sh.v[i][e], sh.v[i][e], sv);
+            so = fma(sh.o[i][e], sh.o[i][e], so);
+        }
+        static_assert(MSZ >= 256, "one partial sum per thread");
+        sh.work[0][tid] = sv;
+        sh.work[1][tid] = so;
+    }
+    __syncthreads();
     if (tid < 16) {
         double sv = 0.0, so = 0.0;
-        for (int i = 0; i < 64; ++i) {
-            sv = fma(sh.v[i][tid], sh.v[i][tid], sv);
-            so = fma(sh.o[i][tid], sh.o[i][tid], so);
+        for (int part = 0; part < 16; ++part) {
+            sv += sh.work[0][16 * part + tid];
+            so += sh.work[1][16 * part + tid];
         }
         double d = 1.0;
         if (sv > 0.0 && so > 0.0 && isfinite(sv) && isfinite(so)) {
@@ -280,11 +328,41 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
         }
     }
     __syncthreads();
-    // A^2, A^4, A^8, B = A^16, B^2, B^4, B^8, G = B^16 = Phi'^C
-    for (int j = 0; j < 8; ++j) {
-        if (wv == 0) mm16m(sh.pw[j], sh.pw[j], sh.pw[j + 1], lane);
-        __syncthreads();
+    // per-lane MFMA operands (TT_TOP order): lane l = 16 g + n, k-step s
+    auto operand = [&](int e) {
+        const int blk = e >> 10, r = e & 1023;
+        const int idx = r >> 8, ln = (r >> 2) & 63, s = r & 3;
+        const int n = ln & 15, g = ln >> 4;
+        double val;
+        if (blk == 0) {            // T: h[16 delta + n - 4g - s]
+            const int m = 16 * idx + n - 4 * g - s;
+            val = m < 0 ? 0.0 : sh.h[m];
+        } else if (blk == 1) {     // Gam'[n][16 b + 4 g + s] = (Phi^(63-k) gamma)[n] / D[n]
+            const int k = 16 * idx + 4 * g + s;
+            val = sh.v[63 - k][n] / sh.dsc[n];
+        } else if (blk == 2) {     // O'[16 r + n][4 g + s] = (c Phi^i)[state] D[state]
+            const int st = 4 * g + s;
+            val = sh.o[16 * idx + n][st] * sh.dsc[st];
+        } else {                   // A^(2^j) or B^(2^j): [n][4 g + s]
+            const double *Pm = sh.pw[(blk == 3 ? 0 : 4) + idx];
+            val = Pm[n * RS + 4 * g + s];
+        }
+        tt[TT_TOP + e] = (float)val;
+    };
+    // A^2, A^4, A^8, B = A^16, B^2, B^4, B^8, G = B^16 = Phi'^C by wave 0
+    // alone (a wave's LDS accesses complete in order), while the other
+    // three waves write the T, Gam and O operands, which need none of them
+    if (wv == 0) {
+        for (int j = 0; j < 8; ++j) {
+            mm16m(sh.pw[j], sh.pw[j], sh.pw[j + 1], lane);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    } else {
+        static_assert(3 * 1024 % 192 == 0, "T, Gam and O operands over waves 1-3");
+#pragma unroll 4
+        for (int i = 0; i < 3 * 1024 / 192; ++i) operand(tid - 64 + 192 * i);
     }
+    __syncthreads();
     // column powers A^c (work[0..15]) and tile powers B^t (work[16..31])
     ident16(sh.work[0], tid);
     ident16(sh.work[16], tid);
@@ -338,33 +416,20 @@ __global__ void __launch_bounds__(256) sos_toep_prep_kernel(const float *section
     if (wv == 0) mm16m(sh.work[10], sh.work[9], sh.work[11], lane);       // H^24
     __syncthreads();
     static_assert(kMaxDist <= 32, "high factors H^0, H^8, H^16, H^24");
-    for (int d = wv; d < kMaxDist; d += 4) {
-        const v4d acc = mm16m_acc(sh.work[8 + (d >> 3)], sh.work[d & 7], lane);
+    static_assert(kMaxDist % 8 == 0, "two independent products per wave and pass");
+    for (int d = wv; d < kMaxDist; d += 8) {
+        const v4d a0 = mm16m_acc(sh.work[8 + (d >> 3)], sh.work[d & 7], lane);
+        const v4d a1 = mm16m_acc(sh.work[8 + ((d + 4) >> 3)], sh.work[(d + 4) & 7], lane);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            tt[TT_HPOW + d * 256 + (4 * r + (lane >> 4)) * 16 + (lane & 15)] = (float)acc[r];
-    }
-    // per-lane MFMA operands: lane l = 16 g + n, k-step s
-    for (int e = tid; e < 5 * 1024; e += 256) {
-        const int blk = e >> 10, r = e & 1023;
-        const int idx = r >> 8, lane = (r >> 2) & 63, s = r & 3;
-        const int n = lane & 15, g = lane >> 4;
-        double val;
-        if (blk == 0) {            // T: h[16 delta + n - 4g - s]
-            const int m = 16 * idx + n - 4 * g - s;
-            val = m < 0 ? 0.0 : sh.h[m];
-        } else if (blk == 1) {     // Gam'[n][16 b + 4 g + s] = (Phi^(63-k) gamma)[n] / D[n]
-            const int k = 16 * idx + 4 * g + s;
-            val = sh.v[63 - k][n] / sh.dsc[n];
-        } else if (blk == 2) {     // O'[16 r + n][4 g + s] = (c Phi^i)[state] D[state]
-            const int st = 4 * g + s;
-            val = sh.o[16 * idx + n][st] * sh.dsc[st];
-        } else {                   // A^(2^j) or B^(2^j): [n][4 g + s]
-            const double *Pm = sh.pw[(blk == 3 ? 0 : 4) + idx];
-            val = Pm[n * RS + 4 * g + s];
+        for (int r = 0; r < 4; ++r) {
+            const int at = (4 * r + (lane >> 4)) * 16 + (lane & 15);
+            tt[TT_HPOW + d * 256 + at] = (float)a0[r];
+            tt[TT_HPOW + (d + 4) * 256 + at] = (float)a1[r];
         }
-        tt[TT_TOP + e] = (float)val;
     }
+    // the scan operands (powers of A and B)
+#pragma unroll
+    for (int i = 0; i < 2 * 1024 / 256; ++i) operand(3 * 1024 + tid + 256 * i);
     if (tid == 0) {
         tt[TT_K] = (float)K;
         tt[TT_NG] = (float)ng;
