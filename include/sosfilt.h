@@ -172,8 +172,8 @@ int sos_get_precision(sos_handle_t h);
  * overrides) instead of one per group and section.
  * Its cost per sample does not grow with K, but a call takes at least about
  * 0.07 ms (its tables, and chunks that must fill the device).
- * SOS_ALG_AUTO takes it for plain FP32 forward calls with K = 8 on at least
- * 2^25 samples, K = 7 on at least 2^26, or K = 6 on at least 2^27, when
+ * SOS_ALG_AUTO takes it for plain FP32 forward calls with K = 7 or 8 on at
+ * least 2^25 samples, or K = 6 on at least 2^26, when
  * every section's peak gain is at most 128 (decided on the device by the
  * table preparation; other signals run as before, in the same call). Tables
  * from sos_prepare, whose signal length is not known, use 8-group chunks.

@@ -185,8 +185,8 @@ class Handle:
         sections through the whole-cascade block-Toeplitz kernel on the
         matrix cores, everything else as "ph"), or None / "default" (the
         environment's SOS_ALG, else "auto"; "auto" also takes the
-        block-Toeplitz kernel for plain calls of order 16 on at least 2^25
-        samples, order 14 on at least 2^26, order 12 on at least 2^27)."""
+        block-Toeplitz kernel for plain calls of orders 14-16 on at least
+        2^25 samples, order 12 on at least 2^26)."""
         code = _ALGS.get(alg if not isinstance(alg, str) else alg.lower())
         if code is None:
             raise ValueError("unknown algorithm %r" % (alg,))

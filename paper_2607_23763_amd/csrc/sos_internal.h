@@ -244,21 +244,21 @@ inline bool ph_sections(int solver)
 // 16-dimensional state), for cascades whose sections all peak at most
 // kToepRhoMax. The automatic choice takes it where it was measured faster
 // than the faster per-section solver (MI355X, per call, tables included):
-// K = 8 from 2^25 samples (+10 / +24 / +32 / +37 % at 2^25 / 2^26 / 2^27 /
-// 2^28; -9 % at 2^24), K = 7 from 2^26 (+12 / +18 / +23 %; level at 2^25)
-// and K = 6 from 2^27 (+6 / +9 %; level at 2^26); K = 5 stays on the
-// section kernels (-4 % at 2^28). A call takes at least about 0.07 ms (the
-// tables, and chunks of 16384-sample groups that must fill the device),
-// which is what shorter signals cannot amortise.
+// K = 8 from 2^25 samples (+14 / +25 / +32 / +37 % at 2^25 / 2^26 / 2^27 /
+// 2^28; -3 % at 2^24), K = 7 from 2^25 (+4 / +14 / +19 %; -13 % at 2^24)
+// and K = 6 from 2^26 (+1 / +6 %, and +5 / +12 % over DC-CR, which the
+// automatic choice runs otherwise; -7 % at 2^25); K = 5 stays on the
+// section kernels (-7 % at 2^27, -4 % at 2^28). A call takes at least about
+// 0.07 ms (the tables, and chunks of 16384-sample groups that must fill the
+// device), which is what shorter signals cannot amortise.
 constexpr int kToepMaxK = 8;
 
 // Shortest signal the automatic choice filters by the block-Toeplitz path for
 // K sections (none: INT64_MAX).
 inline int64_t toep_auto_min_n(int K)
 {
-    if (K == kToepMaxK) return (int64_t)1 << 25;
-    if (K == 7) return (int64_t)1 << 26;
-    if (K == 6) return (int64_t)1 << 27;
+    if (K == kToepMaxK || K == 7) return (int64_t)1 << 25;
+    if (K == 6) return (int64_t)1 << 26;
     return INT64_MAX;
 }
 constexpr double kToepRhoMax = 128.0;
