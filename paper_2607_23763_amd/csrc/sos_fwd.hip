@@ -377,10 +377,12 @@ __device__ void lookback(const FwdArgs &a, const It &it, const T *stv, int s,
 {
     // One window of kSpan predecessors per round. Every descriptor read is an
     // agent-scope load served beyond the XCD's L2, competing with the sample
-    // stream, so reading few per round wins over fewer rounds: measured on
-    // MI355X, 16 beats 64 (order 2: +8-11 %; order 16 at 4 K-sample groups:
-    // +35 %) and, with the next group prefetched, also 8 and 32 at 32 K-sample
-    // groups (+2-4 %); two or four windows per round lose.
+    // stream, so a window far wider than the walk loses: measured on MI355X,
+    // 64 loses to 16 (order 2: 8-11 %; order 16 at 4 K-sample groups: 35 %);
+    // with the fixed sleep between polls, 32 beats 16 at order 2 (+2.1 / +0.9
+    // / +0.3 % at 2^24 / 2^25 / 2^28 samples; order 8: +1.2 % at 2^24, -0.4 %
+    // at 2^28; order 16 and the uneven batch level) and 8 loses 3-4 %; two or
+    // four windows per round lose.
     constexpr int kWin = 1;
     const M2<T> gp = load_m2(stv + LY::GRPPOW + 4 * lane);   // T^(C lane)
     T acc1 = 0, acc2 = 0;
@@ -731,7 +733,7 @@ __device__ __forceinline__ void section_corr(T (&u)[N], Xch<T, W> &xch, float *t
             sg1 = it.zi ? (S)ctab(it.zi)[2 * s + (PAIR ? 1 : 0)] : S(0);
             sg2 = it.zi ? (S)ctab(it.zi)[2 * s + (PAIR ? 0 : 1)] : S(0);
         } else {
-            lookback<16, LY>(a, it, stv, s, epoch, lane, sg1, sg2);
+            lookback<32, LY>(a, it, stv, s, epoch, lane, sg1, sg2);
         }
         unsigned tk = 0;
         if (draw && lane == 0) tk = atomicAdd(&a.ctrl[CTRL_TICKET], 1u);
