@@ -203,6 +203,32 @@ def test_automatic_choice_takes_the_toeplitz_path(env, monkeypatch):
             del ys, yts
 
 
+@pytest.mark.parametrize("K", [6, 8])
+def test_prepared_tables_serve_any_length(env, monkeypatch, K):
+    """Tables from sos_prepare, whose signal length is unknown (8-group
+    chunks), filter signals shorter than a group, ragged inside a chunk and
+    across chunk edges, with zi and zf; the automatic choice's prepared
+    tables give the same parity on lengths below its threshold."""
+    torch, P = env
+    monkeypatch.delenv("SOS_TOEP_CHUNK", raising=False)
+    monkeypatch.delenv("SOS_ALG", raising=False)
+    sos = workloads.sweep_sections(K, "random")
+    for alg in ("toeplitz", "auto"):
+        h = P.Handle(0, algorithm=alg)
+        P.prepare(dev(torch, sos), handle=h)
+        for n in (CG - 3, 3 * CG + 77, CHUNK + 1, 2 * CHUNK + 4097):
+            x = workloads.signal(n, n % 101)
+            zi = workloads.initial_state(K, workloads.rng(n % 7))
+            xd = dev(torch, x)
+            yd = torch.empty_like(xd)
+            zf = torch.empty((K, 2), dtype=torch.float32, device="cuda")
+            P.filter_prepared(xd, yd, zi=dev(torch, zi), zf=zf, handle=h)
+            torch.cuda.synchronize()
+            assert h.last_error() == P.SOS_OK
+            check(sos, x, zi, yd.cpu().numpy(), zf.cpu().numpy(),
+                  "prepared %s K=%d n=%d" % (alg, K, n))
+
+
 def lightly_damped_sections(K=8, r=0.995, seed=9):
     sos = workloads.random_stable_sos(K, workloads.rng(seed), r_fixed=r)
     imp = np.zeros(40000)
