@@ -3,7 +3,8 @@ every signal, stream and gradient the benchmark times is compared with the
 FP64 oracle (the oracle runs on the host's cores, the data moves in slices so
 host memory stays bounded).
 
-* one signal of 2^28 samples (orders 2 and 16, Butterworth and random): the
+* one signal of 2^28 samples (orders 2 and 16, Butterworth and random, with
+  the default solver; orders 2 and 8 with the block-Toeplitz kernel): the
   relative L2 error, the paper's gate max |error| / max |reference| < 1e-4
   (Sec. IV-F), and the relative error of every group of C samples, so that a
   single wrong group cannot hide in the whole signal's norm;
@@ -54,14 +55,18 @@ def group_errors(y, yr, C):
     return np.linalg.norm(e, axis=1) / np.maximum(np.linalg.norm(r, axis=1), 1e-300)
 
 
-@pytest.mark.parametrize("kind,K", [("butter", 1), ("butter", 8), ("random", 8)])
-def test_2p28_every_group(env, kind, K):
-    """2^28 samples with the default handle (the benchmark's plain launch)."""
+@pytest.mark.parametrize("kind,K,alg", [("butter", 1, None), ("butter", 8, None),
+                                        ("random", 8, None), ("butter", 1, "toeplitz"),
+                                        ("random", 4, "toeplitz")])
+def test_2p28_every_group(env, kind, K, alg):
+    """2^28 samples with the default handle (the benchmark's plain launch;
+    order 16 takes the block-Toeplitz kernel), and with an explicit
+    block-Toeplitz handle at lower orders (the sweep's block-Toeplitz legs)."""
     torch, P = env
     sos = workloads.sweep_sections(K, kind)
     n = 1 << 28
     x = workloads.signal(n, seed=2)
-    h = P.Handle(0)
+    h = P.Handle(0) if alg is None else P.Handle(0, algorithm=alg)
     xd = torch.from_numpy(x).cuda()
     y, zf = P.sosfilt(xd, torch.from_numpy(sos).cuda(), handle=h)
     torch.cuda.synchronize()
@@ -73,7 +78,7 @@ def test_2p28_every_group(env, kind, K):
     e = rel_l2(yh, yr)
     mp = max_over_peak(yh, yr)
     ge = group_errors(yh, yr, L * N)
-    print("2^28", kind, "K", K, "rel_l2 %.3e max/peak %.3e groups %d: max %.3e median %.3e"
+    print("2^28", kind, "K", K, alg or "default", "rel_l2 %.3e max/peak %.3e groups %d: max %.3e median %.3e"
           % (e, mp, ge.size, ge.max(), np.median(ge)))
     by = tol_for(K)
     if e > by or ge.max() > by:
