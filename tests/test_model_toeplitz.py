@@ -14,14 +14,17 @@ from tests.gpu_util import fp32_floor, rel_l2
 SMALL = dict(M=8, TC=4, NT=4, NG=2)        # 128-sample groups, 256-sample chunks
 
 
+@pytest.mark.parametrize("ng", [2, 4])
 @pytest.mark.parametrize("K", [1, 3, 8])
 @pytest.mark.parametrize("n", [1, 7, 8, 127, 128, 256, 1000, 2049])
-def test_fp64_model_matches_oracle(K, n):
+def test_fp64_model_matches_oracle(K, n, ng):
+    """Every column, tile, group and chunk boundary of the small shape, with
+    chunks of 2 and 4 groups (the chunk map H = G^NG and its powers)."""
     sos = workloads.sweep_sections(K, "random")
     x = workloads.signal(n, 3 + n)
     zi = workloads.initial_state(K, workloads.rng(K))
     ref, zref = oracle.sosfilt(sos.astype(np.float64), x.astype(np.float64), zi.astype(np.float64))
-    y, zf = TM.run(sos, x, zi, **SMALL, rng=np.random.default_rng(n))
+    y, zf = TM.run(sos, x, zi, **dict(SMALL, NG=ng), rng=np.random.default_rng(n))
     assert rel_l2(y, ref) < 1e-10
     assert rel_l2(zf, np.asarray(zref).reshape(K, 2)) < 1e-10
 
